@@ -1,0 +1,538 @@
+/*
+ * Plain FP64 CPU oracle for WCNS-T (TCNS), arXiv:1810.07806.
+ *
+ * TEST INFRASTRUCTURE ONLY: the reference the HIP path is checked against.
+ * Only tests, the smoke check and the benchmark's CPU-baseline leg load it.
+ * It shares no code with the HIP path.  Built with -O2 -ffp-contract=off and
+ * no fast-math so every operation is rounded as written, in the order the
+ * paper writes it.
+ *
+ * The steps and where they come from:
+ *   semi-discretisation du_i/dt = -f'_i ........... Sec. 2, Eq. (2)
+ *   SSP-RK3 (Shu-Osher form) ...................... Sec. 2 (cites Gottlieb et al. 2001)
+ *   MND / MD flux differences ..................... Sec. 2.1, Eqs. (5) and (3)
+ *   scalar upwind midpoint flux ................... Sec. 2.2, Eq. (6)
+ *   candidate interpolants, derivatives ........... Sec. 2.2, Eqs. (9)-(11)
+ *   optimal linear weights d_k .................... Sec. 2.2, Eq. (13)
+ *   Jiang-Shu weights / smoothness indicator ...... Sec. 2.2, Eqs. (14)-(15)
+ *   TENO measure, normalisation, cut-off, weights . Sec. 2.3, Eqs. (16)-(19)
+ *   characteristic-wise interpolation, ideal gas .. Sec. 3 (opening paragraph)
+ *   Roe flux-difference splitting ................. Sec. 1 (named); the system
+ *                                                   form of Eq. (6) with |A| = R|Lambda|L
+ * The paper does not print the difference coefficients, the Runge-Kutta
+ * form, the Roe average or the eigenvectors; the readings used here are:
+ *   MND: (c1, c2, c3) = (3/2, -3/10, 1/30); MD: (75/64, -25/384, 3/640),
+ *        the unique sixth-order solutions of the Taylor conditions.
+ *   h cancels in beta_k (Eq. (15)) and in the candidates (Eq. (9)); the
+ *        scaled differences D1 = h u^(1), D2 = h^2 u^(2) are used directly.
+ *   delta_k = 1 when chi_k == C_T ("otherwise" branch of Eq. (18)).
+ *   Characteristic projection uses the Roe average of the two nodes next to
+ *   the midpoint and the textbook conserved-variable eigenvectors.
+ *   No entropy fix in the Roe flux (Eq. (6) uses the plain |a|).
+ */
+#include "wcnst_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define GHOST 5
+
+/* ---------------------------------------------------------------- sizes */
+
+int orc_nvar(const orc_problem* p)
+{
+    if (p->system == ORC_EULER) return p->ndim == 1 ? 3 : 4;
+    return 1;
+}
+
+static int first_face(const orc_problem* p) { return p->diff == ORC_MD ? -3 : -2; }
+
+int orc_nfaces(const orc_problem* p, int n) { return p->diff == ORC_MD ? n + 5 : n + 3; }
+
+int64_t orc_flag_count(const orc_problem* p)
+{
+    int64_t nv = orc_nvar(p);
+    int64_t c = nv * (int64_t)p->ny * orc_nfaces(p, p->nx) * 2;
+    if (p->ndim == 2) c += nv * (int64_t)p->nx * orc_nfaces(p, p->ny) * 2;
+    return c;
+}
+
+static int validate(const orc_problem* p)
+{
+    if (p->ndim != 1 && p->ndim != 2) return ORC_E_INVALID;
+    if (p->ndim == 2 && p->system != ORC_EULER) return ORC_E_INVALID;
+    if (p->nx < 5 || p->ny < 1) return ORC_E_INVALID;
+    if (p->ndim == 1 && p->ny != 1) return ORC_E_INVALID;
+    if (p->ndim == 2 && p->ny < 5) return ORC_E_INVALID;
+    if (!(p->dx > 0) || (p->ndim == 2 && !(p->dy > 0))) return ORC_E_INVALID;
+    if (p->system == ORC_EULER && !(p->gamma > 1)) return ORC_E_INVALID;
+    if (p->q < 1) return ORC_E_INVALID;
+    return ORC_OK;
+}
+
+/* ------------------------------------------- Sec. 2.2-2.3 interpolation */
+
+/* Optimal linear weights, Eq. (13). */
+static const double D_OPT[3] = {1.0 / 16.0, 10.0 / 16.0, 5.0 / 16.0};
+
+void orc_candidates(const double s[5], double cand[3], double beta[3])
+{
+    const double a = s[0], b = s[1], c = s[2], d = s[3], e = s[4];
+    double D1[3], D2[3];
+    /* Eq. (10) times h and Eq. (11) times h^2, on the substencils of Eq. (8). */
+    D1[0] = (a - 4.0 * b + 3.0 * c) / 2.0;
+    D1[1] = (d - b) / 2.0;
+    D1[2] = (-3.0 * c + 4.0 * d - e) / 2.0;
+    D2[0] = a - 2.0 * b + c;
+    D2[1] = b - 2.0 * c + d;
+    D2[2] = c - 2.0 * d + e;
+    for (int k = 0; k < 3; ++k) {
+        /* Eq. (9) with Delta x = h/2: u_i + u' h/2 + u'' h^2/8. */
+        cand[k] = c + D1[k] / 2.0 + D2[k] / 8.0;
+        /* Eq. (15). */
+        beta[k] = D1[k] * D1[k] + D2[k] * D2[k];
+    }
+}
+
+double orc_interp_left(const orc_problem* p, const double s[5], double chi[3],
+                       int delta[3])
+{
+    double cand[3], beta[3], w[3];
+    double chi_l[3] = {0, 0, 0};
+    int del_l[3] = {1, 1, 1};
+    orc_candidates(s, cand, beta);
+
+    if (p->scheme == ORC_LINEAR) {
+        /* Eq. (12): the optimal linear scheme. */
+        for (int k = 0; k < 3; ++k) { w[k] = D_OPT[k]; chi_l[k] = D_OPT[k]; }
+    } else if (p->scheme == ORC_JS) {
+        /* Eq. (14). */
+        double alpha[3], sum;
+        for (int k = 0; k < 3; ++k) {
+            double be = beta[k] + p->eps_js;
+            alpha[k] = D_OPT[k] / (be * be);
+        }
+        sum = alpha[0] + alpha[1] + alpha[2];
+        for (int k = 0; k < 3; ++k) { w[k] = alpha[k] / sum; chi_l[k] = w[k]; }
+    } else {
+        /* Eq. (16): gamma_k = (C + tau5 / (beta_k + eps))^q, tau5 = |beta_1 - beta_3|. */
+        double g[3], gsum, dsum;
+        double tau5 = fabs(beta[0] - beta[2]);
+        for (int k = 0; k < 3; ++k) {
+            double x = p->C + tau5 / (beta[k] + p->eps_teno);
+            g[k] = 1.0;
+            for (int m = 0; m < p->q; ++m) g[k] *= x;
+        }
+        /* Eq. (17). */
+        gsum = g[0] + g[1] + g[2];
+        for (int k = 0; k < 3; ++k) chi_l[k] = g[k] / gsum;
+        /* Eq. (18): discard when chi_k < C_T, keep otherwise. */
+        for (int k = 0; k < 3; ++k) del_l[k] = (chi_l[k] < p->CT) ? 0 : 1;
+        /* Eq. (19). */
+        dsum = D_OPT[0] * del_l[0] + D_OPT[1] * del_l[1] + D_OPT[2] * del_l[2];
+        for (int k = 0; k < 3; ++k) w[k] = D_OPT[k] * del_l[k] / dsum;
+    }
+    if (chi) for (int k = 0; k < 3; ++k) chi[k] = chi_l[k];
+    if (delta) for (int k = 0; k < 3; ++k) delta[k] = del_l[k];
+    /* Eq. (12) with the (possibly nonlinear) weights. */
+    return w[0] * cand[0] + w[1] * cand[1] + w[2] * cand[2];
+}
+
+/* ------------------------------------------------------- Euler system */
+
+static double euler_pressure(int nv, double gamma, const double* U)
+{
+    double kin;
+    if (nv == 4) kin = 0.5 * (U[1] * U[1] + U[2] * U[2]) / U[0];
+    else kin = 0.5 * U[1] * U[1] / U[0];
+    /* Ideal gas p = (gamma - 1) rho e, with rho e = E - kinetic energy. */
+    return (gamma - 1.0) * (U[nv - 1] - kin);
+}
+
+void orc_euler_flux(int nv, double gamma, const double* U, double* F)
+{
+    double rho = U[0];
+    double u = U[1] / rho;
+    double p = euler_pressure(nv, gamma, U);
+    F[0] = U[1];
+    F[1] = U[1] * u + p;
+    if (nv == 4) F[2] = U[2] * u;
+    F[nv - 1] = u * (U[nv - 1] + p);
+}
+
+int orc_roe_eigen(int nv, double gamma, const double* UA, const double* UB,
+                  double* L, double* R, double* lam)
+{
+    double rA = UA[0], rB = UB[0];
+    double uA = UA[1] / rA, uB = UB[1] / rB;
+    double vA = nv == 4 ? UA[2] / rA : 0.0, vB = nv == 4 ? UB[2] / rB : 0.0;
+    double HA = (UA[nv - 1] + euler_pressure(nv, gamma, UA)) / rA;
+    double HB = (UB[nv - 1] + euler_pressure(nv, gamma, UB)) / rB;
+    double sA = sqrt(rA), sB = sqrt(rB);
+    double u = (sA * uA + sB * uB) / (sA + sB);
+    double v = (sA * vA + sB * vB) / (sA + sB);
+    double H = (sA * HA + sB * HB) / (sA + sB);
+    double q2 = u * u + v * v;
+    double c2 = (gamma - 1.0) * (H - 0.5 * q2);
+    double c = sqrt(c2);
+    double b1 = (gamma - 1.0) / c2;
+    double b2 = 0.5 * q2 * b1;
+    int bad = !(c2 > 0.0);
+
+    if (nv == 3) {
+        /* columns r_k: (1, u-c, H-uc), (1, u, q2/2), (1, u+c, H+uc) */
+        double Rm[9] = {1.0, 1.0, 1.0,
+                        u - c, u, u + c,
+                        H - u * c, 0.5 * q2, H + u * c};
+        double Lm[9] = {0.5 * (b2 + u / c), -0.5 * (b1 * u + 1.0 / c), 0.5 * b1,
+                        1.0 - b2, b1 * u, -b1,
+                        0.5 * (b2 - u / c), -0.5 * (b1 * u - 1.0 / c), 0.5 * b1};
+        memcpy(R, Rm, sizeof Rm);
+        memcpy(L, Lm, sizeof Lm);
+        lam[0] = u - c; lam[1] = u; lam[2] = u + c;
+    } else {
+        /* columns: acoustic -, entropy, shear, acoustic + */
+        double Rm[16] = {1.0, 1.0, 0.0, 1.0,
+                         u - c, u, 0.0, u + c,
+                         v, v, 1.0, v,
+                         H - u * c, 0.5 * q2, v, H + u * c};
+        double Lm[16] = {0.5 * (b2 + u / c), -0.5 * (b1 * u + 1.0 / c), -0.5 * b1 * v, 0.5 * b1,
+                         1.0 - b2, b1 * u, b1 * v, -b1,
+                         -v, 0.0, 1.0, 0.0,
+                         0.5 * (b2 - u / c), -0.5 * (b1 * u - 1.0 / c), -0.5 * b1 * v, 0.5 * b1};
+        memcpy(R, Rm, sizeof Rm);
+        memcpy(L, Lm, sizeof Lm);
+        lam[0] = u - c; lam[1] = u; lam[2] = u; lam[3] = u + c;
+    }
+    return bad;
+}
+
+static double sound_speed(int nv, double gamma, const double* U)
+{
+    return sqrt(gamma * euler_pressure(nv, gamma, U) / U[0]);
+}
+
+void orc_num_flux(const orc_problem* p, const double* UL, const double* UR, double* F)
+{
+    if (p->system == ORC_ADVECTION) {
+        /* Eq. (6) with f(u) = a u and a_hat = a. */
+        double a = p->adv_speed;
+        F[0] = 0.5 * ((a * UR[0] + a * UL[0]) - fabs(a) * (UR[0] - UL[0]));
+        return;
+    }
+    if (p->system == ORC_BURGERS) {
+        /* Eq. (6) with f(u) = u^2/2; a_hat is the Roe speed (u_L + u_R)/2, or
+         * the local maximum |u| for Lax-Friedrichs. */
+        double fl = 0.5 * UL[0] * UL[0], fr = 0.5 * UR[0] * UR[0];
+        double ah = p->flux == ORC_LF ? fmax(fabs(UL[0]), fabs(UR[0]))
+                                      : 0.5 * (UL[0] + UR[0]);
+        F[0] = 0.5 * ((fr + fl) - fabs(ah) * (UR[0] - UL[0]));
+        return;
+    }
+    {
+        int nv = orc_nvar(p);
+        double FL[4], FR[4], dis[4];
+        orc_euler_flux(nv, p->gamma, UL, FL);
+        orc_euler_flux(nv, p->gamma, UR, FR);
+        if (p->flux == ORC_LF) {
+            double aL = fabs(UL[1] / UL[0]) + sound_speed(nv, p->gamma, UL);
+            double aR = fabs(UR[1] / UR[0]) + sound_speed(nv, p->gamma, UR);
+            double al = fmax(aL, aR);
+            for (int v = 0; v < nv; ++v) dis[v] = al * (UR[v] - UL[v]);
+        } else {
+            /* |A_hat| (U_R - U_L) = R |Lambda| L (U_R - U_L), Roe average of U_L, U_R. */
+            double L[16], R[16], lam[4], alpha[4];
+            orc_roe_eigen(nv, p->gamma, UL, UR, L, R, lam);
+            for (int k = 0; k < nv; ++k) {
+                alpha[k] = 0.0;
+                for (int v = 0; v < nv; ++v) alpha[k] += L[k * nv + v] * (UR[v] - UL[v]);
+            }
+            for (int v = 0; v < nv; ++v) {
+                dis[v] = 0.0;
+                for (int k = 0; k < nv; ++k) dis[v] += R[v * nv + k] * fabs(lam[k]) * alpha[k];
+            }
+        }
+        for (int v = 0; v < nv; ++v) F[v] = 0.5 * ((FR[v] + FL[v]) - dis[v]);
+    }
+}
+
+static void phys_flux(const orc_problem* p, const double* U, double* F)
+{
+    if (p->system == ORC_ADVECTION) F[0] = p->adv_speed * U[0];
+    else if (p->system == ORC_BURGERS) F[0] = 0.5 * U[0] * U[0];
+    else orc_euler_flux(orc_nvar(p), p->gamma, U, F);
+}
+
+/* ----------------------------------------------------- one midpoint flux */
+
+/* st holds the six nodes j-2 .. j+3 around the midpoint x_{j+1/2}, node-major.
+ * fl[v*2 + side] / ch[(v*2 + side)*3 + k] receive the cut flags / chi. */
+static void midpoint_flux(const orc_problem* p, int nv, const double* st, double* F,
+                          uint8_t* fl, double* ch)
+{
+    double W[6][4], wL[4], wR[4], UL[4], UR[4];
+    double L[16], R[16], lam[4];
+    int charwise = p->system == ORC_EULER && p->charwise;
+
+    if (charwise) {
+        orc_roe_eigen(nv, p->gamma, st + 2 * nv, st + 3 * nv, L, R, lam);
+        for (int m = 0; m < 6; ++m)
+            for (int k = 0; k < nv; ++k) {
+                double acc = 0.0;
+                for (int v = 0; v < nv; ++v) acc += L[k * nv + v] * st[m * nv + v];
+                W[m][k] = acc;
+            }
+    } else {
+        for (int m = 0; m < 6; ++m)
+            for (int k = 0; k < nv; ++k) W[m][k] = st[m * nv + k];
+    }
+    for (int k = 0; k < nv; ++k) {
+        double sl[5] = {W[0][k], W[1][k], W[2][k], W[3][k], W[4][k]};
+        /* mirror image for the right state (Sec. 2.2: "symmetrical form") */
+        double sr[5] = {W[5][k], W[4][k], W[3][k], W[2][k], W[1][k]};
+        double chl[3], chr[3];
+        int dl[3], dr[3];
+        wL[k] = orc_interp_left(p, sl, chl, dl);
+        wR[k] = orc_interp_left(p, sr, chr, dr);
+        if (fl) {
+            fl[k * 2 + 0] = (uint8_t)(dl[0] | (dl[1] << 1) | (dl[2] << 2));
+            fl[k * 2 + 1] = (uint8_t)(dr[0] | (dr[1] << 1) | (dr[2] << 2));
+        }
+        if (ch)
+            for (int m = 0; m < 3; ++m) {
+                ch[(k * 2 + 0) * 3 + m] = chl[m];
+                ch[(k * 2 + 1) * 3 + m] = chr[m];
+            }
+    }
+    if (charwise) {
+        for (int v = 0; v < nv; ++v) {
+            double al = 0.0, ar = 0.0;
+            for (int k = 0; k < nv; ++k) {
+                al += R[v * nv + k] * wL[k];
+                ar += R[v * nv + k] * wR[k];
+            }
+            UL[v] = al;
+            UR[v] = ar;
+        }
+    } else {
+        for (int v = 0; v < nv; ++v) { UL[v] = wL[v]; UR[v] = wR[v]; }
+    }
+    orc_num_flux(p, UL, UR, F);
+}
+
+/* ------------------------------------------------ one grid line, Eq. (2) */
+
+/* line: (n + 2*GHOST) nodes x nv, node-major, ghosts already filled.
+ * out: n x nv node-major, receives -f'_i.  Flag / chi outputs are addressed
+ * for line index li of nlines. */
+static void line_rhs(const orc_problem* p, int nv, int n, double h, const double* line,
+                     double* out, uint8_t* flags, double* chi, int li, int nlines,
+                     double* Fface, double* Fnode)
+{
+    const int nf = orc_nfaces(p, n);
+    const int j0 = first_face(p);
+    for (int s = 0; s < nf; ++s) {
+        int j = j0 + s;
+        uint8_t fl[8];
+        double ch[24];
+        const double* st = line + (size_t)(j - 2 + GHOST) * nv;
+        midpoint_flux(p, nv, st, Fface + (size_t)s * nv, flags ? fl : NULL, chi ? ch : NULL);
+        for (int k = 0; k < nv; ++k)
+            for (int side = 0; side < 2; ++side) {
+                size_t idx = (((size_t)k * nlines + li) * nf + s) * 2 + side;
+                if (flags) flags[idx] = fl[k * 2 + side];
+                if (chi)
+                    for (int m = 0; m < 3; ++m) chi[idx * 3 + m] = ch[(k * 2 + side) * 3 + m];
+            }
+    }
+    if (p->diff == ORC_MND) {
+        /* Eq. (5): c1 (F_{i+1/2}-F_{i-1/2}) + c2 (f_{i+1}-f_{i-1}) + c3 (F_{i+3/2}-F_{i-3/2}) */
+        const double c1 = 3.0 / 2.0, c2 = -3.0 / 10.0, c3 = 1.0 / 30.0;
+        for (int i = -1; i <= n; ++i)
+            phys_flux(p, line + (size_t)(i + GHOST) * nv, Fnode + (size_t)(i + 1) * nv);
+        for (int i = 0; i < n; ++i)
+            for (int v = 0; v < nv; ++v) {
+                double Fp1 = Fface[(size_t)(i + 2) * nv + v], Fm1 = Fface[(size_t)(i + 1) * nv + v];
+                double Fp3 = Fface[(size_t)(i + 3) * nv + v], Fm3 = Fface[(size_t)(i + 0) * nv + v];
+                double fp = Fnode[(size_t)(i + 2) * nv + v], fm = Fnode[(size_t)(i + 0) * nv + v];
+                double dfdx = c1 / h * (Fp1 - Fm1) + c2 / h * (fp - fm) + c3 / h * (Fp3 - Fm3);
+                out[(size_t)i * nv + v] = -dfdx;
+            }
+    } else {
+        /* Eq. (3): a1 (F_{i+1/2}-F_{i-1/2}) + a2 (F_{i+3/2}-F_{i-3/2}) + a3 (F_{i+5/2}-F_{i-5/2}) */
+        const double a1 = 75.0 / 64.0, a2 = -25.0 / 384.0, a3 = 3.0 / 640.0;
+        for (int i = 0; i < n; ++i)
+            for (int v = 0; v < nv; ++v) {
+                double Fp1 = Fface[(size_t)(i + 3) * nv + v], Fm1 = Fface[(size_t)(i + 2) * nv + v];
+                double Fp3 = Fface[(size_t)(i + 4) * nv + v], Fm3 = Fface[(size_t)(i + 1) * nv + v];
+                double Fp5 = Fface[(size_t)(i + 5) * nv + v], Fm5 = Fface[(size_t)(i + 0) * nv + v];
+                double dfdx = a1 / h * (Fp1 - Fm1) + a2 / h * (Fp3 - Fm3) + a3 / h * (Fp5 - Fm5);
+                out[(size_t)i * nv + v] = -dfdx;
+            }
+    }
+}
+
+/* Ghost index map: periodic wrap or zero-gradient copy of the end value. */
+static int ghost_index(int g, int n, int bc)
+{
+    if (bc == ORC_PERIODIC) return ((g % n) + n) % n;
+    if (g < 0) return 0;
+    if (g >= n) return n - 1;
+    return g;
+}
+
+int orc_rhs(const orc_problem* p, const double* U, double* R, uint8_t* flags, double* chi,
+            int nthreads)
+{
+    int st = validate(p);
+    if (st) return st;
+    const int nv = orc_nvar(p);
+    const int nx = p->nx, ny = p->ny;
+    const size_t plane = (size_t)nx * ny;
+    if (nthreads < 1) nthreads = 1;
+
+    /* x direction: one line per row, variables in their natural order. */
+#pragma omp parallel num_threads(nthreads)
+    {
+        int nmax = nx > ny ? nx : ny;
+        double* line = (double*)malloc(sizeof(double) * (size_t)(nmax + 2 * GHOST) * nv);
+        double* out = (double*)malloc(sizeof(double) * (size_t)nmax * nv);
+        double* Ff = (double*)malloc(sizeof(double) * (size_t)(nmax + 5) * nv);
+        double* Fn = (double*)malloc(sizeof(double) * (size_t)(nmax + 2) * nv);
+#pragma omp for schedule(static)
+        for (int y = 0; y < ny; ++y) {
+            for (int g = -GHOST; g < nx + GHOST; ++g) {
+                int x = ghost_index(g, nx, p->bc_x);
+                for (int v = 0; v < nv; ++v)
+                    line[(size_t)(g + GHOST) * nv + v] = U[v * plane + (size_t)y * nx + x];
+            }
+            line_rhs(p, nv, nx, p->dx, line, out, flags, chi, y, ny, Ff, Fn);
+            for (int x = 0; x < nx; ++x)
+                for (int v = 0; v < nv; ++v)
+                    R[v * plane + (size_t)y * nx + x] = out[(size_t)x * nv + v];
+        }
+        if (p->ndim == 2) {
+            /* y direction: one line per column, normal momentum first. */
+            static const int perm[4] = {0, 2, 1, 3};
+            uint8_t* fy = flags ? flags + (size_t)nv * ny * orc_nfaces(p, nx) * 2 : NULL;
+            double* cy = chi ? chi + (size_t)nv * ny * orc_nfaces(p, nx) * 2 * 3 : NULL;
+#pragma omp for schedule(static)
+            for (int x = 0; x < nx; ++x) {
+                for (int g = -GHOST; g < ny + GHOST; ++g) {
+                    int y = ghost_index(g, ny, p->bc_y);
+                    for (int v = 0; v < nv; ++v)
+                        line[(size_t)(g + GHOST) * nv + v] = U[perm[v] * plane + (size_t)y * nx + x];
+                }
+                line_rhs(p, nv, ny, p->dy, line, out, fy, cy, x, nx, Ff, Fn);
+                for (int y = 0; y < ny; ++y)
+                    for (int v = 0; v < nv; ++v) {
+                        size_t idx = perm[v] * plane + (size_t)y * nx + x;
+                        R[idx] = R[idx] + out[(size_t)y * nv + v];
+                    }
+            }
+        }
+        free(line); free(out); free(Ff); free(Fn);
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------ time stepping */
+
+double orc_max_speed(const orc_problem* p, const double* U)
+{
+    const int nv = orc_nvar(p);
+    const size_t plane = (size_t)p->nx * p->ny;
+    double smax = 0.0;
+    for (size_t c = 0; c < plane; ++c) {
+        double s;
+        if (p->system == ORC_ADVECTION) {
+            s = fabs(p->adv_speed) / p->dx;
+        } else if (p->system == ORC_BURGERS) {
+            s = fabs(U[c]) / p->dx;
+        } else {
+            double cell[4];
+            for (int v = 0; v < nv; ++v) cell[v] = U[v * plane + c];
+            double a = sound_speed(nv, p->gamma, cell);
+            s = (fabs(cell[1] / cell[0]) + a) / p->dx;
+            if (nv == 4) s = s + (fabs(cell[2] / cell[0]) + a) / p->dy;
+        }
+        /* a NaN speed must poison the maximum */
+        if (!(s <= smax)) smax = s;
+    }
+    return smax;
+}
+
+/* First non-physical cell in row-major order, or -1. */
+static int64_t first_bad_cell(const orc_problem* p, const double* U)
+{
+    const int nv = orc_nvar(p);
+    const size_t plane = (size_t)p->nx * p->ny;
+    for (size_t c = 0; c < plane; ++c) {
+        double cell[4];
+        int bad = 0;
+        for (int v = 0; v < nv; ++v) {
+            cell[v] = U[v * plane + c];
+            if (!isfinite(cell[v])) bad = 1;
+        }
+        if (!bad && p->system == ORC_EULER)
+            bad = !(cell[0] > 0.0) || !(euler_pressure(nv, p->gamma, cell) > 0.0);
+        if (bad) return (int64_t)c;
+    }
+    return -1;
+}
+
+int orc_rk3_step(const orc_problem* p, double* U, double dt, int64_t stage_base,
+                 int64_t* bad_stage, int64_t* bad_cell, int nthreads)
+{
+    int st = validate(p);
+    if (st) return st;
+    const size_t n = (size_t)orc_nvar(p) * p->nx * p->ny;
+    double* R = (double*)malloc(sizeof(double) * n);
+    double* U1 = (double*)malloc(sizeof(double) * n);
+    double* U2 = (double*)malloc(sizeof(double) * n);
+    int64_t bad;
+    int ret = ORC_OK;
+
+    /* U1 = U^n + dt R(U^n) */
+    orc_rhs(p, U, R, NULL, NULL, nthreads);
+    for (size_t i = 0; i < n; ++i) U1[i] = U[i] + dt * R[i];
+    if ((bad = first_bad_cell(p, U1)) >= 0) { *bad_stage = stage_base; *bad_cell = bad; ret = ORC_E_NONPHYSICAL; goto done; }
+    /* U2 = 3/4 U^n + 1/4 (U1 + dt R(U1)) */
+    orc_rhs(p, U1, R, NULL, NULL, nthreads);
+    for (size_t i = 0; i < n; ++i) U2[i] = 0.75 * U[i] + 0.25 * (U1[i] + dt * R[i]);
+    if ((bad = first_bad_cell(p, U2)) >= 0) { *bad_stage = stage_base + 1; *bad_cell = bad; ret = ORC_E_NONPHYSICAL; goto done; }
+    /* U^{n+1} = 1/3 U^n + 2/3 (U2 + dt R(U2)) */
+    orc_rhs(p, U2, R, NULL, NULL, nthreads);
+    for (size_t i = 0; i < n; ++i) U[i] = (1.0 / 3.0) * U[i] + (2.0 / 3.0) * (U2[i] + dt * R[i]);
+    if ((bad = first_bad_cell(p, U)) >= 0) { *bad_stage = stage_base + 2; *bad_cell = bad; ret = ORC_E_NONPHYSICAL; goto done; }
+done:
+    free(R); free(U1); free(U2);
+    return ret;
+}
+
+int orc_solve(const orc_problem* p, double* U, double t0, double t_final, double cfl,
+              int64_t max_steps, double* t_out, int64_t* steps_out, int64_t* bad_stage,
+              int64_t* bad_cell, int nthreads)
+{
+    int st = validate(p);
+    double t = t0;
+    int64_t steps = 0;
+    if (st) return st;
+    for (;;) {
+        if (isfinite(t_final) && t_final - t <= 1e-12 * t_final) break;
+        if (steps >= max_steps) {
+            if (isfinite(t_final)) { st = ORC_E_MAX_STEPS; }
+            break;
+        }
+        double dt = cfl / orc_max_speed(p, U);
+        if (isfinite(t_final) && dt > t_final - t) dt = t_final - t;
+        st = orc_rk3_step(p, U, dt, 3 * steps, bad_stage, bad_cell, nthreads);
+        if (st) break;
+        t = t + dt;
+        steps = steps + 1;
+    }
+    if (t_out) *t_out = t;
+    if (steps_out) *steps_out = steps;
+    return st;
+}

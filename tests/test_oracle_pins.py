@@ -1,0 +1,535 @@
+"""Pins of the CPU oracle to what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: values the
+paper prints (Tables 1-3), closed-form special cases, polynomial exactness,
+Taylor-derived coefficients, invariants (conservation, free stream,
+symmetry, L R = I, the Roe property) and an exact Riemann solution.
+"""
+from __future__ import annotations
+
+import math
+import os
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+from paper_1810_07806_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _table(name):
+    rows = []
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+def _table1():
+    out = {}
+    for r in _table("table1_coefficients.txt"):
+        out[(int(r[0]), int(r[1]), int(r[2]))] = [Fr(x) for x in r[3:]]
+    return out
+
+
+def _scalar(orc, **kw):
+    return orc.problem(W.describe(ndim=1, system="advection", nx=16, **kw))
+
+
+# ------------------------------------------------------------ Table 1, Eq. (7)
+
+def _candidate_rows():
+    """Exact rational coefficient vectors (over u_{i-2}..u_{i+2}) of the three
+    candidates, from Eqs. (9)-(11) with Delta x = h/2."""
+    e = [[Fr(int(i == j)) for j in range(5)] for i in range(5)]
+    a, b, c, d, ee = e
+
+    def lin(*terms):
+        return [sum(co * v[j] for co, v in terms) for j in range(5)]
+
+    D1 = [lin((Fr(1, 2), a), (Fr(-2), b), (Fr(3, 2), c)),
+          lin((Fr(1, 2), d), (Fr(-1, 2), b)),
+          lin((Fr(-3, 2), c), (Fr(2), d), (Fr(-1, 2), ee))]
+    D2 = [lin((1, a), (-2, b), (1, c)), lin((1, b), (-2, c), (1, d)), lin((1, c), (-2, d), (1, ee))]
+    return [lin((1, c), (Fr(1, 2), D1[k]), (Fr(1, 8), D2[k])) for k in range(3)]
+
+
+def test_table1_follows_from_the_weights_of_eq19():
+    """Every Table 1 row equals sum_k omega_k^(T) u_{L,k} in exact rationals."""
+    d = [Fr(1, 16), Fr(10, 16), Fr(5, 16)]
+    cand = _candidate_rows()
+    for mask, row in _table1().items():
+        s = sum(d[k] * mask[k] for k in range(3))
+        w = [d[k] * mask[k] / s for k in range(3)]
+        got = [sum(w[k] * cand[k][j] for k in range(3)) for j in range(5)]
+        assert got == row, mask
+
+
+def test_linear_row_is_eq7():
+    """Eq. (7): u_i + (3u_{i-2} - 20u_{i-1} - 38u_i + 60u_{i+1} - 5u_{i+2})/128."""
+    eq7 = [Fr(3, 128), Fr(-20, 128), 1 + Fr(-38, 128), Fr(60, 128), Fr(-5, 128)]
+    assert _table1()[(1, 1, 1)] == eq7
+
+
+def _probe_coefficients(orc, p, s0, mask):
+    """Recover the linear coefficients the oracle applies around s0 by
+    one-sided probing, checking the cut pattern does not change."""
+    v0, _, d0 = orc.interp_left(p, s0)
+    assert tuple(d0) == mask
+    coef = []
+    for m in range(5):
+        t = 1e-4 * max(1.0, abs(s0[m]))
+        s1 = np.array(s0, dtype=np.float64)
+        s1[m] += t
+        v1, _, d1 = orc.interp_left(p, s1)
+        assert tuple(d1) == mask
+        coef.append((v1 - v0) / t)
+    return np.array(coef), v0
+
+
+def test_oracle_interpolation_reproduces_table1(orc):
+    p = _scalar(orc)
+    table = _table1()
+    rng = np.random.default_rng(1)
+    found = {}
+    for _ in range(200000):
+        s = np.round(rng.normal(size=5) * rng.choice([0.01, 1.0, 100.0], size=5), 3)
+        _, _, dl = orc.interp_left(p, s)
+        key = tuple(int(x) for x in dl)
+        if key not in found:
+            found[key] = s
+        if len(found) == 7:
+            break
+    assert set(found) == set(table)
+    for mask, s in found.items():
+        coef, v0 = _probe_coefficients(orc, p, s, mask)
+        want = np.array([float(x) for x in table[mask]])
+        scale = max(1.0, float(np.abs(s).max()))
+        assert np.allclose(coef, want, rtol=0, atol=1e-8 * scale), (mask, coef, want)
+        assert v0 == pytest.approx(float(np.dot(want, s)), rel=1e-12, abs=1e-12 * scale)
+
+
+def test_linear_scheme_coefficients(orc):
+    p = _scalar(orc, scheme="linear")
+    want = [float(x) for x in _table1()[(1, 1, 1)]]
+    for m in range(5):
+        e = np.zeros(5)
+        e[m] = 1.0
+        assert orc.interp_left(p, e)[0] == pytest.approx(want[m], rel=1e-15)
+
+
+# ----------------------------------------------------- polynomial exactness
+
+@pytest.mark.parametrize("deg", [0, 1, 2])
+def test_candidates_exact_to_degree_2(orc, deg):
+    rng = np.random.default_rng(deg)
+    co = rng.normal(size=deg + 1)
+    h = 0.37
+    x = np.arange(-2, 3) * h
+    s = np.polyval(co, x)
+    cand, _ = orc.candidates(s)
+    assert np.allclose(cand, np.polyval(co, h / 2), rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("deg", [3, 4])
+def test_linear_scheme_exact_to_degree_4(orc, deg):
+    p = _scalar(orc, scheme="linear")
+    rng = np.random.default_rng(10 + deg)
+    co = rng.normal(size=deg + 1)
+    h = 0.21
+    s = np.polyval(co, np.arange(-2, 3) * h)
+    assert orc.interp_left(p, s)[0] == pytest.approx(np.polyval(co, h / 2), rel=1e-12, abs=1e-13)
+    if deg == 4:  # each single candidate is not
+        cand, _ = orc.candidates(s)
+        assert np.abs(cand - np.polyval(co, h / 2)).min() > 1e-6
+
+
+# --------------------------------------------------- TENO closed forms
+
+def test_step_cuts_crossing_stencils(orc):
+    """Jump between i and i+1: beta = (0, 5/4, 13/4), tau5 = 13/4, so
+    chi_2 = (1 + 13/5)^6 / (1 + 13/4 * 1e40)^6 to leading order."""
+    p = _scalar(orc)
+    v, chi, d = orc.interp_left(p, [0, 0, 0, 1, 1])
+    assert tuple(d) == (1, 0, 0) and v == 0.0
+    g1 = (1 + 3.25e40) ** 6
+    assert abs(chi[1] - 3.6 ** 6 / g1) <= 1e-12 * (3.6 ** 6 / g1)
+    assert abs(chi[2] - 2.0 ** 6 / g1) <= 1e-12 * (2.0 ** 6 / g1)
+    # and with q = 2 the same stencil gives the squares
+    p2 = orc.problem(W.describe(ndim=1, system="advection", nx=16, q=2))
+    chi2 = orc.interp_left(p2, [0, 0, 0, 1, 1])[1]
+    g1 = (1 + 3.25e40) ** 2
+    assert abs(chi2[1] - 3.6 ** 2 / g1) <= 1e-12 * (3.6 ** 2 / g1)
+    v, chi, d = orc.interp_left(p, [0, 0, 1, 1, 1])
+    assert tuple(d) == (0, 0, 1) and v == 1.0
+
+
+def test_tau5_zero_keeps_all_stencils(orc):
+    """A one-point spike has beta_1 = beta_3 = 13/4, so tau5 = 0, every gamma_k
+    is C^q = 1, chi_k = 1/3 and the linear value 45/64 is returned."""
+    p = _scalar(orc)
+    v, chi, d = orc.interp_left(p, [0, 0, 1, 0, 0])
+    _, beta = orc.candidates([0, 0, 1, 0, 0])
+    assert list(beta) == [3.25, 4.0, 3.25]
+    assert tuple(d) == (1, 1, 1)
+    assert np.allclose(chi, 1 / 3, rtol=1e-15)
+    assert v == 45 / 64
+
+
+def test_cutoff_threshold_is_inclusive(orc):
+    """chi_k == C_T keeps the stencil (the 'otherwise' branch of Eq. (18)):
+    with C_T set to the exact chi of a stencil the flag flips only below it."""
+    base = W.describe(ndim=1, system="advection", nx=16)
+    s = [0.0, 0.3, 0.1, 1.0, 1.2]
+    chi = orc.interp_left(orc.problem(base), s)[1]
+    k = int(np.argmin(chi))
+    at = dict(base, CT=float(chi[k]))
+    above = dict(base, CT=float(np.nextafter(chi[k], 1.0)))
+    assert orc.interp_left(orc.problem(at), s)[2][k] == 1
+    assert orc.interp_left(orc.problem(above), s)[2][k] == 0
+
+
+@pytest.mark.parametrize("n", [16, 32, 64, 256])
+def test_smooth_data_recovers_linear_scheme_bitwise(orc, n):
+    d, U = W.smooth_periodic(n)
+    R, fl, _ = orc.rhs(orc.problem(d), U, flags=True)
+    assert (fl[0] == 7).all()
+    RL, _, _ = orc.rhs(orc.problem(dict(d, scheme="linear")), U)
+    assert np.array_equal(R, RL)
+
+
+# ------------------------------------------------------- MND, Eq. (5)
+
+def test_mnd_coefficients_solve_the_taylor_system():
+    """Sixth order: sum 2 s c = 1 and sum c s^3 = sum c s^5 = 0 at offsets 1/2, 1, 3/2."""
+    c = [Fr(3, 2), Fr(-3, 10), Fr(1, 30)]
+    s = [Fr(1, 2), Fr(1), Fr(3, 2)]
+    assert sum(2 * ck * sk for ck, sk in zip(c, s)) == 1
+    for pw in (3, 5):
+        assert sum(ck * sk ** pw for ck, sk in zip(c, s)) == 0
+    a = [Fr(75, 64), Fr(-25, 384), Fr(3, 640)]
+    s = [Fr(1, 2), Fr(3, 2), Fr(5, 2)]
+    assert sum(2 * ak * sk for ak, sk in zip(a, s)) == 1
+    for pw in (3, 5):
+        assert sum(ak * sk ** pw for ak, sk in zip(a, s)) == 0
+
+
+@pytest.mark.parametrize("diff", ["mnd", "md"])
+@pytest.mark.parametrize("deg", [1, 2, 3, 4])
+def test_rhs_exact_for_polynomials(orc, diff, deg):
+    """Linear interpolation is exact to degree 4 and MND/MD to degree 6, so the
+    advection RHS equals -a u'(x_i) away from the boundary ghosts."""
+    n = 40
+    d = W.describe(ndim=1, system="advection", nx=n, x0=0.0, x1=1.0, scheme="linear",
+                   diff=diff, adv_speed=1.3)
+    x = W.coords(d)
+    rng = np.random.default_rng(deg)
+    co = rng.normal(size=deg + 1)
+    U = np.polyval(co, x).reshape(1, 1, n)
+    R, _, _ = orc.rhs(orc.problem(d), U)
+    want = -1.3 * np.polyval(np.polyder(co), x)
+    sl = slice(6, n - 6)
+    assert np.allclose(R.ravel()[sl], want[sl], rtol=1e-10, atol=1e-10)
+
+
+# ------------------------------------------------------------- order
+
+def _order(errs, ns):
+    return [math.log(errs[i] / errs[i + 1]) / math.log(ns[i + 1] / ns[i]) for i in range(len(ns) - 1)]
+
+
+@pytest.mark.parametrize("scheme", ["teno", "linear"])
+def test_semidiscrete_order_advection(orc, scheme):
+    ns = [32, 64, 128, 256]
+    errs = []
+    for n in ns:
+        d, U = W.smooth_periodic(n)
+        d["scheme"] = scheme
+        R, _, _ = orc.rhs(orc.problem(d), U)
+        x = W.coords(d)
+        errs.append(np.abs(R.ravel() + np.pi * np.cos(np.pi * x)).max())
+    assert min(_order(errs, ns)[1:]) > 4.8
+
+
+def test_semidiscrete_order_euler_charwise_roe(orc):
+    """Density wave rho = 1 + 0.2 sin(pi x), u = 1, p = 1: F = (rho, rho + 1,
+    E + 1) with E = p/(gamma-1) + rho/2, so dF/dx = rho' (1, 1, 1/2)."""
+    ns = [32, 64, 128, 256]
+    errs = []
+    for n in ns:
+        d = W.describe(ndim=1, system="euler", nx=n, x0=-1.0, x1=1.0, bc_x="periodic")
+        x = W.coords(d)
+        rho = 1 + 0.2 * np.sin(np.pi * x)
+        U = W.conserved_1d(rho, np.ones(n), np.ones(n), 1.4).reshape(3, 1, n)
+        R, _, _ = orc.rhs(orc.problem(d), U)
+        dr = 0.2 * np.pi * np.cos(np.pi * x)
+        want = -np.stack([dr, dr, 0.5 * dr])
+        errs.append(np.abs(R.reshape(3, n) - want).max())
+    assert min(_order(errs, ns)[1:]) > 4.8
+
+
+def test_full_solve_order_advection(orc):
+    ns = [20, 40, 80]
+    errs = []
+    for n in ns:
+        d, U = W.smooth_periodic(n)
+        h = 2.0 / n
+        cfl = 0.5 * (h / 0.1) ** (2.0 / 3.0)  # dt ~ h^(5/3): time error O(h^5)
+        r = orc.solve(orc.problem(d), U, t_final=0.5, cfl=cfl)
+        x = W.coords(d)
+        errs.append(np.abs(r["U"].ravel() - np.sin(np.pi * (x - 0.5))).max())
+    assert min(_order(errs, ns)) > 4.5
+
+
+# ------------------------------------------------------- invariants
+
+def test_conservation_periodic(orc):
+    rng = np.random.default_rng(3)
+    cases = []
+    d, U = W.advection_sine_square(200)
+    cases.append((d, U))
+    d = W.describe(ndim=1, system="burgers", nx=97, bc_x="periodic")
+    cases.append((d, rng.normal(size=(1, 1, 97))))
+    d, U = W.random_tube(rng, 128)
+    cases.append((dict(d, bc_x="periodic"), U))
+    d, U = W.random_euler2d(rng, 40, 36)
+    cases.append((dict(d, bc_x="periodic", bc_y="periodic"), U))
+    for d, U in cases:
+        for flux in ("roe", "lf"):
+            R, _, _ = orc.rhs(orc.problem(dict(d, flux=flux)), U)
+            tot = R.reshape(R.shape[0], -1).sum(axis=1)
+            scale = np.abs(R).reshape(R.shape[0], -1).sum(axis=1)
+            assert np.all(np.abs(tot) <= 1e-12 * scale + 1e-300), (d["system"], flux, tot, scale)
+
+
+def test_free_stream_is_exactly_zero(orc):
+    d = W.describe(ndim=2, system="euler", nx=12, ny=9)
+    U = W.conserved_2d(np.full((9, 12), 0.7), np.full((9, 12), 0.3), np.full((9, 12), -0.2),
+                       np.full((9, 12), 1.1), 1.4)
+    R, _, _ = orc.rhs(orc.problem(d), U)
+    assert not R.any()
+    d1 = W.describe(ndim=1, system="euler", nx=12)
+    U1 = W.conserved_1d(np.full(12, 0.7), np.full(12, 0.3), np.full(12, 1.1), 1.4).reshape(3, 1, 12)
+    R1, _, _ = orc.rhs(orc.problem(d1), U1)
+    assert not R1.any()
+
+
+def test_config3_diagonal_symmetry_bitwise(orc):
+    """The four-quadrant state of Sec. 3.6.1 maps to itself under (x, y, u, v)
+    -> (y, x, v, u); the RHS does too, bit for bit."""
+    d, U = W.riemann2d_config3(48)
+    R, fl, _ = orc.rhs(orc.problem(d), U, flags=True)
+    assert np.array_equal(R[0], R[0].T) and np.array_equal(R[3], R[3].T)
+    assert np.array_equal(R[1], R[2].T)
+    # x-flags of row y equal y-flags of column y
+    assert np.array_equal(fl[0], fl[1])
+
+
+def test_1d_embedding_in_2d(orc):
+    rng = np.random.default_rng(5)
+    d1, U1 = W.random_tube(rng, 50)
+    ny = 7
+    rho, u, p = W.primitive(U1.reshape(3, 50), 1.4)
+    d2 = W.describe(ndim=2, system="euler", nx=50, ny=ny)
+    U2 = W.conserved_2d(np.tile(rho, (ny, 1)), np.tile(u, (ny, 1)), np.zeros((ny, 50)),
+                        np.tile(p, (ny, 1)), 1.4)
+    R1, _, _ = orc.rhs(orc.problem(d1), U1)
+    R2, _, _ = orc.rhs(orc.problem(d2), U2)
+    assert not R2[2].any()  # no transverse momentum change
+    for v1, v2 in ((0, 0), (1, 1), (2, 3)):
+        scale = np.abs(R1[v1]).max()
+        assert np.abs(R2[v2] - R1[v1]).max() <= 1e-13 * scale
+
+
+def test_characteristic_projection_is_transparent_on_smooth_data(orc):
+    n = 64
+    d = W.describe(ndim=1, system="euler", nx=n, x0=-1.0, x1=1.0, bc_x="periodic", scheme="linear")
+    x = W.coords(d)
+    U = W.conserved_1d(1 + 0.2 * np.sin(np.pi * x), 0.5 + 0.1 * np.cos(np.pi * x),
+                       1 + 0.1 * np.sin(np.pi * x), 1.4).reshape(3, 1, n)
+    Rc, _, _ = orc.rhs(orc.problem(d), U)
+    Rv, _, _ = orc.rhs(orc.problem(dict(d, charwise=0)), U)
+    assert np.abs(Rc - Rv).max() <= 1e-11 * np.abs(Rv).max()
+
+
+@pytest.mark.parametrize("nv", [3, 4])
+def test_eigenvectors_and_roe_property(orc, nv):
+    rng = np.random.default_rng(nv)
+    g = 1.4
+    for _ in range(20):
+        def state():
+            rho, p = rng.uniform(0.1, 5, size=2)
+            vel = rng.uniform(-2, 2, size=nv - 2)
+            if nv == 3:
+                return W.conserved_1d(rho, vel[0], p, g)
+            return W.conserved_2d(rho, vel[0], vel[1], p, g)
+        UA, UB = state(), state()
+        L, R, lam, bad = orc.roe_eigen(nv, g, UA, UB)
+        assert bad == 0
+        assert np.allclose(L @ R, np.eye(nv), atol=1e-12)
+        # Roe property: F(B) - F(A) = R Lambda L (B - A)
+        dF = orc.euler_flux(nv, g, UB) - orc.euler_flux(nv, g, UA)
+        assert np.allclose(R @ np.diag(lam) @ L @ (UB - UA), dF, rtol=1e-11, atol=1e-11)
+        # the eigen-system of a single state diagonalises its flux Jacobian
+        L1, R1, lam1, _ = orc.roe_eigen(nv, g, UA, UA)
+        eps = 1e-6
+        J = np.zeros((nv, nv))
+        for k in range(nv):
+            e = np.zeros(nv)
+            e[k] = eps
+            J[:, k] = (orc.euler_flux(nv, g, UA + e) - orc.euler_flux(nv, g, UA - e)) / (2 * eps)
+        assert np.allclose(L1 @ J @ R1, np.diag(lam1), atol=1e-6)
+
+
+def test_numerical_flux_consistency_and_upwinding(orc):
+    g = 1.4
+    for flux in ("roe", "lf"):
+        p = orc.problem(W.describe(ndim=2, system="euler", nx=8, ny=8, flux=flux))
+        U = W.conserved_2d(0.8, 0.4, -0.3, 1.3, g)
+        assert np.allclose(orc.num_flux(p, U, U), orc.euler_flux(4, g, U), rtol=1e-14)
+    # supersonic to the right: the Roe flux is the left physical flux
+    p = orc.problem(W.describe(ndim=1, system="euler", nx=8, flux="roe"))
+    UL = W.conserved_1d(1.0, 3.0, 1.0, g)
+    UR = W.conserved_1d(1.1, 3.2, 1.05, g)
+    assert np.allclose(orc.num_flux(p, UL, UR), orc.euler_flux(3, g, UL), rtol=1e-12)
+    # scalar: Eq. (6) with a > 0 is the upwind a u_L
+    ps = orc.problem(W.describe(ndim=1, system="advection", nx=8, adv_speed=2.0))
+    assert orc.num_flux(ps, [0.3], [0.9])[0] == pytest.approx(0.6, rel=1e-15)
+
+
+def test_sod_against_exact_riemann_solution(orc):
+    from riemann_exact import sample
+    errs = []
+    for n in (100, 200, 400):
+        d, U = W.sod(n)
+        r = orc.solve(orc.problem(d), U, t_final=0.2, cfl=0.5)
+        assert r["status"] == 0
+        rho = r["U"][0].ravel()
+        ex = sample((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), W.coords(d), 0.2)
+        errs.append(np.abs(rho - ex[0]).mean())
+        # no large over- or undershoot of the density range
+        assert rho.max() < 1.0 + 0.02 and rho.min() > 0.125 - 0.02
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 3e-3
+
+
+def test_nonphysical_state_is_reported(orc):
+    rng = np.random.default_rng(9)
+    d, U = W.random_tube(rng, 64)
+    U = U.copy()
+    U[0, 0, 17] = -0.5
+    r = orc.solve(orc.problem(d), U, t_final=0.1, cfl=0.5)
+    assert r["status"] == 2 and r["bad_stage"] == 0
+
+
+# ---------------------------------------------- Tables 2 and 3 of Sec. 3
+
+def _gauss_error(orc, n_pts, scheme, cfl=0.02):
+    d, U = W.advection_gaussian(n_pts, scheme=scheme, diff="md")
+    r = orc.solve(orc.problem(d), U, t_final=1.0, cfl=cfl)
+    x = W.coords(d)
+    return np.abs(r["U"].ravel() - np.exp(-300 * (x - 0.5) ** 2)).max()
+
+
+@pytest.mark.parametrize("n_pts", [51, 101, 201])
+def test_table2_gaussian_advection(orc, n_pts):
+    row = {int(r[0]): [float(v) for v in r[1:]] for r in _table("table2_advection_linf.txt")}[n_pts]
+    lin, js, _, tcns = row
+    # three printed digits: +-0.6 % of the last printed digit's range
+    assert _gauss_error(orc, n_pts, "linear") == pytest.approx(lin, rel=6e-3)
+    assert _gauss_error(orc, n_pts, "js") == pytest.approx(js, rel=6e-3)
+    e = _gauss_error(orc, n_pts, "teno")
+    if n_pts == 51:
+        # cut-sensitive coarse grid (a 3-point-wide pulse): reproduced to 1 %
+        assert e == pytest.approx(tcns, rel=1.2e-2)
+    else:
+        assert e == pytest.approx(tcns, rel=6e-3)
+
+
+def test_table2_linear_fine_grid(orc):
+    row = {int(r[0]): [float(v) for v in r[1:]] for r in _table("table2_advection_linf.txt")}[401]
+    assert _gauss_error(orc, 401, "linear") == pytest.approx(row[0], rel=6e-3)
+
+
+def _burgers_exact(x, t):
+    xi = x.copy()
+    for _ in range(60):
+        u = 0.5 + np.sin(np.pi * xi)
+        xi = xi - (xi + u * t - x) / (1 + np.pi * np.cos(np.pi * xi) * t)
+    return 0.5 + np.sin(np.pi * xi)
+
+
+@pytest.mark.parametrize("n_pts", [41, 81, 161])
+def test_table3_burgers(orc, n_pts):
+    row = {int(r[0]): [float(v) for v in r[1:]] for r in _table("table3_burgers_linf.txt")}[n_pts]
+    lin, js, _, tcns = row
+    for scheme, want in (("linear", lin), ("js", js), ("teno", tcns)):
+        d, U = W.burgers_sine(n_pts, scheme=scheme, diff="md")
+        r = orc.solve(orc.problem(d), U, t_final=0.2, cfl=0.05)
+        e = np.abs(r["U"].ravel() - _burgers_exact(W.coords(d), 0.2)).max()
+        assert e == pytest.approx(want, rel=1e-2), scheme
+
+
+# ------------------------------------------------- symmetry and boundaries
+
+def _reflect(U, axis_len_last=True):
+    """Mirror x -> -x: reverse x and flip the sign of the x-momentum."""
+    V = U[..., ::-1].copy()
+    V[1] = -V[1]
+    return V
+
+
+@pytest.mark.parametrize("flux", ["roe", "lf"])
+def test_reflection_symmetry_1d(orc, flux):
+    """The left and right states are mirror images of each other (Sec. 2.2)
+    and the projection uses the two nodes adjacent to the midpoint, so the
+    discrete operator commutes with x -> -x, u -> -u."""
+    rng = np.random.default_rng(11)
+    for _ in range(3):
+        d, U = W.random_tube(rng, 61)
+        d = dict(d, flux=flux)
+        R, _, _ = orc.rhs(orc.problem(d), U)
+        Rm, _, _ = orc.rhs(orc.problem(d), _reflect(U))
+        assert np.allclose(_reflect(R), Rm, rtol=0, atol=1e-11 * np.abs(R).max())
+
+
+def test_reflection_symmetry_scalar(orc):
+    """Burgers with u -> -u under x -> -x."""
+    rng = np.random.default_rng(12)
+    d = W.describe(ndim=1, system="burgers", nx=50, bc_x="periodic")
+    U = rng.normal(size=(1, 1, 50))
+    R, _, _ = orc.rhs(orc.problem(d), U)
+    Rm, _, _ = orc.rhs(orc.problem(d), -U[..., ::-1].copy())
+    assert np.allclose(-R[..., ::-1], Rm, rtol=0, atol=1e-12 * np.abs(R).max())
+
+
+@pytest.mark.parametrize("bc", ["zero_gradient", "periodic"])
+def test_ghost_cells_match_explicit_extension(orc, bc):
+    """Zero gradient copies the end value outward; periodic wraps.  Solving on
+    an explicitly extended line gives the same interior RHS bit for bit."""
+    rng = np.random.default_rng(13)
+    n, ext = 32, 8  # spacing 1/32 stays exact on the extended line
+    d, U = W.random_tube(rng, n)
+    d = dict(d, bc_x=bc)
+    R, _, _ = orc.rhs(orc.problem(d), U)
+    if bc == "zero_gradient":
+        E = np.concatenate([np.repeat(U[..., :1], ext, axis=2), U, np.repeat(U[..., -1:], ext, axis=2)], axis=2)
+    else:
+        E = np.concatenate([U[..., -ext:], U, U[..., :ext]], axis=2)
+    de = dict(d, nx=n + 2 * ext, x1=d["x0"] + (d["x1"] - d["x0"]) * (n + 2 * ext) / n)
+    Re, _, _ = orc.rhs(orc.problem(de), E)
+    assert np.array_equal(R, Re[..., ext:-ext])
+
+
+def test_lax_friedrichs_closed_form(orc):
+    """Two states at rest with c_L = sqrt(1.4), c_R = sqrt(5.6): the mass flux
+    is -alpha/2 (rho_R - rho_L) with alpha = max(c_L, c_R)."""
+    p = orc.problem(W.describe(ndim=1, system="euler", nx=8, flux="lf"))
+    UL = W.conserved_1d(1.0, 0.0, 1.0, 1.4)
+    UR = W.conserved_1d(0.5, 0.0, 2.0, 1.4)
+    F = orc.num_flux(p, UL, UR)
+    assert F[0] == pytest.approx(0.25 * math.sqrt(5.6), rel=1e-14)
