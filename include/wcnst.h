@@ -1,0 +1,155 @@
+/*
+ * wcnst.h -- C ABI of the MI355X (gfx950) WCNS-T solver core.
+ *
+ * WCNS-T ("TCNS") is the weighted compact nonlinear scheme of Zhang, Zhang &
+ * Xu, "Towards optimal high-order compact schemes for simulating
+ * compressible flows" (arXiv:1810.07806): a fifth-order node-to-midpoint
+ * interpolation whose three 3-point candidates are kept or discarded by the
+ * TENO-like cut-off of Sec. 2.3 (Eqs. (16)-(19)), an upwind midpoint flux
+ * (Sec. 2.2, Eq. (6)), and the explicit midpoint-and-node-to-node difference
+ * of Sec. 2.1, Eq. (5), advanced in time with third-order SSP Runge-Kutta
+ * (Sec. 2).  For the Euler equations the interpolation acts on
+ * characteristic variables (Sec. 3).
+ *
+ * Conventions for every entry point:
+ *   - All state pointers are DEVICE pointers to FP64 arrays laid out
+ *     U[v][y][x] (x fastest, contiguous, no padding), v = 0..nvar-1:
+ *       advection / Burgers: nvar = 1, (u)
+ *       Euler 1D:            nvar = 3, (rho, rho*u, E)
+ *       Euler 2D:            nvar = 4, (rho, rho*u, rho*v, E)
+ *     They are owned by the caller and must stay valid until the work queued
+ *     on the solver's stream has finished.
+ *   - The library never allocates device memory.  The caller provides one
+ *     device workspace of wcnst_workspace_size() bytes at creation; it must
+ *     outlive the handle.
+ *   - Work is queued on the HIP stream given at creation and runs
+ *     asynchronously unless the entry point says otherwise.
+ *   - Every entry point returns a wcnst_status; 0 is success.  Errors found
+ *     on the device (non-physical states) are sticky and surface at the next
+ *     synchronising call.  wcnst_last_error() gives a thread-local message.
+ *   - Handles are not thread-safe; one handle per host thread.
+ */
+#ifndef WCNST_H
+#define WCNST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t wcnst_status;
+
+enum {
+    WCNST_OK = 0,
+    WCNST_E_INVALID_ARG = 1,  /* bad descriptor, pointer, size or workspace */
+    WCNST_E_NONPHYSICAL = 2,  /* rho <= 0, p <= 0 or a non-finite value after a stage */
+    WCNST_E_MAX_STEPS = 3,    /* wcnst_solve hit max_steps before t_final */
+    WCNST_E_HIP = 4           /* a HIP runtime call failed */
+};
+
+enum { WCNST_ADVECTION = 0, WCNST_BURGERS = 1, WCNST_EULER = 2 };
+enum { WCNST_PERIODIC = 0, WCNST_ZERO_GRADIENT = 1 };
+enum { WCNST_ROE = 0, WCNST_LF = 1 };
+enum { WCNST_TENO = 0, WCNST_LINEAR = 1, WCNST_JS = 2 };
+enum { WCNST_MND = 0 };
+
+/* Problem descriptor.  Initialise with wcnst_desc_init(), then set fields. */
+typedef struct wcnst_desc {
+    uint32_t struct_size; /* sizeof(wcnst_desc), for ABI versioning */
+    int32_t ndim;         /* 1 or 2 (2D requires WCNST_EULER) */
+    int32_t system;       /* WCNST_ADVECTION / WCNST_BURGERS / WCNST_EULER */
+    int32_t nx, ny;       /* unknowns per direction, >= 5 (ny = 1 in 1D) */
+    double x0, x1;        /* domain; spacing dx = (x1 - x0) / nx */
+    double y0, y1;        /* dy = (y1 - y0) / ny in 2D */
+    int32_t bc_x, bc_y;   /* WCNST_PERIODIC / WCNST_ZERO_GRADIENT (4 ghost cells) */
+    int32_t flux;         /* WCNST_ROE (no entropy fix) / WCNST_LF (local) */
+    int32_t scheme;       /* WCNST_TENO (Eqs. 16-19) / WCNST_LINEAR (Eq. 12) / WCNST_JS (Eq. 14) */
+    int32_t diff;         /* WCNST_MND (Eq. 5) */
+    int32_t charwise;     /* Euler: 1 = interpolate characteristic variables */
+    int32_t q;            /* TENO integer power, Eq. (16); default 6 */
+    double gamma;         /* ratio of specific heats, > 1; default 1.4 */
+    double adv_speed;     /* advection speed a (flux f = a u) */
+    double CT;            /* TENO cut-off C_T, Eq. (18); default 1e-5 */
+    double C;             /* TENO constant C, Eq. (16); default 1 */
+    double eps_teno;      /* TENO epsilon, Eq. (16); default 1e-40 */
+    double eps_js;        /* Jiang-Shu epsilon, Eq. (14); default 1e-6 */
+} wcnst_desc;
+
+typedef struct wcnst_solver wcnst_solver;
+
+/* Fill *d with the paper's defaults: 1D Euler, Roe, TENO, MND, charwise,
+ * gamma 1.4, C_T 1e-5, C 1, q 6, eps 1e-40, zero-gradient, domain [0, 1]. */
+wcnst_status wcnst_desc_init(wcnst_desc* d);
+
+/* Device workspace bytes needed by a solver for *d (control block plus two
+ * Runge-Kutta stage buffers).  Returns WCNST_E_INVALID_ARG for a bad desc. */
+wcnst_status wcnst_workspace_size(const wcnst_desc* d, size_t* bytes);
+
+/* Validate *d and create a handle bound to hip_stream (a hipStream_t; NULL is
+ * the default stream) and to the caller-owned device workspace (256-byte
+ * aligned, at least wcnst_workspace_size bytes).  Time and step counters
+ * start at 0.  The handle is owned by the library: free it with
+ * wcnst_destroy. */
+wcnst_status wcnst_create(const wcnst_desc* d, void* hip_stream, void* workspace,
+                          size_t ws_bytes, wcnst_solver** out);
+
+/* Discrete right-hand side R = -(dF/dx + dG/dy) of Eq. (2) for the state U
+ * (Sec. 2.1 Eq. (5) on midpoint fluxes from Sec. 2.2-2.3), ghost cells
+ * filled by the boundary conditions.  U and R are device arrays of
+ * nvar*ny*nx doubles and must not overlap.  Asynchronous.
+ * flags (nullable, device, uint8): the stencil-cut pattern of every
+ * interpolation, direction x first then y:
+ *   x block [nvar][ny][nx+3][2], y block [nvar][nx][ny+3][2];
+ * entry [k][line][s][side] is for the midpoint x_{j+1/2}, j = s - 2, of
+ * characteristic field k (conserved variable k when charwise = 0; for y
+ * lines the normal momentum comes first), side 0 = u_L, side 1 = u_R
+ * (mirrored stencil); bit k-1 holds delta_k of Eq. (18).  Scalar schemes
+ * without a cut (LINEAR, JS) report 7. */
+wcnst_status wcnst_rhs(wcnst_solver* s, const double* U, double* R, uint8_t* flags);
+
+/* One SSP-RK3 step of U in place (Sec. 2, Shu-Osher form).  dt > 0 is used
+ * as given; dt <= 0 takes dt = cfl / max((|u|+c)/dx [+ (|v|+c)/dy]) from U
+ * (|a|/dx for advection, |u|/dx for Burgers).  Asynchronous; advances the
+ * device time by dt.  A non-physical stage output sets the sticky status. */
+wcnst_status wcnst_step(wcnst_solver* s, double* U, double dt, double cfl);
+
+/* Advance U in place from the current device time until t_final (dt clipped
+ * so the last step lands on it; stops once t_final - t <= 1e-12 t_final) or
+ * for max_steps steps when t_final is +inf.  Synchronous at return.
+ * Returns WCNST_E_NONPHYSICAL (see wcnst_status_sync for where) or
+ * WCNST_E_MAX_STEPS when t_final was not reached in max_steps steps.
+ * t_out / steps_out (nullable) receive the device time and the steps taken
+ * by this call. */
+wcnst_status wcnst_solve(wcnst_solver* s, double* U, double t_final, double cfl,
+                         int64_t max_steps, double* t_out, int64_t* steps_out);
+
+/* Synchronise the stream and read the device counters: time, total steps,
+ * sticky status, and for WCNST_E_NONPHYSICAL the global stage index
+ * (3*step + stage) and the cell (y*nx + x) of the first offending value
+ * (-1 when none).  Any pointer may be NULL. */
+wcnst_status wcnst_status_sync(wcnst_solver* s, double* t, int64_t* steps, int32_t* status,
+                               int64_t* bad_stage, int64_t* bad_cell);
+
+/* Reset the device time, step counter and sticky status (asynchronous). */
+wcnst_status wcnst_reset(wcnst_solver* s, double t, int64_t steps);
+
+/* Kernel timing for roofline reports: when enabled, every stage kernel is
+ * bracketed by HIP events on the solver's stream.  wcnst_profile_read
+ * synchronises and returns the summed stage-kernel milliseconds and the
+ * number of stage-kernel launches since the last reset. */
+wcnst_status wcnst_profile_enable(wcnst_solver* s, int enable);
+wcnst_status wcnst_profile_read(wcnst_solver* s, double* stage_ms, int64_t* stage_launches);
+
+/* Free the handle (host state only; the workspace stays the caller's). */
+wcnst_status wcnst_destroy(wcnst_solver* s);
+
+/* Message of the last error on this thread ("" when none). */
+const char* wcnst_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,851 @@
+// HIP kernels (gfx950) and the C ABI of the WCNS-T solver core.
+//
+// Hot path per Runge-Kutta stage: one fused kernel computes, for every cell,
+// the midpoint fluxes around it (Sec. 2.2-2.3), the MND difference of
+// Sec. 2.1 Eq. (5) in x and y, and the stage update of SSP-RK3 (Sec. 2);
+// the last stage also reduces the CFL wave speed of the new state.
+//
+// Work decomposition.  One wavefront (64 lanes) owns a strip of TX = 61
+// columns, so one row of the strip needs exactly 64 x-midpoints (j = x0-2 ..
+// x0+61): lane l computes midpoint x0-2+l.  In 2D the wavefront marches up a
+// segment of rows; lane l owns column x0+l and computes one y-midpoint per
+// row, keeping the last four y-midpoint fluxes and three node fluxes in
+// registers, so every midpoint flux is computed once per strip.  The x-flux
+// of a row is exchanged through 1 KiB of LDS per variable.  Ghost cells are
+// an index remap at load time (no extra HBM traffic).
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "wcnst.h"
+#include "wcnst_device.hpp"
+
+namespace wcnst {
+
+constexpr int WAVE = 64;
+constexpr int TX = WAVE - 3;  // cells per strip
+
+struct StepRec {
+    double t;
+    double dt;
+    unsigned long long smax_bits;  // max CFL speed of the state at time t (bit pattern)
+    long long step;
+    int done;
+    int pad;
+};
+
+struct Ctrl {
+    StepRec rec[2];  // current / next record, alternating by step parity
+    unsigned long long bad_key;  // (global stage << 36) | cell of the first non-physical value
+    long long call_step0;        // step counter at the start of the current solve call
+    int status;
+    int pad[3];
+};
+
+enum { MODE_RHS = 0, MODE_STAGE = 1 };
+
+struct StageArgs {
+    double t_final;
+    double cfl;
+    double fixed_dt;
+    int stage;   // 0, 1, 2
+    int parity;  // which record is current
+};
+
+__device__ __forceinline__ bool first_thread()
+{
+    return threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0;
+}
+
+// Reads the step record; stage 0 also decides dt (every block computes the
+// same value from the same inputs) and opens the next record.
+__device__ __forceinline__ bool stage_prologue(Ctrl* ctrl, const StageArgs& A, double& dt,
+                                               long long& step)
+{
+    const StepRec* cur = &ctrl->rec[A.parity];
+    if (ctrl->status != 0 || cur->done) return false;
+    step = cur->step;
+    if (A.stage != 0) {
+        dt = cur->dt;
+        return true;
+    }
+    const double t = cur->t;
+    const bool fin = isfinite(A.t_final);
+    if (fin && A.t_final - t <= 1e-12 * A.t_final) {
+        if (first_thread()) ctrl->rec[A.parity].done = 1;
+        return false;
+    }
+    const double smax = __longlong_as_double((long long)cur->smax_bits);
+    dt = A.fixed_dt > 0.0 ? A.fixed_dt : A.cfl / smax;
+    if (fin && dt > A.t_final - t) dt = A.t_final - t;
+    if (first_thread()) {
+        StepRec* nx = &ctrl->rec[A.parity ^ 1];
+        ctrl->rec[A.parity].dt = dt;
+        nx->t = t + dt;
+        nx->dt = 0.0;
+        nx->step = step + 1;
+        nx->smax_bits = 0ull;
+        nx->done = 0;
+    }
+    return true;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_bits(unsigned long long m)
+{
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(m, off);
+        m = o > m ? o : m;
+    }
+    return m;
+}
+
+// Stage update in the Shu-Osher form; returns the new cell state in o.
+template <int NV>
+__device__ __forceinline__ void rk_combine(int stage, double dt, const double* Uk, const double* Un,
+                                           const double* R, double* o)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double w = Uk[v] + dt * R[v];
+        if (stage == 0) o[v] = w;
+        else if (stage == 1) o[v] = 0.75 * Un[v] + 0.25 * w;
+        else o[v] = (1.0 / 3.0) * Un[v] + (2.0 / 3.0) * w;
+    }
+}
+
+template <int SYS, int NV>
+__device__ __forceinline__ void stage_epilogue(Ctrl* ctrl, const Params& P, int stage, long long step,
+                                               long long cell, const double* o,
+                                               unsigned long long& smax_loc)
+{
+    if (cell_bad<SYS, NV>(o, P)) {
+        const unsigned long long key =
+            ((unsigned long long)(step * 3 + stage) << 36) | (unsigned long long)cell;
+        atomicMin(&ctrl->bad_key, key);
+        atomicOr(&ctrl->status, (int)WCNST_E_NONPHYSICAL);
+    }
+    if (stage == 2) {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(cell_speed<SYS, NV>(o, P));
+        smax_loc = b > smax_loc ? b : smax_loc;
+    }
+}
+
+__device__ __forceinline__ void flush_speed(Ctrl* ctrl, int parity, unsigned long long smax_loc)
+{
+    const unsigned long long m = wave_max_bits(smax_loc);
+    if (threadIdx.x == 0) atomicMax(&ctrl->rec[parity ^ 1].smax_bits, m);
+}
+
+// Owner of midpoint j (j in [-2, n]) among tiles of width w.
+__device__ __forceinline__ int face_owner(int j, int n, int w)
+{
+    j = j < 0 ? 0 : (j > n - 1 ? n - 1 : j);
+    return j / w;
+}
+
+template <int NV>
+__device__ __forceinline__ void write_flags(uint8_t* fl, int nlines, int nfaces, int line, int slot,
+                                            unsigned fb)
+{
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const size_t idx = (((size_t)k * nlines + line) * nfaces + slot) * 2;
+        fl[idx] = (uint8_t)((fb >> (6 * k)) & 7u);
+        fl[idx + 1] = (uint8_t)((fb >> (6 * k + 3)) & 7u);
+    }
+}
+
+// ------------------------------------------------------------------ 1D
+
+template <int SYS, int NV, int FLUX, int MODE, bool FLAGS>
+__global__ void __launch_bounds__(WAVE)
+sweep1d(const double* __restrict__ U, const double* __restrict__ Un, double* __restrict__ out,
+        uint8_t* __restrict__ flags, Ctrl* __restrict__ ctrl, Params P, StageArgs A)
+{
+    double dt = 0.0;
+    long long step = 0;
+    if constexpr (MODE == MODE_STAGE) {
+        if (!stage_prologue(ctrl, A, dt, step)) return;
+    }
+    __shared__ double sF[NV][WAVE];
+    __shared__ double sN[NV][WAVE];
+    const int nx = P.nx;
+    const int lane = threadIdx.x;
+    const int x0 = blockIdx.x * TX;
+    const int c = x0 + lane;
+    const bool cell_ok = lane < TX && c < nx;
+    const int jx = x0 - 2 + lane;
+    const int jxl = min(jx, nx);  // lanes past the last midpoint load in-range data
+
+    double s[6][NV];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        const int col = ghost_map(jxl - 2 + m, nx, P.bc_x);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s[m][v] = U[(size_t)v * nx + col];
+    }
+    double F[NV], fn[NV];
+    unsigned fb;
+    face_flux<SYS, NV, FLUX>(s, P, F, fb);
+    if constexpr (FLAGS) {
+        if (jx <= nx && face_owner(jx, nx, TX) == (int)blockIdx.x)
+            write_flags<NV>(flags, 1, nx + 3, 0, jx + 2, fb);
+    }
+    node_flux<SYS, NV>(s[3], P, fn);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        sF[v][lane] = F[v];
+        sN[v][lane] = fn[v];
+    }
+    __syncthreads();
+    unsigned long long sm = 0ull;
+    if (cell_ok) {
+        double R[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            R[v] = -(P.c1x * (sF[v][lane + 2] - sF[v][lane + 1]) + P.c2x * (sN[v][lane + 2] - sN[v][lane]) +
+                     P.c3x * (sF[v][lane + 3] - sF[v][lane]));
+        if constexpr (MODE == MODE_RHS) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) out[(size_t)v * nx + c] = R[v];
+        } else {
+            double un[NV], o[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) un[v] = A.stage ? Un[(size_t)v * nx + c] : 0.0;
+            rk_combine<NV>(A.stage, dt, s[4], un, R, o);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) out[(size_t)v * nx + c] = o[v];
+            stage_epilogue<SYS, NV>(ctrl, P, A.stage, step, c, o, sm);
+        }
+    }
+    if constexpr (MODE == MODE_STAGE) {
+        if (A.stage == 2) flush_speed(ctrl, A.parity, sm);
+    }
+}
+
+// ------------------------------------------------------------------ 2D
+
+template <int NV, int FLUX, int MODE, bool FLAGS>
+__global__ void __launch_bounds__(WAVE)
+sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __restrict__ out,
+        uint8_t* __restrict__ flags, Ctrl* __restrict__ ctrl, Params P, StageArgs A, int ty)
+{
+    double dt = 0.0;
+    long long step = 0;
+    if constexpr (MODE == MODE_STAGE) {
+        if (!stage_prologue(ctrl, A, dt, step)) return;
+    }
+    __shared__ double sF[NV][WAVE];
+    __shared__ double sN[NV][WAVE];
+    const int nx = P.nx, ny = P.ny;
+    const size_t plane = (size_t)nx * ny;
+    const int lane = threadIdx.x;
+    const int x0 = blockIdx.x * TX;
+    const int y0 = blockIdx.y * ty;
+    const int y1 = min(y0 + ty, ny);
+    const int c = x0 + lane;
+    const bool cell_ok = lane < TX && c < nx;
+    const int cy = min(c, nx - 1);
+    const int jx = x0 - 2 + lane;
+    const int jxl = min(jx, nx);  // lanes past the last midpoint load in-range data
+    const bool own_x = FLAGS && jx <= nx && face_owner(jx, nx, TX) == (int)blockIdx.x;
+
+    // y-midpoint fluxes j-3 .. j and y node fluxes of rows j-2 .. j, in
+    // y-normal variable order (rho, rho v, rho u, E).
+    double fy[4][NV], gn[3][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        fy[0][v] = fy[1][v] = fy[2][v] = fy[3][v] = 0.0;
+        gn[0][v] = gn[1][v] = gn[2][v] = 0.0;
+    }
+    unsigned long long smax_loc = 0ull;
+
+    for (int j = y0 - 2; j <= y1; ++j) {
+        {
+            double s[6][NV];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                const double* p = U + (size_t)ghost_map(j - 2 + m, ny, P.bc_y) * nx + cy;
+                s[m][0] = p[0];
+                s[m][1] = p[2 * plane];
+                s[m][2] = p[plane];
+                s[m][3] = p[3 * plane];
+            }
+            double F[NV];
+            unsigned fb;
+            face_flux<SYS_EULER, NV, FLUX>(s, P, F, fb);
+            if constexpr (FLAGS) {
+                if (cell_ok && j <= ny && face_owner(j, ny, ty) == (int)blockIdx.y)
+                    write_flags<NV>(flags + (size_t)NV * ny * (nx + 3) * 2, nx, ny + 3, c, j + 2, fb);
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                fy[0][v] = fy[1][v];
+                fy[1][v] = fy[2][v];
+                fy[2][v] = fy[3][v];
+                fy[3][v] = F[v];
+                gn[0][v] = gn[1][v];
+                gn[1][v] = gn[2][v];
+            }
+            node_flux<SYS_EULER, NV>(s[2], P, gn[2]);
+        }
+        const int i = j - 1;
+        if (i < y0) continue;
+
+        double Uc[NV];
+        {
+            double s[6][NV];
+            const double* row = U + (size_t)i * nx;
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                const int col = ghost_map(jxl - 2 + m, nx, P.bc_x);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) s[m][v] = row[(size_t)v * plane + col];
+            }
+            double F[NV], fn[NV];
+            unsigned fb;
+            face_flux<SYS_EULER, NV, FLUX>(s, P, F, fb);
+            if constexpr (FLAGS) {
+                if (own_x) write_flags<NV>(flags, ny, nx + 3, i, jx + 2, fb);
+            }
+            node_flux<SYS_EULER, NV>(s[3], P, fn);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                sF[v][lane] = F[v];
+                sN[v][lane] = fn[v];
+                Uc[v] = s[4][v];
+            }
+        }
+        __syncthreads();
+        if (cell_ok) {
+            double Rx[NV], Ry[NV], R[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                Rx[v] = -(P.c1x * (sF[v][lane + 2] - sF[v][lane + 1]) +
+                          P.c2x * (sN[v][lane + 2] - sN[v][lane]) +
+                          P.c3x * (sF[v][lane + 3] - sF[v][lane]));
+                Ry[v] = -(P.c1y * (fy[2][v] - fy[1][v]) + P.c2y * (gn[2][v] - gn[0][v]) +
+                          P.c3y * (fy[3][v] - fy[0][v]));
+            }
+            R[0] = Rx[0] + Ry[0];
+            R[1] = Rx[1] + Ry[2];
+            R[2] = Rx[2] + Ry[1];
+            R[3] = Rx[3] + Ry[3];
+            const size_t cell = (size_t)i * nx + c;
+            if constexpr (MODE == MODE_RHS) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) out[(size_t)v * plane + cell] = R[v];
+            } else {
+                double un[NV], o[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) un[v] = A.stage ? Un[(size_t)v * plane + cell] : 0.0;
+                rk_combine<NV>(A.stage, dt, Uc, un, R, o);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) out[(size_t)v * plane + cell] = o[v];
+                stage_epilogue<SYS_EULER, NV>(ctrl, P, A.stage, step, (long long)cell, o, smax_loc);
+            }
+        }
+        __syncthreads();
+    }
+    if constexpr (MODE == MODE_STAGE) {
+        if (A.stage == 2) flush_speed(ctrl, A.parity, smax_loc);
+    }
+}
+
+// ----------------------------------------------------- control kernels
+
+__global__ void ctrl_init(Ctrl* ctrl, double t, long long step)
+{
+    if (threadIdx.x != 0) return;
+    for (int k = 0; k < 2; ++k) {
+        ctrl->rec[k].t = t;
+        ctrl->rec[k].dt = 0.0;
+        ctrl->rec[k].smax_bits = 0ull;
+        ctrl->rec[k].step = step;
+        ctrl->rec[k].done = 0;
+    }
+    ctrl->bad_key = ~0ull;
+    ctrl->call_step0 = step;
+    ctrl->status = 0;
+}
+
+// Opens a solve / step call: clears the done flag and the speed accumulator
+// of the current record and remembers the step counter.
+__global__ void ctrl_open(Ctrl* ctrl, int parity)
+{
+    if (threadIdx.x != 0) return;
+    ctrl->rec[parity].smax_bits = 0ull;
+    ctrl->rec[parity].done = 0;
+    ctrl->call_step0 = ctrl->rec[parity].step;
+}
+
+template <int SYS, int NV>
+__global__ void __launch_bounds__(256) wavespeed(const double* __restrict__ U, Ctrl* ctrl, Params P,
+                                                  int parity)
+{
+    const size_t plane = (size_t)P.nx * P.ny;
+    unsigned long long m = 0ull;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < plane;
+         i += (size_t)gridDim.x * blockDim.x) {
+        double u[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v] = U[(size_t)v * plane + i];
+        const unsigned long long b = (unsigned long long)__double_as_longlong(cell_speed<SYS, NV>(u, P));
+        m = b > m ? b : m;
+    }
+    m = wave_max_bits(m);
+    if ((threadIdx.x & (WAVE - 1)) == 0) atomicMax(&ctrl->rec[parity].smax_bits, m);
+}
+
+}  // namespace wcnst
+
+// ====================================================================== host
+
+using namespace wcnst;
+
+static thread_local char g_err[512] = "";
+
+static wcnst_status fail(wcnst_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static wcnst_status fail(wcnst_status st, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(WCNST_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+
+enum Kind { K_ADV1 = 0, K_BURG1 = 1, K_EUL1 = 2, K_EUL2 = 3 };
+
+struct wcnst_solver {
+    wcnst_desc d;
+    Params P;
+    Kind kind;
+    int nv;
+    hipStream_t stream;
+    Ctrl* ctrl;
+    double* U1;
+    double* U2;
+    Ctrl* host_ctrl[2];  // pinned snapshots for polling
+    hipEvent_t snap_ev[2];
+    int parity;
+    int ty;  // rows per 2D segment
+    bool prof;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used;
+};
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static wcnst_status check_desc(const wcnst_desc* d)
+{
+    if (!d) return fail(WCNST_E_INVALID_ARG, "null descriptor");
+    if (d->struct_size != sizeof(wcnst_desc))
+        return fail(WCNST_E_INVALID_ARG, "struct_size %u != %zu", d->struct_size, sizeof(wcnst_desc));
+    if (d->ndim != 1 && d->ndim != 2) return fail(WCNST_E_INVALID_ARG, "ndim must be 1 or 2");
+    if (d->system < WCNST_ADVECTION || d->system > WCNST_EULER)
+        return fail(WCNST_E_INVALID_ARG, "unknown system %d", d->system);
+    if (d->ndim == 2 && d->system != WCNST_EULER)
+        return fail(WCNST_E_INVALID_ARG, "2D grids require the Euler system");
+    if (d->nx < 5) return fail(WCNST_E_INVALID_ARG, "nx must be >= 5");
+    if (d->ndim == 1 && d->ny != 1) return fail(WCNST_E_INVALID_ARG, "ny must be 1 in 1D");
+    if (d->ndim == 2 && d->ny < 5) return fail(WCNST_E_INVALID_ARG, "ny must be >= 5");
+    if ((int64_t)d->nx * d->ny > ((int64_t)1 << 34)) return fail(WCNST_E_INVALID_ARG, "grid too large");
+    if (!(d->x1 > d->x0) || (d->ndim == 2 && !(d->y1 > d->y0)))
+        return fail(WCNST_E_INVALID_ARG, "empty domain");
+    for (int b : {d->bc_x, d->bc_y})
+        if (b != WCNST_PERIODIC && b != WCNST_ZERO_GRADIENT)
+            return fail(WCNST_E_INVALID_ARG, "unknown boundary condition %d", b);
+    if (d->flux != WCNST_ROE && d->flux != WCNST_LF) return fail(WCNST_E_INVALID_ARG, "unknown flux");
+    if (d->scheme < WCNST_TENO || d->scheme > WCNST_JS) return fail(WCNST_E_INVALID_ARG, "unknown scheme");
+    if (d->diff != WCNST_MND) return fail(WCNST_E_INVALID_ARG, "only the MND difference is built");
+    if (d->system == WCNST_EULER && !(d->gamma > 1.0)) return fail(WCNST_E_INVALID_ARG, "gamma must be > 1");
+    if (d->q < 1 || d->q > 64) return fail(WCNST_E_INVALID_ARG, "q must be in [1, 64]");
+    if (!(d->CT > 0.0 && d->CT < 1.0 / 3.0)) return fail(WCNST_E_INVALID_ARG, "C_T must be in (0, 1/3)");
+    if (!(d->C > 0.0) || !(d->eps_teno > 0.0) || !(d->eps_js > 0.0))
+        return fail(WCNST_E_INVALID_ARG, "C and epsilons must be positive");
+    return WCNST_OK;
+}
+
+static int desc_nvar(const wcnst_desc* d)
+{
+    return d->system == WCNST_EULER ? (d->ndim == 1 ? 3 : 4) : 1;
+}
+
+extern "C" wcnst_status wcnst_desc_init(wcnst_desc* d)
+{
+    if (!d) return fail(WCNST_E_INVALID_ARG, "null descriptor");
+    memset(d, 0, sizeof *d);
+    d->struct_size = sizeof(wcnst_desc);
+    d->ndim = 1;
+    d->system = WCNST_EULER;
+    d->nx = 64;
+    d->ny = 1;
+    d->x0 = 0.0;
+    d->x1 = 1.0;
+    d->y0 = 0.0;
+    d->y1 = 1.0;
+    d->bc_x = d->bc_y = WCNST_ZERO_GRADIENT;
+    d->flux = WCNST_ROE;
+    d->scheme = WCNST_TENO;
+    d->diff = WCNST_MND;
+    d->charwise = 1;
+    d->q = 6;
+    d->gamma = 1.4;
+    d->adv_speed = 1.0;
+    d->CT = 1e-5;
+    d->C = 1.0;
+    d->eps_teno = 1e-40;
+    d->eps_js = 1e-6;
+    return WCNST_OK;
+}
+
+extern "C" wcnst_status wcnst_workspace_size(const wcnst_desc* d, size_t* bytes)
+{
+    wcnst_status st = check_desc(d);
+    if (st) return st;
+    if (!bytes) return fail(WCNST_E_INVALID_ARG, "null size pointer");
+    const size_t state = (size_t)desc_nvar(d) * d->nx * d->ny * sizeof(double);
+    *bytes = align256(sizeof(Ctrl)) + 2 * align256(state);
+    return WCNST_OK;
+}
+
+extern "C" wcnst_status wcnst_create(const wcnst_desc* d, void* hip_stream, void* workspace,
+                                     size_t ws_bytes, wcnst_solver** out)
+{
+    wcnst_status st = check_desc(d);
+    if (st) return st;
+    if (!out) return fail(WCNST_E_INVALID_ARG, "null output handle");
+    size_t need = 0;
+    wcnst_workspace_size(d, &need);
+    if (!workspace || ws_bytes < need)
+        return fail(WCNST_E_INVALID_ARG, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    if (((uintptr_t)workspace & 255u) != 0) return fail(WCNST_E_INVALID_ARG, "workspace not 256-byte aligned");
+
+    wcnst_solver* s = new wcnst_solver();
+    s->d = *d;
+    s->nv = desc_nvar(d);
+    s->kind = d->system == WCNST_ADVECTION ? K_ADV1
+              : d->system == WCNST_BURGERS ? K_BURG1
+              : d->ndim == 1               ? K_EUL1
+                                           : K_EUL2;
+    s->stream = (hipStream_t)hip_stream;
+    uint8_t* ws = (uint8_t*)workspace;
+    const size_t state = (size_t)s->nv * d->nx * d->ny * sizeof(double);
+    s->ctrl = (Ctrl*)ws;
+    s->U1 = (double*)(ws + align256(sizeof(Ctrl)));
+    s->U2 = (double*)(ws + align256(sizeof(Ctrl)) + align256(state));
+    s->parity = 0;
+    s->ty = 32;
+    s->prof = false;
+    s->ev_used = 0;
+
+    Params& P = s->P;
+    P.CT = d->CT;
+    P.C = d->C;
+    P.eps_teno = d->eps_teno;
+    P.eps_js = d->eps_js;
+    P.gamma = d->gamma;
+    P.gm1 = d->gamma - 1.0;
+    P.adv = d->adv_speed;
+    P.nx = d->nx;
+    P.ny = d->ny;
+    P.dx = (d->x1 - d->x0) / d->nx;
+    P.dy = d->ndim == 2 ? (d->y1 - d->y0) / d->ny : 1.0;
+    // Eq. (5) coefficients (3/2, -3/10, 1/30) divided by the spacing
+    P.c1x = (3.0 / 2.0) / P.dx;
+    P.c2x = (-3.0 / 10.0) / P.dx;
+    P.c3x = (1.0 / 30.0) / P.dx;
+    P.c1y = (3.0 / 2.0) / P.dy;
+    P.c2y = (-3.0 / 10.0) / P.dy;
+    P.c3y = (1.0 / 30.0) / P.dy;
+    P.q = d->q;
+    P.scheme = d->scheme;
+    P.charwise = d->charwise ? 1 : 0;
+    P.bc_x = d->bc_x;
+    P.bc_y = d->bc_y;
+
+    for (int k = 0; k < 2; ++k) {
+        hipError_t e = hipHostMalloc((void**)&s->host_ctrl[k], sizeof(Ctrl), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->snap_ev[k], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            delete s;
+            return fail(WCNST_E_HIP, "host staging allocation failed: %s", hipGetErrorString(e));
+        }
+    }
+    hipLaunchKernelGGL(ctrl_init, dim3(1), dim3(64), 0, s->stream, s->ctrl, 0.0, 0LL);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        wcnst_destroy(s);
+        return fail(WCNST_E_HIP, "control init launch failed: %s", hipGetErrorString(e));
+    }
+    *out = s;
+    return WCNST_OK;
+}
+
+extern "C" wcnst_status wcnst_destroy(wcnst_solver* s)
+{
+    if (!s) return WCNST_OK;
+    (void)hipStreamSynchronize(s->stream);
+    for (int k = 0; k < 2; ++k) {
+        if (s->host_ctrl[k]) (void)hipHostFree(s->host_ctrl[k]);
+        if (s->snap_ev[k]) (void)hipEventDestroy(s->snap_ev[k]);
+    }
+    for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+    delete s;
+    return WCNST_OK;
+}
+
+// ---------------------------------------------------------- launchers
+
+template <int SYS, int NV, int FLUX, int MODE, bool FLAGS>
+static void launch_sweep_t(const wcnst_solver* s, const double* U, const double* Un, double* out,
+                           uint8_t* flags, const StageArgs& A)
+{
+    const int nstrips = (s->d.nx + TX - 1) / TX;
+    if constexpr (SYS == SYS_EULER && NV == 4) {
+        const int nseg = (s->d.ny + s->ty - 1) / s->ty;
+        hipLaunchKernelGGL((sweep2d<NV, FLUX, MODE, FLAGS>), dim3(nstrips, nseg), dim3(WAVE), 0,
+                           s->stream, U, Un, out, flags, s->ctrl, s->P, A, s->ty);
+    } else {
+        hipLaunchKernelGGL((sweep1d<SYS, NV, FLUX, MODE, FLAGS>), dim3(nstrips), dim3(WAVE), 0,
+                           s->stream, U, Un, out, flags, s->ctrl, s->P, A);
+    }
+}
+
+template <int MODE, bool FLAGS>
+static void launch_sweep(const wcnst_solver* s, const double* U, const double* Un, double* out,
+                         uint8_t* flags, const StageArgs& A)
+{
+    const bool lf = s->d.flux == WCNST_LF;
+    switch (s->kind) {
+    case K_ADV1: launch_sweep_t<SYS_ADV, 1, FLUX_ROE, MODE, FLAGS>(s, U, Un, out, flags, A); break;
+    case K_BURG1:
+        if (lf) launch_sweep_t<SYS_BURG, 1, FLUX_LF, MODE, FLAGS>(s, U, Un, out, flags, A);
+        else launch_sweep_t<SYS_BURG, 1, FLUX_ROE, MODE, FLAGS>(s, U, Un, out, flags, A);
+        break;
+    case K_EUL1:
+        if (lf) launch_sweep_t<SYS_EULER, 3, FLUX_LF, MODE, FLAGS>(s, U, Un, out, flags, A);
+        else launch_sweep_t<SYS_EULER, 3, FLUX_ROE, MODE, FLAGS>(s, U, Un, out, flags, A);
+        break;
+    case K_EUL2:
+        if (lf) launch_sweep_t<SYS_EULER, 4, FLUX_LF, MODE, FLAGS>(s, U, Un, out, flags, A);
+        else launch_sweep_t<SYS_EULER, 4, FLUX_ROE, MODE, FLAGS>(s, U, Un, out, flags, A);
+        break;
+    }
+}
+
+static void launch_wavespeed(const wcnst_solver* s, const double* U)
+{
+    const size_t cells = (size_t)s->d.nx * s->d.ny;
+    int blocks = (int)std::min<size_t>((cells + 255) / 256, 2048);
+    switch (s->kind) {
+    case K_ADV1: hipLaunchKernelGGL((wavespeed<SYS_ADV, 1>), dim3(blocks), dim3(256), 0, s->stream, U, s->ctrl, s->P, s->parity); break;
+    case K_BURG1: hipLaunchKernelGGL((wavespeed<SYS_BURG, 1>), dim3(blocks), dim3(256), 0, s->stream, U, s->ctrl, s->P, s->parity); break;
+    case K_EUL1: hipLaunchKernelGGL((wavespeed<SYS_EULER, 3>), dim3(blocks), dim3(256), 0, s->stream, U, s->ctrl, s->P, s->parity); break;
+    case K_EUL2: hipLaunchKernelGGL((wavespeed<SYS_EULER, 4>), dim3(blocks), dim3(256), 0, s->stream, U, s->ctrl, s->P, s->parity); break;
+    }
+}
+
+static hipEvent_t pool_event(wcnst_solver* s)
+{
+    if (s->ev_used == s->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        s->ev_pool.push_back(e);
+    }
+    return s->ev_pool[s->ev_used++];
+}
+
+// One SSP-RK3 step: three fused stage kernels.
+static void launch_step(wcnst_solver* s, double* U, double t_final, double cfl, double fixed_dt)
+{
+    const double* in[3] = {U, s->U1, s->U2};
+    double* outp[3] = {s->U1, s->U2, U};
+    for (int st = 0; st < 3; ++st) {
+        StageArgs A;
+        A.t_final = t_final;
+        A.cfl = cfl;
+        A.fixed_dt = fixed_dt;
+        A.stage = st;
+        A.parity = s->parity;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (s->prof) {
+            e0 = pool_event(s);
+            e1 = pool_event(s);
+            if (e0) (void)hipEventRecord(e0, s->stream);
+        }
+        launch_sweep<MODE_STAGE, false>(s, in[st], U, outp[st], nullptr, A);
+        if (s->prof && e1) (void)hipEventRecord(e1, s->stream);
+    }
+    s->parity ^= 1;
+}
+
+extern "C" wcnst_status wcnst_rhs(wcnst_solver* s, const double* U, double* R, uint8_t* flags)
+{
+    if (!s || !U || !R) return fail(WCNST_E_INVALID_ARG, "null argument");
+    if (U == R) return fail(WCNST_E_INVALID_ARG, "U and R must not alias");
+    StageArgs A = {};
+    if (flags) launch_sweep<MODE_RHS, true>(s, U, nullptr, R, flags, A);
+    else launch_sweep<MODE_RHS, false>(s, U, nullptr, R, nullptr, A);
+    HIP_TRY(hipGetLastError());
+    return WCNST_OK;
+}
+
+extern "C" wcnst_status wcnst_step(wcnst_solver* s, double* U, double dt, double cfl)
+{
+    if (!s || !U) return fail(WCNST_E_INVALID_ARG, "null argument");
+    if (!(dt > 0.0) && !(cfl > 0.0)) return fail(WCNST_E_INVALID_ARG, "need dt > 0 or cfl > 0");
+    hipLaunchKernelGGL(ctrl_open, dim3(1), dim3(64), 0, s->stream, s->ctrl, s->parity);
+    if (!(dt > 0.0)) launch_wavespeed(s, U);
+    launch_step(s, U, INFINITY, cfl, dt > 0.0 ? dt : 0.0);
+    HIP_TRY(hipGetLastError());
+    return WCNST_OK;
+}
+
+static wcnst_status read_ctrl(wcnst_solver* s, Ctrl* c)
+{
+    HIP_TRY(hipMemcpyAsync(c, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return WCNST_OK;
+}
+
+// The record holding the newest completed state.
+static const StepRec& newest(const Ctrl& c)
+{
+    return c.rec[0].step >= c.rec[1].step ? c.rec[0] : c.rec[1];
+}
+
+extern "C" wcnst_status wcnst_solve(wcnst_solver* s, double* U, double t_final, double cfl,
+                                    int64_t max_steps, double* t_out, int64_t* steps_out)
+{
+    if (!s || !U) return fail(WCNST_E_INVALID_ARG, "null argument");
+    if (!(cfl > 0.0)) return fail(WCNST_E_INVALID_ARG, "cfl must be > 0");
+    if (max_steps < 0) return fail(WCNST_E_INVALID_ARG, "max_steps must be >= 0");
+    if (std::isnan(t_final)) return fail(WCNST_E_INVALID_ARG, "t_final is NaN");
+    const bool timed = std::isfinite(t_final);
+
+    hipLaunchKernelGGL(ctrl_open, dim3(1), dim3(64), 0, s->stream, s->ctrl, s->parity);
+    launch_wavespeed(s, U);
+    HIP_TRY(hipGetLastError());
+
+    int64_t launched = 0;
+    int64_t chunk = 4;
+    int slot = 0;
+    bool have_prev = false;
+    int64_t prev_launched = 0;
+    while (launched < max_steps) {
+        const int64_t k = std::min(chunk, max_steps - launched);
+        for (int64_t i = 0; i < k; ++i) launch_step(s, U, t_final, cfl, 0.0);
+        launched += k;
+        HIP_TRY(hipGetLastError());
+        if (!timed) continue;
+        // snapshot after this chunk; inspect the previous one (one chunk of look-ahead)
+        HIP_TRY(hipMemcpyAsync(s->host_ctrl[slot], s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipEventRecord(s->snap_ev[slot], s->stream));
+        const int prev = slot ^ 1;
+        slot ^= 1;
+        if (!have_prev) {
+            have_prev = true;
+            prev_launched = launched;
+            continue;
+        }
+        HIP_TRY(hipEventSynchronize(s->snap_ev[prev]));
+        const Ctrl& c = *s->host_ctrl[prev];
+        const StepRec& r = newest(c);
+        if (c.status != 0 || c.rec[0].done || c.rec[1].done) break;
+        // estimate the steps still needed beyond what is already queued
+        const int64_t done_steps = r.step - c.call_step0;
+        const double dt = c.rec[0].step >= c.rec[1].step ? c.rec[1].dt : c.rec[0].dt;
+        int64_t est = 8;
+        if (dt > 0.0 && std::isfinite(dt)) est = (int64_t)std::ceil((t_final - r.t) / dt) + 1;
+        const int64_t queued = launched - done_steps;
+        (void)prev_launched;
+        prev_launched = launched;
+        chunk = std::max<int64_t>(1, std::min<int64_t>(est - queued, 512));
+    }
+    Ctrl c;
+    wcnst_status st = read_ctrl(s, &c);
+    if (st) return st;
+    const StepRec& r = newest(c);
+    if (t_out) *t_out = r.t;
+    if (steps_out) *steps_out = r.step - c.call_step0;
+    if (c.status != 0) {
+        const long long stg = c.bad_key == ~0ull ? -1 : (long long)(c.bad_key >> 36);
+        const long long cell = c.bad_key == ~0ull ? -1 : (long long)(c.bad_key & ((1ull << 36) - 1));
+        return fail(WCNST_E_NONPHYSICAL, "non-physical state at global stage %lld, cell %lld", stg, cell);
+    }
+    if (timed && !(t_final - r.t <= 1e-12 * t_final))
+        return fail(WCNST_E_MAX_STEPS, "t_final not reached in %lld steps (t = %.17g)",
+                    (long long)max_steps, r.t);
+    return WCNST_OK;
+}
+
+extern "C" wcnst_status wcnst_status_sync(wcnst_solver* s, double* t, int64_t* steps, int32_t* status,
+                                          int64_t* bad_stage, int64_t* bad_cell)
+{
+    if (!s) return fail(WCNST_E_INVALID_ARG, "null handle");
+    Ctrl c;
+    wcnst_status st = read_ctrl(s, &c);
+    if (st) return st;
+    const StepRec& r = newest(c);
+    if (t) *t = r.t;
+    if (steps) *steps = r.step;
+    if (status) *status = c.status;
+    const bool none = c.bad_key == ~0ull;
+    if (bad_stage) *bad_stage = none ? -1 : (int64_t)(c.bad_key >> 36);
+    if (bad_cell) *bad_cell = none ? -1 : (int64_t)(c.bad_key & ((1ull << 36) - 1));
+    return WCNST_OK;
+}
+
+extern "C" wcnst_status wcnst_reset(wcnst_solver* s, double t, int64_t steps)
+{
+    if (!s) return fail(WCNST_E_INVALID_ARG, "null handle");
+    hipLaunchKernelGGL(ctrl_init, dim3(1), dim3(64), 0, s->stream, s->ctrl, t, (long long)steps);
+    s->parity = 0;
+    HIP_TRY(hipGetLastError());
+    return WCNST_OK;
+}
+
+extern "C" wcnst_status wcnst_profile_enable(wcnst_solver* s, int enable)
+{
+    if (!s) return fail(WCNST_E_INVALID_ARG, "null handle");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->prof = enable != 0;
+    s->ev_used = 0;
+    return WCNST_OK;
+}
+
+extern "C" wcnst_status wcnst_profile_read(wcnst_solver* s, double* stage_ms, int64_t* stage_launches)
+{
+    if (!s) return fail(WCNST_E_INVALID_ARG, "null handle");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    double total = 0.0;
+    for (size_t i = 0; i + 1 < s->ev_used; i += 2) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, s->ev_pool[i], s->ev_pool[i + 1]));
+        total += ms;
+    }
+    if (stage_ms) *stage_ms = total;
+    if (stage_launches) *stage_launches = (int64_t)(s->ev_used / 2);
+    s->ev_used = 0;
+    return WCNST_OK;
+}
+
+extern "C" const char* wcnst_last_error(void) { return g_err; }

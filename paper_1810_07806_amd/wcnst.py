@@ -1,0 +1,222 @@
+"""Python binding of the C ABI in ``include/wcnst.h`` (``libwcnst.so``).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels
+of the library.  PyTorch supplies device memory (state arrays, workspace) and
+the HIP stream.  Importing works without a GPU; creating a solver requires the
+built library and raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+from .build import LIB_PATH
+
+OK, E_INVALID_ARG, E_NONPHYSICAL, E_MAX_STEPS, E_HIP = 0, 1, 2, 3, 4
+_SYSTEM = {"advection": 0, "burgers": 1, "euler": 2}
+_BC = {"periodic": 0, "zero_gradient": 1}
+_FLUX = {"roe": 0, "lf": 1}
+_SCHEME = {"teno": 0, "linear": 1, "js": 2}
+_DIFF = {"mnd": 0}
+
+EXPORTS = ("wcnst_desc_init", "wcnst_workspace_size", "wcnst_create", "wcnst_rhs", "wcnst_step",
+           "wcnst_solve", "wcnst_status_sync", "wcnst_reset", "wcnst_profile_enable",
+           "wcnst_profile_read", "wcnst_destroy", "wcnst_last_error")
+
+
+class WcnstError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"wcnst status {status}: {msg}")
+        self.status = status
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("ndim", ctypes.c_int32), ("system", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+        ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("flux", ctypes.c_int32),
+        ("scheme", ctypes.c_int32), ("diff", ctypes.c_int32), ("charwise", ctypes.c_int32),
+        ("q", ctypes.c_int32),
+        ("gamma", ctypes.c_double), ("adv_speed", ctypes.c_double), ("CT", ctypes.c_double),
+        ("C", ctypes.c_double), ("eps_teno", ctypes.c_double), ("eps_js", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib(path: str | None = None):
+    """Load ``libwcnst.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is missing: build it with "
+                           "`python -m paper_1810_07806_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(path)
+    vp, i64p, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
+    D = ctypes.POINTER(Desc)
+    L.wcnst_desc_init.argtypes = [D]
+    L.wcnst_workspace_size.argtypes = [D, ctypes.POINTER(ctypes.c_size_t)]
+    L.wcnst_create.argtypes = [D, vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.wcnst_rhs.argtypes = [vp, vp, vp, vp]
+    L.wcnst_step.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double]
+    L.wcnst_solve.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int64, dp, i64p]
+    L.wcnst_status_sync.argtypes = [vp, dp, i64p, ctypes.POINTER(ctypes.c_int32), i64p, i64p]
+    L.wcnst_reset.argtypes = [vp, ctypes.c_double, ctypes.c_int64]
+    L.wcnst_profile_enable.argtypes = [vp, ctypes.c_int]
+    L.wcnst_profile_read.argtypes = [vp, dp, i64p]
+    L.wcnst_destroy.argtypes = [vp]
+    L.wcnst_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "wcnst_last_error":
+            getattr(L, name).restype = ctypes.c_int32
+    _lib = L
+    return L
+
+
+def _check(st: int):
+    if st != OK:
+        raise WcnstError(st, lib().wcnst_last_error().decode())
+
+
+def make_desc(desc: dict) -> Desc:
+    d = Desc()
+    _check(lib().wcnst_desc_init(ctypes.byref(d)))
+    d.ndim = int(desc.get("ndim", 1))
+    d.system = _SYSTEM[desc.get("system", "euler")]
+    d.nx = int(desc["nx"])
+    d.ny = int(desc.get("ny", 1)) if d.ndim == 2 else 1
+    d.x0, d.x1 = float(desc.get("x0", 0.0)), float(desc.get("x1", 1.0))
+    d.y0, d.y1 = float(desc.get("y0", 0.0)), float(desc.get("y1", 1.0))
+    d.bc_x = _BC[desc.get("bc_x", "zero_gradient")]
+    d.bc_y = _BC[desc.get("bc_y", "zero_gradient")]
+    d.flux = _FLUX[desc.get("flux", "roe")]
+    d.scheme = _SCHEME[desc.get("scheme", "teno")]
+    d.diff = _DIFF[desc.get("diff", "mnd")]
+    d.charwise = int(desc.get("charwise", 1))
+    d.q = int(desc.get("q", 6))
+    d.gamma = float(desc.get("gamma", 1.4))
+    d.adv_speed = float(desc.get("adv_speed", 1.0))
+    d.CT = float(desc.get("CT", 1e-5))
+    d.C = float(desc.get("C", 1.0))
+    d.eps_teno = float(desc.get("eps_teno", 1e-40))
+    d.eps_js = float(desc.get("eps_js", 1e-6))
+    return d
+
+
+def nvar(desc: dict) -> int:
+    if desc.get("system", "euler") != "euler":
+        return 1
+    return 3 if int(desc.get("ndim", 1)) == 1 else 4
+
+
+def flag_count(desc: dict) -> int:
+    nv, nx = nvar(desc), int(desc["nx"])
+    if int(desc.get("ndim", 1)) == 1:
+        return nv * (nx + 3) * 2
+    ny = int(desc["ny"])
+    return nv * ny * (nx + 3) * 2 + nv * nx * (ny + 3) * 2
+
+
+class Solver:
+    """One WCNS-T solver bound to a torch CUDA stream and a torch-owned workspace."""
+
+    def __init__(self, desc: dict, stream=None, device: str = "cuda"):
+        import torch
+        self._torch = torch
+        self.desc = dict(desc)
+        self.nv = nvar(desc)
+        self.ny = int(desc.get("ny", 1)) if int(desc.get("ndim", 1)) == 2 else 1
+        self.nx = int(desc["nx"])
+        self._d = make_desc(desc)
+        n = ctypes.c_size_t(0)
+        _check(lib().wcnst_workspace_size(ctypes.byref(self._d), ctypes.byref(n)))
+        self.ws_bytes = n.value
+        raw = torch.empty(n.value + 256, dtype=torch.uint8, device=device)
+        off = (-raw.data_ptr()) % 256
+        self._ws_raw = raw
+        self.ws = raw[off:off + n.value]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(raw.device)
+        h = ctypes.c_void_p()
+        _check(lib().wcnst_create(ctypes.byref(self._d), ctypes.c_void_p(self.stream.cuda_stream),
+                                  ctypes.c_void_p(self.ws.data_ptr()), n.value, ctypes.byref(h)))
+        self._h = h
+
+    # -- helpers
+    def _state(self, U):
+        t = self._torch
+        if not (isinstance(U, t.Tensor) and U.is_cuda and U.dtype == t.float64 and U.is_contiguous()):
+            raise TypeError("state must be a contiguous float64 CUDA tensor")
+        if U.numel() != self.nv * self.ny * self.nx:
+            raise ValueError(f"state has {U.numel()} values, expected {self.nv}x{self.ny}x{self.nx}")
+        return ctypes.c_void_p(U.data_ptr())
+
+    def new_state(self, U_host):
+        """Copy a host array (nv, ny, nx) to a new device tensor."""
+        t = self._torch
+        return t.as_tensor(U_host, dtype=t.float64).reshape(self.nv, self.ny, self.nx).to(
+            self.ws.device).contiguous()
+
+    # -- C ABI
+    def rhs(self, U, flags: bool = False, out=None):
+        t = self._torch
+        R = out if out is not None else t.empty_like(U)
+        fl = t.zeros(flag_count(self.desc), dtype=t.uint8, device=U.device) if flags else None
+        _check(lib().wcnst_rhs(self._h, self._state(U), self._state(R),
+                               ctypes.c_void_p(fl.data_ptr()) if fl is not None else None))
+        return (R, fl) if flags else R
+
+    def step(self, U, dt: float = 0.0, cfl: float = 0.5):
+        _check(lib().wcnst_step(self._h, self._state(U), float(dt), float(cfl)))
+
+    def solve(self, U, t_final: float = math.inf, cfl: float = 0.5, max_steps: int = 1 << 62):
+        t = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        st = lib().wcnst_solve(self._h, self._state(U), float(t_final), float(cfl), int(max_steps),
+                               ctypes.byref(t), ctypes.byref(n))
+        if st not in (OK,):
+            raise WcnstError(st, lib().wcnst_last_error().decode())
+        return t.value, n.value
+
+    def status(self) -> dict:
+        t, n, s = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int32()
+        bs, bc = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().wcnst_status_sync(self._h, ctypes.byref(t), ctypes.byref(n), ctypes.byref(s),
+                                       ctypes.byref(bs), ctypes.byref(bc)))
+        return dict(t=t.value, steps=n.value, status=s.value, bad_stage=bs.value, bad_cell=bc.value)
+
+    def reset(self, t: float = 0.0, steps: int = 0):
+        _check(lib().wcnst_reset(self._h, float(t), int(steps)))
+
+    def profile_enable(self, on: bool = True):
+        _check(lib().wcnst_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().wcnst_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().wcnst_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def split_flags(desc: dict, fl):
+    """Views of a flat flag buffer as the x (and y) blocks of ``wcnst_rhs``."""
+    nv, nx = nvar(desc), int(desc["nx"])
+    if int(desc.get("ndim", 1)) == 1:
+        return [fl.reshape(nv, 1, nx + 3, 2)]
+    ny = int(desc["ny"])
+    nxb = nv * ny * (nx + 3) * 2
+    return [fl[:nxb].reshape(nv, ny, nx + 3, 2), fl[nxb:].reshape(nv, nx, ny + 3, 2)]

@@ -1,0 +1,82 @@
+"""The C-ABI library loads and exports every symbol its header declares; the
+host-side descriptor validation behaves as documented (no GPU work)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wcnst.h")
+
+
+def _lib():
+    from paper_1810_07806_amd import build, wcnst
+    if not os.path.exists(build.LIB_PATH):
+        build.build()
+    return wcnst, wcnst.lib()
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(wcnst_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("wcnst_create", "wcnst_rhs", "wcnst_step", "wcnst_solve", "wcnst_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    wc, L = _lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert set(_declared()) == set(wc.EXPORTS)
+
+
+def test_struct_layout_matches_header():
+    wc, L = _lib()
+    d = wc.Desc()
+    assert L.wcnst_desc_init(ctypes.byref(d)) == 0
+    assert d.struct_size == ctypes.sizeof(wc.Desc)
+    assert (d.q, d.CT, d.C, d.eps_teno, d.gamma) == (6, 1e-5, 1.0, 1e-40, 1.4)
+
+
+def _ws(wc, L, **kw):
+    base = dict(ndim=1, system="euler", nx=64)
+    base.update(kw)
+    d = wc.make_desc(base)
+    n = ctypes.c_size_t(0)
+    return L.wcnst_workspace_size(ctypes.byref(d), ctypes.byref(n)), n.value
+
+
+def test_workspace_size_and_validation():
+    wc, L = _lib()
+    st, n = _ws(wc, L, nx=100)
+    assert st == 0 and n >= 2 * 3 * 100 * 8
+    st, n2 = _ws(wc, L, ndim=2, nx=2048, ny=2048)
+    assert st == 0 and n2 >= 2 * 4 * 2048 * 2048 * 8
+    bad = [dict(nx=4), dict(ndim=3), dict(ndim=2, system="advection", nx=8, ny=8),
+           dict(ndim=2, nx=8, ny=4), dict(gamma=1.0), dict(CT=0.5), dict(q=0),
+           dict(x0=1.0, x1=1.0)]
+    for kw in bad:
+        st, _ = _ws(wc, L, **kw)
+        assert st == wc.E_INVALID_ARG, kw
+        assert L.wcnst_last_error()
+
+
+def test_binding_refuses_a_missing_library(tmp_path):
+    import importlib
+    from paper_1810_07806_amd import wcnst
+    saved = wcnst._lib
+    try:
+        wcnst._lib = None
+        with pytest.raises(RuntimeError):
+            wcnst.lib(str(tmp_path / "absent.so"))
+    finally:
+        wcnst._lib = saved
+    importlib.reload  # keep the import used

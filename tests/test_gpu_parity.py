@@ -1,0 +1,238 @@
+"""GPU (HIP, gfx950) path against the CPU oracle, through the C ABI.
+
+RHS within 1e-12 (per-component inf-norm relative), stencil-cut flags
+identical outside the 1e-12 C_T tie band, fields within 1e-10 after 100
+steps, at sizes spanning several 61-column strips and row segments with
+ragged tails, plus the full 2048^2 four-quadrant case.
+"""
+from __future__ import annotations
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1810_07806_amd import workloads as W
+from parity import FIELD_TOL, assert_rhs_close, check_flags, rel_inf_err, rhs_mask_from_flips
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_1810_07806_amd import wcnst
+    wcnst.lib()
+    return T
+
+
+def _solver(desc):
+    from paper_1810_07806_amd.wcnst import Solver
+    return Solver(desc)
+
+
+def _rhs_case(orc, torch, desc, U, name):
+    _say(f"rhs {name} {desc.get('system')} {desc.get('ndim')}D nx={desc['nx']} ny={desc.get('ny', 1)} "
+         f"flux={desc.get('flux')} scheme={desc.get('scheme')} charwise={desc.get('charwise')}")
+    from paper_1810_07806_amd.wcnst import split_flags
+    s = _solver(desc)
+    Ug = s.new_state(U)
+    Rg, fg = s.rhs(Ug, flags=True)
+    torch.cuda.synchronize()
+    Rg = Rg.cpu().numpy()
+    fg = [b.cpu().numpy() for b in split_flags(desc, fg)]
+    p = orc.problem(desc)
+    Ro, fo, co = orc.rhs(p, U, flags=True, chi=True, nthreads=NTHREADS)
+    flips = check_flags(fg, fo, co, desc.get("CT", 1e-5))
+    ny, nx = Ro.shape[1], Ro.shape[2]
+    keep = rhs_mask_from_flips((ny, nx), flips, desc.get("ndim", 1))
+    err = assert_rhs_close(Rg, Ro, keep)
+    s.close()
+    return err, fo
+
+
+CASES_1D = []
+for flux in ("roe", "lf"):
+    for scheme in ("teno", "linear", "js"):
+        CASES_1D.append(dict(flux=flux, scheme=scheme, charwise=1, bc_x="zero_gradient"))
+CASES_1D.append(dict(flux="roe", scheme="teno", charwise=0, bc_x="zero_gradient"))
+CASES_1D.append(dict(flux="roe", scheme="teno", charwise=1, bc_x="periodic"))
+CASES_1D.append(dict(flux="lf", scheme="teno", charwise=0, bc_x="periodic"))
+
+
+@pytest.mark.parametrize("kw", CASES_1D, ids=lambda k: "-".join(str(v) for v in k.values()))
+def test_rhs_euler1d(orc, torch, kw):
+    rng = np.random.default_rng(100)
+    for n in (245, 61, 62, 5):
+        d, U = W.random_tube(rng, n)
+        d.update(kw)
+        _, fo = _rhs_case(orc, torch, d, U, f"tube{n}")
+    # both kept and cut stencils occurred on the large case
+    d, U = W.random_tube(np.random.default_rng(7), 300)
+    d.update(kw)
+    _, fo = _rhs_case(orc, torch, d, U, "tube300")
+    if kw["scheme"] == "teno":
+        assert (fo[0] == 7).any() and (fo[0] != 7).any()
+
+
+def test_rhs_shu_osher_2048(orc, torch):
+    d, U = W.shu_osher(2048)
+    _rhs_case(orc, torch, d, U, "shu-osher")
+
+
+@pytest.mark.parametrize("n", [200, 199, 5])
+def test_rhs_advection(orc, torch, n):
+    d, U = W.advection_sine_square(n) if n >= 8 else W.smooth_periodic(n)
+    _, fo = _rhs_case(orc, torch, d, U, f"advection{n}")
+    if n == 200:
+        assert (fo[0] != 7).any()
+
+
+@pytest.mark.parametrize("flux", ["roe", "lf"])
+def test_rhs_burgers(orc, torch, flux):
+    rng = np.random.default_rng(5)
+    d = W.describe(ndim=1, system="burgers", nx=150, bc_x="periodic", flux=flux)
+    U = rng.normal(size=(1, 1, 150))
+    _rhs_case(orc, torch, d, U, "burgers")
+
+
+CASES_2D = [dict(flux="roe", scheme="teno", charwise=1),
+            dict(flux="lf", scheme="teno", charwise=1),
+            dict(flux="roe", scheme="linear", charwise=1),
+            dict(flux="roe", scheme="teno", charwise=0),
+            dict(flux="roe", scheme="js", charwise=1)]
+
+
+@pytest.mark.parametrize("kw", CASES_2D, ids=lambda k: "-".join(str(v) for v in k.values()))
+def test_rhs_euler2d(orc, torch, kw):
+    rng = np.random.default_rng(200)
+    for (nx, ny) in ((133, 97), (61, 33), (5, 5), (130, 65)):
+        d, U = W.random_euler2d(rng, nx, ny)
+        d.update(kw)
+        _rhs_case(orc, torch, d, U, f"quad{nx}x{ny}")
+    d, U = W.random_euler2d(rng, 70, 40)
+    d.update(kw, bc_x="periodic", bc_y="periodic")
+    _rhs_case(orc, torch, d, U, "quad-periodic")
+
+
+def test_rhs_config3_full_size(orc, torch):
+    """The 2048^2 four-quadrant state in the launch configuration of the
+    benchmark; the whole field is compared."""
+    d, U = W.riemann2d_config3(2048)
+    _rhs_case(orc, torch, d, U, "config3-2048")
+
+
+# ------------------------------------------------------------ time stepping
+
+def _solve_case(orc, torch, desc, U, t_final, steps, name, tol=FIELD_TOL):
+    _say(f"solve {name} t_final={t_final} steps={steps}")
+    s = _solver(desc)
+    Ug = s.new_state(U)
+    tg, ng = s.solve(Ug, t_final=t_final, cfl=0.5, max_steps=steps)
+    Ugh = Ug.cpu().numpy()
+    r = orc.solve(orc.problem(desc), U, t_final=t_final, cfl=0.5, max_steps=steps, nthreads=NTHREADS)
+    assert r["status"] == 0
+    assert ng == r["steps"], (ng, r["steps"])
+    assert abs(tg - r["t"]) <= 1e-12 * max(1.0, abs(r["t"]))
+    err = rel_inf_err(Ugh, r["U"])
+    assert (err <= tol).all(), f"{name}: field error {err}"
+    s.close()
+    return Ugh
+
+
+def test_solve_advection_config1(orc, torch):
+    d, U = W.advection_sine_square(200)
+    _solve_case(orc, torch, d, U, 2.0, 1 << 40, "advection-t2")
+
+
+def test_solve_shu_osher_100_steps(orc, torch):
+    d, U = W.shu_osher(2048)
+    _solve_case(orc, torch, d, U, np.inf, 100, "shu-osher-100")
+
+
+def test_solve_tube_to_time(orc, torch):
+    rng = np.random.default_rng(3)
+    d, U = W.random_tube(rng, 257)
+    _solve_case(orc, torch, d, U, 0.05, 1 << 40, "tube-to-t")
+
+
+def test_solve_config3_100_steps(orc, torch):
+    d, U = W.riemann2d_config3(128)
+    _solve_case(orc, torch, d, U, np.inf, 100, "config3-128-100")
+
+
+def test_solve_random2d_periodic_100_steps(orc, torch):
+    rng = np.random.default_rng(11)
+    d, U = W.random_euler2d(rng, 96, 70)
+    d.update(bc_x="periodic", bc_y="periodic")
+    _solve_case(orc, torch, d, U, np.inf, 100, "quad-periodic-100")
+
+
+def test_step_api_matches_oracle_step(orc, torch):
+    rng = np.random.default_rng(4)
+    d, U = W.random_euler2d(rng, 64, 48)
+    _say("step api")
+    s = _solver(d)
+    Ug = s.new_state(U)
+    s.step(Ug, dt=1e-3)
+    s.step(Ug, dt=0.0, cfl=0.4)
+    st = s.status()
+    p = orc.problem(d)
+    V, ok, _, _ = orc.rk3_step(p, U, 1e-3)
+    dt2 = 0.4 / orc.max_speed(p, V)
+    V, ok2, _, _ = orc.rk3_step(p, V, dt2, stage_base=3)
+    assert ok == 0 and ok2 == 0 and st["status"] == 0 and st["steps"] == 2
+    assert abs(st["t"] - (1e-3 + dt2)) <= 1e-14
+    assert (rel_inf_err(Ug.cpu().numpy(), V) <= FIELD_TOL).all()
+
+
+def test_nonphysical_state_reported_like_oracle(orc, torch):
+    from paper_1810_07806_amd.wcnst import WcnstError
+    rng = np.random.default_rng(9)
+    d, U = W.random_tube(rng, 64)
+    U = U.copy()
+    U[0, 0, 17] = -0.5
+    _say("nonphysical")
+    r = orc.solve(orc.problem(d), U, t_final=0.1, cfl=0.5)
+    s = _solver(d)
+    Ug = s.new_state(U)
+    with pytest.raises(WcnstError) as ei:
+        s.solve(Ug, t_final=0.1, cfl=0.5)
+    assert ei.value.status == 2
+    st = s.status()
+    assert (st["bad_stage"], st["bad_cell"]) == (r["bad_stage"], r["bad_cell"])
+
+
+def test_config3_diagonal_symmetry_bitwise(torch):
+    """Identical arithmetic in the x and y sweeps keeps the symmetric state
+    of Sec. 3.6.1 symmetric bit for bit."""
+    d, U = W.riemann2d_config3(256)
+    _say("symmetry 256 x 30 steps")
+    s = _solver(d)
+    Ug = s.new_state(U)
+    s.solve(Ug, t_final=np.inf, cfl=0.5, max_steps=30)
+    V = Ug.cpu().numpy()
+    assert np.array_equal(V[0], V[0].T) and np.array_equal(V[3], V[3].T)
+    assert np.array_equal(V[1], V[2].T)
+
+
+def test_repeat_runs_are_bitwise_identical(torch):
+    rng = np.random.default_rng(21)
+    d, U = W.random_euler2d(rng, 150, 90)
+    _say("determinism")
+    outs = []
+    for _ in range(2):
+        s = _solver(d)
+        Ug = s.new_state(U)
+        s.solve(Ug, t_final=np.inf, cfl=0.5, max_steps=20)
+        outs.append(Ug.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
