@@ -457,8 +457,8 @@ double orc_max_speed(const orc_problem* p, const double* U)
             s = (fabs(cell[1] / cell[0]) + a) / p->dx;
             if (nv == 4) s = s + (fabs(cell[2] / cell[0]) + a) / p->dy;
         }
-        /* a NaN speed must poison the maximum */
-        if (!(s <= smax)) smax = s;
+        /* a NaN speed poisons the maximum for good */
+        if (isnan(s) || (!isnan(smax) && s > smax)) smax = s;
     }
     return smax;
 }

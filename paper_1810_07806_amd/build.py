@@ -29,7 +29,7 @@ def build(verbose: bool = False) -> str:
     tmp = LIB_PATH + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-ffp-contract=fast", "-fno-fast-math", "-Wall", "-Wno-unused-result",
+           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unused-result",
            "-I", INCLUDE, "-I", CSRC, "-o", tmp, *SOURCES]
     if verbose:
         print(" ".join(cmd))

@@ -5,14 +5,27 @@
 //   characteristic projection (Roe average of nodes j, j+1)      Sec. 3
 //   TENO-5 interpolation of u_L and of the mirrored u_R          Sec. 2.2-2.3
 //   back-projection and the Roe / local Lax-Friedrichs flux      Sec. 2.2, Eq. (6)
-// Written for throughput: fused multiply-adds, compile-time unrolled
-// eigenvector rows, a comparison form of the cut-off test and a select
-// chain for the weights of Eq. (19) (their values are the exact quotients
-// d_k / sum d_m over the kept stencils).
+//
+// Reproducible arithmetic.  The method is sensitive to rounding in two ways:
+// (1) with eps = 1e-40 in Eq. (16), a stencil whose data are flat to
+// round-off has beta_k ~ 1e-32 of pure rounding noise, so the last bits of
+// beta decide the cut; (2) the cut is discontinuous, so over many steps a
+// solution amplifies last-bit differences (two correct FP64 evaluation
+// orders drift apart by ~1e-5 after 100 steps on the four-quadrant
+// problem).  Every operation that produces a value is therefore evaluated
+// in the plain order of its definition with IEEE division and square root
+// and without contraction (this file and the kernels are compiled with
+// -ffp-contract=off), so results are reproducible bit for bit.  Only the
+// cut-off test itself, which is decided far from its threshold except in
+// genuine ties, uses a fast reciprocal and the comparison form
+// gamma_k < C_T * sum(gamma).
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+// The arithmetic is host-callable too, so it can be checked on a CPU.
+#define WCNST_HD __host__ __device__ __forceinline__
 
 namespace wcnst {
 
@@ -23,19 +36,19 @@ enum { BC_PERIODIC = 0, BC_ZG = 1 };
 
 struct Params {
     double CT, C, eps_teno, eps_js;
-    double gamma, gm1;
+    double gamma;
     double adv;
     double dx, dy;
     double c1x, c2x, c3x;  // MND coefficients divided by dx
     double c1y, c2y, c3y;  // ... and by dy
-    int q, scheme, charwise;
+    int q, charwise;
     int bc_x, bc_y;
     int nx, ny;
 };
 
 // ------------------------------------------------------------ helpers
 
-__device__ __forceinline__ int ghost_map(int g, int n, int bc)
+WCNST_HD int ghost_map(int g, int n, int bc)
 {
     if (bc == BC_PERIODIC) {
         g = g < 0 ? g + n : g;
@@ -45,10 +58,25 @@ __device__ __forceinline__ int ghost_map(int g, int n, int bc)
     return g >= n ? n - 1 : g;
 }
 
-__device__ __forceinline__ double pow_q(double x, int q)
+// 1/x to about one ulp for the cut-off test (two Newton steps on the
+// hardware estimate); exact division on the host.
+WCNST_HD double approx_rcp(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+#else
+    return 1.0 / x;
+#endif
+}
+
+WCNST_HD double pow_q(double x, int q)
 {
     if (q == 6) {
-        double x2 = x * x;
+        const double x2 = x * x;
         return x2 * x2 * x2;
     }
     double r = 1.0;
@@ -60,206 +88,187 @@ __device__ __forceinline__ double pow_q(double x, int q)
 
 // u_L at x_{i+1/2} from (a, b, c, d, e) = (u_{i-2} .. u_{i+2}); mask receives
 // delta_1 | delta_2 << 1 | delta_3 << 2.
-__device__ __forceinline__ double interp5(double a, double b, double c, double d, double e,
-                                          const Params& P, unsigned& mask)
+template <int SCHEME>
+WCNST_HD double interp5(double a, double b, double c, double d, double e, const Params& P,
+                        unsigned& mask)
 {
     // h u^(1)_k and h^2 u^(2)_k of Eqs. (10)-(11)
-    const double D10 = 0.5 * (a - 4.0 * b + 3.0 * c);
-    const double D11 = 0.5 * (d - b);
-    const double D12 = 0.5 * (-3.0 * c + 4.0 * d - e);
+    const double D10 = (a - 4.0 * b + 3.0 * c) / 2.0;
+    const double D11 = (d - b) / 2.0;
+    const double D12 = (-3.0 * c + 4.0 * d - e) / 2.0;
     const double D20 = a - 2.0 * b + c;
     const double D21 = b - 2.0 * c + d;
     const double D22 = c - 2.0 * d + e;
     // candidates, Eq. (9) with Delta x = h/2
-    const double q0 = c + 0.5 * D10 + 0.125 * D20;
-    const double q1 = c + 0.5 * D11 + 0.125 * D21;
-    const double q2 = c + 0.5 * D12 + 0.125 * D22;
-    if (P.scheme == SCH_LINEAR) {
+    const double q0 = c + D10 / 2.0 + D20 / 8.0;
+    const double q1 = c + D11 / 2.0 + D21 / 8.0;
+    const double q2 = c + D12 / 2.0 + D22 / 8.0;
+    double w0, w1, w2;
+    if constexpr (SCHEME == SCH_LINEAR) {
         mask = 7u;
-        return 0.0625 * q0 + 0.625 * q1 + 0.3125 * q2;
+        w0 = 1.0 / 16.0;
+        w1 = 10.0 / 16.0;
+        w2 = 5.0 / 16.0;
+    } else {
+        // Eq. (15)
+        const double b0 = D10 * D10 + D20 * D20;
+        const double b1 = D11 * D11 + D21 * D21;
+        const double b2 = D12 * D12 + D22 * D22;
+        if constexpr (SCHEME == SCH_JS) {
+            // Eq. (14)
+            mask = 7u;
+            const double e0 = b0 + P.eps_js, e1 = b1 + P.eps_js, e2 = b2 + P.eps_js;
+            const double a0 = (1.0 / 16.0) / (e0 * e0);
+            const double a1 = (10.0 / 16.0) / (e1 * e1);
+            const double a2 = (5.0 / 16.0) / (e2 * e2);
+            const double s = a0 + a1 + a2;
+            w0 = a0 / s;
+            w1 = a1 / s;
+            w2 = a2 / s;
+        } else {
+            // Eq. (16); Eqs. (17)-(18) as gamma_k < C_T * sum(gamma)
+            const double tau = fabs(b0 - b2);
+            const double g0 = pow_q(P.C + tau * approx_rcp(b0 + P.eps_teno), P.q);
+            const double g1 = pow_q(P.C + tau * approx_rcp(b1 + P.eps_teno), P.q);
+            const double g2 = pow_q(P.C + tau * approx_rcp(b2 + P.eps_teno), P.q);
+            const double thr = P.CT * (g0 + g1 + g2);
+            const bool k0 = !(g0 < thr), k1 = !(g1 < thr), k2 = !(g2 < thr);
+            mask = (unsigned)k0 | ((unsigned)k1 << 1) | ((unsigned)k2 << 2);
+            // Eq. (19): d_k delta_k / sum_m d_m delta_m, the exact quotient
+            // for each of the seven patterns
+            w0 = k0 ? (k1 ? (k2 ? 1.0 / 16.0 : 1.0 / 11.0) : (k2 ? 1.0 / 6.0 : 1.0)) : 0.0;
+            w1 = k1 ? (k0 ? (k2 ? 10.0 / 16.0 : 10.0 / 11.0) : (k2 ? 2.0 / 3.0 : 1.0)) : 0.0;
+            w2 = k2 ? (k0 ? (k1 ? 5.0 / 16.0 : 5.0 / 6.0) : (k1 ? 1.0 / 3.0 : 1.0)) : 0.0;
+        }
     }
-    // smoothness indicators, Eq. (15)
-    const double b0 = D10 * D10 + D20 * D20;
-    const double b1 = D11 * D11 + D21 * D21;
-    const double b2 = D12 * D12 + D22 * D22;
-    if (P.scheme == SCH_JS) {
-        mask = 7u;
-        const double e0 = b0 + P.eps_js, e1 = b1 + P.eps_js, e2 = b2 + P.eps_js;
-        const double a0 = 0.0625 / (e0 * e0), a1 = 0.625 / (e1 * e1), a2 = 0.3125 / (e2 * e2);
-        const double s = a0 + a1 + a2;
-        return (a0 * q0 + a1 * q1 + a2 * q2) / s;
-    }
-    // Eq. (16)
-    const double tau = fabs(b0 - b2);
-    const double g0 = pow_q(P.C + tau / (b0 + P.eps_teno), P.q);
-    const double g1 = pow_q(P.C + tau / (b1 + P.eps_teno), P.q);
-    const double g2 = pow_q(P.C + tau / (b2 + P.eps_teno), P.q);
-    // Eqs. (17)-(18): chi_k < C_T  <=>  gamma_k < C_T * sum(gamma)
-    const double thr = P.CT * (g0 + g1 + g2);
-    const bool k0 = !(g0 < thr), k1 = !(g1 < thr), k2 = !(g2 < thr);
-    mask = (unsigned)k0 | ((unsigned)k1 << 1) | ((unsigned)k2 << 2);
-    // Eq. (19): d_k delta_k / sum_m d_m delta_m for the seven patterns
-    const double w0 = k0 ? (k1 ? (k2 ? 0.0625 : 1.0 / 11.0) : (k2 ? 1.0 / 6.0 : 1.0)) : 0.0;
-    const double w1 = k1 ? (k0 ? (k2 ? 0.625 : 10.0 / 11.0) : (k2 ? 2.0 / 3.0 : 1.0)) : 0.0;
-    const double w2 = k2 ? (k0 ? (k1 ? 0.3125 : 5.0 / 6.0) : (k1 ? 1.0 / 3.0 : 1.0)) : 0.0;
+    // Eq. (12)
     return w0 * q0 + w1 * q1 + w2 * q2;
 }
 
 // ------------------------------------------------------------ Euler
 
-// Roe-averaged state and the scalars its eigenvectors are built from.
-struct Eig {
-    double u, v, H, c, ic, b1, b2, hq2;  // hq2 = (u^2 + v^2) / 2
-};
-
+// Ideal gas p = (gamma - 1)(E - |m|^2 / (2 rho)).
 template <int NV>
-__device__ __forceinline__ void prim(const double* U, const Params& P, double& u, double& v,
-                                     double& p, double& H)
+WCNST_HD double pressure(const double* U, double gamma)
 {
-    const double ir = 1.0 / U[0];
-    u = U[1] * ir;
-    v = NV == 4 ? U[2] * ir : 0.0;
-    const double kin = NV == 4 ? 0.5 * (U[1] * u + U[2] * v) : 0.5 * U[1] * u;
-    p = P.gm1 * (U[NV - 1] - kin);
-    H = (U[NV - 1] + p) * ir;
+    double kin;
+    if constexpr (NV == 4) kin = 0.5 * (U[1] * U[1] + U[2] * U[2]) / U[0];
+    else kin = 0.5 * U[1] * U[1] / U[0];
+    return (gamma - 1.0) * (U[NV - 1] - kin);
 }
 
+// Normal flux (rho u, rho u^2 + p, rho v u, u (E + p)).
 template <int NV>
-__device__ __forceinline__ Eig roe_average(const double* A, const double* B, const Params& P)
+WCNST_HD void euler_flux(const double* U, double gamma, double* F)
 {
-    double uA, vA, pA, HA, uB, vB, pB, HB;
-    prim<NV>(A, P, uA, vA, pA, HA);
-    prim<NV>(B, P, uB, vB, pB, HB);
-    const double sA = sqrt(A[0]), sB = sqrt(B[0]);
-    const double iw = 1.0 / (sA + sB);
-    Eig E;
-    E.u = (sA * uA + sB * uB) * iw;
-    E.v = NV == 4 ? (sA * vA + sB * vB) * iw : 0.0;
-    E.H = (sA * HA + sB * HB) * iw;
-    E.hq2 = 0.5 * (E.u * E.u + E.v * E.v);
-    const double c2 = P.gm1 * (E.H - E.hq2);
-    E.c = sqrt(c2);
-    E.ic = 1.0 / E.c;
-    E.b1 = P.gm1 / c2;
-    E.b2 = E.hq2 * E.b1;
-    return E;
-}
-
-// Left eigenvector row k (normal momentum first; fields: u-c, u, [shear], u+c).
-template <int NV, int K>
-__device__ __forceinline__ double lrow_dot(const Eig& E, const double* x)
-{
-    if constexpr (K == 0) {
-        double r = (E.b2 + E.u * E.ic) * x[0] - (E.b1 * E.u + E.ic) * x[1] + E.b1 * x[NV - 1];
-        if constexpr (NV == 4) r -= E.b1 * E.v * x[2];
-        return 0.5 * r;
-    } else if constexpr (K == 1) {
-        double r = (1.0 - E.b2) * x[0] + E.b1 * E.u * x[1] - E.b1 * x[NV - 1];
-        if constexpr (NV == 4) r += E.b1 * E.v * x[2];
-        return r;
-    } else if constexpr (NV == 4 && K == 2) {
-        return x[2] - E.v * x[0];
-    } else {
-        double r = (E.b2 - E.u * E.ic) * x[0] - (E.b1 * E.u - E.ic) * x[1] + E.b1 * x[NV - 1];
-        if constexpr (NV == 4) r -= E.b1 * E.v * x[2];
-        return 0.5 * r;
-    }
-}
-
-// acc += w * (right eigenvector column k)
-template <int NV, int K>
-__device__ __forceinline__ void rcol_axpy(const Eig& E, double w, double* acc)
-{
-    if constexpr (K == 0) {
-        acc[0] += w;
-        acc[1] += w * (E.u - E.c);
-        if constexpr (NV == 4) acc[2] += w * E.v;
-        acc[NV - 1] += w * (E.H - E.u * E.c);
-    } else if constexpr (K == 1) {
-        acc[0] += w;
-        acc[1] += w * E.u;
-        if constexpr (NV == 4) acc[2] += w * E.v;
-        acc[NV - 1] += w * E.hq2;
-    } else if constexpr (NV == 4 && K == 2) {
-        acc[2] += w;
-        acc[3] += w * E.v;
-    } else {
-        acc[0] += w;
-        acc[1] += w * (E.u + E.c);
-        if constexpr (NV == 4) acc[2] += w * E.v;
-        acc[NV - 1] += w * (E.H + E.u * E.c);
-    }
-}
-
-template <int NV, int K>
-__device__ __forceinline__ double eigval(const Eig& E)
-{
-    if constexpr (K == 0) return E.u - E.c;
-    else if constexpr (K == NV - 1) return E.u + E.c;
-    else return E.u;
-}
-
-template <int NV>
-__device__ __forceinline__ void euler_flux(const double* U, const Params& P, double* F)
-{
-    double u, v, p, H;
-    prim<NV>(U, P, u, v, p, H);
+    const double u = U[1] / U[0];
+    const double p = pressure<NV>(U, gamma);
     F[0] = U[1];
     F[1] = U[1] * u + p;
     if constexpr (NV == 4) F[2] = U[2] * u;
     F[NV - 1] = u * (U[NV - 1] + p);
 }
 
-template <int NV, int K>
-__device__ __forceinline__ void proj_interp(const Eig& E, const double (&s)[6][NV], const Params& P,
-                                            double* UL, double* UR, unsigned& fb)
+// Eigen-system of the normal flux Jacobian at the Roe average of A and B
+// (normal momentum first).  Fields: u-c, u, [shear], u+c.
+//   r_1 = (1, u-c, v, H-uc), r_2 = (1, u, v, q^2/2), r_3 = (0, 0, 1, v),
+//   r_4 = (1, u+c, v, H+uc);  with b1 = (gamma-1)/c^2, b2 = b1 q^2/2:
+//   l_1 = ( (b2 + u/c)/2, -(b1 u + 1/c)/2, -b1 v/2, b1/2 )
+//   l_2 = ( 1 - b2, b1 u, b1 v, -b1 ),  l_3 = ( -v, 0, 1, 0 )
+//   l_4 = ( (b2 - u/c)/2, -(b1 u - 1/c)/2, -b1 v/2, b1/2 )
+// The 1D system drops the v entries and the shear pair.
+template <int NV>
+struct Eigen {
+    double u, v, H, c, q2, b1, b2, uc, ic;
+
+    // entry (k, j) of L and (j, k) of R, each formed by the same expression
+    // wherever it is used
+    WCNST_HD double L(int k, int j) const
+    {
+        if (k == 0) {
+            if (j == 0) return 0.5 * (b2 + uc);
+            if (j == 1) return -0.5 * (b1 * u + ic);
+            if (j == NV - 1) return 0.5 * b1;
+            return -0.5 * b1 * v;
+        }
+        if (k == 1) {
+            if (j == 0) return 1.0 - b2;
+            if (j == 1) return b1 * u;
+            if (j == NV - 1) return -b1;
+            return b1 * v;
+        }
+        if (NV == 4 && k == 2) return j == 0 ? -v : (j == 2 ? 1.0 : 0.0);
+        if (j == 0) return 0.5 * (b2 - uc);
+        if (j == 1) return -0.5 * (b1 * u - ic);
+        if (j == NV - 1) return 0.5 * b1;
+        return -0.5 * b1 * v;
+    }
+    WCNST_HD double R(int j, int k) const
+    {
+        if (NV == 4 && k == 2) return j == 2 ? 1.0 : (j == 3 ? v : 0.0);
+        if (j == 0) return 1.0;
+        if (j == NV - 1) return k == 0 ? H - u * c : (k == 1 ? 0.5 * q2 : H + u * c);
+        if (j == 1) return k == 0 ? u - c : (k == 1 ? u : u + c);
+        return v;
+    }
+    WCNST_HD double lam(int k) const { return k == 0 ? u - c : (k == NV - 1 ? u + c : u); }
+};
+
+template <int NV>
+WCNST_HD void roe_eigen(const double* A, const double* B, double gamma, Eigen<NV>& E)
 {
-    double w[6];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) w[m] = lrow_dot<NV, K>(E, s[m]);
-    unsigned mL, mR;
-    const double wl = interp5(w[0], w[1], w[2], w[3], w[4], P, mL);
-    const double wr = interp5(w[5], w[4], w[3], w[2], w[1], P, mR);
-    rcol_axpy<NV, K>(E, wl, UL);
-    rcol_axpy<NV, K>(E, wr, UR);
-    fb |= (mL | (mR << 3)) << (6 * K);
+    const double rA = A[0], rB = B[0];
+    const double uA = A[1] / rA, uB = B[1] / rB;
+    const double vA = NV == 4 ? A[2] / rA : 0.0, vB = NV == 4 ? B[2] / rB : 0.0;
+    const double HA = (A[NV - 1] + pressure<NV>(A, gamma)) / rA;
+    const double HB = (B[NV - 1] + pressure<NV>(B, gamma)) / rB;
+    const double sA = sqrt(rA), sB = sqrt(rB);
+    E.u = (sA * uA + sB * uB) / (sA + sB);
+    E.v = (sA * vA + sB * vB) / (sA + sB);
+    E.H = (sA * HA + sB * HB) / (sA + sB);
+    E.q2 = E.u * E.u + E.v * E.v;
+    const double c2 = (gamma - 1.0) * (E.H - 0.5 * E.q2);
+    E.c = sqrt(c2);
+    E.b1 = (gamma - 1.0) / c2;
+    E.b2 = 0.5 * E.q2 * E.b1;
+    E.uc = E.u / E.c;
+    E.ic = 1.0 / E.c;
 }
 
-template <int NV, int K>
-__device__ __forceinline__ void roe_dissipation(const Eig& E, const double* dU, double* dis)
-{
-    const double a = fabs(eigval<NV, K>(E)) * lrow_dot<NV, K>(E, dU);
-    rcol_axpy<NV, K>(E, a, dis);
-}
-
-// Numerical flux of the Euler equations from the interpolated states.
+// Numerical flux of the Euler equations from the interpolated states: the
+// system form of Eq. (6), 1/2 [(F(U_R) + F(U_L)) - |A| (U_R - U_L)], with
+// |A| = R |Lambda| L at the Roe average of U_L and U_R (no entropy fix), or
+// the local Lax-Friedrichs speed max(|u| + c).
 template <int NV, int FLUX>
-__device__ __forceinline__ void euler_num_flux(const double* UL, const double* UR, const Params& P,
-                                               double* F)
+WCNST_HD void euler_num_flux(const double* UL, const double* UR, double gamma, double* F)
 {
     double FL[NV], FR[NV], dis[NV];
-    euler_flux<NV>(UL, P, FL);
-    euler_flux<NV>(UR, P, FR);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) dis[v] = 0.0;
+    euler_flux<NV>(UL, gamma, FL);
+    euler_flux<NV>(UR, gamma, FR);
     if constexpr (FLUX == FLUX_LF) {
-        double uL, vL, pL, HL, uR, vR, pR, HR;
-        prim<NV>(UL, P, uL, vL, pL, HL);
-        prim<NV>(UR, P, uR, vR, pR, HR);
-        const double aL = fabs(uL) + sqrt(P.gamma * pL / UL[0]);
-        const double aR = fabs(uR) + sqrt(P.gamma * pR / UR[0]);
+        const double aL = fabs(UL[1] / UL[0]) + sqrt(gamma * pressure<NV>(UL, gamma) / UL[0]);
+        const double aR = fabs(UR[1] / UR[0]) + sqrt(gamma * pressure<NV>(UR, gamma) / UR[0]);
         const double al = fmax(aL, aR);
 #pragma unroll
         for (int v = 0; v < NV; ++v) dis[v] = al * (UR[v] - UL[v]);
     } else {
-        const Eig E = roe_average<NV>(UL, UR, P);
-        double dU[NV];
+        Eigen<NV> E;
+        roe_eigen<NV>(UL, UR, gamma, E);
+        double alpha[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) dU[v] = UR[v] - UL[v];
-        roe_dissipation<NV, 0>(E, dU, dis);
-        roe_dissipation<NV, 1>(E, dU, dis);
-        roe_dissipation<NV, 2>(E, dU, dis);
-        if constexpr (NV == 4) roe_dissipation<NV, 3>(E, dU, dis);
+        for (int k = 0; k < NV; ++k) {
+            double acc = 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc += E.L(k, v) * (UR[v] - UL[v]);
+            alpha[k] = acc;
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) acc += E.R(v, k) * fabs(E.lam(k)) * alpha[k];
+            dis[v] = acc;
+        }
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) F[v] = 0.5 * ((FR[v] + FL[v]) - dis[v]);
@@ -269,82 +278,125 @@ __device__ __forceinline__ void euler_num_flux(const double* UL, const double* U
 
 // s: nodes j-2 .. j+3 (normal momentum first).  F: flux at x_{j+1/2}.
 // fb: 6 flag bits per field (left mask | right mask << 3).
-template <int SYS, int NV, int FLUX>
-__device__ __forceinline__ void face_flux(const double (&s)[6][NV], const Params& P, double (&F)[NV],
-                                          unsigned& fb)
+template <int SYS, int NV, int FLUX, int SCHEME>
+WCNST_HD void face_flux(const double (&s)[6][NV], const Params& P, double (&F)[NV], unsigned& fb)
 {
     fb = 0u;
     if constexpr (SYS == SYS_EULER) {
         double UL[NV], UR[NV];
         if (P.charwise) {
-            const Eig E = roe_average<NV>(s[2], s[3], P);
+            Eigen<NV> E;
+            roe_eigen<NV>(s[2], s[3], P.gamma, E);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) { UL[v] = 0.0; UR[v] = 0.0; }
-            proj_interp<NV, 0>(E, s, P, UL, UR, fb);
-            proj_interp<NV, 1>(E, s, P, UL, UR, fb);
-            proj_interp<NV, 2>(E, s, P, UL, UR, fb);
-            if constexpr (NV == 4) proj_interp<NV, 3>(E, s, P, UL, UR, fb);
+            for (int v = 0; v < NV; ++v) {
+                UL[v] = 0.0;
+                UR[v] = 0.0;
+            }
+            // one characteristic field at a time: project, interpolate both
+            // sides, and add its share of the back-projection (sums over k in
+            // increasing order, as in U = sum_k r_k w_k)
+#pragma unroll 1
+            for (int k = 0; k < NV; ++k) {
+                double w[6];
+#pragma unroll
+                for (int m = 0; m < 6; ++m) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) acc += E.L(k, v) * s[m][v];
+                    w[m] = acc;
+                }
+                unsigned mL, mR;
+                const double wl = interp5<SCHEME>(w[0], w[1], w[2], w[3], w[4], P, mL);
+                const double wr = interp5<SCHEME>(w[5], w[4], w[3], w[2], w[1], P, mR);
+                fb |= (mL | (mR << 3)) << (6 * k);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const double r = E.R(v, k);
+                    UL[v] += r * wl;
+                    UR[v] += r * wr;
+                }
+            }
         } else {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 unsigned mL, mR;
-                UL[v] = interp5(s[0][v], s[1][v], s[2][v], s[3][v], s[4][v], P, mL);
-                UR[v] = interp5(s[5][v], s[4][v], s[3][v], s[2][v], s[1][v], P, mR);
+                UL[v] = interp5<SCHEME>(s[0][v], s[1][v], s[2][v], s[3][v], s[4][v], P, mL);
+                UR[v] = interp5<SCHEME>(s[5][v], s[4][v], s[3][v], s[2][v], s[1][v], P, mR);
                 fb |= (mL | (mR << 3)) << (6 * v);
             }
         }
-        euler_num_flux<NV, FLUX>(UL, UR, P, F);
+        euler_num_flux<NV, FLUX>(UL, UR, P.gamma, F);
     } else {
         unsigned mL, mR;
-        const double uL = interp5(s[0][0], s[1][0], s[2][0], s[3][0], s[4][0], P, mL);
-        const double uR = interp5(s[5][0], s[4][0], s[3][0], s[2][0], s[1][0], P, mR);
+        const double uL = interp5<SCHEME>(s[0][0], s[1][0], s[2][0], s[3][0], s[4][0], P, mL);
+        const double uR = interp5<SCHEME>(s[5][0], s[4][0], s[3][0], s[2][0], s[1][0], P, mR);
         fb = mL | (mR << 3);
         if constexpr (SYS == SYS_ADV) {
-            F[0] = 0.5 * ((P.adv * uR + P.adv * uL) - fabs(P.adv) * (uR - uL));
+            // Eq. (6) with f = a u, a_hat = a
+            const double a = P.adv;
+            F[0] = 0.5 * ((a * uR + a * uL) - fabs(a) * (uR - uL));
         } else {
+            // Eq. (6) with f = u^2 / 2; a_hat = Roe speed or local max |u|
+            const double fl = 0.5 * uL * uL, fr = 0.5 * uR * uR;
             const double ah = FLUX == FLUX_LF ? fmax(fabs(uL), fabs(uR)) : 0.5 * (uL + uR);
-            F[0] = 0.5 * ((0.5 * uR * uR + 0.5 * uL * uL) - fabs(ah) * (uR - uL));
+            F[0] = 0.5 * ((fr + fl) - fabs(ah) * (uR - uL));
         }
     }
 }
 
 template <int SYS, int NV>
-__device__ __forceinline__ void node_flux(const double* U, const Params& P, double* F)
+WCNST_HD void node_flux(const double* U, const Params& P, double* F)
 {
-    if constexpr (SYS == SYS_EULER) euler_flux<NV>(U, P, F);
+    if constexpr (SYS == SYS_EULER) euler_flux<NV>(U, P.gamma, F);
     else if constexpr (SYS == SYS_ADV) F[0] = P.adv * U[0];
     else F[0] = 0.5 * U[0] * U[0];
 }
 
-// CFL denominator contribution of one cell.
+// CFL denominator contribution of one cell: (|u| + c)/dx [+ (|v| + c)/dy].
 template <int SYS, int NV>
-__device__ __forceinline__ double cell_speed(const double* U, const Params& P)
+WCNST_HD double cell_speed(const double* U, const Params& P)
 {
     if constexpr (SYS == SYS_ADV) return fabs(P.adv) / P.dx;
     else if constexpr (SYS == SYS_BURG) return fabs(U[0]) / P.dx;
     else {
-        double u, v, p, H;
-        prim<NV>(U, P, u, v, p, H);
-        const double a = sqrt(P.gamma * p / U[0]);
-        double s = (fabs(u) + a) / P.dx;
-        if constexpr (NV == 4) s = s + (fabs(v) + a) / P.dy;
+        const double a = sqrt(P.gamma * pressure<NV>(U, P.gamma) / U[0]);
+        double s = (fabs(U[1] / U[0]) + a) / P.dx;
+        if constexpr (NV == 4) s = s + (fabs(U[2] / U[0]) + a) / P.dy;
         return s;
     }
 }
 
 // Non-physical check of a stage output.
 template <int SYS, int NV>
-__device__ __forceinline__ bool cell_bad(const double* U, const Params& P)
+WCNST_HD bool cell_bad(const double* U, const Params& P)
 {
     bool bad = false;
 #pragma unroll
     for (int v = 0; v < NV; ++v) bad |= !isfinite(U[v]);
-    if constexpr (SYS == SYS_EULER) {
-        double u, v, p, H;
-        prim<NV>(U, P, u, v, p, H);
-        bad |= !(U[0] > 0.0) || !(p > 0.0);
-    }
+    if constexpr (SYS == SYS_EULER) bad |= !(U[0] > 0.0) || !(pressure<NV>(U, P.gamma) > 0.0);
     return bad;
+}
+
+// Stage update in the Shu-Osher form of SSP-RK3.
+template <int NV>
+WCNST_HD void rk_combine(int stage, double dt, const double* Uk, const double* Un, const double* R,
+                         double* o)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (stage == 0) o[v] = Uk[v] + dt * R[v];
+        else if (stage == 1) o[v] = 0.75 * Un[v] + 0.25 * (Uk[v] + dt * R[v]);
+        else o[v] = (1.0 / 3.0) * Un[v] + (2.0 / 3.0) * (Uk[v] + dt * R[v]);
+    }
+}
+
+// MND difference, Eq. (5): -(c1 (F_{i+1/2} - F_{i-1/2}) + c2 (f_{i+1} - f_{i-1})
+// + c3 (F_{i+3/2} - F_{i-3/2})) with c_k already divided by h.
+WCNST_HD double mnd(double c1, double c2, double c3, double Fm3, double Fm1, double Fp1, double Fp3,
+                    double fm, double fp)
+{
+    const double dfdx = c1 * (Fp1 - Fm1) + c2 * (fp - fm) + c3 * (Fp3 - Fm3);
+    return -dfdx;
 }
 
 }  // namespace wcnst

@@ -38,16 +38,15 @@ struct StepRec {
     double dt;
     unsigned long long smax_bits;  // max CFL speed of the state at time t (bit pattern)
     long long step;
-    int done;
-    int pad;
 };
 
 struct Ctrl {
     StepRec rec[2];  // current / next record, alternating by step parity
     unsigned long long bad_key;  // (global stage << 36) | cell of the first non-physical value
     long long call_step0;        // step counter at the start of the current solve call
-    int status;
-    int pad[3];
+    int status;                  // sticky WCNST_E_NONPHYSICAL
+    int done;                    // sticky: t_final reached in the current call
+    int pad[2];
 };
 
 enum { MODE_RHS = 0, MODE_STAGE = 1 };
@@ -71,7 +70,7 @@ __device__ __forceinline__ bool stage_prologue(Ctrl* ctrl, const StageArgs& A, d
                                                long long& step)
 {
     const StepRec* cur = &ctrl->rec[A.parity];
-    if (ctrl->status != 0 || cur->done) return false;
+    if (ctrl->status != 0 || ctrl->done != 0) return false;
     step = cur->step;
     if (A.stage != 0) {
         dt = cur->dt;
@@ -80,7 +79,7 @@ __device__ __forceinline__ bool stage_prologue(Ctrl* ctrl, const StageArgs& A, d
     const double t = cur->t;
     const bool fin = isfinite(A.t_final);
     if (fin && A.t_final - t <= 1e-12 * A.t_final) {
-        if (first_thread()) ctrl->rec[A.parity].done = 1;
+        if (first_thread()) ctrl->done = 1;
         return false;
     }
     const double smax = __longlong_as_double((long long)cur->smax_bits);
@@ -93,7 +92,6 @@ __device__ __forceinline__ bool stage_prologue(Ctrl* ctrl, const StageArgs& A, d
         nx->dt = 0.0;
         nx->step = step + 1;
         nx->smax_bits = 0ull;
-        nx->done = 0;
     }
     return true;
 }
@@ -106,20 +104,6 @@ __device__ __forceinline__ unsigned long long wave_max_bits(unsigned long long m
         m = o > m ? o : m;
     }
     return m;
-}
-
-// Stage update in the Shu-Osher form; returns the new cell state in o.
-template <int NV>
-__device__ __forceinline__ void rk_combine(int stage, double dt, const double* Uk, const double* Un,
-                                           const double* R, double* o)
-{
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double w = Uk[v] + dt * R[v];
-        if (stage == 0) o[v] = w;
-        else if (stage == 1) o[v] = 0.75 * Un[v] + 0.25 * w;
-        else o[v] = (1.0 / 3.0) * Un[v] + (2.0 / 3.0) * w;
-    }
 }
 
 template <int SYS, int NV>
@@ -166,7 +150,7 @@ __device__ __forceinline__ void write_flags(uint8_t* fl, int nlines, int nfaces,
 
 // ------------------------------------------------------------------ 1D
 
-template <int SYS, int NV, int FLUX, int MODE, bool FLAGS>
+template <int SYS, int NV, int FLUX, int SCHEME, int MODE, bool FLAGS>
 __global__ void __launch_bounds__(WAVE)
 sweep1d(const double* __restrict__ U, const double* __restrict__ Un, double* __restrict__ out,
         uint8_t* __restrict__ flags, Ctrl* __restrict__ ctrl, Params P, StageArgs A)
@@ -195,7 +179,7 @@ sweep1d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
     }
     double F[NV], fn[NV];
     unsigned fb;
-    face_flux<SYS, NV, FLUX>(s, P, F, fb);
+    face_flux<SYS, NV, FLUX, SCHEME>(s, P, F, fb);
     if constexpr (FLAGS) {
         if (jx <= nx && face_owner(jx, nx, TX) == (int)blockIdx.x)
             write_flags<NV>(flags, 1, nx + 3, 0, jx + 2, fb);
@@ -212,8 +196,8 @@ sweep1d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
         double R[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v)
-            R[v] = -(P.c1x * (sF[v][lane + 2] - sF[v][lane + 1]) + P.c2x * (sN[v][lane + 2] - sN[v][lane]) +
-                     P.c3x * (sF[v][lane + 3] - sF[v][lane]));
+            R[v] = mnd(P.c1x, P.c2x, P.c3x, sF[v][lane], sF[v][lane + 1], sF[v][lane + 2], sF[v][lane + 3],
+                       sN[v][lane], sN[v][lane + 2]);
         if constexpr (MODE == MODE_RHS) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) out[(size_t)v * nx + c] = R[v];
@@ -234,7 +218,7 @@ sweep1d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
 
 // ------------------------------------------------------------------ 2D
 
-template <int NV, int FLUX, int MODE, bool FLAGS>
+template <int NV, int FLUX, int SCHEME, int MODE, bool FLAGS>
 __global__ void __launch_bounds__(WAVE)
 sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __restrict__ out,
         uint8_t* __restrict__ flags, Ctrl* __restrict__ ctrl, Params P, StageArgs A, int ty)
@@ -270,71 +254,73 @@ sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
     unsigned long long smax_loc = 0ull;
 
     for (int j = y0 - 2; j <= y1; ++j) {
-        {
+        const int i = j - 1;  // row finished once y-midpoint j is known
+        const int npass = i >= y0 ? 2 : 1;
+        double Uc[NV];
+        // pass 0: y-midpoint (c, j+1/2); pass 1: x-midpoint (jx+1/2, i).  One
+        // rolled loop so both share a single set of registers.
+#pragma unroll 1
+        for (int pass = 0; pass < npass; ++pass) {
             double s[6][NV];
+            if (pass == 0) {
 #pragma unroll
-            for (int m = 0; m < 6; ++m) {
-                const double* p = U + (size_t)ghost_map(j - 2 + m, ny, P.bc_y) * nx + cy;
-                s[m][0] = p[0];
-                s[m][1] = p[2 * plane];
-                s[m][2] = p[plane];
-                s[m][3] = p[3 * plane];
+                for (int m = 0; m < 6; ++m) {
+                    const double* p = U + (size_t)ghost_map(j - 2 + m, ny, P.bc_y) * nx + cy;
+                    s[m][0] = p[0];
+                    s[m][1] = p[2 * plane];
+                    s[m][2] = p[plane];
+                    s[m][3] = p[3 * plane];
+                }
+            } else {
+                const double* row = U + (size_t)i * nx;
+#pragma unroll
+                for (int m = 0; m < 6; ++m) {
+                    const int col = ghost_map(jxl - 2 + m, nx, P.bc_x);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) s[m][v] = row[(size_t)v * plane + col];
+                }
             }
             double F[NV];
             unsigned fb;
-            face_flux<SYS_EULER, NV, FLUX>(s, P, F, fb);
-            if constexpr (FLAGS) {
-                if (cell_ok && j <= ny && face_owner(j, ny, ty) == (int)blockIdx.y)
-                    write_flags<NV>(flags + (size_t)NV * ny * (nx + 3) * 2, nx, ny + 3, c, j + 2, fb);
-            }
+            face_flux<SYS_EULER, NV, FLUX, SCHEME>(s, P, F, fb);
+            if (pass == 0) {
+                if constexpr (FLAGS) {
+                    if (cell_ok && j <= ny && face_owner(j, ny, ty) == (int)blockIdx.y)
+                        write_flags<NV>(flags + (size_t)NV * ny * (nx + 3) * 2, nx, ny + 3, c, j + 2, fb);
+                }
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                fy[0][v] = fy[1][v];
-                fy[1][v] = fy[2][v];
-                fy[2][v] = fy[3][v];
-                fy[3][v] = F[v];
-                gn[0][v] = gn[1][v];
-                gn[1][v] = gn[2][v];
-            }
-            node_flux<SYS_EULER, NV>(s[2], P, gn[2]);
-        }
-        const int i = j - 1;
-        if (i < y0) continue;
-
-        double Uc[NV];
-        {
-            double s[6][NV];
-            const double* row = U + (size_t)i * nx;
+                for (int v = 0; v < NV; ++v) {
+                    fy[0][v] = fy[1][v];
+                    fy[1][v] = fy[2][v];
+                    fy[2][v] = fy[3][v];
+                    fy[3][v] = F[v];
+                    gn[0][v] = gn[1][v];
+                    gn[1][v] = gn[2][v];
+                }
+                node_flux<SYS_EULER, NV>(s[2], P, gn[2]);
+            } else {
+                if constexpr (FLAGS) {
+                    if (own_x) write_flags<NV>(flags, ny, nx + 3, i, jx + 2, fb);
+                }
+                double fn[NV];
+                node_flux<SYS_EULER, NV>(s[3], P, fn);
 #pragma unroll
-            for (int m = 0; m < 6; ++m) {
-                const int col = ghost_map(jxl - 2 + m, nx, P.bc_x);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) s[m][v] = row[(size_t)v * plane + col];
-            }
-            double F[NV], fn[NV];
-            unsigned fb;
-            face_flux<SYS_EULER, NV, FLUX>(s, P, F, fb);
-            if constexpr (FLAGS) {
-                if (own_x) write_flags<NV>(flags, ny, nx + 3, i, jx + 2, fb);
-            }
-            node_flux<SYS_EULER, NV>(s[3], P, fn);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                sF[v][lane] = F[v];
-                sN[v][lane] = fn[v];
-                Uc[v] = s[4][v];
+                for (int v = 0; v < NV; ++v) {
+                    sF[v][lane] = F[v];
+                    sN[v][lane] = fn[v];
+                    Uc[v] = s[4][v];
+                }
             }
         }
+        if (npass == 1) continue;
         __syncthreads();
         if (cell_ok) {
             double Rx[NV], Ry[NV], R[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                Rx[v] = -(P.c1x * (sF[v][lane + 2] - sF[v][lane + 1]) +
-                          P.c2x * (sN[v][lane + 2] - sN[v][lane]) +
-                          P.c3x * (sF[v][lane + 3] - sF[v][lane]));
-                Ry[v] = -(P.c1y * (fy[2][v] - fy[1][v]) + P.c2y * (gn[2][v] - gn[0][v]) +
-                          P.c3y * (fy[3][v] - fy[0][v]));
+                Rx[v] = mnd(P.c1x, P.c2x, P.c3x, sF[v][lane], sF[v][lane + 1], sF[v][lane + 2],
+                            sF[v][lane + 3], sN[v][lane], sN[v][lane + 2]);
+                Ry[v] = mnd(P.c1y, P.c2y, P.c3y, fy[0][v], fy[1][v], fy[2][v], fy[3][v], gn[0][v], gn[2][v]);
             }
             R[0] = Rx[0] + Ry[0];
             R[1] = Rx[1] + Ry[2];
@@ -371,11 +357,11 @@ __global__ void ctrl_init(Ctrl* ctrl, double t, long long step)
         ctrl->rec[k].dt = 0.0;
         ctrl->rec[k].smax_bits = 0ull;
         ctrl->rec[k].step = step;
-        ctrl->rec[k].done = 0;
     }
     ctrl->bad_key = ~0ull;
     ctrl->call_step0 = step;
     ctrl->status = 0;
+    ctrl->done = 0;
 }
 
 // Opens a solve / step call: clears the done flag and the speed accumulator
@@ -384,7 +370,7 @@ __global__ void ctrl_open(Ctrl* ctrl, int parity)
 {
     if (threadIdx.x != 0) return;
     ctrl->rec[parity].smax_bits = 0ull;
-    ctrl->rec[parity].done = 0;
+    ctrl->done = 0;
     ctrl->call_step0 = ctrl->rec[parity].step;
 }
 
@@ -562,7 +548,6 @@ extern "C" wcnst_status wcnst_create(const wcnst_desc* d, void* hip_stream, void
     P.eps_teno = d->eps_teno;
     P.eps_js = d->eps_js;
     P.gamma = d->gamma;
-    P.gm1 = d->gamma - 1.0;
     P.adv = d->adv_speed;
     P.nx = d->nx;
     P.ny = d->ny;
@@ -576,7 +561,6 @@ extern "C" wcnst_status wcnst_create(const wcnst_desc* d, void* hip_stream, void
     P.c2y = (-3.0 / 10.0) / P.dy;
     P.c3y = (1.0 / 30.0) / P.dy;
     P.q = d->q;
-    P.scheme = d->scheme;
     P.charwise = d->charwise ? 1 : 0;
     P.bc_x = d->bc_x;
     P.bc_y = d->bc_y;
@@ -614,18 +598,29 @@ extern "C" wcnst_status wcnst_destroy(wcnst_solver* s)
 
 // ---------------------------------------------------------- launchers
 
-template <int SYS, int NV, int FLUX, int MODE, bool FLAGS>
+template <int SYS, int NV, int FLUX, int SCHEME, int MODE, bool FLAGS>
 static void launch_sweep_t(const wcnst_solver* s, const double* U, const double* Un, double* out,
                            uint8_t* flags, const StageArgs& A)
 {
     const int nstrips = (s->d.nx + TX - 1) / TX;
     if constexpr (SYS == SYS_EULER && NV == 4) {
         const int nseg = (s->d.ny + s->ty - 1) / s->ty;
-        hipLaunchKernelGGL((sweep2d<NV, FLUX, MODE, FLAGS>), dim3(nstrips, nseg), dim3(WAVE), 0,
+        hipLaunchKernelGGL((sweep2d<NV, FLUX, SCHEME, MODE, FLAGS>), dim3(nstrips, nseg), dim3(WAVE), 0,
                            s->stream, U, Un, out, flags, s->ctrl, s->P, A, s->ty);
     } else {
-        hipLaunchKernelGGL((sweep1d<SYS, NV, FLUX, MODE, FLAGS>), dim3(nstrips), dim3(WAVE), 0,
+        hipLaunchKernelGGL((sweep1d<SYS, NV, FLUX, SCHEME, MODE, FLAGS>), dim3(nstrips), dim3(WAVE), 0,
                            s->stream, U, Un, out, flags, s->ctrl, s->P, A);
+    }
+}
+
+template <int SYS, int NV, int FLUX, int MODE, bool FLAGS>
+static void launch_scheme(const wcnst_solver* s, const double* U, const double* Un, double* out,
+                          uint8_t* flags, const StageArgs& A)
+{
+    switch (s->d.scheme) {
+    case WCNST_LINEAR: launch_sweep_t<SYS, NV, FLUX, SCH_LINEAR, MODE, FLAGS>(s, U, Un, out, flags, A); break;
+    case WCNST_JS: launch_sweep_t<SYS, NV, FLUX, SCH_JS, MODE, FLAGS>(s, U, Un, out, flags, A); break;
+    default: launch_sweep_t<SYS, NV, FLUX, SCH_TENO, MODE, FLAGS>(s, U, Un, out, flags, A); break;
     }
 }
 
@@ -635,18 +630,18 @@ static void launch_sweep(const wcnst_solver* s, const double* U, const double* U
 {
     const bool lf = s->d.flux == WCNST_LF;
     switch (s->kind) {
-    case K_ADV1: launch_sweep_t<SYS_ADV, 1, FLUX_ROE, MODE, FLAGS>(s, U, Un, out, flags, A); break;
+    case K_ADV1: launch_scheme<SYS_ADV, 1, FLUX_ROE, MODE, FLAGS>(s, U, Un, out, flags, A); break;
     case K_BURG1:
-        if (lf) launch_sweep_t<SYS_BURG, 1, FLUX_LF, MODE, FLAGS>(s, U, Un, out, flags, A);
-        else launch_sweep_t<SYS_BURG, 1, FLUX_ROE, MODE, FLAGS>(s, U, Un, out, flags, A);
+        if (lf) launch_scheme<SYS_BURG, 1, FLUX_LF, MODE, FLAGS>(s, U, Un, out, flags, A);
+        else launch_scheme<SYS_BURG, 1, FLUX_ROE, MODE, FLAGS>(s, U, Un, out, flags, A);
         break;
     case K_EUL1:
-        if (lf) launch_sweep_t<SYS_EULER, 3, FLUX_LF, MODE, FLAGS>(s, U, Un, out, flags, A);
-        else launch_sweep_t<SYS_EULER, 3, FLUX_ROE, MODE, FLAGS>(s, U, Un, out, flags, A);
+        if (lf) launch_scheme<SYS_EULER, 3, FLUX_LF, MODE, FLAGS>(s, U, Un, out, flags, A);
+        else launch_scheme<SYS_EULER, 3, FLUX_ROE, MODE, FLAGS>(s, U, Un, out, flags, A);
         break;
     case K_EUL2:
-        if (lf) launch_sweep_t<SYS_EULER, 4, FLUX_LF, MODE, FLAGS>(s, U, Un, out, flags, A);
-        else launch_sweep_t<SYS_EULER, 4, FLUX_ROE, MODE, FLAGS>(s, U, Un, out, flags, A);
+        if (lf) launch_scheme<SYS_EULER, 4, FLUX_LF, MODE, FLAGS>(s, U, Un, out, flags, A);
+        else launch_scheme<SYS_EULER, 4, FLUX_ROE, MODE, FLAGS>(s, U, Un, out, flags, A);
         break;
     }
 }
@@ -769,7 +764,7 @@ extern "C" wcnst_status wcnst_solve(wcnst_solver* s, double* U, double t_final, 
         HIP_TRY(hipEventSynchronize(s->snap_ev[prev]));
         const Ctrl& c = *s->host_ctrl[prev];
         const StepRec& r = newest(c);
-        if (c.status != 0 || c.rec[0].done || c.rec[1].done) break;
+        if (c.status != 0 || c.done) break;
         // estimate the steps still needed beyond what is already queued
         const int64_t done_steps = r.step - c.call_step0;
         const double dt = c.rec[0].step >= c.rec[1].step ? c.rec[1].dt : c.rec[0].dt;

@@ -1,0 +1,121 @@
+// Host build of the HIP path's per-midpoint arithmetic (wcnst_device.hpp),
+// for CPU tests of that arithmetic against the oracle.  It evaluates whole
+// grid lines the way the stage kernels do (ghost remap, midpoint flux, node
+// flux, MND difference) but on the host, so no GPU is needed.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "wcnst_device.hpp"
+
+using namespace wcnst;
+
+namespace {
+
+template <int SYS, int NV, int FLUX, int SCHEME>
+void line(const Params& P, int n, int bc, double c1, double c2, double c3, const double* U, int stride,
+          const int* perm, double* R, uint8_t* flags, int nlines, int li)
+{
+    std::vector<double> F((size_t)(n + 3) * NV), fn((size_t)(n + 2) * NV);
+    for (int j = -2; j <= n; ++j) {
+        double s[6][NV];
+        for (int m = 0; m < 6; ++m) {
+            const int g = ghost_map(j - 2 + m, n, bc);
+            for (int v = 0; v < NV; ++v) s[m][v] = U[(size_t)perm[v] * stride + g];
+        }
+        double f[NV];
+        unsigned fb;
+        face_flux<SYS, NV, FLUX, SCHEME>(s, P, f, fb);
+        for (int v = 0; v < NV; ++v) F[(size_t)(j + 2) * NV + v] = f[v];
+        if (flags)
+            for (int k = 0; k < NV; ++k) {
+                const size_t idx = (((size_t)k * nlines + li) * (n + 3) + (j + 2)) * 2;
+                flags[idx] = (uint8_t)((fb >> (6 * k)) & 7u);
+                flags[idx + 1] = (uint8_t)((fb >> (6 * k + 3)) & 7u);
+            }
+    }
+    for (int i = -1; i <= n; ++i) {
+        double u[NV], f[NV];
+        const int g = ghost_map(i, n, bc);
+        for (int v = 0; v < NV; ++v) u[v] = U[(size_t)perm[v] * stride + g];
+        node_flux<SYS, NV>(u, P, f);
+        for (int v = 0; v < NV; ++v) fn[(size_t)(i + 1) * NV + v] = f[v];
+    }
+    for (int i = 0; i < n; ++i)
+        for (int v = 0; v < NV; ++v) {
+            const double r = mnd(c1, c2, c3, F[(size_t)i * NV + v], F[(size_t)(i + 1) * NV + v],
+                                 F[(size_t)(i + 2) * NV + v], F[(size_t)(i + 3) * NV + v],
+                                 fn[(size_t)i * NV + v], fn[(size_t)(i + 2) * NV + v]);
+            R[(size_t)perm[v] * stride + i] += r;
+        }
+}
+
+template <int SYS, int NV, int FLUX>
+void line_scheme(int scheme, const Params& P, int n, int bc, double c1, double c2, double c3, const double* U,
+                 int stride, const int* perm, double* R, uint8_t* flags, int nlines, int li)
+{
+    if (scheme == SCH_LINEAR) line<SYS, NV, FLUX, SCH_LINEAR>(P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+    else if (scheme == SCH_JS) line<SYS, NV, FLUX, SCH_JS>(P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+    else line<SYS, NV, FLUX, SCH_TENO>(P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+}
+
+void run_line(int sys, int nv, int flux, int scheme, const Params& P, int n, int bc, double c1, double c2,
+              double c3, const double* U, int stride, const int* perm, double* R, uint8_t* flags, int nlines,
+              int li)
+{
+    if (sys == 0) line_scheme<SYS_ADV, 1, FLUX_ROE>(scheme, P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+    else if (sys == 1 && flux == 0) line_scheme<SYS_BURG, 1, FLUX_ROE>(scheme, P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+    else if (sys == 1) line_scheme<SYS_BURG, 1, FLUX_LF>(scheme, P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+    else if (nv == 3 && flux == 0) line_scheme<SYS_EULER, 3, FLUX_ROE>(scheme, P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+    else if (nv == 3) line_scheme<SYS_EULER, 3, FLUX_LF>(scheme, P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+    else if (flux == 0) line_scheme<SYS_EULER, 4, FLUX_ROE>(scheme, P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+    else line_scheme<SYS_EULER, 4, FLUX_LF>(scheme, P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+}
+
+}  // namespace
+
+extern "C" {
+
+// sys: 0 advection, 1 Burgers, 2 Euler; flux: 0 Roe, 1 LF.  U, R: [nv][ny][nx].
+// R is accumulated (the caller zeroes it).  flags: [x block][y block] like wcnst_rhs.
+int hc_rhs(int ndim, int sys, int flux, int nx, int ny, double dx, double dy, int bc_x, int bc_y,
+           int scheme, int charwise, int q, double gamma, double adv, double CT, double C,
+           double eps_teno, double eps_js, const double* U, double* R, uint8_t* flags)
+{
+    Params P{};
+    P.CT = CT; P.C = C; P.eps_teno = eps_teno; P.eps_js = eps_js;
+    P.gamma = gamma; P.adv = adv; P.dx = dx; P.dy = dy;
+    P.q = q; P.charwise = charwise; P.bc_x = bc_x; P.bc_y = bc_y;
+    P.nx = nx; P.ny = ny;
+    const int nv = sys == 2 ? (ndim == 1 ? 3 : 4) : 1;
+    const size_t plane = (size_t)nx * ny;
+    const double c1x = (3.0 / 2.0) / dx, c2x = (-3.0 / 10.0) / dx, c3x = (1.0 / 30.0) / dx;
+    const double c1y = (3.0 / 2.0) / dy, c2y = (-3.0 / 10.0) / dy, c3y = (1.0 / 30.0) / dy;
+    static const int idp[4] = {0, 1, 2, 3};
+    static const int yperm[4] = {0, 2, 1, 3};
+    // x lines
+    for (int y = 0; y < ny; ++y) {
+        std::vector<double> row((size_t)nv * nx), r((size_t)nv * nx, 0.0);
+        for (int v = 0; v < nv; ++v)
+            for (int x = 0; x < nx; ++x) row[(size_t)v * nx + x] = U[v * plane + (size_t)y * nx + x];
+        run_line(sys, nv, flux, scheme, P, nx, bc_x, c1x, c2x, c3x, row.data(), nx, idp, r.data(), flags, ny, y);
+        for (int v = 0; v < nv; ++v)
+            for (int x = 0; x < nx; ++x) R[v * plane + (size_t)y * nx + x] += r[(size_t)v * nx + x];
+    }
+    if (ndim == 2) {
+        uint8_t* fy = flags ? flags + (size_t)nv * ny * (nx + 3) * 2 : nullptr;
+        for (int x = 0; x < nx; ++x) {
+            std::vector<double> col((size_t)nv * ny), r((size_t)nv * ny, 0.0);
+            for (int v = 0; v < nv; ++v)
+                for (int y = 0; y < ny; ++y) col[(size_t)v * ny + y] = U[v * plane + (size_t)y * nx + x];
+            run_line(2, 4, flux, scheme, P, ny, bc_y, c1y, c2y, c3y, col.data(), ny, yperm, r.data(), fy, nx, x);
+            for (int v = 0; v < nv; ++v)
+                for (int y = 0; y < ny; ++y) R[v * plane + (size_t)y * nx + x] += r[(size_t)v * ny + y];
+        }
+    }
+    return 0;
+}
+
+}  // extern "C"

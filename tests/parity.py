@@ -17,13 +17,23 @@ BAND = 1e-12
 
 
 def rel_inf_err(a, b):
-    """Per-component ||a - b||_inf / ||b||_inf over the leading axis."""
+    """Per-component ||a - b||_inf / ||b||_inf over the leading axis.  NaN
+    entries must sit at the same places on both sides (a non-physical
+    intermediate state gives NaN in both); they are then left out."""
     a = np.asarray(a, dtype=np.float64).reshape(a.shape[0], -1)
     b = np.asarray(b, dtype=np.float64).reshape(b.shape[0], -1)
     out = []
     for v in range(a.shape[0]):
-        scale = np.abs(b[v]).max()
-        err = np.abs(a[v] - b[v]).max()
+        na, nb = np.isnan(a[v]), np.isnan(b[v])
+        if not np.array_equal(na, nb):
+            out.append(np.inf)
+            continue
+        ok = ~nb
+        if not ok.any():
+            out.append(0.0)
+            continue
+        scale = np.abs(b[v][ok]).max()
+        err = np.abs(a[v][ok] - b[v][ok]).max()
         out.append(err / scale if scale > 0 else err)
     return np.array(out)
 

@@ -1,0 +1,110 @@
+"""CPU check of the HIP path's arithmetic: the device header compiled for the
+host (tests/hostcheck) against the oracle.  Flags must be identical and the
+RHS within 1e-12 -- the same bar as the GPU parity tests, without a GPU --
+and, since both evaluate every value in the order of its definition, the RHS
+is identical bit for bit."""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1810_07806_amd import workloads as W
+from parity import assert_rhs_close
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(HERE, "hostcheck", "wcnst_hostcheck.cpp")
+LIB = os.path.join(HERE, "hostcheck", "libhostcheck.so")
+_SYS = {"advection": 0, "burgers": 1, "euler": 2}
+
+
+@pytest.fixture(scope="module")
+def hc():
+    dev = os.path.join(ROOT, "paper_1810_07806_amd", "csrc", "wcnst_device.hpp")
+    if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(SRC), os.path.getmtime(dev)):
+        cmd = ["/opt/rocm/bin/hipcc", "--offload-host-only", "-O3", "-std=c++17", "-fPIC", "-shared",
+               "-ffp-contract=off", "-I", os.path.dirname(dev), "-o", LIB + ".tmp", SRC]
+        subprocess.run(cmd, check=True, capture_output=True)
+        os.replace(LIB + ".tmp", LIB)
+    L = ctypes.CDLL(LIB)
+    dp = ctypes.c_void_p
+    i, d = ctypes.c_int, ctypes.c_double
+    L.hc_rhs.argtypes = [i, i, i, i, i, d, d, i, i, i, i, i, d, d, d, d, d, d, dp, dp, dp]
+    return L
+
+
+def _hc_rhs(hc, desc, U):
+    from paper_1810_07806_amd.wcnst import flag_count, split_flags
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    R = np.zeros_like(U)
+    fl = np.zeros(flag_count(desc), dtype=np.uint8)
+    ndim = desc["ndim"]
+    nx, ny = desc["nx"], desc["ny"] if ndim == 2 else 1
+    dx = (desc["x1"] - desc["x0"]) / nx
+    dy = (desc["y1"] - desc["y0"]) / ny if ndim == 2 else 1.0
+    bc = {"periodic": 0, "zero_gradient": 1}
+    hc.hc_rhs(ndim, _SYS[desc["system"]], 0 if desc["flux"] == "roe" else 1, nx, ny, dx, dy,
+              bc[desc["bc_x"]], bc[desc["bc_y"]], {"teno": 0, "linear": 1, "js": 2}[desc["scheme"]],
+              int(desc["charwise"]), int(desc["q"]), desc["gamma"], desc["adv_speed"], desc["CT"],
+              desc["C"], desc["eps_teno"], desc["eps_js"], U.ctypes.data, R.ctypes.data, fl.ctypes.data)
+    return R, [np.asarray(b) for b in split_flags(desc, fl)]
+
+
+def _compare(orc, hc, desc, U):
+    Rh, fh = _hc_rhs(hc, desc, U)
+    Ro, fo, _ = orc.rhs(orc.problem(desc), U, flags=True)
+    for a, b in zip(fh, fo):
+        assert np.array_equal(a, b), f"{int((a != b).sum())} flags differ"
+    assert_rhs_close(Rh, Ro)
+    # the value arithmetic follows the definitions operation for operation
+    assert np.array_equal(Rh, Ro, equal_nan=True), f"max diff {np.nanmax(np.abs(Rh - Ro))}"
+    return fo
+
+
+@pytest.mark.parametrize("flux", ["roe", "lf"])
+@pytest.mark.parametrize("scheme", ["teno", "linear", "js"])
+@pytest.mark.parametrize("charwise", [1, 0])
+def test_euler1d_lines(orc, hc, flux, scheme, charwise):
+    rng = np.random.default_rng(31)
+    for n in (5, 37, 128):
+        for bc in ("zero_gradient", "periodic"):
+            d, U = W.random_tube(rng, n)
+            d.update(flux=flux, scheme=scheme, charwise=charwise, bc_x=bc)
+            _compare(orc, hc, d, U)
+
+
+def test_scalar_lines(orc, hc):
+    d, U = W.advection_sine_square(200)
+    fo = _compare(orc, hc, d, U)
+    assert (fo[0] != 7).any()
+    rng = np.random.default_rng(2)
+    for flux in ("roe", "lf"):
+        d = W.describe(ndim=1, system="burgers", nx=90, bc_x="periodic", flux=flux)
+        _compare(orc, hc, d, rng.normal(size=(1, 1, 90)))
+
+
+@pytest.mark.parametrize("flux", ["roe", "lf"])
+def test_euler2d_planes(orc, hc, flux):
+    rng = np.random.default_rng(41)
+    d, U = W.random_euler2d(rng, 33, 27)
+    d.update(flux=flux)
+    _compare(orc, hc, d, U)
+    d, U = W.riemann2d_config3(40)
+    d.update(flux=flux)
+    _compare(orc, hc, d, U)
+
+
+def test_state_after_steps_with_rounding_noise(orc, hc):
+    """After time steps the flat regions carry rounding noise; the cut
+    decisions there depend on the last bits, and still agree."""
+    d, U = W.riemann2d_config3(32)
+    V = orc.solve(orc.problem(d), U, cfl=0.5, max_steps=3)["U"]
+    _compare(orc, hc, d, V)
+    rng = np.random.default_rng(8)
+    d1, U1 = W.random_tube(rng, 80)
+    V1 = orc.solve(orc.problem(d1), U1, cfl=0.5, max_steps=5)["U"]
+    _compare(orc, hc, d1, V1)

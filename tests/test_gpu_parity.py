@@ -236,3 +236,28 @@ def test_repeat_runs_are_bitwise_identical(torch):
         s.solve(Ug, t_final=np.inf, cfl=0.5, max_steps=20)
         outs.append(Ug.cpu().numpy())
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_bitwise_agreement_with_oracle(orc, torch):
+    """Both sides evaluate every value in the order of its definition with
+    IEEE division and square root, so the RHS and whole trajectories agree
+    bit for bit (the stated tolerances are looser than this)."""
+    d, U = W.riemann2d_config3(192)
+    _say("bitwise rhs config3-192")
+    s = _solver(d)
+    Ug = s.new_state(U)
+    Rg = s.rhs(Ug).cpu().numpy()
+    Ro, _, _ = orc.rhs(orc.problem(d), U, nthreads=NTHREADS)
+    assert np.array_equal(Rg, Ro)
+    _say("bitwise 60 steps config3-192")
+    s.solve(Ug, t_final=np.inf, cfl=0.5, max_steps=60)
+    r = orc.solve(orc.problem(d), U, cfl=0.5, max_steps=60, nthreads=NTHREADS)
+    assert np.array_equal(Ug.cpu().numpy(), r["U"])
+    rng = np.random.default_rng(77)
+    d1, U1 = W.random_tube(rng, 300)
+    _say("bitwise tube to t=0.1")
+    s1 = _solver(d1)
+    V = s1.new_state(U1)
+    s1.solve(V, t_final=0.1, cfl=0.5)
+    r1 = orc.solve(orc.problem(d1), U1, t_final=0.1, cfl=0.5)
+    assert np.array_equal(V.cpu().numpy(), r1["U"])
