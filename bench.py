@@ -86,6 +86,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=N_SIDE, help="grid side (default: the 2048^2 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rows", type=int, default=0, help="rows per 2D segment (0: library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -100,6 +101,8 @@ def main():
     torch.cuda.set_device(0)
     d, U0 = W.riemann2d_config3(args.n)
     s = Solver(d)
+    if args.rows > 0:
+        s.set_tuning(args.rows)
     U0g = s.new_state(U0)
     U = U0g.clone()
     if args.warmup > 0:
@@ -140,7 +143,7 @@ def main():
         "config": {"workload": f"2D Euler four-quadrant Riemann (Lax-Liu 3), {args.n}x{args.n} cells, "
                                f"WCNS-T TENO C_T=1e-5, Roe, MND, SSP-RK3 CFL 0.5, {nsteps} steps",
                    "nx": args.n, "ny": args.n, "t_reached": t_end, "kernel_ms_avg": avg_launch_s * 1e3,
-                   "stage_launches": launches},
+                   "stage_launches": launches, "rows_per_segment": args.rows or None},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                      "flops_per_unit": fl["per_stage_cell"],

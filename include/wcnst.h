@@ -135,6 +135,11 @@ wcnst_status wcnst_status_sync(wcnst_solver* s, double* t, int64_t* steps, int32
 /* Reset the device time, step counter and sticky status (asynchronous). */
 wcnst_status wcnst_reset(wcnst_solver* s, double t, int64_t steps);
 
+/* Launch shape of the 2D stage kernel: one 64-lane wavefront per strip of
+ * 61 columns marches up a segment of rows_per_segment rows (>= 1; default
+ * 35).  Changes only the work decomposition, never the results. */
+wcnst_status wcnst_set_tuning(wcnst_solver* s, int32_t rows_per_segment);
+
 /* Kernel timing for roofline reports: when enabled, every stage kernel is
  * bracketed by HIP events on the solver's stream.  wcnst_profile_read
  * synchronises and returns the summed stage-kernel milliseconds and the

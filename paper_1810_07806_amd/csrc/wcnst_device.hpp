@@ -58,6 +58,15 @@ WCNST_HD int ghost_map(int g, int n, int bc)
     return g >= n ? n - 1 : g;
 }
 
+// Same map for an index any distance outside [0, n) (periodic wraps as often
+// as needed); used where lanes past the last needed column stage data.
+WCNST_HD int ghost_map_any(int g, int n, int bc)
+{
+    if (bc == BC_PERIODIC) return ((g % n) + n) % n;
+    g = g < 0 ? 0 : g;
+    return g >= n ? n - 1 : g;
+}
+
 // 1/x to about one ulp for the cut-off test (two Newton steps on the
 // hardware estimate); exact division on the host.
 WCNST_HD double approx_rcp(double x)
@@ -214,6 +223,19 @@ struct Eigen {
     WCNST_HD double lam(int k) const { return k == 0 ? u - c : (k == NV - 1 ? u + c : u); }
 };
 
+// An empty register constraint: the compiler must treat the values as
+// changed here, so expressions built from them are formed after this point.
+template <int NV>
+WCNST_HD void opaque(Eigen<NV>& E)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+v"(E.u), "+v"(E.v), "+v"(E.H), "+v"(E.c), "+v"(E.q2));
+    asm volatile("" : "+v"(E.b1), "+v"(E.b2), "+v"(E.uc), "+v"(E.ic));
+#else
+    (void)E;
+#endif
+}
+
 template <int NV>
 WCNST_HD void roe_eigen(const double* A, const double* B, double gamma, Eigen<NV>& E)
 {
@@ -276,17 +298,36 @@ WCNST_HD void euler_num_flux(const double* UL, const double* UR, double gamma, d
 
 // --------------------------------------------------------- midpoint flux
 
-// s: nodes j-2 .. j+3 (normal momentum first).  F: flux at x_{j+1/2}.
+// Stencil accessors: st(m, v) is variable v (normal momentum first) of node
+// j-2+m.  refresh() marks the point where values are read again (a register
+// stencil ignores it; a stencil staged in LDS re-reads it per field rather
+// than holding all 6 x NV values in registers).
+template <int NV>
+struct RegStencil {
+    const double (&s)[6][NV];
+    WCNST_HD double operator()(int m, int v) const { return s[m][v]; }
+    WCNST_HD void refresh() {}
+};
+
+// s: nodes j-2 .. j+3 around x_{j+1/2}.  F: flux at x_{j+1/2}.
 // fb: 6 flag bits per field (left mask | right mask << 3).
-template <int SYS, int NV, int FLUX, int SCHEME>
-WCNST_HD void face_flux(const double (&s)[6][NV], const Params& P, double (&F)[NV], unsigned& fb)
+template <int SYS, int NV, int FLUX, int SCHEME, class ST>
+WCNST_HD void face_flux(ST& st, const Params& P, double (&F)[NV], unsigned& fb)
 {
     fb = 0u;
     if constexpr (SYS == SYS_EULER) {
         double UL[NV], UR[NV];
         if (P.charwise) {
             Eigen<NV> E;
-            roe_eigen<NV>(s[2], s[3], P.gamma, E);
+            {
+                double A[NV], B[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    A[v] = st(2, v);
+                    B[v] = st(3, v);
+                }
+                roe_eigen<NV>(A, B, P.gamma, E);
+            }
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 UL[v] = 0.0;
@@ -297,12 +338,17 @@ WCNST_HD void face_flux(const double (&s)[6][NV], const Params& P, double (&F)[N
             // increasing order, as in U = sum_k r_k w_k)
 #pragma unroll 1
             for (int k = 0; k < NV; ++k) {
+                // keep the eigenvector entries and the stencil reads of field
+                // k local to this iteration (not hoisted and held for all k)
+                Eigen<NV> Ek = E;
+                opaque(Ek);
+                st.refresh();
                 double w[6];
 #pragma unroll
                 for (int m = 0; m < 6; ++m) {
                     double acc = 0.0;
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) acc += E.L(k, v) * s[m][v];
+                    for (int v = 0; v < NV; ++v) acc += Ek.L(k, v) * st(m, v);
                     w[m] = acc;
                 }
                 unsigned mL, mR;
@@ -311,7 +357,7 @@ WCNST_HD void face_flux(const double (&s)[6][NV], const Params& P, double (&F)[N
                 fb |= (mL | (mR << 3)) << (6 * k);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    const double r = E.R(v, k);
+                    const double r = Ek.R(v, k);
                     UL[v] += r * wl;
                     UR[v] += r * wr;
                 }
@@ -320,16 +366,16 @@ WCNST_HD void face_flux(const double (&s)[6][NV], const Params& P, double (&F)[N
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 unsigned mL, mR;
-                UL[v] = interp5<SCHEME>(s[0][v], s[1][v], s[2][v], s[3][v], s[4][v], P, mL);
-                UR[v] = interp5<SCHEME>(s[5][v], s[4][v], s[3][v], s[2][v], s[1][v], P, mR);
+                UL[v] = interp5<SCHEME>(st(0, v), st(1, v), st(2, v), st(3, v), st(4, v), P, mL);
+                UR[v] = interp5<SCHEME>(st(5, v), st(4, v), st(3, v), st(2, v), st(1, v), P, mR);
                 fb |= (mL | (mR << 3)) << (6 * v);
             }
         }
         euler_num_flux<NV, FLUX>(UL, UR, P.gamma, F);
     } else {
         unsigned mL, mR;
-        const double uL = interp5<SCHEME>(s[0][0], s[1][0], s[2][0], s[3][0], s[4][0], P, mL);
-        const double uR = interp5<SCHEME>(s[5][0], s[4][0], s[3][0], s[2][0], s[1][0], P, mR);
+        const double uL = interp5<SCHEME>(st(0, 0), st(1, 0), st(2, 0), st(3, 0), st(4, 0), P, mL);
+        const double uR = interp5<SCHEME>(st(5, 0), st(4, 0), st(3, 0), st(2, 0), st(1, 0), P, mR);
         fb = mL | (mR << 3);
         if constexpr (SYS == SYS_ADV) {
             // Eq. (6) with f = a u, a_hat = a

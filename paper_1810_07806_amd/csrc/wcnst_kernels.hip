@@ -179,7 +179,8 @@ sweep1d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
     }
     double F[NV], fn[NV];
     unsigned fb;
-    face_flux<SYS, NV, FLUX, SCHEME>(s, P, F, fb);
+    RegStencil<NV> st{s};
+    face_flux<SYS, NV, FLUX, SCHEME>(st, P, F, fb);
     if constexpr (FLAGS) {
         if (jx <= nx && face_owner(jx, nx, TX) == (int)blockIdx.x)
             write_flags<NV>(flags, 1, nx + 3, 0, jx + 2, fb);
@@ -218,6 +219,47 @@ sweep1d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
 
 // ------------------------------------------------------------------ 2D
 
+// Width of a staged row: columns x0-4 .. x0+64 cover the x-stencils of the
+// 64 midpoints and the y-stencils of the 64 lanes.
+constexpr int XW = WAVE + 5;
+constexpr int NSLOT = 6;  // rows j-2 .. j+3 around y-midpoint j
+
+// Stencil read from the staged rows: element (m, v) at base[off[m] + vs[v]].
+template <int NV>
+struct LdsStencil {
+    const double* base;
+    int off[6];
+    int vs[NV];
+    __device__ double operator()(int m, int v) const { return base[off[m] + vs[v]]; }
+    // re-read per characteristic field: the offsets are treated as changed
+    __device__ void refresh()
+    {
+        asm volatile("" : "+v"(off[0]), "+v"(off[1]), "+v"(off[2]), "+v"(off[3]), "+v"(off[4]), "+v"(off[5]));
+    }
+};
+
+template <int NV>
+__device__ __forceinline__ void load_row(const double* __restrict__ U, size_t plane, size_t rowoff,
+                                         int colA, int colB, bool hasB, double (&ra)[NV], double (&rb)[NV])
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        ra[v] = U[(size_t)v * plane + rowoff + colA];
+        rb[v] = hasB ? U[(size_t)v * plane + rowoff + colB] : 0.0;
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ void store_row(double (*slot)[XW], int lane, bool hasB, const double (&ra)[NV],
+                                          const double (&rb)[NV])
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        slot[v][lane] = ra[v];
+        if (hasB) slot[v][WAVE + lane] = rb[v];
+    }
+}
+
 template <int NV, int FLUX, int SCHEME, int MODE, bool FLAGS>
 __global__ void __launch_bounds__(WAVE)
 sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __restrict__ out,
@@ -228,6 +270,9 @@ sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
     if constexpr (MODE == MODE_STAGE) {
         if (!stage_prologue(ctrl, A, dt, step)) return;
     }
+    // Ring of staged rows (all variables, XW columns) and the x-midpoint /
+    // x node fluxes of the current row.
+    __shared__ double ring[NSLOT][NV][XW];
     __shared__ double sF[NV][WAVE];
     __shared__ double sN[NV][WAVE];
     const int nx = P.nx, ny = P.ny;
@@ -238,89 +283,105 @@ sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
     const int y1 = min(y0 + ty, ny);
     const int c = x0 + lane;
     const bool cell_ok = lane < TX && c < nx;
-    const int cy = min(c, nx - 1);
     const int jx = x0 - 2 + lane;
-    const int jxl = min(jx, nx);  // lanes past the last midpoint load in-range data
     const bool own_x = FLAGS && jx <= nx && face_owner(jx, nx, TX) == (int)blockIdx.x;
+    // columns this lane stages (ghost cells by index remap, any distance)
+    const bool hasB = lane < XW - WAVE;
+    const int colA = ghost_map_any(x0 - 4 + lane, nx, P.bc_x);
+    const int colB = ghost_map_any(x0 - 4 + WAVE + lane, nx, P.bc_x);
 
-    // y-midpoint fluxes j-3 .. j and y node fluxes of rows j-2 .. j, in
-    // y-normal variable order (rho, rho v, rho u, E).
-    double fy[4][NV], gn[3][NV];
+    // y-midpoint fluxes j-3 .. j of this lane's column, in y-normal
+    // variable order (rho, rho v, rho u, E)
+    double fy[4][NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        fy[0][v] = fy[1][v] = fy[2][v] = fy[3][v] = 0.0;
-        gn[0][v] = gn[1][v] = gn[2][v] = 0.0;
-    }
+    for (int v = 0; v < NV; ++v) fy[0][v] = fy[1][v] = fy[2][v] = fy[3][v] = 0.0;
     unsigned long long smax_loc = 0ull;
 
+    // stage rows y0-4 .. y0+1 into slots 0 .. 5
+#pragma unroll 1
+    for (int k = 0; k < NSLOT; ++k) {
+        double ra[NV], rb[NV];
+        const size_t rowoff = (size_t)ghost_map(y0 - 4 + k, ny, P.bc_y) * nx;
+        load_row<NV>(U, plane, rowoff, colA, colB, hasB, ra, rb);
+        store_row<NV>(ring[k], lane, hasB, ra, rb);
+    }
+    __syncthreads();
+
+    int base = 0;  // slot of row j-2
     for (int j = y0 - 2; j <= y1; ++j) {
         const int i = j - 1;  // row finished once y-midpoint j is known
         const int npass = i >= y0 ? 2 : 1;
-        double Uc[NV];
-        // pass 0: y-midpoint (c, j+1/2); pass 1: x-midpoint (jx+1/2, i).  One
-        // rolled loop so both share a single set of registers.
+        // pass 0: y-midpoint (c, j+1/2) from rows j-2 .. j+3 at this lane's
+        // column (normal momentum = rho v first); pass 1: x-midpoint
+        // (jx+1/2, i) from row i.  Both passes run the same instructions on
+        // different staged data (selects, no branches), so they share one
+        // set of registers.
 #pragma unroll 1
         for (int pass = 0; pass < npass; ++pass) {
-            double s[6][NV];
-            if (pass == 0) {
+            const bool py = pass == 0;
+            LdsStencil<NV> st;
+            st.base = &ring[0][0][0];
+            const int slx = base + 1 < NSLOT ? base + 1 : base + 1 - NSLOT;
 #pragma unroll
-                for (int m = 0; m < 6; ++m) {
-                    const double* p = U + (size_t)ghost_map(j - 2 + m, ny, P.bc_y) * nx + cy;
-                    s[m][0] = p[0];
-                    s[m][1] = p[2 * plane];
-                    s[m][2] = p[plane];
-                    s[m][3] = p[3 * plane];
-                }
-            } else {
-                const double* row = U + (size_t)i * nx;
-#pragma unroll
-                for (int m = 0; m < 6; ++m) {
-                    const int col = ghost_map(jxl - 2 + m, nx, P.bc_x);
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) s[m][v] = row[(size_t)v * plane + col];
-                }
+            for (int m = 0; m < 6; ++m) {
+                const int sl = base + m < NSLOT ? base + m : base + m - NSLOT;
+                st.off[m] = py ? sl * NV * XW + lane + 4 : slx * NV * XW + lane + m;
             }
+            st.vs[0] = 0;
+            st.vs[1] = py ? 2 * XW : XW;
+            st.vs[2] = py ? XW : 2 * XW;
+            st.vs[3] = 3 * XW;
             double F[NV];
             unsigned fb;
-            face_flux<SYS_EULER, NV, FLUX, SCHEME>(s, P, F, fb);
-            if (pass == 0) {
-                if constexpr (FLAGS) {
+            face_flux<SYS_EULER, NV, FLUX, SCHEME>(st, P, F, fb);
+            if constexpr (FLAGS) {
+                if (py) {
                     if (cell_ok && j <= ny && face_owner(j, ny, ty) == (int)blockIdx.y)
                         write_flags<NV>(flags + (size_t)NV * ny * (nx + 3) * 2, nx, ny + 3, c, j + 2, fb);
+                } else if (own_x) {
+                    write_flags<NV>(flags, ny, nx + 3, i, jx + 2, fb);
                 }
+            }
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    fy[0][v] = fy[1][v];
-                    fy[1][v] = fy[2][v];
-                    fy[2][v] = fy[3][v];
-                    fy[3][v] = F[v];
-                    gn[0][v] = gn[1][v];
-                    gn[1][v] = gn[2][v];
-                }
-                node_flux<SYS_EULER, NV>(s[2], P, gn[2]);
-            } else {
-                if constexpr (FLAGS) {
-                    if (own_x) write_flags<NV>(flags, ny, nx + 3, i, jx + 2, fb);
-                }
-                double fn[NV];
-                node_flux<SYS_EULER, NV>(s[3], P, fn);
+            for (int v = 0; v < NV; ++v) {
+                fy[0][v] = py ? fy[1][v] : fy[0][v];
+                fy[1][v] = py ? fy[2][v] : fy[1][v];
+                fy[2][v] = py ? fy[3][v] : fy[2][v];
+                fy[3][v] = py ? F[v] : fy[3][v];
+            }
+            if (!py) {
+                // x node flux at node jx+1 of row i
+                double sn[NV], fn[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sn[v] = st(3, v);
+                node_flux<SYS_EULER, NV>(sn, P, fn);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
                     sF[v][lane] = F[v];
                     sN[v][lane] = fn[v];
-                    Uc[v] = s[4][v];
                 }
             }
         }
-        if (npass == 1) continue;
         __syncthreads();
-        if (cell_ok) {
+        if (npass == 2 && cell_ok) {
+            // rows i-1, i, i+1 of this lane's column are still staged
+            const int s_im = base;                                  // row j-2 = i-1
+            const int s_i = base + 1 < NSLOT ? base + 1 : base + 1 - NSLOT;  // row i
+            const int s_ip = base + 2 < NSLOT ? base + 2 : base + 2 - NSLOT; // row i+1
+            double um[NV], up[NV], Uc[NV], gm[NV], gp[NV];
+            um[0] = ring[s_im][0][lane + 4]; um[1] = ring[s_im][2][lane + 4];
+            um[2] = ring[s_im][1][lane + 4]; um[3] = ring[s_im][3][lane + 4];
+            up[0] = ring[s_ip][0][lane + 4]; up[1] = ring[s_ip][2][lane + 4];
+            up[2] = ring[s_ip][1][lane + 4]; up[3] = ring[s_ip][3][lane + 4];
+            node_flux<SYS_EULER, NV>(um, P, gm);
+            node_flux<SYS_EULER, NV>(up, P, gp);
             double Rx[NV], Ry[NV], R[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
+                Uc[v] = ring[s_i][v][lane + 4];
                 Rx[v] = mnd(P.c1x, P.c2x, P.c3x, sF[v][lane], sF[v][lane + 1], sF[v][lane + 2],
                             sF[v][lane + 3], sN[v][lane], sN[v][lane + 2]);
-                Ry[v] = mnd(P.c1y, P.c2y, P.c3y, fy[0][v], fy[1][v], fy[2][v], fy[3][v], gn[0][v], gn[2][v]);
+                Ry[v] = mnd(P.c1y, P.c2y, P.c3y, fy[0][v], fy[1][v], fy[2][v], fy[3][v], gm[v], gp[v]);
             }
             R[0] = Rx[0] + Ry[0];
             R[1] = Rx[1] + Ry[2];
@@ -340,6 +401,15 @@ sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
                 stage_epilogue<SYS_EULER, NV>(ctrl, P, A.stage, step, (long long)cell, o, smax_loc);
             }
         }
+        __syncthreads();
+        // row j-2 is no longer read: its slot takes row j+4
+        if (j < y1) {
+            double ra[NV], rb[NV];
+            const size_t rowoff = (size_t)ghost_map(j + 4, ny, P.bc_y) * nx;
+            load_row<NV>(U, plane, rowoff, colA, colB, hasB, ra, rb);
+            store_row<NV>(ring[base], lane, hasB, ra, rb);
+        }
+        base = base + 1 < NSLOT ? base + 1 : 0;
         __syncthreads();
     }
     if constexpr (MODE == MODE_STAGE) {
@@ -538,7 +608,7 @@ extern "C" wcnst_status wcnst_create(const wcnst_desc* d, void* hip_stream, void
     s->U1 = (double*)(ws + align256(sizeof(Ctrl)));
     s->U2 = (double*)(ws + align256(sizeof(Ctrl)) + align256(state));
     s->parity = 0;
-    s->ty = 32;
+    s->ty = 35;
     s->prof = false;
     s->ev_used = 0;
 
@@ -815,6 +885,14 @@ extern "C" wcnst_status wcnst_reset(wcnst_solver* s, double t, int64_t steps)
     hipLaunchKernelGGL(ctrl_init, dim3(1), dim3(64), 0, s->stream, s->ctrl, t, (long long)steps);
     s->parity = 0;
     HIP_TRY(hipGetLastError());
+    return WCNST_OK;
+}
+
+extern "C" wcnst_status wcnst_set_tuning(wcnst_solver* s, int32_t rows_per_segment)
+{
+    if (!s) return fail(WCNST_E_INVALID_ARG, "null handle");
+    if (rows_per_segment < 1) return fail(WCNST_E_INVALID_ARG, "rows_per_segment must be >= 1");
+    s->ty = rows_per_segment;
     return WCNST_OK;
 }
 

@@ -21,7 +21,7 @@ _SCHEME = {"teno": 0, "linear": 1, "js": 2}
 _DIFF = {"mnd": 0}
 
 EXPORTS = ("wcnst_desc_init", "wcnst_workspace_size", "wcnst_create", "wcnst_rhs", "wcnst_step",
-           "wcnst_solve", "wcnst_status_sync", "wcnst_reset", "wcnst_profile_enable",
+           "wcnst_solve", "wcnst_status_sync", "wcnst_reset", "wcnst_set_tuning", "wcnst_profile_enable",
            "wcnst_profile_read", "wcnst_destroy", "wcnst_last_error")
 
 
@@ -67,6 +67,7 @@ def lib(path: str | None = None):
     L.wcnst_solve.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int64, dp, i64p]
     L.wcnst_status_sync.argtypes = [vp, dp, i64p, ctypes.POINTER(ctypes.c_int32), i64p, i64p]
     L.wcnst_reset.argtypes = [vp, ctypes.c_double, ctypes.c_int64]
+    L.wcnst_set_tuning.argtypes = [vp, ctypes.c_int32]
     L.wcnst_profile_enable.argtypes = [vp, ctypes.c_int]
     L.wcnst_profile_read.argtypes = [vp, dp, i64p]
     L.wcnst_destroy.argtypes = [vp]
@@ -191,6 +192,9 @@ class Solver:
 
     def reset(self, t: float = 0.0, steps: int = 0):
         _check(lib().wcnst_reset(self._h, float(t), int(steps)))
+
+    def set_tuning(self, rows_per_segment: int):
+        _check(lib().wcnst_set_tuning(self._h, int(rows_per_segment)))
 
     def profile_enable(self, on: bool = True):
         _check(lib().wcnst_profile_enable(self._h, 1 if on else 0))

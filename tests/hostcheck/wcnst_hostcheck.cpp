@@ -27,7 +27,8 @@ void line(const Params& P, int n, int bc, double c1, double c2, double c3, const
         }
         double f[NV];
         unsigned fb;
-        face_flux<SYS, NV, FLUX, SCHEME>(s, P, f, fb);
+        RegStencil<NV> st{s};
+        face_flux<SYS, NV, FLUX, SCHEME>(st, P, f, fb);
         for (int v = 0; v < NV; ++v) F[(size_t)(j + 2) * NV + v] = f[v];
         if (flags)
             for (int k = 0; k < NV; ++k) {

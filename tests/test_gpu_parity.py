@@ -261,3 +261,21 @@ def test_bitwise_agreement_with_oracle(orc, torch):
     s1.solve(V, t_final=0.1, cfl=0.5)
     r1 = orc.solve(orc.problem(d1), U1, t_final=0.1, cfl=0.5)
     assert np.array_equal(V.cpu().numpy(), r1["U"])
+
+
+def test_launch_shape_does_not_change_results(torch):
+    """Segment heights (including ragged last segments and 1-row segments)
+    only change the work decomposition: results are bit-identical."""
+    rng = np.random.default_rng(5)
+    d, U = W.random_euler2d(rng, 140, 75)
+    outs = []
+    for rows in (35, 1, 16, 75, 200):
+        _say(f"launch shape rows={rows}")
+        s = _solver(d)
+        s.set_tuning(rows)
+        Ug = s.new_state(U)
+        R = s.rhs(Ug).cpu().numpy()
+        s.solve(Ug, t_final=np.inf, cfl=0.5, max_steps=5)
+        outs.append((R, Ug.cpu().numpy()))
+    for R, V in outs[1:]:
+        assert np.array_equal(R, outs[0][0]) and np.array_equal(V, outs[0][1])
