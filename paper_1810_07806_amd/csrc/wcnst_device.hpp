@@ -31,7 +31,8 @@ namespace wcnst {
 
 enum { SYS_ADV = 0, SYS_BURG = 1, SYS_EULER = 2 };
 enum { FLUX_ROE = 0, FLUX_LF = 1 };
-enum { SCH_TENO = 0, SCH_LINEAR = 1, SCH_JS = 2 };
+// SCH_TENO: Eq. (16) with the paper's q = 6; SCH_TENO_Q: any integer q
+enum { SCH_TENO = 0, SCH_LINEAR = 1, SCH_JS = 2, SCH_TENO_Q = 3 };
 enum { BC_PERIODIC = 0, BC_ZG = 1 };
 
 struct Params {
@@ -95,6 +96,32 @@ WCNST_HD double pow_q(double x, int q)
 
 // ------------------------------------------------- Sec. 2.2-2.3 interpolation
 
+// Weight of candidate k under cut pattern mask (bit k-1 = delta_k), Eq. (19):
+// d_k delta_k / sum_m d_m delta_m with d = (1, 10, 5)/16, written as the
+// exact quotient of each pattern.
+WCNST_HD double teno_weight(unsigned mask, int k)
+{
+    const bool k0 = mask & 1u, k1 = mask & 2u, k2 = mask & 4u;
+    if (k == 0) return k0 ? (k1 ? (k2 ? 1.0 / 16.0 : 1.0 / 11.0) : (k2 ? 1.0 / 6.0 : 1.0)) : 0.0;
+    if (k == 1) return k1 ? (k0 ? (k2 ? 10.0 / 16.0 : 10.0 / 11.0) : (k2 ? 2.0 / 3.0 : 1.0)) : 0.0;
+    return k2 ? (k0 ? (k1 ? 5.0 / 16.0 : 5.0 / 6.0) : (k1 ? 1.0 / 3.0 : 1.0)) : 0.0;
+}
+
+// The 8 x 3 weights in LDS (one copy per workgroup): three LDS reads per
+// interpolation instead of a chain of selects.  Kernels that interpolate
+// call init_weight_table() first.
+__device__ __forceinline__ double* weight_table()
+{
+    __shared__ double tab[24];
+    return tab;
+}
+
+__device__ __forceinline__ void init_weight_table()
+{
+    if (threadIdx.x < 24) weight_table()[threadIdx.x] = teno_weight(threadIdx.x / 3, threadIdx.x % 3);
+    __syncthreads();
+}
+
 // u_L at x_{i+1/2} from (a, b, c, d, e) = (u_{i-2} .. u_{i+2}); mask receives
 // delta_1 | delta_2 << 1 | delta_3 << 2.
 template <int SCHEME>
@@ -137,17 +164,25 @@ WCNST_HD double interp5(double a, double b, double c, double d, double e, const 
         } else {
             // Eq. (16); Eqs. (17)-(18) as gamma_k < C_T * sum(gamma)
             const double tau = fabs(b0 - b2);
-            const double g0 = pow_q(P.C + tau * approx_rcp(b0 + P.eps_teno), P.q);
-            const double g1 = pow_q(P.C + tau * approx_rcp(b1 + P.eps_teno), P.q);
-            const double g2 = pow_q(P.C + tau * approx_rcp(b2 + P.eps_teno), P.q);
+            const int q = SCHEME == SCH_TENO ? 6 : P.q;
+            const double g0 = pow_q(P.C + tau * approx_rcp(b0 + P.eps_teno), q);
+            const double g1 = pow_q(P.C + tau * approx_rcp(b1 + P.eps_teno), q);
+            const double g2 = pow_q(P.C + tau * approx_rcp(b2 + P.eps_teno), q);
             const double thr = P.CT * (g0 + g1 + g2);
             const bool k0 = !(g0 < thr), k1 = !(g1 < thr), k2 = !(g2 < thr);
             mask = (unsigned)k0 | ((unsigned)k1 << 1) | ((unsigned)k2 << 2);
             // Eq. (19): d_k delta_k / sum_m d_m delta_m, the exact quotient
             // for each of the seven patterns
-            w0 = k0 ? (k1 ? (k2 ? 1.0 / 16.0 : 1.0 / 11.0) : (k2 ? 1.0 / 6.0 : 1.0)) : 0.0;
-            w1 = k1 ? (k0 ? (k2 ? 10.0 / 16.0 : 10.0 / 11.0) : (k2 ? 2.0 / 3.0 : 1.0)) : 0.0;
-            w2 = k2 ? (k0 ? (k1 ? 5.0 / 16.0 : 5.0 / 6.0) : (k1 ? 1.0 / 3.0 : 1.0)) : 0.0;
+#if defined(__HIP_DEVICE_COMPILE__)
+            const double* tab = weight_table();
+            w0 = tab[mask * 3 + 0];
+            w1 = tab[mask * 3 + 1];
+            w2 = tab[mask * 3 + 2];
+#else
+            w0 = teno_weight(mask, 0);
+            w1 = teno_weight(mask, 1);
+            w2 = teno_weight(mask, 2);
+#endif
         }
     }
     // Eq. (12)
@@ -222,6 +257,14 @@ struct Eigen {
     }
     WCNST_HD double lam(int k) const { return k == 0 ? u - c : (k == NV - 1 ? u + c : u); }
 };
+
+// Scheduling fence between characteristic fields (no instruction emitted).
+WCNST_HD void field_fence()
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_sched_barrier(0);
+#endif
+}
 
 // An empty register constraint: the compiler must treat the values as
 // changed here, so expressions built from them are formed after this point.
@@ -311,13 +354,13 @@ struct RegStencil {
 
 // s: nodes j-2 .. j+3 around x_{j+1/2}.  F: flux at x_{j+1/2}.
 // fb: 6 flag bits per field (left mask | right mask << 3).
-template <int SYS, int NV, int FLUX, int SCHEME, class ST>
+template <int SYS, int NV, int FLUX, int SCHEME, bool CHAR, class ST>
 WCNST_HD void face_flux(ST& st, const Params& P, double (&F)[NV], unsigned& fb)
 {
     fb = 0u;
     if constexpr (SYS == SYS_EULER) {
         double UL[NV], UR[NV];
-        if (P.charwise) {
+        if constexpr (CHAR) {
             Eigen<NV> E;
             {
                 double A[NV], B[NV];
@@ -336,10 +379,12 @@ WCNST_HD void face_flux(ST& st, const Params& P, double (&F)[NV], unsigned& fb)
             // one characteristic field at a time: project, interpolate both
             // sides, and add its share of the back-projection (sums over k in
             // increasing order, as in U = sum_k r_k w_k)
-#pragma unroll 1
+#pragma unroll
             for (int k = 0; k < NV; ++k) {
                 // keep the eigenvector entries and the stencil reads of field
-                // k local to this iteration (not hoisted and held for all k)
+                // k local to this field (formed here, not hoisted and held for
+                // all k, and not interleaved with the next field)
+                field_fence();
                 Eigen<NV> Ek = E;
                 opaque(Ek);
                 st.refresh();

@@ -150,7 +150,7 @@ __device__ __forceinline__ void write_flags(uint8_t* fl, int nlines, int nfaces,
 
 // ------------------------------------------------------------------ 1D
 
-template <int SYS, int NV, int FLUX, int SCHEME, int MODE, bool FLAGS>
+template <int SYS, int NV, int FLUX, int SCHEME, bool CHAR, int MODE>
 __global__ void __launch_bounds__(WAVE)
 sweep1d(const double* __restrict__ U, const double* __restrict__ Un, double* __restrict__ out,
         uint8_t* __restrict__ flags, Ctrl* __restrict__ ctrl, Params P, StageArgs A)
@@ -162,6 +162,7 @@ sweep1d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
     }
     __shared__ double sF[NV][WAVE];
     __shared__ double sN[NV][WAVE];
+    init_weight_table();
     const int nx = P.nx;
     const int lane = threadIdx.x;
     const int x0 = blockIdx.x * TX;
@@ -180,11 +181,9 @@ sweep1d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
     double F[NV], fn[NV];
     unsigned fb;
     RegStencil<NV> st{s};
-    face_flux<SYS, NV, FLUX, SCHEME>(st, P, F, fb);
-    if constexpr (FLAGS) {
-        if (jx <= nx && face_owner(jx, nx, TX) == (int)blockIdx.x)
-            write_flags<NV>(flags, 1, nx + 3, 0, jx + 2, fb);
-    }
+    face_flux<SYS, NV, FLUX, SCHEME, CHAR>(st, P, F, fb);
+    if (flags && jx <= nx && face_owner(jx, nx, TX) == (int)blockIdx.x)
+        write_flags<NV>(flags, 1, nx + 3, 0, jx + 2, fb);
     node_flux<SYS, NV>(s[3], P, fn);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -260,8 +259,10 @@ __device__ __forceinline__ void store_row(double (*slot)[XW], int lane, bool has
     }
 }
 
-template <int NV, int FLUX, int SCHEME, int MODE, bool FLAGS>
-__global__ void __launch_bounds__(WAVE)
+// Two wavefronts per SIMD: the register budget is capped at 256 (a few
+// values spill); measured faster than one wavefront with no spills.
+template <int NV, int FLUX, int SCHEME, bool CHAR, int MODE>
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2)))
 sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __restrict__ out,
         uint8_t* __restrict__ flags, Ctrl* __restrict__ ctrl, Params P, StageArgs A, int ty)
 {
@@ -275,6 +276,7 @@ sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
     __shared__ double ring[NSLOT][NV][XW];
     __shared__ double sF[NV][WAVE];
     __shared__ double sN[NV][WAVE];
+    init_weight_table();
     const int nx = P.nx, ny = P.ny;
     const size_t plane = (size_t)nx * ny;
     const int lane = threadIdx.x;
@@ -284,7 +286,7 @@ sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
     const int c = x0 + lane;
     const bool cell_ok = lane < TX && c < nx;
     const int jx = x0 - 2 + lane;
-    const bool own_x = FLAGS && jx <= nx && face_owner(jx, nx, TX) == (int)blockIdx.x;
+    const bool own_x = flags && jx <= nx && face_owner(jx, nx, TX) == (int)blockIdx.x;
     // columns this lane stages (ghost cells by index remap, any distance)
     const bool hasB = lane < XW - WAVE;
     const int colA = ghost_map_any(x0 - 4 + lane, nx, P.bc_x);
@@ -333,8 +335,8 @@ sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
             st.vs[3] = 3 * XW;
             double F[NV];
             unsigned fb;
-            face_flux<SYS_EULER, NV, FLUX, SCHEME>(st, P, F, fb);
-            if constexpr (FLAGS) {
+            face_flux<SYS_EULER, NV, FLUX, SCHEME, CHAR>(st, P, F, fb);
+            if (flags) {
                 if (py) {
                     if (cell_ok && j <= ny && face_owner(j, ny, ty) == (int)blockIdx.y)
                         write_flags<NV>(flags + (size_t)NV * ny * (nx + 3) * 2, nx, ny + 3, c, j + 2, fb);
@@ -668,50 +670,61 @@ extern "C" wcnst_status wcnst_destroy(wcnst_solver* s)
 
 // ---------------------------------------------------------- launchers
 
-template <int SYS, int NV, int FLUX, int SCHEME, int MODE, bool FLAGS>
+template <int SYS, int NV, int FLUX, int SCHEME, bool CHAR, int MODE>
 static void launch_sweep_t(const wcnst_solver* s, const double* U, const double* Un, double* out,
                            uint8_t* flags, const StageArgs& A)
 {
     const int nstrips = (s->d.nx + TX - 1) / TX;
     if constexpr (SYS == SYS_EULER && NV == 4) {
         const int nseg = (s->d.ny + s->ty - 1) / s->ty;
-        hipLaunchKernelGGL((sweep2d<NV, FLUX, SCHEME, MODE, FLAGS>), dim3(nstrips, nseg), dim3(WAVE), 0,
+        hipLaunchKernelGGL((sweep2d<NV, FLUX, SCHEME, CHAR, MODE>), dim3(nstrips, nseg), dim3(WAVE), 0,
                            s->stream, U, Un, out, flags, s->ctrl, s->P, A, s->ty);
     } else {
-        hipLaunchKernelGGL((sweep1d<SYS, NV, FLUX, SCHEME, MODE, FLAGS>), dim3(nstrips), dim3(WAVE), 0,
+        hipLaunchKernelGGL((sweep1d<SYS, NV, FLUX, SCHEME, CHAR, MODE>), dim3(nstrips), dim3(WAVE), 0,
                            s->stream, U, Un, out, flags, s->ctrl, s->P, A);
     }
 }
 
-template <int SYS, int NV, int FLUX, int MODE, bool FLAGS>
+template <int SYS, int NV, int FLUX, bool CHAR, int MODE>
 static void launch_scheme(const wcnst_solver* s, const double* U, const double* Un, double* out,
                           uint8_t* flags, const StageArgs& A)
 {
     switch (s->d.scheme) {
-    case WCNST_LINEAR: launch_sweep_t<SYS, NV, FLUX, SCH_LINEAR, MODE, FLAGS>(s, U, Un, out, flags, A); break;
-    case WCNST_JS: launch_sweep_t<SYS, NV, FLUX, SCH_JS, MODE, FLAGS>(s, U, Un, out, flags, A); break;
-    default: launch_sweep_t<SYS, NV, FLUX, SCH_TENO, MODE, FLAGS>(s, U, Un, out, flags, A); break;
+    case WCNST_LINEAR: launch_sweep_t<SYS, NV, FLUX, SCH_LINEAR, CHAR, MODE>(s, U, Un, out, flags, A); break;
+    case WCNST_JS: launch_sweep_t<SYS, NV, FLUX, SCH_JS, CHAR, MODE>(s, U, Un, out, flags, A); break;
+    default:
+        if (s->d.q == 6) launch_sweep_t<SYS, NV, FLUX, SCH_TENO, CHAR, MODE>(s, U, Un, out, flags, A);
+        else launch_sweep_t<SYS, NV, FLUX, SCH_TENO_Q, CHAR, MODE>(s, U, Un, out, flags, A);
+        break;
     }
 }
 
-template <int MODE, bool FLAGS>
+template <int SYS, int NV, int FLUX, int MODE>
+static void launch_char(const wcnst_solver* s, const double* U, const double* Un, double* out,
+                        uint8_t* flags, const StageArgs& A)
+{
+    if (SYS == SYS_EULER && s->d.charwise) launch_scheme<SYS, NV, FLUX, true, MODE>(s, U, Un, out, flags, A);
+    else launch_scheme<SYS, NV, FLUX, false, MODE>(s, U, Un, out, flags, A);
+}
+
+template <int MODE>
 static void launch_sweep(const wcnst_solver* s, const double* U, const double* Un, double* out,
                          uint8_t* flags, const StageArgs& A)
 {
     const bool lf = s->d.flux == WCNST_LF;
     switch (s->kind) {
-    case K_ADV1: launch_scheme<SYS_ADV, 1, FLUX_ROE, MODE, FLAGS>(s, U, Un, out, flags, A); break;
+    case K_ADV1: launch_scheme<SYS_ADV, 1, FLUX_ROE, false, MODE>(s, U, Un, out, flags, A); break;
     case K_BURG1:
-        if (lf) launch_scheme<SYS_BURG, 1, FLUX_LF, MODE, FLAGS>(s, U, Un, out, flags, A);
-        else launch_scheme<SYS_BURG, 1, FLUX_ROE, MODE, FLAGS>(s, U, Un, out, flags, A);
+        if (lf) launch_scheme<SYS_BURG, 1, FLUX_LF, false, MODE>(s, U, Un, out, flags, A);
+        else launch_scheme<SYS_BURG, 1, FLUX_ROE, false, MODE>(s, U, Un, out, flags, A);
         break;
     case K_EUL1:
-        if (lf) launch_scheme<SYS_EULER, 3, FLUX_LF, MODE, FLAGS>(s, U, Un, out, flags, A);
-        else launch_scheme<SYS_EULER, 3, FLUX_ROE, MODE, FLAGS>(s, U, Un, out, flags, A);
+        if (lf) launch_char<SYS_EULER, 3, FLUX_LF, MODE>(s, U, Un, out, flags, A);
+        else launch_char<SYS_EULER, 3, FLUX_ROE, MODE>(s, U, Un, out, flags, A);
         break;
     case K_EUL2:
-        if (lf) launch_scheme<SYS_EULER, 4, FLUX_LF, MODE, FLAGS>(s, U, Un, out, flags, A);
-        else launch_scheme<SYS_EULER, 4, FLUX_ROE, MODE, FLAGS>(s, U, Un, out, flags, A);
+        if (lf) launch_char<SYS_EULER, 4, FLUX_LF, MODE>(s, U, Un, out, flags, A);
+        else launch_char<SYS_EULER, 4, FLUX_ROE, MODE>(s, U, Un, out, flags, A);
         break;
     }
 }
@@ -756,7 +769,7 @@ static void launch_step(wcnst_solver* s, double* U, double t_final, double cfl, 
             e1 = pool_event(s);
             if (e0) (void)hipEventRecord(e0, s->stream);
         }
-        launch_sweep<MODE_STAGE, false>(s, in[st], U, outp[st], nullptr, A);
+        launch_sweep<MODE_STAGE>(s, in[st], U, outp[st], nullptr, A);
         if (s->prof && e1) (void)hipEventRecord(e1, s->stream);
     }
     s->parity ^= 1;
@@ -767,8 +780,7 @@ extern "C" wcnst_status wcnst_rhs(wcnst_solver* s, const double* U, double* R, u
     if (!s || !U || !R) return fail(WCNST_E_INVALID_ARG, "null argument");
     if (U == R) return fail(WCNST_E_INVALID_ARG, "U and R must not alias");
     StageArgs A = {};
-    if (flags) launch_sweep<MODE_RHS, true>(s, U, nullptr, R, flags, A);
-    else launch_sweep<MODE_RHS, false>(s, U, nullptr, R, nullptr, A);
+    launch_sweep<MODE_RHS>(s, U, nullptr, R, flags, A);
     HIP_TRY(hipGetLastError());
     return WCNST_OK;
 }

@@ -14,7 +14,7 @@ using namespace wcnst;
 
 namespace {
 
-template <int SYS, int NV, int FLUX, int SCHEME>
+template <int SYS, int NV, int FLUX, int SCHEME, bool CHAR>
 void line(const Params& P, int n, int bc, double c1, double c2, double c3, const double* U, int stride,
           const int* perm, double* R, uint8_t* flags, int nlines, int li)
 {
@@ -28,7 +28,7 @@ void line(const Params& P, int n, int bc, double c1, double c2, double c3, const
         double f[NV];
         unsigned fb;
         RegStencil<NV> st{s};
-        face_flux<SYS, NV, FLUX, SCHEME>(st, P, f, fb);
+        face_flux<SYS, NV, FLUX, SCHEME, CHAR>(st, P, f, fb);
         for (int v = 0; v < NV; ++v) F[(size_t)(j + 2) * NV + v] = f[v];
         if (flags)
             for (int k = 0; k < NV; ++k) {
@@ -53,13 +53,22 @@ void line(const Params& P, int n, int bc, double c1, double c2, double c3, const
         }
 }
 
+template <int SYS, int NV, int FLUX, bool CHAR>
+void line_char(int scheme, const Params& P, int n, int bc, double c1, double c2, double c3, const double* U,
+               int stride, const int* perm, double* R, uint8_t* flags, int nlines, int li)
+{
+    if (scheme == SCH_LINEAR) line<SYS, NV, FLUX, SCH_LINEAR, CHAR>(P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+    else if (scheme == SCH_JS) line<SYS, NV, FLUX, SCH_JS, CHAR>(P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+    else if (P.q == 6) line<SYS, NV, FLUX, SCH_TENO, CHAR>(P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+    else line<SYS, NV, FLUX, SCH_TENO_Q, CHAR>(P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+}
+
 template <int SYS, int NV, int FLUX>
 void line_scheme(int scheme, const Params& P, int n, int bc, double c1, double c2, double c3, const double* U,
                  int stride, const int* perm, double* R, uint8_t* flags, int nlines, int li)
 {
-    if (scheme == SCH_LINEAR) line<SYS, NV, FLUX, SCH_LINEAR>(P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
-    else if (scheme == SCH_JS) line<SYS, NV, FLUX, SCH_JS>(P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
-    else line<SYS, NV, FLUX, SCH_TENO>(P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+    if (SYS == SYS_EULER && P.charwise) line_char<SYS, NV, FLUX, true>(scheme, P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+    else line_char<SYS, NV, FLUX, false>(scheme, P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
 }
 
 void run_line(int sys, int nv, int flux, int scheme, const Params& P, int n, int bc, double c1, double c2,
