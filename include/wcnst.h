@@ -150,6 +150,54 @@ wcnst_status wcnst_profile_read(wcnst_solver* s, double* stage_ms, int64_t* stag
 /* Free the handle (host state only; the workspace stays the caller's). */
 wcnst_status wcnst_destroy(wcnst_solver* s);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent 1D Euler problems advanced in one persistent launch
+ * (captured once into a HIP graph and replayed).  Every instance follows
+ * exactly the arithmetic of wcnst_solve (Sec. 2-3 as above), so it gives the
+ * same bits batched as alone.  All descriptors must be 1D Euler with the
+ * same scheme parameters (flux, scheme, charwise, q, gamma, C_T, C, eps);
+ * nx, the domain and the boundary conditions may differ.
+ *
+ * States live in one packed device buffer of FP64: instance i occupies
+ * offsets[i] .. offsets[i] + 3*nx_i - 1 with layout [v][nx_i]
+ * (wcnst_batch_offsets; offsets[n] is the buffer length in doubles). */
+typedef struct wcnst_batch wcnst_batch;
+
+/* Device workspace bytes for a batch of n descriptors (instance table, job
+ * slots, two packed stage buffers). */
+wcnst_status wcnst_batch_workspace_size(const wcnst_desc* descs, int32_t n, size_t* bytes);
+
+/* Validate and create a batch bound to hip_stream and to a caller-owned
+ * 256-byte-aligned workspace.  The handle is owned by the library. */
+wcnst_status wcnst_batch_create(const wcnst_desc* descs, int32_t n, void* hip_stream, void* workspace,
+                                size_t ws_bytes, wcnst_batch** out);
+
+/* Host array of n + 1 element offsets into the packed state buffer. */
+wcnst_status wcnst_batch_offsets(const wcnst_batch* b, int64_t* offsets);
+
+/* Advance every instance of the packed device buffer U in place from t = 0
+ * to t_final[i] (host array; +inf means exactly max_steps steps) with the
+ * CFL rule of wcnst_solve.  Synchronous.  status, t_out, steps_out are host
+ * arrays of n (t_out / steps_out nullable); status[i] is WCNST_OK,
+ * WCNST_E_NONPHYSICAL or WCNST_E_MAX_STEPS and the return value is the first
+ * non-zero one.  WCNST_E_HIP if a cooperating part waited past its bounded
+ * limit. */
+wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const double* t_final, double cfl, int64_t max_steps,
+                               int32_t* status, double* t_out, int64_t* steps_out);
+
+/* For each instance of the last solve: global stage (3*step + stage) and
+ * cell of the first non-physical value, or -1 (host arrays of n). */
+wcnst_status wcnst_batch_bad_cells(const wcnst_batch* b, int64_t* bad_stage, int64_t* bad_cell);
+
+/* Work decomposition (never changes results): an instance is split over
+ * up to 64 cooperating wavefronts when its estimated cost exceeds
+ * split x (total cost / wavefronts); split = 0 keeps one wavefront per
+ * instance (default 1).  workgroups > 0 overrides the persistent grid size
+ * (default: as many 256-lane workgroups as are resident at once). */
+wcnst_status wcnst_batch_set_tuning(wcnst_batch* b, double split, int32_t workgroups);
+
+wcnst_status wcnst_batch_destroy(wcnst_batch* b);
+
 /* Message of the last error on this thread ("" when none). */
 const char* wcnst_last_error(void);
 

@@ -27,6 +27,7 @@
 
 #include "wcnst.h"
 #include "wcnst_device.hpp"
+#include "wcnst_host.hpp"
 
 namespace wcnst {
 
@@ -472,8 +473,7 @@ using namespace wcnst;
 
 static thread_local char g_err[512] = "";
 
-static wcnst_status fail(wcnst_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-static wcnst_status fail(wcnst_status st, const char* fmt, ...)
+wcnst_status wcnst_fail(wcnst_status st, const char* fmt, ...)
 {
     va_list ap;
     va_start(ap, fmt);
@@ -481,6 +481,7 @@ static wcnst_status fail(wcnst_status st, const char* fmt, ...)
     va_end(ap);
     return st;
 }
+#define fail wcnst_fail
 
 #define HIP_TRY(expr)                                                                      \
     do {                                                                                   \
@@ -509,9 +510,10 @@ struct wcnst_solver {
     size_t ev_used;
 };
 
-static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+size_t wcnst_align256(size_t b) { return (b + 255) & ~(size_t)255; }
+#define align256 wcnst_align256
 
-static wcnst_status check_desc(const wcnst_desc* d)
+wcnst_status wcnst_check_desc(const wcnst_desc* d)
 {
     if (!d) return fail(WCNST_E_INVALID_ARG, "null descriptor");
     if (d->struct_size != sizeof(wcnst_desc))
@@ -541,7 +543,7 @@ static wcnst_status check_desc(const wcnst_desc* d)
     return WCNST_OK;
 }
 
-static int desc_nvar(const wcnst_desc* d)
+int wcnst_desc_nvar(const wcnst_desc* d)
 {
     return d->system == WCNST_EULER ? (d->ndim == 1 ? 3 : 4) : 1;
 }
@@ -576,10 +578,10 @@ extern "C" wcnst_status wcnst_desc_init(wcnst_desc* d)
 
 extern "C" wcnst_status wcnst_workspace_size(const wcnst_desc* d, size_t* bytes)
 {
-    wcnst_status st = check_desc(d);
+    wcnst_status st = wcnst_check_desc(d);
     if (st) return st;
     if (!bytes) return fail(WCNST_E_INVALID_ARG, "null size pointer");
-    const size_t state = (size_t)desc_nvar(d) * d->nx * d->ny * sizeof(double);
+    const size_t state = (size_t)wcnst_desc_nvar(d) * d->nx * d->ny * sizeof(double);
     *bytes = align256(sizeof(Ctrl)) + 2 * align256(state);
     return WCNST_OK;
 }
@@ -587,7 +589,7 @@ extern "C" wcnst_status wcnst_workspace_size(const wcnst_desc* d, size_t* bytes)
 extern "C" wcnst_status wcnst_create(const wcnst_desc* d, void* hip_stream, void* workspace,
                                      size_t ws_bytes, wcnst_solver** out)
 {
-    wcnst_status st = check_desc(d);
+    wcnst_status st = wcnst_check_desc(d);
     if (st) return st;
     if (!out) return fail(WCNST_E_INVALID_ARG, "null output handle");
     size_t need = 0;
@@ -598,7 +600,7 @@ extern "C" wcnst_status wcnst_create(const wcnst_desc* d, void* hip_stream, void
 
     wcnst_solver* s = new wcnst_solver();
     s->d = *d;
-    s->nv = desc_nvar(d);
+    s->nv = wcnst_desc_nvar(d);
     s->kind = d->system == WCNST_ADVECTION ? K_ADV1
               : d->system == WCNST_BURGERS ? K_BURG1
               : d->ndim == 1               ? K_EUL1

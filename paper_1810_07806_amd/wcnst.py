@@ -22,7 +22,9 @@ _DIFF = {"mnd": 0}
 
 EXPORTS = ("wcnst_desc_init", "wcnst_workspace_size", "wcnst_create", "wcnst_rhs", "wcnst_step",
            "wcnst_solve", "wcnst_status_sync", "wcnst_reset", "wcnst_set_tuning", "wcnst_profile_enable",
-           "wcnst_profile_read", "wcnst_destroy", "wcnst_last_error")
+           "wcnst_profile_read", "wcnst_destroy", "wcnst_last_error",
+           "wcnst_batch_workspace_size", "wcnst_batch_create", "wcnst_batch_offsets", "wcnst_batch_solve",
+           "wcnst_batch_bad_cells", "wcnst_batch_set_tuning", "wcnst_batch_destroy")
 
 
 class WcnstError(RuntimeError):
@@ -73,6 +75,14 @@ def lib(path: str | None = None):
     L.wcnst_profile_read.argtypes = [vp, dp, i64p]
     L.wcnst_destroy.argtypes = [vp]
     L.wcnst_last_error.restype = ctypes.c_char_p
+    L.wcnst_batch_workspace_size.argtypes = [D, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+    L.wcnst_batch_create.argtypes = [D, ctypes.c_int32, vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.wcnst_batch_offsets.argtypes = [vp, i64p]
+    L.wcnst_batch_solve.argtypes = [vp, vp, dp, ctypes.c_double, ctypes.c_int64,
+                                    ctypes.POINTER(ctypes.c_int32), dp, i64p]
+    L.wcnst_batch_bad_cells.argtypes = [vp, i64p, i64p]
+    L.wcnst_batch_set_tuning.argtypes = [vp, ctypes.c_double, ctypes.c_int32]
+    L.wcnst_batch_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name != "wcnst_last_error":
             getattr(L, name).restype = ctypes.c_int32
@@ -225,3 +235,86 @@ def split_flags(desc: dict, fl):
     ny = int(desc["ny"])
     nxb = nv * ny * (nx + 3) * 2
     return [fl[:nxb].reshape(nv, ny, nx + 3, 2), fl[nxb:].reshape(nv, nx, ny + 3, 2)]
+
+
+class Batch:
+    """Many independent 1D Euler problems advanced in one persistent launch.
+
+    States are packed into one device tensor (``pack``/``unpack``); instance i
+    occupies ``offsets[i] : offsets[i] + 3 * nx_i`` with layout [v][nx_i]."""
+
+    def __init__(self, descs, stream=None, device: str = "cuda"):
+        import numpy as np
+        import torch
+        self._torch = torch
+        self.descs = [dict(d) for d in descs]
+        self.n = len(descs)
+        arr = (Desc * self.n)(*[make_desc(d) for d in descs])
+        self._arr = arr
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().wcnst_batch_workspace_size(arr, self.n, ctypes.byref(nbytes)))
+        raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=device)
+        off = (-raw.data_ptr()) % 256
+        self._ws_raw = raw
+        self.ws = raw[off:off + nbytes.value]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(raw.device)
+        h = ctypes.c_void_p()
+        _check(lib().wcnst_batch_create(arr, self.n, ctypes.c_void_p(self.stream.cuda_stream),
+                                        ctypes.c_void_p(self.ws.data_ptr()), nbytes.value, ctypes.byref(h)))
+        self._h = h
+        offs = (ctypes.c_int64 * (self.n + 1))()
+        _check(lib().wcnst_batch_offsets(self._h, offs))
+        self.offsets = np.array(list(offs), dtype=np.int64)
+
+    def pack(self, states):
+        """Device tensor holding every instance's (3, 1, nx) state."""
+        import numpy as np
+        host = np.zeros(int(self.offsets[-1]), dtype=np.float64)
+        for i, U in enumerate(states):
+            a = np.ascontiguousarray(U, dtype=np.float64).ravel()
+            host[self.offsets[i]:self.offsets[i] + a.size] = a
+        return self._torch.as_tensor(host).to(self.ws.device)
+
+    def unpack(self, Ug):
+        h = Ug.cpu().numpy()
+        return [h[self.offsets[i]:self.offsets[i] + 3 * int(d["nx"])].reshape(3, 1, int(d["nx"])).copy()
+                for i, d in enumerate(self.descs)]
+
+    def set_tuning(self, split: float = 1.0, workgroups: int = 0):
+        _check(lib().wcnst_batch_set_tuning(self._h, float(split), int(workgroups)))
+
+    def solve(self, Ug, t_final, cfl: float = 0.5, max_steps: int = 1 << 40):
+        """Returns dict(status, t, steps) arrays; raises only on HIP errors."""
+        import numpy as np
+        t = self._torch
+        if not (isinstance(Ug, t.Tensor) and Ug.is_cuda and Ug.dtype == t.float64 and Ug.is_contiguous()
+                and Ug.numel() >= int(self.offsets[-1])):
+            raise TypeError("packed state must be a contiguous float64 CUDA tensor of the batch length")
+        tf = np.broadcast_to(np.asarray(t_final, dtype=np.float64), (self.n,)).copy()
+        st = (ctypes.c_int32 * self.n)()
+        to = (ctypes.c_double * self.n)()
+        so = (ctypes.c_int64 * self.n)()
+        ret = lib().wcnst_batch_solve(self._h, ctypes.c_void_p(Ug.data_ptr()),
+                                      tf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(cfl),
+                                      int(max_steps), st, to, so)
+        if ret == E_HIP or ret == E_INVALID_ARG:
+            raise WcnstError(ret, lib().wcnst_last_error().decode())
+        return dict(status=np.array(list(st)), t=np.array(list(to)), steps=np.array(list(so)))
+
+    def bad_cells(self):
+        import numpy as np
+        bs = (ctypes.c_int64 * self.n)()
+        bc = (ctypes.c_int64 * self.n)()
+        _check(lib().wcnst_batch_bad_cells(self._h, bs, bc))
+        return np.array(list(bs)), np.array(list(bc))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().wcnst_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

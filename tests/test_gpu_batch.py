@@ -1,0 +1,129 @@
+"""Batched persistent solve: every instance gives the same bits as solving
+it alone through wcnst_solve, and matches the oracle; faults stay local;
+the launch decomposition never changes results."""
+from __future__ import annotations
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1810_07806_amd import workloads as W
+from parity import FIELD_TOL, rel_inf_err
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available()
+    from paper_1810_07806_amd import wcnst
+    wcnst.lib()
+    return T
+
+
+def _tubes(count, seed, n_min=64, n_max=600, t_final=0.05):
+    return W.shock_tube_batch(count=count, seed=seed, n_min=n_min, n_max=n_max, t_final=t_final)
+
+
+@pytest.mark.parametrize("split", [0.0, 0.05])
+def test_batch_equals_alone_and_oracle(orc, torch, split):
+    from paper_1810_07806_amd.wcnst import Batch, Solver
+    items = _tubes(24, seed=1)
+    descs = [d for d, _ in items]
+    _say(f"batch of {len(items)} split={split}")
+    b = Batch(descs)
+    b.set_tuning(split, 0)
+    Ug = b.pack([U for _, U in items])
+    res = b.solve(Ug, [d["t_final"] for d in descs], cfl=0.5)
+    assert (res["status"] == 0).all(), res["status"]
+    out = b.unpack(Ug)
+    for i, (d, U) in enumerate(items):
+        s = Solver(d)
+        V = s.new_state(U)
+        t, n = s.solve(V, t_final=d["t_final"], cfl=0.5)
+        alone = V.cpu().numpy()
+        assert np.array_equal(out[i], alone), f"instance {i} differs from the single solve"
+        assert n == res["steps"][i] and t == res["t"][i]
+        s.close()
+        if i % 4 == 0:
+            r = orc.solve(orc.problem(d), U, t_final=d["t_final"], cfl=0.5)
+            assert r["steps"] == n
+            assert (rel_inf_err(out[i], r["U"]) <= FIELD_TOL).all()
+    b.close()
+
+
+def test_batch_decomposition_does_not_change_results(orc, torch):
+    """Seed 2 holds one tube (index 17, a strong double rarefaction) on which
+    the Roe flux without entropy fix loses positivity; the oracle fails it at
+    the same stage and cell, and every decomposition must report the same."""
+    from paper_1810_07806_amd.wcnst import Batch
+    items = _tubes(40, seed=2, n_min=100, n_max=2000, t_final=0.03)
+    descs = [d for d, _ in items]
+    outs = []
+    for split, wgs in ((0.0, 0), (0.02, 0), (0.5, 7), (1.0, 1)):
+        _say(f"decomposition split={split} workgroups={wgs}")
+        b = Batch(descs)
+        b.set_tuning(split, wgs)
+        Ug = b.pack([U for _, U in items])
+        res = b.solve(Ug, 0.03, cfl=0.5)
+        outs.append((Ug.cpu().numpy(), res["steps"].copy(), res["status"].copy(), b.bad_cells()))
+        b.close()
+    o0, st0, s0, (bs0, bc0) = outs[0]
+    failed = np.flatnonzero(s0)
+    assert list(failed) == [17]
+    r = orc.solve(orc.problem(descs[17]), items[17][1], t_final=0.03, cfl=0.5)
+    assert r["status"] == 2 and (bs0[17], bc0[17]) == (r["bad_stage"], r["bad_cell"])
+    for o, st, s, (bs, bc) in outs[1:]:
+        assert np.array_equal(s, s0) and np.array_equal(bs, bs0) and np.array_equal(bc, bc0)
+        assert np.array_equal(st, st0)
+        # a failing instance stops after the whole failing stage in every
+        # decomposition, so even its stored state agrees
+        assert np.array_equal(o, o0)
+
+
+def test_batch_fault_stays_local(orc, torch):
+    from paper_1810_07806_amd.wcnst import Batch
+    items = _tubes(12, seed=3)
+    descs = [d for d, _ in items]
+    states = [U.copy() for _, U in items]
+    bad_i = 5
+    states[bad_i][0, 0, 17] = -0.5
+    _say("fault isolation")
+    for split in (0.0, 0.02):
+        b = Batch(descs)
+        b.set_tuning(split, 0)
+        Ug = b.pack(states)
+        res = b.solve(Ug, 0.05, cfl=0.5)
+        bs, bc = b.bad_cells()
+        assert res["status"][bad_i] == 2 and (np.delete(res["status"], bad_i) == 0).all()
+        r = orc.solve(orc.problem(descs[bad_i]), states[bad_i], t_final=0.05, cfl=0.5)
+        assert (bs[bad_i], bc[bad_i]) == (r["bad_stage"], r["bad_cell"])
+        clean = Batch(descs)
+        Uc = clean.pack([U for _, U in items])
+        clean.solve(Uc, 0.05, cfl=0.5)
+        a, c = b.unpack(Ug), clean.unpack(Uc)
+        for i in range(len(items)):
+            if i != bad_i:
+                assert np.array_equal(a[i], c[i])
+        b.close()
+        clean.close()
+
+
+def test_batch_fixed_steps(torch):
+    from paper_1810_07806_amd.wcnst import Batch
+    items = _tubes(8, seed=4)
+    b = Batch([d for d, _ in items])
+    Ug = b.pack([U for _, U in items])
+    res = b.solve(Ug, np.inf, cfl=0.5, max_steps=37)
+    assert (res["status"] == 0).all() and (res["steps"] == 37).all()
+    b.close()
