@@ -1,6 +1,6 @@
 """Benchmark: RK-stage cell-updates/s of WCNS-T on one MI355X.
 
-Workload: 2D Euler four-quadrant Riemann problem (Sec. 3.6.1 states) on
+Default workload (`--workload quadrant2d`): 2D Euler four-quadrant Riemann problem (Sec. 3.6.1 states) on
 [0,1]^2, 2048 x 2048 cells, FP64, characteristic-wise TENO-5 interpolation,
 Roe flux, MND difference, SSP-RK3, CFL 0.5, zero-gradient boundaries.  One
 benchmark step = one SSP-RK3 step (three fused stage kernels, CFL reduction
@@ -12,6 +12,13 @@ Prints one JSON line.  `roofline` prices the stage kernel against the FP64
 vector peak with the algorithmic flop count per stage-cell-update (see
 `flops_per_stage_cell`); `cpu_baseline` times the CPU oracle on one full
 SSP-RK3 step of the same grid on the host cores.
+
+`--workload tubes`: 4096 independent 1D Euler shock tubes of uneven length
+(N log-uniform in [256, 8192], random left/right states, t = 0.15, Roe,
+characteristic TENO, MND) advanced to their final times by the batched
+persistent solver in one graph-captured launch.  One benchmark step = the
+whole batch solved once.  Also times the plain one-solve-per-instance path
+on a seeded subset of the same tubes and the CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -57,6 +64,25 @@ def bytes_per_stage_cell() -> float:
     return (3 * 32 + 2 * 32 + 3 * 32) / 3.0
 
 
+def flops_per_stage_cell_1d() -> dict:
+    """Algorithmic flops of one stage-cell-update of 1D Euler WCNS-T (Roe,
+    TENO, characteristic-wise, MND), counted as for 2D with 3 variables and
+    3-term dot products (5 flops).  Per midpoint:"""
+    interp = 42 + 46
+    eigen = 55                # Roe average, c, R and L entries (1D)
+    midpoint = (eigen
+                + 6 * 3 * 5   # project six nodes
+                + 2 * 3 * interp
+                + 2 * 3 * 5   # back-project u_L, u_R
+                + 2 * 9 + eigen + 3 + 3 * 5 + 3 + 3 * 5 + 9)  # Roe flux
+    per_cell = (midpoint
+                + 9           # node flux f(U_i)
+                + 3 * 8       # MND, Eq. (5)
+                + 12          # Shu-Osher stage combination (mean of 6, 15, 15)
+                + 6)          # CFL speed (18 per cell per step)
+    return dict(interp=interp, midpoint=midpoint, per_stage_cell=per_cell)
+
+
 def cpu_baseline(steps: int = 1) -> dict:
     import numpy as np
 
@@ -79,19 +105,162 @@ def cpu_baseline(steps: int = 1) -> dict:
                       f"({el:.1f} s wall on {cores} threads)"}
 
 
+def _oracle_tube_steps(job):
+    """Worker: `steps` oracle RK3 steps of one tube (process pool)."""
+    import oracle
+    d, U, steps = job
+    p = oracle.problem(d)
+    done = 0
+    for k in range(steps):
+        s = oracle.max_speed(p, U)
+        if not (s > 0 and math.isfinite(s)):
+            break
+        U, st, _, _ = oracle.rk3_step(p, U, 0.5 / s, stage_base=3 * k, nthreads=1)
+        if st != 0:
+            break
+        done += 1
+    return 3 * done * d["nx"]
+
+
+def cpu_baseline_tubes(items, idx, steps: int) -> dict:
+    from concurrent.futures import ProcessPoolExecutor
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    jobs = [(items[int(i)][0], items[int(i)][1], steps) for i in idx]
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(cores) as ex:
+        units = sum(ex.map(_oracle_tube_steps, jobs))
+    el = time.perf_counter() - t0
+    return {"value": units / el, "unit": "stage-cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} SSP-RK3 steps of each of {len(jobs)} seeded tubes of the batch, one process "
+                      f"per core ({el:.1f} s wall incl. pool start-up)"}
+
+
+def bench_tubes(args):
+    import numpy as np
+    import torch
+
+    from paper_1810_07806_amd import autotune
+    from paper_1810_07806_amd import workloads as W
+    from paper_1810_07806_amd.wcnst import Batch, Solver
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    count, seed, t_final = args.count, args.seed, 0.15
+    items = W.shock_tube_batch(count=count, seed=seed, t_final=t_final)
+    descs = [d for d, _ in items]
+    b = Batch(descs)
+    U0 = b.pack([U for _, U in items])
+    Ug = torch.empty_like(U0)
+    log(f"tubes: {count} instances, {int(sum(d['nx'] for d in descs))} cells")
+    if args.split is not None:
+        b.set_tuning(args.split, 0, args.wpg)
+        tune = dict(split=args.split, waves_per_group=args.wpg, cached=False, table=[])
+    else:
+        tune = autotune.tune_batch(b, U0, t_final, cfl=0.5, cache=args.tune_cache,
+                                   device_name=torch.cuda.get_device_name(0), log=log)
+    log(f"tuning: split={tune['split']} waves/group={tune['waves_per_group']}")
+    for _ in range(args.warmup):
+        Ug.copy_(U0)
+        b.solve(Ug, t_final * 0.05, cfl=0.5)
+    units = 0.0
+    wall = 0.0
+    kernel_ms = []
+    for k in range(args.steps):
+        Ug.copy_(U0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = b.solve(Ug, t_final, cfl=0.5)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        kernel_ms.append(b.kernel_ms())
+        units += float(np.sum(3.0 * res["steps"] * np.array([d["nx"] for d in descs])))
+        log(f"batch solve {k}: {kernel_ms[-1]:.1f} ms kernel")
+    failed = int(np.count_nonzero(res["status"]))
+    units_per_solve = units / args.steps
+    avg_kernel_s = float(np.mean(kernel_ms)) / 1e3
+
+    # plain path: one wcnst_solve per instance, on a seeded subset
+    rng = np.random.default_rng(seed + 1)
+    sub = np.sort(rng.choice(count, size=min(args.per_solve, count), replace=False))
+    ps_units, ps_wall = 0.0, 0.0
+    for i in sub:
+        d, U = items[int(i)]
+        s = Solver(d)
+        V = s.new_state(U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            _, n = s.solve(V, t_final=t_final, cfl=0.5)
+        except Exception:
+            n = s.status()["steps"]
+        torch.cuda.synchronize()
+        ps_wall += time.perf_counter() - t0
+        ps_units += 3.0 * n * d["nx"]
+        s.close()
+    log(f"per-solve subset: {len(sub)} tubes in {ps_wall:.2f} s")
+
+    fl = flops_per_stage_cell_1d()
+    achieved = fl["per_stage_cell"] * units_per_solve / avg_kernel_s / 1e12
+    rec = {
+        "metric": "RK-stage cell-updates/s",
+        "value": units / wall,
+        "unit": "stage-cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded random shock tubes)",
+        "config": {"workload": f"batched 1D Euler shock tubes: {count} instances, N log-uniform in [256, 8192], "
+                               f"t = {t_final}, WCNS-T TENO C_T=1e-5, Roe, MND, SSP-RK3 CFL 0.5, seed {seed}",
+                   "instances": count, "cells": int(sum(d["nx"] for d in descs)),
+                   "stage_cell_updates_per_solve": units_per_solve, "failed_instances": failed,
+                   "kernel_ms_avg": avg_kernel_s * 1e3, "split": tune["split"],
+                   "waves_per_group": tune["waves_per_group"], "tuning_cached": tune.get("cached", False)},
+        "per_solve": {"value": ps_units / ps_wall, "unit": "stage-cell-updates/s", "instances": int(len(sub)),
+                      "wall_s": ps_wall, "speedup_batched": (units / wall) / (ps_units / ps_wall)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "flops_per_unit": fl["per_stage_cell"]},
+    }
+    if not args.no_cpu_baseline:
+        idx = np.random.default_rng(seed + 2).choice(count, size=min(64, count), replace=False)
+        rec["cpu_baseline"] = cpu_baseline_tubes(items, idx, steps=args.cpu_steps)
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=("quadrant2d", "tubes"), default="quadrant2d")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 200; tubes: 1 batch solve)")
+    ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--n", type=int, default=N_SIDE, help="grid side (default: the 2048^2 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rows", type=int, default=0, help="rows per 2D segment (0: library default)")
+    ap.add_argument("--count", type=int, default=4096, help="tubes: instances")
+    ap.add_argument("--seed", type=int, default=0, help="tubes: generator seed")
+    ap.add_argument("--split", type=float, default=None, help="tubes: fixed split (default: autotune)")
+    ap.add_argument("--wpg", type=int, default=4, help="tubes: waves per workgroup with --split")
+    ap.add_argument("--tune-cache", default=None, help="tubes: JSON autotune cache")
+    ap.add_argument("--per-solve", type=int, default=32, help="tubes: instances timed on the per-solve path")
+    ap.add_argument("--cpu-steps", type=int, default=200, help="tubes: oracle steps per sampled tube")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "tubes":
+        args.steps = 1 if args.steps is None else args.steps
+        args.warmup = 1 if args.warmup is None else args.warmup
+        return bench_tubes(args)
+    args.steps = 200 if args.steps is None else args.steps
+    args.warmup = 3 if args.warmup is None else args.warmup
 
     import torch
 

@@ -189,12 +189,20 @@ wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const double* t_final,
  * cell of the first non-physical value, or -1 (host arrays of n). */
 wcnst_status wcnst_batch_bad_cells(const wcnst_batch* b, int64_t* bad_stage, int64_t* bad_cell);
 
-/* Work decomposition (never changes results): an instance is split over
- * up to 64 cooperating wavefronts when its estimated cost exceeds
- * split x (total cost / wavefronts); split = 0 keeps one wavefront per
- * instance (default 1).  workgroups > 0 overrides the persistent grid size
- * (default: as many 256-lane workgroups as are resident at once). */
-wcnst_status wcnst_batch_set_tuning(wcnst_batch* b, double split, int32_t workgroups);
+/* Work decomposition (never changes results).  Estimated cost of an
+ * instance = nx x estimated steps (from the CFL speed of its initial
+ * state).  An instance is split over k = ceil(cost / (split x total cost /
+ * wavefronts)) cooperating wavefronts, at most 64, its strip count and the
+ * resident wavefront count; split = 0 keeps one wavefront per instance
+ * (default 1).  waves_per_group in {1, 2, 4} sets the workgroup size
+ * (0 keeps the current, default 4).  workgroups > 0 fixes the persistent
+ * grid; 0 sizes it to the workgroups resident at once.  WCNST_E_INVALID_ARG
+ * for other values. */
+wcnst_status wcnst_batch_set_tuning(wcnst_batch* b, double split, int32_t workgroups, int32_t waves_per_group);
+
+/* Device time in milliseconds of the persistent launch of the last
+ * wcnst_batch_solve (HIP events on the batch's stream). */
+wcnst_status wcnst_batch_kernel_ms(const wcnst_batch* b, double* ms);
 
 wcnst_status wcnst_batch_destroy(wcnst_batch* b);
 

@@ -364,8 +364,13 @@ struct wcnst_batch {
     double* U2 = nullptr;
     Params P{};
     double split = 1.0;
-    int grid = 0;
+    int grid = 0;        // persistent workgroups
+    int wpg = 4;         // wavefronts per workgroup
+    int resident = 0;    // workgroups of wpg waves resident at once
+    int cus = 0;
     long long wait_ticks = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double kernel_ms = 0.0;
     hipGraphExec_t exec = nullptr;
     const void* exec_kernel = nullptr;
     double* exec_U = nullptr;
@@ -443,6 +448,18 @@ static const void* pick_kernel(const wcnst_desc& d)
     return d.charwise ? pick2<FLUX_ROE, true>(d) : pick2<FLUX_ROE, false>(d);
 }
 
+extern "C" wcnst_status wcnst_batch_destroy(wcnst_batch* b);
+
+// As many workgroups of wpg waves as are resident at once on the device.
+static hipError_t batch_default_grid(wcnst_batch* b)
+{
+    int per_cu = 0;
+    const hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick_kernel(b->d0), WAVE * b->wpg, 0);
+    if (e == hipSuccess) b->resident = std::max(1, per_cu) * b->cus;
+    return e;
+}
+
 extern "C" wcnst_status wcnst_batch_create(const wcnst_desc* descs, int32_t n, void* hip_stream, void* workspace,
                                            size_t ws_bytes, wcnst_batch** out)
 {
@@ -497,18 +514,21 @@ extern "C" wcnst_status wcnst_batch_create(const wcnst_desc* descs, int32_t n, v
     P.ny = 1;
     P.dy = 1.0;
 
-    int dev = 0, cus = 0, per_cu = 0;
+    int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick_kernel(d), 256, 0);
     int clock_khz = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev1);
+    b->cus = std::max(1, cus);
+    if (e == hipSuccess) e = batch_default_grid(b);
+    b->grid = b->resident;
     if (e != hipSuccess) {
-        delete b;
+        wcnst_batch_destroy(b);
         return wcnst_fail(WCNST_E_HIP, "batch setup failed: %s", hipGetErrorString(e));
     }
-    b->grid = std::max(1, per_cu) * std::max(1, cus);
     b->wait_ticks = (long long)(WAIT_LIMIT_S * 1e3 * std::max(1, clock_khz));
     *out = b;
     return WCNST_OK;
@@ -521,25 +541,36 @@ extern "C" wcnst_status wcnst_batch_offsets(const wcnst_batch* b, int64_t* offse
     return WCNST_OK;
 }
 
-extern "C" wcnst_status wcnst_batch_set_tuning(wcnst_batch* b, double split, int32_t workgroups)
+extern "C" wcnst_status wcnst_batch_set_tuning(wcnst_batch* b, double split, int32_t workgroups,
+                                               int32_t waves_per_group)
 {
     if (!b) return wcnst_fail(WCNST_E_INVALID_ARG, "null handle");
     if (!(split >= 0.0)) return wcnst_fail(WCNST_E_INVALID_ARG, "split must be >= 0");
     if (workgroups < 0) return wcnst_fail(WCNST_E_INVALID_ARG, "workgroups must be >= 0");
+    if (waves_per_group != 0 && waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4)
+        return wcnst_fail(WCNST_E_INVALID_ARG, "waves_per_group must be 1, 2 or 4 (0 keeps it)");
     b->split = split;
-    if (workgroups > 0) {
-        b->grid = workgroups;
-        if (b->exec) {
-            (void)hipGraphExecDestroy(b->exec);
-            b->exec = nullptr;
-        }
+    if (waves_per_group) b->wpg = waves_per_group;
+    hipError_t e = batch_default_grid(b);
+    if (e != hipSuccess) return wcnst_fail(WCNST_E_HIP, "occupancy query failed: %s", hipGetErrorString(e));
+    b->grid = workgroups > 0 ? workgroups : b->resident;
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
     }
     return WCNST_OK;
 }
 
-// Longest-part-first plan: instance i gets k_i parts, about cost_i / (4
-// split total / workers), so that with split = 1 no part is longer than
-// four average shares.  k never exceeds the number of resident waves: slots
+extern "C" wcnst_status wcnst_batch_kernel_ms(const wcnst_batch* b, double* ms)
+{
+    if (!b || !ms) return wcnst_fail(WCNST_E_INVALID_ARG, "null argument");
+    *ms = b->kernel_ms;
+    return WCNST_OK;
+}
+
+// Longest-part-first plan: instance i gets k_i = ceil(cost_i / (split x
+// total / workers)) parts, so that no part is longer than split x the
+// average share of a wave.  k never exceeds the number of resident waves: slots
 // are taken in order, so at any time at most one job has parts not yet
 // taken, and its k waiting parts are then always completed by free waves.
 static int plan(wcnst_batch* b, const std::vector<double>& speed, const double* t_final, double cfl,
@@ -555,14 +586,17 @@ static int plan(wcnst_batch* b, const std::vector<double>& speed, const double* 
         cost[(size_t)i] = (double)b->rec[(size_t)i].n * steps;
         total += cost[(size_t)i];
     }
-    const double workers = 4.0 * b->grid;
+    const double workers = (double)b->wpg * b->grid;
+    // waves that are certainly running together (a grid larger than the
+    // resident set runs in turns)
+    const int running = b->wpg * std::min(b->grid, b->resident);
     std::vector<int> order((size_t)n);
     for (int i = 0; i < n; ++i) {
         const int strips = (b->rec[(size_t)i].n + TX - 1) / TX;
         int k = 1;
         if (b->split > 0.0 && total > 0.0)
-            k = (int)std::ceil(cost[(size_t)i] * workers / (b->split * total * 4.0));
-        k = std::max(1, std::min(k, std::min(std::min(KMAX, strips), (int)workers)));
+            k = (int)std::min(1e9, std::ceil(cost[(size_t)i] * workers / (b->split * total)));
+        k = std::max(1, std::min(k, std::min(std::min(KMAX, strips), running)));
         b->rec[(size_t)i].k = k;
         order[(size_t)i] = i;
     }
@@ -631,7 +665,7 @@ extern "C" wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const doubl
         hipLaunchKernelGGL(batch_open, dim3(1), dim3(64), 0, b->cap, b->d_head);
         void* args[] = {(void*)&b->d_inst, (void*)&b->d_slots, (void*)&b->d_head, (void*)&b->P,
                         (void*)&U,         (void*)&b->U1,      (void*)&b->U2};
-        hipError_t le = hipLaunchKernel(kern, dim3(b->grid), dim3(256), args, 0, b->cap);
+        hipError_t le = hipLaunchKernel(kern, dim3(b->grid), dim3(WAVE * b->wpg), args, 0, b->cap);
         hipError_t ce = hipStreamEndCapture(b->cap, &g);
         if (le != hipSuccess || ce != hipSuccess)
             return wcnst_fail(WCNST_E_HIP, "graph capture failed: %s / %s", hipGetErrorString(le),
@@ -642,11 +676,16 @@ extern "C" wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const doubl
         b->exec_kernel = kern;
         b->exec_U = U;
     }
+    WCNST_HIP_TRY(hipEventRecord(b->ev0, b->stream));
     WCNST_HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    WCNST_HIP_TRY(hipEventRecord(b->ev1, b->stream));
     WCNST_HIP_TRY(hipMemcpyAsync(b->rec.data(), b->d_inst, sizeof(BInst) * (size_t)n, hipMemcpyDeviceToHost,
                                  b->stream));
     WCNST_HIP_TRY(hipMemcpyAsync(&h, b->d_head, sizeof(BHead), hipMemcpyDeviceToHost, b->stream));
     WCNST_HIP_TRY(hipStreamSynchronize(b->stream));
+    float ms = 0.0f;
+    WCNST_HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+    b->kernel_ms = ms;
     if (h.err) return wcnst_fail(WCNST_E_HIP, "a cooperating part waited past its limit");
     wcnst_status ret = WCNST_OK;
     for (int i = 0; i < n; ++i) {
@@ -680,6 +719,8 @@ extern "C" wcnst_status wcnst_batch_destroy(wcnst_batch* b)
     (void)hipStreamSynchronize(b->stream);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
     delete b;
     return WCNST_OK;
 }

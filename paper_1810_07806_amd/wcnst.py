@@ -24,7 +24,7 @@ EXPORTS = ("wcnst_desc_init", "wcnst_workspace_size", "wcnst_create", "wcnst_rhs
            "wcnst_solve", "wcnst_status_sync", "wcnst_reset", "wcnst_set_tuning", "wcnst_profile_enable",
            "wcnst_profile_read", "wcnst_destroy", "wcnst_last_error",
            "wcnst_batch_workspace_size", "wcnst_batch_create", "wcnst_batch_offsets", "wcnst_batch_solve",
-           "wcnst_batch_bad_cells", "wcnst_batch_set_tuning", "wcnst_batch_destroy")
+           "wcnst_batch_bad_cells", "wcnst_batch_set_tuning", "wcnst_batch_kernel_ms", "wcnst_batch_destroy")
 
 
 class WcnstError(RuntimeError):
@@ -81,7 +81,8 @@ def lib(path: str | None = None):
     L.wcnst_batch_solve.argtypes = [vp, vp, dp, ctypes.c_double, ctypes.c_int64,
                                     ctypes.POINTER(ctypes.c_int32), dp, i64p]
     L.wcnst_batch_bad_cells.argtypes = [vp, i64p, i64p]
-    L.wcnst_batch_set_tuning.argtypes = [vp, ctypes.c_double, ctypes.c_int32]
+    L.wcnst_batch_set_tuning.argtypes = [vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32]
+    L.wcnst_batch_kernel_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.wcnst_batch_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name != "wcnst_last_error":
@@ -280,8 +281,13 @@ class Batch:
         return [h[self.offsets[i]:self.offsets[i] + 3 * int(d["nx"])].reshape(3, 1, int(d["nx"])).copy()
                 for i, d in enumerate(self.descs)]
 
-    def set_tuning(self, split: float = 1.0, workgroups: int = 0):
-        _check(lib().wcnst_batch_set_tuning(self._h, float(split), int(workgroups)))
+    def set_tuning(self, split: float = 1.0, workgroups: int = 0, waves_per_group: int = 0):
+        _check(lib().wcnst_batch_set_tuning(self._h, float(split), int(workgroups), int(waves_per_group)))
+
+    def kernel_ms(self) -> float:
+        ms = ctypes.c_double(0.0)
+        _check(lib().wcnst_batch_kernel_ms(self._h, ctypes.byref(ms)))
+        return ms.value
 
     def solve(self, Ug, t_final, cfl: float = 0.5, max_steps: int = 1 << 40):
         """Returns dict(status, t, steps) arrays; raises only on HIP errors."""

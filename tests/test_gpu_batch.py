@@ -70,10 +70,10 @@ def test_batch_decomposition_does_not_change_results(orc, torch):
     items = _tubes(40, seed=2, n_min=100, n_max=2000, t_final=0.03)
     descs = [d for d, _ in items]
     outs = []
-    for split, wgs in ((0.0, 0), (0.02, 0), (0.5, 7), (1.0, 1)):
-        _say(f"decomposition split={split} workgroups={wgs}")
+    for split, wgs, wpg in ((0.0, 0, 4), (0.02, 0, 4), (0.5, 7, 2), (1.0, 1, 1), (0.1, 0, 1), (0.05, 3000, 2)):
+        _say(f"decomposition split={split} workgroups={wgs} waves/group={wpg}")
         b = Batch(descs)
-        b.set_tuning(split, wgs)
+        b.set_tuning(split, wgs, wpg)
         Ug = b.pack([U for _, U in items])
         res = b.solve(Ug, 0.03, cfl=0.5)
         outs.append((Ug.cpu().numpy(), res["steps"].copy(), res["status"].copy(), b.bad_cells()))
