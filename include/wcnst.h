@@ -162,6 +162,7 @@ wcnst_status wcnst_destroy(wcnst_solver* s);
  * offsets[i] .. offsets[i] + 3*nx_i - 1 with layout [v][nx_i]
  * (wcnst_batch_offsets; offsets[n] is the buffer length in doubles). */
 typedef struct wcnst_batch wcnst_batch;
+typedef struct wcnst_pool wcnst_pool;
 
 /* Device workspace bytes for a batch of n descriptors (instance table, job
  * slots, two packed stage buffers). */
@@ -205,6 +206,56 @@ wcnst_status wcnst_batch_set_tuning(wcnst_batch* b, double split, int32_t workgr
 wcnst_status wcnst_batch_kernel_ms(const wcnst_batch* b, double* ms);
 
 wcnst_status wcnst_batch_destroy(wcnst_batch* b);
+
+/* ------------------------------------------------------------ request pools
+ * A pool keeps many independent Euler solves (1D and 2D, any sizes, one
+ * scheme) resident on the device and advances them together in ticks, so
+ * that requests join and leave between ticks (continuous batching).  Each
+ * request follows exactly the arithmetic of wcnst_solve (Sec. 2-3, SSP-RK3
+ * with the CFL rule and final-step clipping), so its result is the same
+ * bits alone or in any mix.  The library allocates no device memory: the
+ * pool's tables live in a caller workspace and every request brings its own
+ * three state buffers.
+ *
+ * Bytes of the device workspace of a pool for `capacity` requests. */
+wcnst_status wcnst_pool_workspace_size(int32_t capacity, size_t* bytes);
+
+/* Create a pool for Euler requests with the scheme parameters of `scheme`
+ * (its sizes are ignored) on hip_stream (1D passes and result copies; the
+ * pool adds one stream of its own, default priority, for 2D launches). */
+wcnst_status wcnst_pool_create(const wcnst_desc* scheme, int32_t capacity, void* hip_stream, void* workspace,
+                               size_t ws_bytes, wcnst_pool** out);
+
+/* Admit a request: U holds its initial state ([nvar][ny][nx] FP64, nvar =
+ * 3 in 1D, 4 in 2D) and, with U1 and U2 of the same size, stays owned by
+ * the caller and must not be touched until the request is released.  The
+ * state at t = 0 must be in U before the next tick starts on hip_stream.
+ * t_final must be finite.  Returns the slot, or WCNST_E_INVALID_ARG when
+ * the pool is full or d does not match the pool's scheme. */
+wcnst_status wcnst_pool_admit(wcnst_pool* p, const wcnst_desc* d, double* U, double* U1, double* U2,
+                              double t_final, double cfl, int32_t* slot);
+
+/* One tick: every admitted, unfinished request advances by up to `steps`
+ * steps (fewer when it reaches t_final or a non-physical state).
+ * Synchronous.  n_active (nullable) = requests that were advanced. */
+wcnst_status wcnst_pool_tick(wcnst_pool* p, int64_t steps, int32_t* n_active);
+
+/* Outcome of the request in `slot` after the last tick: finished (t_final
+ * reached or failed), status (WCNST_OK or WCNST_E_NONPHYSICAL), t, steps,
+ * and the global stage and cell of the first non-physical value (-1 when
+ * none).  All outputs nullable. */
+wcnst_status wcnst_pool_result(const wcnst_pool* p, int32_t slot, int32_t* finished, int32_t* status, double* t,
+                               int64_t* steps, int64_t* bad_stage, int64_t* bad_cell);
+
+/* Free the slot (the request's buffers return to the caller). */
+wcnst_status wcnst_pool_release(wcnst_pool* p, int32_t slot);
+
+/* Work decomposition of 1D passes (as wcnst_batch_set_tuning: split,
+ * waves_per_group, 0 keeps) and rows per 2D segment (0 keeps, default 35);
+ * never changes results. */
+wcnst_status wcnst_pool_set_tuning(wcnst_pool* p, double split, int32_t waves_per_group, int32_t rows_per_segment);
+
+wcnst_status wcnst_pool_destroy(wcnst_pool* p);
 
 /* Message of the last error on this thread ("" when none). */
 const char* wcnst_last_error(void);

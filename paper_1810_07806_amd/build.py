@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
-SOURCES = [os.path.join(CSRC, "wcnst_kernels.hip"), os.path.join(CSRC, "wcnst_batch.hip")]
+SOURCES = [os.path.join(CSRC, n) for n in ("wcnst_kernels.hip", "wcnst_batch.hip", "wcnst_pool.hip")]
 LIB_PATH = os.path.join(PKG, "libwcnst.so")
 ARCH = os.environ.get("WCNST_OFFLOAD_ARCH", "gfx950")
 

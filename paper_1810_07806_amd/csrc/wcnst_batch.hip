@@ -30,46 +30,12 @@
 
 #include "wcnst.h"
 #include "wcnst_device.hpp"
+#include "wcnst_batch.hpp"
 #include "wcnst_host.hpp"
 
 namespace wcnstb {
 
 using namespace wcnst;
-
-constexpr int WAVE = 64;
-constexpr int TX = WAVE - 3;  // cells per strip
-constexpr int NV = 3;
-constexpr int KMAX = 64;  // most waves cooperating on one instance
-constexpr double WAIT_LIMIT_S = 30.0;  // longest wait of a part at a barrier
-
-struct BInst {
-    long long off;  // element offset in the packed buffers, layout [v][n]
-    int n, bc;
-    int k, pad0;
-    double dx, c1, c2, c3;
-    double t_final;
-    // results and the state shared by the parts of one instance
-    double t;
-    long long steps;
-    unsigned long long bad_key;  // (global stage << 36) | cell
-    int status, pad1;
-    unsigned arrive, gen;
-    unsigned long long smax_bits[2];
-};
-
-struct BSlot {
-    int inst, part;
-};
-
-struct BHead {
-    unsigned head;  // next slot
-    int nslots;
-    int err;  // a bounded wait expired
-    int pad;
-    double cfl;
-    long long max_steps;
-    long long wait_ticks;  // WAIT_LIMIT_S in wall-clock ticks
-};
 
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long m)
 {
@@ -113,7 +79,8 @@ __device__ bool part_sync(BInst* I, int k, unsigned& gen, BHead* hd, int clear_s
         } else {
             const long long t0 = (long long)wall_clock64();
             while (__hip_atomic_load(&I->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                if ((long long)wall_clock64() - t0 > hd->wait_ticks ||
+                if ((long long)wall_clock64() - t0 >
+                        __hip_atomic_load(&hd->wait_ticks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) ||
                     __hip_atomic_load(&hd->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                     __hip_atomic_fetch_or(&hd->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     ok = 0;
@@ -190,29 +157,32 @@ __device__ bool part_stage(const Params& P, int n, int s0, int s1, int stage, do
 }
 
 template <int FLUX, int SCHEME, bool CHAR>
-__device__ void run_part(BInst* I, int part, const Params& Pc, BHead* hd, double* Ub, double* U1b, double* U2b,
-                         double (*sF)[WAVE], double (*sN)[WAVE])
+__device__ void run_part(BInst* I, int part, const Params& Pc, BHead* hd, double (*sF)[WAVE], double (*sN)[WAVE])
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    const int n = I->n, k = I->k;
+    // Every part of the instance takes its control flow (k, t, steps, the
+    // step bound) from the same host-written values.
+    const BInstIn R = load_host_written(reinterpret_cast<const BInstIn*>(I));
+    const int n = R.n, k = R.k;
     const int S = (n + TX - 1) / TX;
     const int s0 = (int)((long long)part * S / k), s1 = (int)((long long)(part + 1) * S / k);
     Params P = Pc;
     P.nx = n;
-    P.dx = I->dx;
-    P.c1x = I->c1;
-    P.c2x = I->c2;
-    P.c3x = I->c3;
-    P.bc_x = I->bc;
-    double* U = Ub + I->off;
-    double* U1 = U1b + I->off;
-    double* U2 = U2b + I->off;
-    const double t_final = I->t_final, cfl = hd->cfl;
-    const long long max_steps = hd->max_steps;
+    P.dx = R.dx;
+    P.c1x = R.c1;
+    P.c2x = R.c2;
+    P.c3x = R.c3;
+    P.bc_x = R.bc;
+    double* U = R.u;
+    double* U1 = R.u1;
+    double* U2 = R.u2;
+    const double t_final = R.t_final, cfl = R.cfl;
+    const long long step_end = R.step_end;
     const bool fin = isfinite(t_final);
 
+    // CFL speed of the state at the start of the launch (the same bits as
+    // the speed the previous step reduced from the same cells)
     unsigned gen = 0;
-    // speed of the initial state
     unsigned long long sm = 0ull;
     for (int s = s0; s < s1; ++s) {
         const int c = s * TX + lane;
@@ -226,16 +196,19 @@ __device__ void run_part(BInst* I, int part, const Params& Pc, BHead* hd, double
     }
     sm = wave_max_u64(sm);
     if (k > 1) {
-        if (lane == 0) __hip_atomic_fetch_max(&I->smax_bits[0], sm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // Slot s & 1 of step s: every part reads it before stage 0 and the
+        // stage-2 barrier of step s clears it, after all parts arrived.
+        const int sl = (int)(R.steps & 1);
+        if (lane == 0) __hip_atomic_fetch_max(&I->smax_bits[sl], sm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (!part_sync(I, k, gen, hd, -1)) return;
-        sm = __hip_atomic_load(&I->smax_bits[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sm = __hip_atomic_load(&I->smax_bits[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 
-    double t = 0.0;
-    long long step = 0;
+    double t = R.t;
+    long long step = R.steps;
     unsigned long long bad_key = ~0ull;
     bool bad = false;
-    while (step < max_steps) {
+    while (step < step_end) {
         if (fin && t_final - t <= 1e-12 * t_final) break;
         double dt = cfl / __longlong_as_double((long long)sm);
         if (fin && dt > t_final - t) dt = t_final - t;
@@ -274,45 +247,45 @@ __device__ void run_part(BInst* I, int part, const Params& Pc, BHead* hd, double
     if (k == 1 && bad) {
         bad_key = wave_min_u64(bad_key);
         if (lane == 0) {
-            I->bad_key = bad_key;
-            I->status = WCNST_E_NONPHYSICAL;
+            __hip_atomic_store(&I->bad_key, bad_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&I->status, (int)WCNST_E_NONPHYSICAL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
     if (part == 0 && lane == 0) {
-        I->t = t;
-        I->steps = step;
+        __hip_atomic_store(&I->t, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&I->steps, step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
 template <int FLUX, int SCHEME, bool CHAR>
 __global__ void __launch_bounds__(256) batch_kernel(BInst* __restrict__ insts, const BSlot* __restrict__ slots,
-                                                    BHead* hd, Params Pc, double* Ub, double* U1b, double* U2b)
+                                                    BHead* hd, Params Pc)
 {
     init_weight_table();
     __shared__ double sFall[256 / WAVE][NV][WAVE];
     __shared__ double sNall[256 / WAVE][NV][WAVE];
     const int w = threadIdx.x / WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
+    const int nslots = __hip_atomic_load(&hd->nslots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     for (;;) {
         int slot = 0;
         if (lane == 0) slot = (int)atomicAdd(&hd->head, 1u);
         slot = __shfl(slot, 0);
-        if (slot >= hd->nslots) break;
+        if (slot >= nslots) break;
         if (__hip_atomic_load(&hd->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-        const BSlot sl = slots[slot];
-        run_part<FLUX, SCHEME, CHAR>(&insts[sl.inst], sl.part, Pc, hd, Ub, U1b, U2b, sFall[w], sNall[w]);
+        const BSlot sl = load_host_written(&slots[slot]);
+        run_part<FLUX, SCHEME, CHAR>(&insts[sl.inst], sl.part, Pc, hd, sFall[w], sNall[w]);
     }
 }
 
 // Initial CFL speed of each instance (one workgroup per instance), for planning.
-__global__ void __launch_bounds__(256) batch_speed(const BInst* __restrict__ insts, Params Pc, const double* Ub,
-                                                   double* speed)
+__global__ void __launch_bounds__(256) batch_speed(const BInst* __restrict__ insts, Params Pc, double* speed)
 {
-    const BInst& I = insts[blockIdx.x];
+    const BInstIn I = load_host_written(reinterpret_cast<const BInstIn*>(&insts[blockIdx.x]));
     Params P = Pc;
     P.nx = I.n;
     P.dx = I.dx;
-    const double* U = Ub + I.off;
+    const double* U = I.u;
     unsigned long long m = 0ull;
     for (int c = threadIdx.x; c < I.n; c += blockDim.x) {
         double u[NV];
@@ -346,87 +319,52 @@ __global__ void batch_open(BHead* hd)
 
 // ====================================================================== host
 
-using namespace wcnstb;
+namespace wcnstb {
 
-struct wcnst_batch {
-    int n = 0;
-    wcnst_desc d0{};
-    std::vector<BInst> rec;
-    std::vector<long long> offs;  // n + 1
-    long long total = 0;          // doubles per packed buffer
-    hipStream_t stream = nullptr;
-    hipStream_t cap = nullptr;  // private stream for graph capture
-    BInst* d_inst = nullptr;
-    BSlot* d_slots = nullptr;
-    BHead* d_head = nullptr;
-    double* d_speed = nullptr;
-    double* U1 = nullptr;
-    double* U2 = nullptr;
+void inst_init(BInst& r, const wcnst_desc& d, double* u, double* u1, double* u2, double t_final, double cfl)
+{
+    r = BInst{};
+    r.u = u;
+    r.u1 = u1;
+    r.u2 = u2;
+    r.n = d.nx;
+    r.bc = d.bc_x;
+    r.k = 1;
+    r.dx = (d.x1 - d.x0) / d.nx;
+    // the same expressions as the single-solve path (Eq. (5) over h)
+    r.c1 = (3.0 / 2.0) / r.dx;
+    r.c2 = (-3.0 / 10.0) / r.dx;
+    r.c3 = (1.0 / 30.0) / r.dx;
+    r.t_final = t_final;
+    r.cfl = cfl;
+    r.t = 0.0;
+    r.steps = 0;
+    r.bad_key = ~0ull;
+    r.status = 0;
+}
+
+void inst_arm(BInst& r, long long step_end)
+{
+    r.step_end = step_end;
+    r.arrive = 0;
+    r.gen = 0;
+    r.smax_bits[0] = r.smax_bits[1] = 0ull;
+}
+
+void scheme_params(const wcnst_desc& d, Params* out)
+{
     Params P{};
-    double split = 1.0;
-    int grid = 0;        // persistent workgroups
-    int wpg = 4;         // wavefronts per workgroup
-    int resident = 0;    // workgroups of wpg waves resident at once
-    int cus = 0;
-    long long wait_ticks = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    double kernel_ms = 0.0;
-    hipGraphExec_t exec = nullptr;
-    const void* exec_kernel = nullptr;
-    double* exec_U = nullptr;
-};
-
-static size_t batch_layout(int n, long long total, size_t* o_inst, size_t* o_slots, size_t* o_head, size_t* o_speed,
-                           size_t* o_u1, size_t* o_u2)
-{
-    size_t o = 0;
-    *o_inst = o;
-    o = wcnst_align256(o + sizeof(BInst) * (size_t)n);
-    *o_slots = o;
-    o = wcnst_align256(o + sizeof(BSlot) * (size_t)n * KMAX);
-    *o_head = o;
-    o = wcnst_align256(o + sizeof(BHead));
-    *o_speed = o;
-    o = wcnst_align256(o + sizeof(double) * (size_t)n);
-    *o_u1 = o;
-    o = wcnst_align256(o + sizeof(double) * (size_t)total);
-    *o_u2 = o;
-    o = wcnst_align256(o + sizeof(double) * (size_t)total);
-    return o;
-}
-
-static wcnst_status batch_check(const wcnst_desc* descs, int32_t n, long long* total, std::vector<long long>* offs)
-{
-    if (!descs || n < 1) return wcnst_fail(WCNST_E_INVALID_ARG, "need at least one descriptor");
-    const wcnst_desc& a = descs[0];
-    long long off = 0;
-    if (offs) offs->assign((size_t)n + 1, 0);
-    for (int i = 0; i < n; ++i) {
-        const wcnst_desc& d = descs[i];
-        wcnst_status st = wcnst_check_desc(&d);
-        if (st) return wcnst_fail(st, "descriptor %d: %s", i, wcnst_last_error());
-        if (d.ndim != 1 || d.system != WCNST_EULER)
-            return wcnst_fail(WCNST_E_INVALID_ARG, "descriptor %d: batches hold 1D Euler problems", i);
-        if (d.flux != a.flux || d.scheme != a.scheme || d.charwise != a.charwise || d.q != a.q ||
-            d.gamma != a.gamma || d.CT != a.CT || d.C != a.C || d.eps_teno != a.eps_teno || d.eps_js != a.eps_js)
-            return wcnst_fail(WCNST_E_INVALID_ARG, "descriptor %d: scheme parameters differ from descriptor 0", i);
-        if (offs) (*offs)[i] = off;
-        off += ((long long)NV * d.nx + 63) / 64 * 64;  // 512-byte aligned instances
-    }
-    if (offs) (*offs)[n] = off;
-    if (total) *total = off;
-    return WCNST_OK;
-}
-
-extern "C" wcnst_status wcnst_batch_workspace_size(const wcnst_desc* descs, int32_t n, size_t* bytes)
-{
-    long long total = 0;
-    wcnst_status st = batch_check(descs, n, &total, nullptr);
-    if (st) return st;
-    if (!bytes) return wcnst_fail(WCNST_E_INVALID_ARG, "null size pointer");
-    size_t a, b, c, d, e, f;
-    *bytes = batch_layout(n, total, &a, &b, &c, &d, &e, &f);
-    return WCNST_OK;
+    P.CT = d.CT;
+    P.C = d.C;
+    P.eps_teno = d.eps_teno;
+    P.eps_js = d.eps_js;
+    P.gamma = d.gamma;
+    P.adv = d.adv_speed;
+    P.q = d.q;
+    P.charwise = d.charwise ? 1 : 0;
+    P.ny = 1;
+    P.dy = 1.0;
+    *out = P;
 }
 
 template <int FLUX, int SCHEME, bool CHAR>
@@ -448,15 +386,158 @@ static const void* pick_kernel(const wcnst_desc& d)
     return d.charwise ? pick2<FLUX_ROE, true>(d) : pick2<FLUX_ROE, false>(d);
 }
 
+hipError_t resident_per_cu(const wcnst_desc& d, int wpg, int* per_cu)
+{
+    *per_cu = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, pick_kernel(d), WAVE * wpg, 0);
+    if (*per_cu < 1) *per_cu = 1;
+    return e;
+}
+
+int plan_parts(std::vector<BInst>& rec, const std::vector<double>& cost, double split, double workers, int running,
+               std::vector<BSlot>& slots)
+{
+    const int n = (int)rec.size();
+    double total = 0.0;
+    for (double c : cost) total += c;
+    std::vector<int> order((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const int strips = (rec[(size_t)i].n + TX - 1) / TX;
+        int k = 1;
+        if (split > 0.0 && total > 0.0)
+            k = (int)std::min(1e9, std::ceil(cost[(size_t)i] * workers / (split * total)));
+        k = std::max(1, std::min(k, std::min(std::min(KMAX, strips), std::max(1, running))));
+        rec[(size_t)i].k = k;
+        order[(size_t)i] = i;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return cost[(size_t)x] / rec[(size_t)x].k > cost[(size_t)y] / rec[(size_t)y].k;
+    });
+    slots.clear();
+    for (int i : order)
+        for (int p = 0; p < rec[(size_t)i].k; ++p) slots.push_back(BSlot{i, p});
+    return (int)slots.size();
+}
+
+hipError_t launch_pass(const wcnst_desc& d, BInst* insts, BSlot* slots, BHead* head, const Params& P, int grid,
+                       int wpg, hipStream_t st)
+{
+    hipLaunchKernelGGL(batch_open, dim3(1), dim3(64), 0, st, head);
+    void* args[] = {(void*)&insts, (void*)&slots, (void*)&head, (void*)&P};
+    const hipError_t e = hipLaunchKernel(pick_kernel(d), dim3(grid), dim3(WAVE * wpg), args, 0, st);
+    return e != hipSuccess ? e : hipGetLastError();
+}
+
+hipError_t wait_ticks(long long* ticks)
+{
+    int dev = 0, khz = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    *ticks = (long long)(WAIT_LIMIT_S * 1e3 * std::max(1, khz));
+    return e;
+}
+
+}  // namespace wcnstb
+
+using namespace wcnstb;
+
+struct wcnst_batch {
+    int n = 0;
+    wcnst_desc d0{};
+    std::vector<wcnst_desc> descs;
+    std::vector<BInst> rec;
+    std::vector<long long> offs;  // n + 1
+    long long total = 0;          // doubles per packed buffer
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;  // private stream for graph capture
+    BInst* d_inst = nullptr;
+    BSlot* d_slots = nullptr;
+    BHead* d_head = nullptr;
+    double* d_speed = nullptr;
+    double* U1 = nullptr;
+    double* U2 = nullptr;
+    Params P{};
+    double split = 1.0;
+    int grid = 0;      // persistent workgroups
+    int wpg = 4;       // wavefronts per workgroup
+    int resident = 0;  // workgroups of wpg waves resident at once
+    int cus = 0;
+    long long wait_ticks = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double kernel_ms = 0.0;
+    hipGraphExec_t exec = nullptr;
+    const void* exec_key = nullptr;
+    int exec_grid = 0, exec_wpg = 0;
+};
+
+static size_t batch_layout(int n, long long total, size_t* o_inst, size_t* o_slots, size_t* o_head, size_t* o_speed,
+                           size_t* o_u1, size_t* o_u2)
+{
+    size_t o = 0;
+    *o_inst = o;
+    o = wcnst_align256(o + sizeof(BInst) * (size_t)n);
+    *o_slots = o;
+    o = wcnst_align256(o + sizeof(BSlot) * (size_t)n * KMAX);
+    *o_head = o;
+    o = wcnst_align256(o + sizeof(BHead));
+    *o_speed = o;
+    o = wcnst_align256(o + sizeof(double) * (size_t)n);
+    *o_u1 = o;
+    o = wcnst_align256(o + sizeof(double) * (size_t)total);
+    *o_u2 = o;
+    o = wcnst_align256(o + sizeof(double) * (size_t)total);
+    return o;
+}
+
+// All descriptors 1D Euler with the scheme parameters of the first.
+wcnst_status wcnst_check_same_scheme(const wcnst_desc& a, const wcnst_desc& d)
+{
+    if (d.flux != a.flux || d.scheme != a.scheme || d.charwise != a.charwise || d.q != a.q || d.gamma != a.gamma ||
+        d.CT != a.CT || d.C != a.C || d.eps_teno != a.eps_teno || d.eps_js != a.eps_js || d.diff != a.diff)
+        return WCNST_E_INVALID_ARG;
+    return WCNST_OK;
+}
+
+static wcnst_status batch_check(const wcnst_desc* descs, int32_t n, long long* total, std::vector<long long>* offs)
+{
+    if (!descs || n < 1) return wcnst_fail(WCNST_E_INVALID_ARG, "need at least one descriptor");
+    const wcnst_desc& a = descs[0];
+    long long off = 0;
+    if (offs) offs->assign((size_t)n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        const wcnst_desc& d = descs[i];
+        wcnst_status st = wcnst_check_desc(&d);
+        if (st) return wcnst_fail(st, "descriptor %d: %s", i, wcnst_last_error());
+        if (d.ndim != 1 || d.system != WCNST_EULER)
+            return wcnst_fail(WCNST_E_INVALID_ARG, "descriptor %d: batches hold 1D Euler problems", i);
+        if (wcnst_check_same_scheme(a, d))
+            return wcnst_fail(WCNST_E_INVALID_ARG, "descriptor %d: scheme parameters differ from descriptor 0", i);
+        if (offs) (*offs)[i] = off;
+        off += ((long long)NV * d.nx + 63) / 64 * 64;  // 512-byte aligned instances
+    }
+    if (offs) (*offs)[n] = off;
+    if (total) *total = off;
+    return WCNST_OK;
+}
+
+extern "C" wcnst_status wcnst_batch_workspace_size(const wcnst_desc* descs, int32_t n, size_t* bytes)
+{
+    long long total = 0;
+    wcnst_status st = batch_check(descs, n, &total, nullptr);
+    if (st) return st;
+    if (!bytes) return wcnst_fail(WCNST_E_INVALID_ARG, "null size pointer");
+    size_t a, b, c, d, e, f;
+    *bytes = batch_layout(n, total, &a, &b, &c, &d, &e, &f);
+    return WCNST_OK;
+}
+
 extern "C" wcnst_status wcnst_batch_destroy(wcnst_batch* b);
 
-// As many workgroups of wpg waves as are resident at once on the device.
-static hipError_t batch_default_grid(wcnst_batch* b)
+static hipError_t batch_resident(wcnst_batch* b)
 {
     int per_cu = 0;
-    const hipError_t e =
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick_kernel(b->d0), WAVE * b->wpg, 0);
-    if (e == hipSuccess) b->resident = std::max(1, per_cu) * b->cus;
+    const hipError_t e = resident_per_cu(b->d0, b->wpg, &per_cu);
+    b->resident = per_cu * b->cus;
     return e;
 }
 
@@ -477,6 +558,7 @@ extern "C" wcnst_status wcnst_batch_create(const wcnst_desc* descs, int32_t n, v
     wcnst_batch* b = new wcnst_batch();
     b->n = n;
     b->d0 = descs[0];
+    b->descs.assign(descs, descs + n);
     b->offs = offs;
     b->total = total;
     b->stream = (hipStream_t)hip_stream;
@@ -488,48 +570,22 @@ extern "C" wcnst_status wcnst_batch_create(const wcnst_desc* descs, int32_t n, v
     b->U1 = (double*)(ws + o_u1);
     b->U2 = (double*)(ws + o_u2);
     b->rec.assign((size_t)n, BInst{});
-    for (int i = 0; i < n; ++i) {
-        const wcnst_desc& d = descs[i];
-        BInst& r = b->rec[(size_t)i];
-        r.off = offs[(size_t)i];
-        r.n = d.nx;
-        r.bc = d.bc_x;
-        r.k = 1;
-        r.dx = (d.x1 - d.x0) / d.nx;
-        // the same expressions as the single-solve path (Eq. (5) over h)
-        r.c1 = (3.0 / 2.0) / r.dx;
-        r.c2 = (-3.0 / 10.0) / r.dx;
-        r.c3 = (1.0 / 30.0) / r.dx;
-    }
-    Params& P = b->P;
-    const wcnst_desc& d = descs[0];
-    P.CT = d.CT;
-    P.C = d.C;
-    P.eps_teno = d.eps_teno;
-    P.eps_js = d.eps_js;
-    P.gamma = d.gamma;
-    P.adv = d.adv_speed;
-    P.q = d.q;
-    P.charwise = d.charwise ? 1 : 0;
-    P.ny = 1;
-    P.dy = 1.0;
+    scheme_params(descs[0], &b->P);
 
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    int clock_khz = 0;
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev);
+    if (e == hipSuccess) e = wait_ticks(&b->wait_ticks);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&b->ev0);
     if (e == hipSuccess) e = hipEventCreate(&b->ev1);
     b->cus = std::max(1, cus);
-    if (e == hipSuccess) e = batch_default_grid(b);
+    if (e == hipSuccess) e = batch_resident(b);
     b->grid = b->resident;
     if (e != hipSuccess) {
         wcnst_batch_destroy(b);
         return wcnst_fail(WCNST_E_HIP, "batch setup failed: %s", hipGetErrorString(e));
     }
-    b->wait_ticks = (long long)(WAIT_LIMIT_S * 1e3 * std::max(1, clock_khz));
     *out = b;
     return WCNST_OK;
 }
@@ -551,13 +607,9 @@ extern "C" wcnst_status wcnst_batch_set_tuning(wcnst_batch* b, double split, int
         return wcnst_fail(WCNST_E_INVALID_ARG, "waves_per_group must be 1, 2 or 4 (0 keeps it)");
     b->split = split;
     if (waves_per_group) b->wpg = waves_per_group;
-    hipError_t e = batch_default_grid(b);
+    hipError_t e = batch_resident(b);
     if (e != hipSuccess) return wcnst_fail(WCNST_E_HIP, "occupancy query failed: %s", hipGetErrorString(e));
     b->grid = workgroups > 0 ? workgroups : b->resident;
-    if (b->exec) {
-        (void)hipGraphExecDestroy(b->exec);
-        b->exec = nullptr;
-    }
     return WCNST_OK;
 }
 
@@ -568,104 +620,65 @@ extern "C" wcnst_status wcnst_batch_kernel_ms(const wcnst_batch* b, double* ms)
     return WCNST_OK;
 }
 
-// Longest-part-first plan: instance i gets k_i = ceil(cost_i / (split x
-// total / workers)) parts, so that no part is longer than split x the
-// average share of a wave.  k never exceeds the number of resident waves: slots
-// are taken in order, so at any time at most one job has parts not yet
-// taken, and its k waiting parts are then always completed by free waves.
-static int plan(wcnst_batch* b, const std::vector<double>& speed, const double* t_final, double cfl,
-                long long max_steps, std::vector<BSlot>& slots)
-{
-    const int n = b->n;
-    std::vector<double> cost((size_t)n);
-    double total = 0.0;
-    for (int i = 0; i < n; ++i) {
-        double steps = (double)max_steps;
-        if (std::isfinite(t_final[i]) && std::isfinite(speed[(size_t)i]))
-            steps = std::min(steps, std::ceil(t_final[i] * speed[(size_t)i] / cfl) + 1.0);
-        cost[(size_t)i] = (double)b->rec[(size_t)i].n * steps;
-        total += cost[(size_t)i];
-    }
-    const double workers = (double)b->wpg * b->grid;
-    // waves that are certainly running together (a grid larger than the
-    // resident set runs in turns)
-    const int running = b->wpg * std::min(b->grid, b->resident);
-    std::vector<int> order((size_t)n);
-    for (int i = 0; i < n; ++i) {
-        const int strips = (b->rec[(size_t)i].n + TX - 1) / TX;
-        int k = 1;
-        if (b->split > 0.0 && total > 0.0)
-            k = (int)std::min(1e9, std::ceil(cost[(size_t)i] * workers / (b->split * total)));
-        k = std::max(1, std::min(k, std::min(std::min(KMAX, strips), running)));
-        b->rec[(size_t)i].k = k;
-        order[(size_t)i] = i;
-    }
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        return cost[(size_t)x] / b->rec[(size_t)x].k > cost[(size_t)y] / b->rec[(size_t)y].k;
-    });
-    slots.clear();
-    for (int i : order)
-        for (int p = 0; p < b->rec[(size_t)i].k; ++p) slots.push_back(BSlot{i, p});
-    return (int)slots.size();
-}
-
 extern "C" wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const double* t_final, double cfl,
                                           int64_t max_steps, int32_t* status, double* t_out, int64_t* steps_out)
 {
     if (!b || !U || !t_final || !status) return wcnst_fail(WCNST_E_INVALID_ARG, "null argument");
     if (!(cfl > 0.0)) return wcnst_fail(WCNST_E_INVALID_ARG, "cfl must be > 0");
     if (max_steps < 0) return wcnst_fail(WCNST_E_INVALID_ARG, "max_steps must be >= 0");
+    if (((uintptr_t)U & 7u) != 0) return wcnst_fail(WCNST_E_INVALID_ARG, "U not 8-byte aligned");
     const int n = b->n;
     for (int i = 0; i < n; ++i) {
         if (std::isnan(t_final[i])) return wcnst_fail(WCNST_E_INVALID_ARG, "t_final[%d] is NaN", i);
         if (!std::isfinite(t_final[i]) && max_steps >= ((int64_t)1 << 40))
             return wcnst_fail(WCNST_E_INVALID_ARG, "t_final[%d] is infinite and max_steps unbounded", i);
         BInst& r = b->rec[(size_t)i];
-        r.t_final = t_final[i];
-        r.t = 0.0;
-        r.steps = 0;
-        r.bad_key = ~0ull;
-        r.status = 0;
-        r.arrive = 0;
-        r.gen = 0;
-        r.smax_bits[0] = r.smax_bits[1] = 0ull;
-        r.k = 1;
+        const long long o = b->offs[(size_t)i];
+        inst_init(r, b->descs[(size_t)i], U + o, b->U1 + o, b->U2 + o, t_final[i], cfl);
+        inst_arm(r, (long long)max_steps);
     }
     // initial speeds for the plan
     WCNST_HIP_TRY(hipMemcpyAsync(b->d_inst, b->rec.data(), sizeof(BInst) * (size_t)n, hipMemcpyHostToDevice,
                                  b->stream));
-    hipLaunchKernelGGL(batch_speed, dim3(n), dim3(256), 0, b->stream, b->d_inst, b->P, U, b->d_speed);
+    hipLaunchKernelGGL(batch_speed, dim3(n), dim3(256), 0, b->stream, b->d_inst, b->P, b->d_speed);
     WCNST_HIP_TRY(hipGetLastError());
     std::vector<double> speed((size_t)n);
     WCNST_HIP_TRY(hipMemcpyAsync(speed.data(), b->d_speed, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost,
                                  b->stream));
     WCNST_HIP_TRY(hipStreamSynchronize(b->stream));
+    std::vector<double> cost((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        double steps = (double)max_steps;
+        if (std::isfinite(t_final[i]) && std::isfinite(speed[(size_t)i]))
+            steps = std::min(steps, std::ceil(t_final[i] * speed[(size_t)i] / cfl) + 1.0);
+        cost[(size_t)i] = (double)b->rec[(size_t)i].n * steps;
+    }
     std::vector<BSlot> slots;
-    const int nslots = plan(b, speed, t_final, cfl, (long long)max_steps, slots);
+    const int running = b->wpg * std::min(b->grid, b->resident);
+    const int nslots = plan_parts(b->rec, cost, b->split, (double)b->wpg * b->grid, running, slots);
     BHead h{};
     h.nslots = nslots;
-    h.cfl = cfl;
-    h.max_steps = (long long)max_steps;
     h.wait_ticks = b->wait_ticks;
     WCNST_HIP_TRY(hipMemcpyAsync(b->d_inst, b->rec.data(), sizeof(BInst) * (size_t)n, hipMemcpyHostToDevice,
                                  b->stream));
     WCNST_HIP_TRY(hipMemcpyAsync(b->d_slots, slots.data(), sizeof(BSlot) * slots.size(), hipMemcpyHostToDevice,
                                  b->stream));
     WCNST_HIP_TRY(hipMemcpyAsync(b->d_head, &h, sizeof(BHead), hipMemcpyHostToDevice, b->stream));
+    // the tables must be in device memory before the graph's kernels start
+    WCNST_HIP_TRY(hipStreamSynchronize(b->stream));
 
-    // one persistent launch, captured once into a graph and replayed
-    const void* kern = pick_kernel(b->d0);
-    if (!b->exec || b->exec_kernel != kern || b->exec_U != U) {
+    // one persistent launch, captured once into a graph and replayed (the
+    // buffers are reached through the instance table, so the graph does
+    // not depend on U)
+    const void* key = pick_kernel(b->d0);
+    if (!b->exec || b->exec_key != key || b->exec_grid != b->grid || b->exec_wpg != b->wpg) {
         if (b->exec) {
             (void)hipGraphExecDestroy(b->exec);
             b->exec = nullptr;
         }
         hipGraph_t g = nullptr;
         WCNST_HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-        hipLaunchKernelGGL(batch_open, dim3(1), dim3(64), 0, b->cap, b->d_head);
-        void* args[] = {(void*)&b->d_inst, (void*)&b->d_slots, (void*)&b->d_head, (void*)&b->P,
-                        (void*)&U,         (void*)&b->U1,      (void*)&b->U2};
-        hipError_t le = hipLaunchKernel(kern, dim3(b->grid), dim3(WAVE * b->wpg), args, 0, b->cap);
+        hipError_t le = launch_pass(b->d0, b->d_inst, b->d_slots, b->d_head, b->P, b->grid, b->wpg, b->cap);
         hipError_t ce = hipStreamEndCapture(b->cap, &g);
         if (le != hipSuccess || ce != hipSuccess)
             return wcnst_fail(WCNST_E_HIP, "graph capture failed: %s / %s", hipGetErrorString(le),
@@ -673,8 +686,9 @@ extern "C" wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const doubl
         hipError_t ie = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (ie != hipSuccess) return wcnst_fail(WCNST_E_HIP, "graph instantiate failed: %s", hipGetErrorString(ie));
-        b->exec_kernel = kern;
-        b->exec_U = U;
+        b->exec_key = key;
+        b->exec_grid = b->grid;
+        b->exec_wpg = b->wpg;
     }
     WCNST_HIP_TRY(hipEventRecord(b->ev0, b->stream));
     WCNST_HIP_TRY(hipGraphLaunch(b->exec, b->stream));
@@ -716,7 +730,7 @@ extern "C" wcnst_status wcnst_batch_bad_cells(const wcnst_batch* b, int64_t* bad
 extern "C" wcnst_status wcnst_batch_destroy(wcnst_batch* b)
 {
     if (!b) return WCNST_OK;
-    (void)hipStreamSynchronize(b->stream);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->ev0) (void)hipEventDestroy(b->ev0);

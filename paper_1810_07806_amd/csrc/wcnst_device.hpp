@@ -47,7 +47,58 @@ struct Params {
     int nx, ny;
 };
 
+// Step records of one solve, alternating by step parity: the current
+// record holds t, the step count and the CFL speed of the state at t; stage
+// 0 of a step writes dt into it and opens the other one.
+struct StepRec {
+    double t;
+    double dt;
+    unsigned long long smax_bits;  // max CFL speed of the state at time t (bit pattern)
+    long long step;
+};
+
+struct Ctrl {
+    StepRec rec[2];
+    unsigned long long bad_key;  // (global stage << 36) | cell of the first non-physical value
+    long long call_step0;        // step counter at the start of the current solve call
+    int status;                  // sticky WCNST_E_NONPHYSICAL
+    int done;                    // sticky: t_final reached in the current call
+    int pad[2];
+};
+
+// One 2D grid of a multi-grid stage launch: its buffers (U holds the state
+// at t^n, U1 / U2 the stage states), control block, parameters, and its
+// first block in the launch (blocks blk0 .. blk0 + nstrips*nseg - 1).
+struct Req2D {
+    double* U;
+    double* U1;
+    double* U2;
+    Ctrl* ctrl;
+    Params P;
+    double t_final, cfl;
+    int nstrips, blk0;
+    int parity0;  // step parity at tick step 0
+    int pad;
+};
+
 // ------------------------------------------------------------ helpers
+
+// A copy of a table entry that the host wrote before this launch, read with
+// system-scope loads: they are coherent with host copies whatever an L2
+// still holds of the same memory from an earlier launch (entries that
+// decide the control flow of cooperating waves must be seen alike by all).
+template <class T>
+__device__ __forceinline__ T load_host_written(const T* p)
+{
+    static_assert(sizeof(T) % 8 == 0 && alignof(T) >= 8, "8-byte granular entries");
+    T out;
+    const unsigned long long* s = reinterpret_cast<const unsigned long long*>(p);
+    unsigned long long* d = reinterpret_cast<unsigned long long*>(&out);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 8); ++i)
+        d[i] = __hip_atomic_load(s + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return out;
+}
 
 WCNST_HD int ghost_map(int g, int n, int bc)
 {

@@ -11,7 +11,24 @@
 wcnst_status wcnst_fail(wcnst_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 wcnst_status wcnst_check_desc(const wcnst_desc* d);
 int wcnst_desc_nvar(const wcnst_desc* d);
+// WCNST_OK when d has the scheme parameters of a (flux, scheme, charwise,
+// q, gamma, C_T, C, epsilons, difference).
+wcnst_status wcnst_check_same_scheme(const wcnst_desc& a, const wcnst_desc& d);
 size_t wcnst_align256(size_t b);
+
+namespace wcnst {
+struct Params;
+}
+// Solver parameters of a validated descriptor (spacing, Eq. (5) coefficients).
+void wcnst_make_params(const wcnst_desc* d, wcnst::Params* out);
+
+// Request pools: bytes of one 2D control block; reset it to t = 0 and
+// accumulate the CFL speed of U into its record 0; one stage of every grid
+// of a Req2D table (nblocks = total segments, ty rows per segment).
+size_t wcnst_ctrl_bytes();
+hipError_t wcnst_launch_init2d(const wcnst_desc* d, const double* U, void* ctrl, hipStream_t st);
+hipError_t wcnst_launch_multi2d(const wcnst_desc* d, const void* reqs, int nreq, int nblocks, int stage,
+                                int tick_step, int ty, hipStream_t st);
 
 #define WCNST_HIP_TRY(expr)                                                                \
     do {                                                                                   \

@@ -34,22 +34,6 @@ namespace wcnst {
 constexpr int WAVE = 64;
 constexpr int TX = WAVE - 3;  // cells per strip
 
-struct StepRec {
-    double t;
-    double dt;
-    unsigned long long smax_bits;  // max CFL speed of the state at time t (bit pattern)
-    long long step;
-};
-
-struct Ctrl {
-    StepRec rec[2];  // current / next record, alternating by step parity
-    unsigned long long bad_key;  // (global stage << 36) | cell of the first non-physical value
-    long long call_step0;        // step counter at the start of the current solve call
-    int status;                  // sticky WCNST_E_NONPHYSICAL
-    int done;                    // sticky: t_final reached in the current call
-    int pad[2];
-};
-
 enum { MODE_RHS = 0, MODE_STAGE = 1 };
 
 struct StageArgs {
@@ -68,7 +52,7 @@ __device__ __forceinline__ bool first_thread()
 // Reads the step record; stage 0 also decides dt (every block computes the
 // same value from the same inputs) and opens the next record.
 __device__ __forceinline__ bool stage_prologue(Ctrl* ctrl, const StageArgs& A, double& dt,
-                                               long long& step)
+                                               long long& step, bool lead)
 {
     const StepRec* cur = &ctrl->rec[A.parity];
     if (ctrl->status != 0 || ctrl->done != 0) return false;
@@ -80,13 +64,13 @@ __device__ __forceinline__ bool stage_prologue(Ctrl* ctrl, const StageArgs& A, d
     const double t = cur->t;
     const bool fin = isfinite(A.t_final);
     if (fin && A.t_final - t <= 1e-12 * A.t_final) {
-        if (first_thread()) ctrl->done = 1;
+        if (lead) ctrl->done = 1;
         return false;
     }
     const double smax = __longlong_as_double((long long)cur->smax_bits);
     dt = A.fixed_dt > 0.0 ? A.fixed_dt : A.cfl / smax;
     if (fin && dt > A.t_final - t) dt = A.t_final - t;
-    if (first_thread()) {
+    if (lead) {
         StepRec* nx = &ctrl->rec[A.parity ^ 1];
         ctrl->rec[A.parity].dt = dt;
         nx->t = t + dt;
@@ -159,7 +143,7 @@ sweep1d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
     double dt = 0.0;
     long long step = 0;
     if constexpr (MODE == MODE_STAGE) {
-        if (!stage_prologue(ctrl, A, dt, step)) return;
+        if (!stage_prologue(ctrl, A, dt, step, first_thread())) return;
     }
     __shared__ double sF[NV][WAVE];
     __shared__ double sN[NV][WAVE];
@@ -260,17 +244,18 @@ __device__ __forceinline__ void store_row(double (*slot)[XW], int lane, bool has
     }
 }
 
-// Two wavefronts per SIMD: the register budget is capped at 256 (a few
-// values spill); measured faster than one wavefront with no spills.
+// One segment (strip bx, rows by*ty ..) of one 2D grid.  Thread 0 of
+// segment (0, 0) opens the next step record.
 template <int NV, int FLUX, int SCHEME, bool CHAR, int MODE>
-__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2)))
-sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __restrict__ out,
-        uint8_t* __restrict__ flags, Ctrl* __restrict__ ctrl, Params P, StageArgs A, int ty)
+__device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, const double* __restrict__ Un,
+                                              double* __restrict__ out, uint8_t* __restrict__ flags,
+                                              Ctrl* __restrict__ ctrl, const Params& P, const StageArgs& A,
+                                              int ty, int bx, int by)
 {
     double dt = 0.0;
     long long step = 0;
     if constexpr (MODE == MODE_STAGE) {
-        if (!stage_prologue(ctrl, A, dt, step)) return;
+        if (!stage_prologue(ctrl, A, dt, step, bx == 0 && by == 0 && threadIdx.x == 0)) return;
     }
     // Ring of staged rows (all variables, XW columns) and the x-midpoint /
     // x node fluxes of the current row.
@@ -281,13 +266,13 @@ sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
     const int nx = P.nx, ny = P.ny;
     const size_t plane = (size_t)nx * ny;
     const int lane = threadIdx.x;
-    const int x0 = blockIdx.x * TX;
-    const int y0 = blockIdx.y * ty;
+    const int x0 = bx * TX;
+    const int y0 = by * ty;
     const int y1 = min(y0 + ty, ny);
     const int c = x0 + lane;
     const bool cell_ok = lane < TX && c < nx;
     const int jx = x0 - 2 + lane;
-    const bool own_x = flags && jx <= nx && face_owner(jx, nx, TX) == (int)blockIdx.x;
+    const bool own_x = flags && jx <= nx && face_owner(jx, nx, TX) == bx;
     // columns this lane stages (ghost cells by index remap, any distance)
     const bool hasB = lane < XW - WAVE;
     const int colA = ghost_map_any(x0 - 4 + lane, nx, P.bc_x);
@@ -339,7 +324,7 @@ sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
             face_flux<SYS_EULER, NV, FLUX, SCHEME, CHAR>(st, P, F, fb);
             if (flags) {
                 if (py) {
-                    if (cell_ok && j <= ny && face_owner(j, ny, ty) == (int)blockIdx.y)
+                    if (cell_ok && j <= ny && face_owner(j, ny, ty) == by)
                         write_flags<NV>(flags + (size_t)NV * ny * (nx + 3) * 2, nx, ny + 3, c, j + 2, fb);
                 } else if (own_x) {
                     write_flags<NV>(flags, ny, nx + 3, i, jx + 2, fb);
@@ -418,6 +403,48 @@ sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
     if constexpr (MODE == MODE_STAGE) {
         if (A.stage == 2) flush_speed(ctrl, A.parity, smax_loc);
     }
+}
+
+// Two wavefronts per SIMD: the register budget is capped at 256 (a few
+// values spill); measured faster than one wavefront with no spills.
+template <int NV, int FLUX, int SCHEME, bool CHAR, int MODE>
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2)))
+sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __restrict__ out,
+        uint8_t* __restrict__ flags, Ctrl* __restrict__ ctrl, Params P, StageArgs A, int ty)
+{
+    sweep2d_block<NV, FLUX, SCHEME, CHAR, MODE>(U, Un, out, flags, ctrl, P, A, ty, (int)blockIdx.x,
+                                                (int)blockIdx.y);
+}
+
+// One stage of many independent 2D grids in one launch: block b belongs to
+// the request r with blk0[r] <= b < blk0[r+1] (binary search over the
+// table, uniform per block), then runs segment b - blk0[r] of that grid with
+// the grid's own parameters, buffers, control block and step parity.
+template <int NV, int FLUX, int SCHEME, bool CHAR>
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2)))
+sweep2d_multi(const Req2D* __restrict__ reqs, int nreq, int stage, int tick_step, int ty)
+{
+    // the request table is host-written for each tick: system-scope reads
+    const int b = (int)blockIdx.x;
+    int lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (__hip_atomic_load(&reqs[mid].blk0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const Req2D R = load_host_written(&reqs[lo]);
+    const Params& P = R.P;
+    const int local = b - R.blk0;
+    StageArgs A;
+    A.t_final = R.t_final;
+    A.cfl = R.cfl;
+    A.fixed_dt = 0.0;
+    A.stage = stage;
+    A.parity = (R.parity0 + tick_step) & 1;
+    const double* in = stage == 0 ? R.U : (stage == 1 ? R.U1 : R.U2);
+    double* out = stage == 0 ? R.U1 : (stage == 1 ? R.U2 : R.U);
+    sweep2d_block<NV, FLUX, SCHEME, CHAR, MODE_STAGE>(in, R.U, out, nullptr, R.ctrl, P, A, ty, local % R.nstrips,
+                                                      local / R.nstrips);
 }
 
 // ----------------------------------------------------- control kernels
@@ -586,6 +613,33 @@ extern "C" wcnst_status wcnst_workspace_size(const wcnst_desc* d, size_t* bytes)
     return WCNST_OK;
 }
 
+void wcnst_make_params(const wcnst_desc* d, Params* out)
+{
+    Params P{};
+    P.CT = d->CT;
+    P.C = d->C;
+    P.eps_teno = d->eps_teno;
+    P.eps_js = d->eps_js;
+    P.gamma = d->gamma;
+    P.adv = d->adv_speed;
+    P.nx = d->nx;
+    P.ny = d->ny;
+    P.dx = (d->x1 - d->x0) / d->nx;
+    P.dy = d->ndim == 2 ? (d->y1 - d->y0) / d->ny : 1.0;
+    // Eq. (5) coefficients (3/2, -3/10, 1/30) divided by the spacing
+    P.c1x = (3.0 / 2.0) / P.dx;
+    P.c2x = (-3.0 / 10.0) / P.dx;
+    P.c3x = (1.0 / 30.0) / P.dx;
+    P.c1y = (3.0 / 2.0) / P.dy;
+    P.c2y = (-3.0 / 10.0) / P.dy;
+    P.c3y = (1.0 / 30.0) / P.dy;
+    P.q = d->q;
+    P.charwise = d->charwise ? 1 : 0;
+    P.bc_x = d->bc_x;
+    P.bc_y = d->bc_y;
+    *out = P;
+}
+
 extern "C" wcnst_status wcnst_create(const wcnst_desc* d, void* hip_stream, void* workspace,
                                      size_t ws_bytes, wcnst_solver** out)
 {
@@ -616,28 +670,7 @@ extern "C" wcnst_status wcnst_create(const wcnst_desc* d, void* hip_stream, void
     s->prof = false;
     s->ev_used = 0;
 
-    Params& P = s->P;
-    P.CT = d->CT;
-    P.C = d->C;
-    P.eps_teno = d->eps_teno;
-    P.eps_js = d->eps_js;
-    P.gamma = d->gamma;
-    P.adv = d->adv_speed;
-    P.nx = d->nx;
-    P.ny = d->ny;
-    P.dx = (d->x1 - d->x0) / d->nx;
-    P.dy = d->ndim == 2 ? (d->y1 - d->y0) / d->ny : 1.0;
-    // Eq. (5) coefficients (3/2, -3/10, 1/30) divided by the spacing
-    P.c1x = (3.0 / 2.0) / P.dx;
-    P.c2x = (-3.0 / 10.0) / P.dx;
-    P.c3x = (1.0 / 30.0) / P.dx;
-    P.c1y = (3.0 / 2.0) / P.dy;
-    P.c2y = (-3.0 / 10.0) / P.dy;
-    P.c3y = (1.0 / 30.0) / P.dy;
-    P.q = d->q;
-    P.charwise = d->charwise ? 1 : 0;
-    P.bc_x = d->bc_x;
-    P.bc_y = d->bc_y;
+    wcnst_make_params(d, &s->P);
 
     for (int k = 0; k < 2; ++k) {
         hipError_t e = hipHostMalloc((void**)&s->host_ctrl[k], sizeof(Ctrl), hipHostMallocDefault);
@@ -933,6 +966,57 @@ extern "C" wcnst_status wcnst_profile_read(wcnst_solver* s, double* stage_ms, in
     if (stage_launches) *stage_launches = (int64_t)(s->ev_used / 2);
     s->ev_used = 0;
     return WCNST_OK;
+}
+
+// ------------------------------------------- launchers for request pools
+
+size_t wcnst_ctrl_bytes() { return sizeof(Ctrl); }
+
+hipError_t wcnst_launch_init2d(const wcnst_desc* d, const double* U, void* ctrl, hipStream_t st)
+{
+    Params P;
+    wcnst_make_params(d, &P);
+    hipLaunchKernelGGL(ctrl_init, dim3(1), dim3(64), 0, st, (Ctrl*)ctrl, 0.0, 0LL);
+    const size_t cells = (size_t)d->nx * d->ny;
+    const int blocks = (int)std::min<size_t>((cells + 255) / 256, 2048);
+    hipLaunchKernelGGL((wavespeed<SYS_EULER, 4>), dim3(blocks), dim3(256), 0, st, U, (Ctrl*)ctrl, P, 0);
+    return hipGetLastError();
+}
+
+template <int FLUX, int SCHEME, bool CHAR>
+static void launch_multi_t(const Req2D* reqs, int nreq, int nblocks, int stage, int tick_step, int ty,
+                           hipStream_t st)
+{
+    hipLaunchKernelGGL((sweep2d_multi<4, FLUX, SCHEME, CHAR>), dim3(nblocks), dim3(WAVE), 0, st, reqs, nreq,
+                       stage, tick_step, ty);
+}
+
+template <int FLUX, bool CHAR>
+static void launch_multi_s(const wcnst_desc* d, const Req2D* reqs, int nreq, int nblocks, int stage,
+                           int tick_step, int ty, hipStream_t st)
+{
+    switch (d->scheme) {
+    case WCNST_LINEAR: launch_multi_t<FLUX, SCH_LINEAR, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, st); break;
+    case WCNST_JS: launch_multi_t<FLUX, SCH_JS, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, st); break;
+    default:
+        if (d->q == 6) launch_multi_t<FLUX, SCH_TENO, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, st);
+        else launch_multi_t<FLUX, SCH_TENO_Q, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, st);
+        break;
+    }
+}
+
+hipError_t wcnst_launch_multi2d(const wcnst_desc* d, const void* reqs, int nreq, int nblocks, int stage,
+                                int tick_step, int ty, hipStream_t st)
+{
+    const Req2D* r = (const Req2D*)reqs;
+    if (d->flux == WCNST_LF) {
+        if (d->charwise) launch_multi_s<FLUX_LF, true>(d, r, nreq, nblocks, stage, tick_step, ty, st);
+        else launch_multi_s<FLUX_LF, false>(d, r, nreq, nblocks, stage, tick_step, ty, st);
+    } else {
+        if (d->charwise) launch_multi_s<FLUX_ROE, true>(d, r, nreq, nblocks, stage, tick_step, ty, st);
+        else launch_multi_s<FLUX_ROE, false>(d, r, nreq, nblocks, stage, tick_step, ty, st);
+    }
+    return hipGetLastError();
 }
 
 extern "C" const char* wcnst_last_error(void) { return g_err; }

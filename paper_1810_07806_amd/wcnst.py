@@ -24,7 +24,9 @@ EXPORTS = ("wcnst_desc_init", "wcnst_workspace_size", "wcnst_create", "wcnst_rhs
            "wcnst_solve", "wcnst_status_sync", "wcnst_reset", "wcnst_set_tuning", "wcnst_profile_enable",
            "wcnst_profile_read", "wcnst_destroy", "wcnst_last_error",
            "wcnst_batch_workspace_size", "wcnst_batch_create", "wcnst_batch_offsets", "wcnst_batch_solve",
-           "wcnst_batch_bad_cells", "wcnst_batch_set_tuning", "wcnst_batch_kernel_ms", "wcnst_batch_destroy")
+           "wcnst_batch_bad_cells", "wcnst_batch_set_tuning", "wcnst_batch_kernel_ms", "wcnst_batch_destroy",
+           "wcnst_pool_workspace_size", "wcnst_pool_create", "wcnst_pool_admit", "wcnst_pool_tick",
+           "wcnst_pool_result", "wcnst_pool_release", "wcnst_pool_set_tuning", "wcnst_pool_destroy")
 
 
 class WcnstError(RuntimeError):
@@ -84,6 +86,15 @@ def lib(path: str | None = None):
     L.wcnst_batch_set_tuning.argtypes = [vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32]
     L.wcnst_batch_kernel_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.wcnst_batch_destroy.argtypes = [vp]
+    i32, i32p = ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)
+    L.wcnst_pool_workspace_size.argtypes = [i32, ctypes.POINTER(ctypes.c_size_t)]
+    L.wcnst_pool_create.argtypes = [D, i32, vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.wcnst_pool_admit.argtypes = [vp, D, vp, vp, vp, ctypes.c_double, ctypes.c_double, i32p]
+    L.wcnst_pool_tick.argtypes = [vp, ctypes.c_int64, i32p]
+    L.wcnst_pool_result.argtypes = [vp, i32, i32p, i32p, dp, i64p, i64p, i64p]
+    L.wcnst_pool_release.argtypes = [vp, i32]
+    L.wcnst_pool_set_tuning.argtypes = [vp, ctypes.c_double, i32, i32]
+    L.wcnst_pool_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name != "wcnst_last_error":
             getattr(L, name).restype = ctypes.c_int32
@@ -317,6 +328,80 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             lib().wcnst_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pool:
+    """Device-resident pool of Euler solves advanced together in ticks
+    (continuous batching).  Request buffers are torch float64 CUDA tensors
+    owned by the caller (for instance views of one arena)."""
+
+    def __init__(self, scheme: dict | None = None, capacity: int = 256, stream=None, device: str = "cuda"):
+        import torch
+        self._torch = torch
+        sch = dict(scheme or {})
+        sch.setdefault("nx", 64)
+        self._scheme = make_desc(sch)
+        self.capacity = int(capacity)
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().wcnst_pool_workspace_size(self.capacity, ctypes.byref(nbytes)))
+        raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=device)
+        off = (-raw.data_ptr()) % 256
+        self._ws_raw = raw
+        self.ws = raw[off:off + nbytes.value]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(raw.device)
+        h = ctypes.c_void_p()
+        _check(lib().wcnst_pool_create(ctypes.byref(self._scheme), self.capacity,
+                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.c_void_p(self.ws.data_ptr()),
+                                       nbytes.value, ctypes.byref(h)))
+        self._h = h
+        self._held = {}
+
+    def admit(self, desc: dict, U, U1, U2, t_final: float, cfl: float = 0.5) -> int:
+        t = self._torch
+        n = nvar(desc) * int(desc["nx"]) * (int(desc.get("ny", 1)) if int(desc.get("ndim", 1)) == 2 else 1)
+        for a in (U, U1, U2):
+            if not (isinstance(a, t.Tensor) and a.is_cuda and a.dtype == t.float64 and a.is_contiguous()
+                    and a.numel() == n):
+                raise TypeError(f"request buffers must be contiguous float64 CUDA tensors of {n} elements")
+        d = make_desc(desc)
+        slot = ctypes.c_int32(-1)
+        _check(lib().wcnst_pool_admit(self._h, ctypes.byref(d), ctypes.c_void_p(U.data_ptr()),
+                                      ctypes.c_void_p(U1.data_ptr()), ctypes.c_void_p(U2.data_ptr()),
+                                      float(t_final), float(cfl), ctypes.byref(slot)))
+        self._held[slot.value] = (U, U1, U2)
+        return slot.value
+
+    def tick(self, steps: int) -> int:
+        n = ctypes.c_int32(0)
+        _check(lib().wcnst_pool_tick(self._h, int(steps), ctypes.byref(n)))
+        return n.value
+
+    def result(self, slot: int) -> dict:
+        f, s = ctypes.c_int32(), ctypes.c_int32()
+        tt = ctypes.c_double()
+        n, bs, bc = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().wcnst_pool_result(self._h, int(slot), ctypes.byref(f), ctypes.byref(s), ctypes.byref(tt),
+                                       ctypes.byref(n), ctypes.byref(bs), ctypes.byref(bc)))
+        return dict(finished=bool(f.value), status=s.value, t=tt.value, steps=n.value, bad_stage=bs.value,
+                    bad_cell=bc.value)
+
+    def release(self, slot: int):
+        _check(lib().wcnst_pool_release(self._h, int(slot)))
+        self._held.pop(slot, None)
+
+    def set_tuning(self, split: float = 1.0, waves_per_group: int = 0, rows_per_segment: int = 0):
+        _check(lib().wcnst_pool_set_tuning(self._h, float(split), int(waves_per_group), int(rows_per_segment)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().wcnst_pool_destroy(self._h)
             self._h = None
 
     def __del__(self):

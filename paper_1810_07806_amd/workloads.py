@@ -271,3 +271,32 @@ def random_quadrants_params(rng: np.random.Generator, side_min: int = 256, side_
             ok &= _vacuum_free(st[a][0], st[a][2], st[a][3], st[b][0], st[b][2], st[b][3], gamma)
         if ok:
             return dict(n=side, states=st)
+
+
+# -------------------------------------------------- serving request stream
+
+def serving_trace(count: int = 200, seed: int = 0, rate: float = 10.0, frac_1d: float = 0.7,
+                  n1_min: int = 512, n1_max: int = 16384, side_min: int = 256, side_max: int = 1024,
+                  t_1d: float = 0.15, t_2d: float = 0.1, gamma: float = 1.4):
+    """Poisson stream of mixed solve requests: exponential inter-arrival
+    times of mean 1/rate seconds; with probability frac_1d a 1D shock tube
+    (as the batched tubes, N log-uniform in [n1_min, n1_max], to t_1d), else
+    a 2D four-quadrant Riemann problem with random states (side log-uniform
+    in [side_min, side_max] rounded to 64, to t_2d).  Returns a list of
+    dict(rid, arrival, desc, U0, t_final), arrivals increasing."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for rid in range(count):
+        t += rng.exponential(1.0 / rate)
+        if rng.uniform() < frac_1d:
+            prm = shock_tube_params(rng, n1_min, n1_max, gamma)
+            d, U = riemann_1d(prm["nx"], prm["left"], prm["right"], prm["x_split"], gamma=gamma)
+            tf = t_1d
+        else:
+            prm = random_quadrants_params(rng, side_min, side_max, gamma)
+            d, U = quadrants(prm["n"], prm["n"], prm["states"], gamma=gamma)
+            tf = t_2d
+        d["t_final"] = tf
+        out.append(dict(rid=rid, arrival=t, desc=d, U0=U, t_final=tf))
+    return out

@@ -1,0 +1,156 @@
+"""Request pool and serving loop: each request gives the same bits in the
+mix as solved alone (wcnst_solve), whenever it joins, whatever else runs,
+and under any tuning; a failing request stays local."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1810_07806_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available()
+    from paper_1810_07806_amd import wcnst
+    wcnst.lib()
+    return T
+
+
+def _mix(seed, n1=5, n2=3, t1=0.02, t2=0.01):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n1):
+        prm = W.shock_tube_params(rng, 64, 3000)
+        d, U = W.riemann_1d(prm["nx"], prm["left"], prm["right"], prm["x_split"])
+        out.append((d, U, t1))
+    for i in range(n2):
+        prm = W.random_quadrants_params(rng, 64, 192)
+        ny = prm["n"] + 64 * (i % 2)  # some non-square grids
+        d, U = W.quadrants(prm["n"], ny, prm["states"])
+        out.append((d, U, t2))
+    return out
+
+
+def _alone(d, U, tf):
+    from paper_1810_07806_amd.wcnst import Solver, WcnstError
+    s = Solver(d)
+    V = s.new_state(U)
+    try:
+        t, n = s.solve(V, t_final=tf, cfl=0.5)
+        st = dict(status=0, t=t, steps=n, bad_stage=-1, bad_cell=-1)
+    except WcnstError:
+        st = s.status()
+    out = V.cpu().numpy()
+    s.close()
+    return out, st
+
+
+def _run_pool(torch, items, steps_per_tick, join_after=None, tuning=None):
+    from paper_1810_07806_amd.wcnst import Pool
+    pool = Pool(capacity=16)
+    if tuning:
+        pool.set_tuning(*tuning)
+    bufs = {}
+    first = items if join_after is None else items[:join_after[0]]
+    later = [] if join_after is None else items[join_after[0]:]
+
+    def admit(i, d, U, tf):
+        nv = U.size
+        b = [torch.empty(nv, dtype=torch.float64, device="cuda") for _ in range(3)]
+        b[0].copy_(torch.from_numpy(np.ascontiguousarray(U).ravel()))
+        slot = pool.admit(d, b[0], b[1], b[2], tf, 0.5)
+        bufs[i] = (slot, b[0])
+
+    for i, (d, U, tf) in enumerate(first):
+        admit(i, d, U, tf)
+    ticks = 0
+    joined = join_after is None
+    while True:
+        n = pool.tick(steps_per_tick)
+        ticks += 1
+        if not joined and (ticks == join_after[1] or n == 0):
+            for j, (d, U, tf) in enumerate(later):
+                admit(len(first) + j, d, U, tf)
+            joined = True
+            continue
+        if n == 0:
+            break
+        assert ticks < 10000
+    res = {}
+    for i, (slot, U) in bufs.items():
+        r = pool.result(slot)
+        assert r["finished"]
+        res[i] = (U.cpu().numpy().reshape(items[i][1].shape), r)
+    pool.close()
+    return res
+
+
+def _compare(items, res):
+    for i, (d, U, tf) in enumerate(items):
+        ref, st = _alone(d, U, tf)
+        got, r = res[i]
+        assert r["status"] == st["status"], (i, r, st)
+        if st["status"] == 0:
+            assert r["steps"] == st["steps"] and r["t"] == st["t"], (i, r, st)
+            assert np.array_equal(got, ref), f"request {i} (ndim {d['ndim']}) differs from the single solve"
+        else:
+            assert (r["bad_stage"], r["bad_cell"]) == (st["bad_stage"], st["bad_cell"])
+
+
+@pytest.mark.parametrize("steps_per_tick", [1, 7, 1000])
+def test_pool_mix_equals_alone(torch, steps_per_tick):
+    items = _mix(1)
+    _say(f"pool mix, {steps_per_tick} steps per tick")
+    _compare(items, _run_pool(torch, items, steps_per_tick))
+
+
+def test_pool_join_midway_and_tuning(torch):
+    items = _mix(2, n1=6, n2=3)
+    _say("pool join after 3 ticks")
+    _compare(items, _run_pool(torch, items, 5, join_after=(4, 3)))
+    _say("pool with split 0.05, 1 wave/group, 17 rows/segment")
+    _compare(items, _run_pool(torch, items, 9, tuning=(0.05, 1, 17)))
+
+
+def test_pool_fault_stays_local(torch):
+    items = _mix(3, n1=4, n2=2)
+    d, U, tf = items[1]
+    U = U.copy()
+    U[2, 0, 40] = -1.0  # negative energy: non-physical from the start
+    items[1] = (d, U, tf)
+    d, U, tf = items[5]
+    U = U.copy()
+    U[0, 10, 10] = -0.5
+    items[5] = (d, U, tf)
+    _say("pool with two failing requests")
+    res = _run_pool(torch, items, 6)
+    assert res[1][1]["status"] == 2 and res[5][1]["status"] == 2
+    _compare(items, res)
+
+
+def test_server_results_equal_per_solve(torch):
+    from paper_1810_07806_amd.serve import Server, per_solve_service
+    tr = W.serving_trace(count=10, seed=4, rate=1e9, n1_min=64, n1_max=1500, side_min=64, side_max=192,
+                         t_1d=0.02, t_2d=0.01)
+    _say("server run of 10 requests")
+    srv = Server(budget_bytes=64 << 20, capacity=4, tick_ms=2.0)
+    keep = {r["rid"] for r in tr}
+    done = srv.run(tr, realtime=False, keep=keep)
+    srv.close()
+    assert sorted(c["rid"] for c in done) == list(range(10))
+    ps = {c["rid"]: c for c in per_solve_service(tr, keep=keep)}
+    for c in done:
+        p = ps[c["rid"]]
+        assert c["status"] == p["status"] == 0 and c["steps"] == p["steps"]
+        assert np.array_equal(c["U"].ravel(), p["U"].ravel())
