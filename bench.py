@@ -13,6 +13,14 @@ vector peak with the algorithmic flop count per stage-cell-update (see
 `flops_per_stage_cell`); `cpu_baseline` times the CPU oracle on one full
 SSP-RK3 step of the same grid on the host cores.
 
+`--workload serve`: a Poisson stream of mixed requests (70 % 1D tubes with
+N in [512, 16384] to t = 0.15, 30 % 2D random four-quadrant problems of
+side 256-1024 to t = 0.1) served with continuous batching from an HBM
+arena; the arrival rate is `--load` x the capacity measured with all
+requests queued at once.  Reports p50/p99 time-to-solution and throughput,
+beside the plain path (one wcnst_solve per request, FIFO) on the same
+arrival times.
+
 `--workload tubes`: 4096 independent 1D Euler shock tubes of uneven length
 (N log-uniform in [256, 8192], random left/right states, t = 0.15, Roe,
 characteristic TENO, MND) advanced to their final times by the batched
@@ -234,10 +242,89 @@ def bench_tubes(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_serve(args):
+    import numpy as np
+    import torch
+
+    from paper_1810_07806_amd import workloads as W
+    from paper_1810_07806_amd.serve import Server, fifo_latencies, per_solve_service, percentiles
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.75 * free) if args.budget_gb <= 0 else int(args.budget_gb * 2**30)
+    budget = min(budget, int(0.75 * free))
+    count, seed = args.count, args.seed
+    unit = W.serving_trace(count=count, seed=seed, rate=1.0)  # arrivals in units of 1 / rate
+
+    def work(done):
+        return sum(3.0 * c["steps"] * c["cells"] for c in done)
+
+    # warm-up: the first few requests, all at once
+    srv = Server(budget_bytes=budget, capacity=args.capacity, tick_ms=args.tick_ms)
+    srv.run(unit[:min(4, count)], realtime=False)
+    # capacity: everything queued at t = 0
+    log(f"serve: {count} requests, arena {budget / 2**30:.1f} GiB")
+    t0 = time.perf_counter()
+    done_cap = srv.run(unit, realtime=False)
+    cap_s = time.perf_counter() - t0
+    capacity = count / cap_s
+    log(f"capacity run: {cap_s:.2f} s, {capacity:.2f} requests/s, {srv.ticks} ticks")
+    # served run at load x capacity
+    rate = args.load * capacity
+    trace = [dict(r, arrival=r["arrival"] / rate) for r in unit]
+    rng = np.random.default_rng(seed + 7)
+    keep = set(int(i) for i in rng.choice(count, size=min(6, count), replace=False))
+    t0 = time.perf_counter()
+    done = srv.run(trace, realtime=True, keep=keep)
+    served_s = time.perf_counter() - t0
+    ticks = srv.ticks
+    srv.close()
+    lat = percentiles([c["latency"] for c in done])
+    failed = sum(1 for c in done if c["status"] != 0)
+    log(f"served run: {served_s:.2f} s, p50 {lat['p50']:.3f} s, p99 {lat['p99']:.3f} s")
+    # plain path: each request alone, one after the other (FIFO on the same arrivals)
+    ps = per_solve_service(trace, keep=keep)
+    ps_lat = percentiles(fifo_latencies([r["arrival"] for r in trace], [c["service"] for c in ps]))
+    ps_busy = sum(c["service"] for c in ps)
+    log(f"per-solve: {ps_busy:.2f} s of service, p50 {ps_lat['p50']:.3f} s, p99 {ps_lat['p99']:.3f} s")
+    byid = {c["rid"]: c for c in done}
+    same = all(np.array_equal(byid[c["rid"]]["U"].ravel(), c["U"].ravel()) for c in ps if c["rid"] in keep)
+    w = work(done)
+    rec = {
+        "metric": "RK-stage cell-updates/s",
+        "value": w / served_s,
+        "unit": "stage-cell-updates/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": served_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Poisson stream of random shock tubes and four-quadrant problems)",
+        "config": {"workload": f"served mixed requests: {count} (70 % 1D tubes N 512-16384 to t 0.15, 30 % 2D "
+                               f"four-quadrant 256^2-1024^2 to t 0.1), Poisson arrivals at {args.load} x capacity "
+                               f"({rate:.2f}/s), WCNS-T TENO, Roe, MND, SSP-RK3 CFL 0.5, seed {seed}",
+                   "requests": count, "failed": failed, "arena_GiB": budget / 2**30, "ticks": ticks,
+                   "tick_ms_target": args.tick_ms, "capacity_req_s": capacity, "rate_req_s": rate},
+        "latency_s": {"p50": lat["p50"], "p99": lat["p99"], "mean": lat["mean"], "max": lat["max"]},
+        "throughput_req_s": count / served_s,
+        "per_solve": {"latency_s": {"p50": ps_lat["p50"], "p99": ps_lat["p99"]},
+                      "capacity_req_s": count / ps_busy, "service_s": ps_busy,
+                      "stage_cell_updates_per_s": w / ps_busy},
+        "sampled_results_bitwise_equal": bool(same),
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("quadrant2d", "tubes"), default="quadrant2d")
+    ap.add_argument("--workload", choices=("quadrant2d", "tubes", "serve"), default="quadrant2d")
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 200; tubes: 1 batch solve)")
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--n", type=int, default=N_SIDE, help="grid side (default: the 2048^2 workload)")
@@ -250,11 +337,18 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="tubes: JSON autotune cache")
     ap.add_argument("--per-solve", type=int, default=32, help="tubes: instances timed on the per-solve path")
     ap.add_argument("--cpu-steps", type=int, default=200, help="tubes: oracle steps per sampled tube")
+    ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / measured capacity")
+    ap.add_argument("--tick-ms", type=float, default=25.0, help="serve: target tick duration")
+    ap.add_argument("--capacity", type=int, default=256, help="serve: pool slots")
+    ap.add_argument("--budget-gb", type=float, default=0.0, help="serve: arena GiB (0: 75 %% of free)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serve":
+        args.count = 80 if args.count == 4096 else args.count
+        return bench_serve(args)
     if args.workload == "tubes":
         args.steps = 1 if args.steps is None else args.steps
         args.warmup = 1 if args.warmup is None else args.warmup
