@@ -46,6 +46,33 @@ PEAK_HBM_GBS = 8000.0
 N_SIDE = 2048
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "paper_1810_07806_amd", "traffic.json")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the sources of the stage kernels (counter figures taken on
+    another build of them are not reported)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("wcnst_kernels.hip", "wcnst_device.hpp"):
+        with open(os.path.join(ROOT, "paper_1810_07806_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the dominant kernel from FETCH_SIZE and
+    WRITE_SIZE counter runs, scaled by the same counters on a plain copy of
+    known size; None when the record was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        rec = json.load(f).get(workload)
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def flops_per_stage_cell() -> dict:
     """Algorithmic flops of one stage-cell-update of 2D Euler WCNS-T (Roe,
     TENO, characteristic-wise, MND), counting +, -, *, /, sqrt as written in
@@ -321,10 +348,36 @@ def bench_serve(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_copy(args):
+    """Plain device copy of a known size: the reference for scaling the
+    FETCH_SIZE / WRITE_SIZE counters to HBM bytes."""
+    import torch
+    torch.cuda.set_device(0)
+    n = (args.copy_mib << 20) // 8
+    src = torch.rand(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(max(1, args.warmup)):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    nbytes = 2 * 8 * n
+    print(json.dumps({"metric": "copy GB/s", "value": nbytes / ms / 1e6, "unit": "GB/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+                      "dtype": "f64", "config": {"workload": f"device copy of {args.copy_mib} MiB",
+                                                 "bytes_read_per_launch": 8 * n, "bytes_written_per_launch": 8 * n}}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("quadrant2d", "tubes", "serve"), default="quadrant2d")
+    ap.add_argument("--workload", choices=("quadrant2d", "tubes", "serve", "copy"), default="quadrant2d")
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 200; tubes: 1 batch solve)")
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--n", type=int, default=N_SIDE, help="grid side (default: the 2048^2 workload)")
@@ -341,11 +394,16 @@ def main():
     ap.add_argument("--tick-ms", type=float, default=25.0, help="serve: target tick duration")
     ap.add_argument("--capacity", type=int, default=256, help="serve: pool slots")
     ap.add_argument("--budget-gb", type=float, default=0.0, help="serve: arena GiB (0: 75 %% of free)")
+    ap.add_argument("--copy-mib", type=int, default=1024, help="copy: bytes copied per launch (MiB)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "copy":
+        args.steps = 20 if args.steps is None else args.steps
+        args.warmup = 2 if args.warmup is None else args.warmup
+        return bench_copy(args)
     if args.workload == "serve":
         args.count = 80 if args.count == 4096 else args.count
         return bench_serve(args)
@@ -408,8 +466,10 @@ def main():
                    "nx": args.n, "ny": args.n, "t_reached": t_end, "kernel_ms_avg": avg_launch_s * 1e3,
                    "stage_launches": launches, "rows_per_segment": args.rows or None},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": measured_traffic(f"quadrant2d_{args.n}") if not args.rows else None,
                      "flops_per_unit": fl["per_stage_cell"],
+                     "bytes_per_launch_algorithmic": bytes_per_stage_cell() * cells,
                      "hbm_GBs_algorithmic": bytes_per_stage_cell() * cells / avg_launch_s / 1e9},
     }
     if not args.no_cpu_baseline and args.n == N_SIDE:
