@@ -24,7 +24,7 @@ arrival times.
 `--workload tubes`: 4096 independent 1D Euler shock tubes of uneven length
 (N log-uniform in [256, 8192], random left/right states, t = 0.15, Roe,
 characteristic TENO, MND) advanced to their final times by the batched
-persistent solver in one graph-captured launch.  One benchmark step = the
+solver (graph-captured ticks of multi-instance stage launches).  One benchmark step = the
 whole batch solved once.  Also times the plain one-solve-per-instance path
 on a seeded subset of the same tubes and the CPU oracle on a bounded sample.
 """
@@ -189,13 +189,13 @@ def bench_tubes(args):
     U0 = b.pack([U for _, U in items])
     Ug = torch.empty_like(U0)
     log(f"tubes: {count} instances, {int(sum(d['nx'] for d in descs))} cells")
-    if args.split is not None:
-        b.set_tuning(args.split, 0, args.wpg)
-        tune = dict(split=args.split, waves_per_group=args.wpg, cached=False, table=[])
+    if args.steps_per_tick:
+        b.set_tuning(args.steps_per_tick)
+        tune = dict(steps_per_tick=args.steps_per_tick, cached=False, table=[])
     else:
         tune = autotune.tune_batch(b, U0, t_final, cfl=0.5, cache=args.tune_cache,
                                    device_name=torch.cuda.get_device_name(0), log=log)
-    log(f"tuning: split={tune['split']} waves/group={tune['waves_per_group']}")
+    log(f"tuning: steps/tick={tune['steps_per_tick']}")
     for _ in range(args.warmup):
         Ug.copy_(U0)
         b.solve(Ug, t_final * 0.05, cfl=0.5)
@@ -210,6 +210,7 @@ def bench_tubes(args):
         torch.cuda.synchronize()
         wall += time.perf_counter() - t0
         kernel_ms.append(b.kernel_ms())
+        stats = b.stats()
         units += float(np.sum(3.0 * res["steps"] * np.array([d["nx"] for d in descs])))
         log(f"batch solve {k}: {kernel_ms[-1]:.1f} ms kernel")
     failed = int(np.count_nonzero(res["status"]))
@@ -255,8 +256,9 @@ def bench_tubes(args):
                                f"t = {t_final}, WCNS-T TENO C_T=1e-5, Roe, MND, SSP-RK3 CFL 0.5, seed {seed}",
                    "instances": count, "cells": int(sum(d["nx"] for d in descs)),
                    "stage_cell_updates_per_solve": units_per_solve, "failed_instances": failed,
-                   "kernel_ms_avg": avg_kernel_s * 1e3, "split": tune["split"],
-                   "waves_per_group": tune["waves_per_group"], "tuning_cached": tune.get("cached", False)},
+                   "kernel_ms_avg": avg_kernel_s * 1e3, "steps_per_tick": tune["steps_per_tick"],
+                   "tuning_cached": tune.get("cached", False), "ticks": stats["ticks"],
+                   "graphs_captured": stats["graphs"]},
         "per_solve": {"value": ps_units / ps_wall, "unit": "stage-cell-updates/s", "instances": int(len(sub)),
                       "wall_s": ps_wall, "speedup_batched": (units / wall) / (ps_units / ps_wall)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
@@ -385,8 +387,7 @@ def main():
     ap.add_argument("--rows", type=int, default=0, help="rows per 2D segment (0: library default)")
     ap.add_argument("--count", type=int, default=4096, help="tubes: instances")
     ap.add_argument("--seed", type=int, default=0, help="tubes: generator seed")
-    ap.add_argument("--split", type=float, default=None, help="tubes: fixed split (default: autotune)")
-    ap.add_argument("--wpg", type=int, default=4, help="tubes: waves per workgroup with --split")
+    ap.add_argument("--steps-per-tick", type=int, default=0, help="tubes: fixed tick length (default: autotune)")
     ap.add_argument("--tune-cache", default=None, help="tubes: JSON autotune cache")
     ap.add_argument("--per-solve", type=int, default=32, help="tubes: instances timed on the per-solve path")
     ap.add_argument("--cpu-steps", type=int, default=200, help="tubes: oracle steps per sampled tube")

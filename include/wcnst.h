@@ -151,12 +151,16 @@ wcnst_status wcnst_profile_read(wcnst_solver* s, double* stage_ms, int64_t* stag
 wcnst_status wcnst_destroy(wcnst_solver* s);
 
 /* ---------------------------------------------------------------- batches
- * Many independent 1D Euler problems advanced in one persistent launch
- * (captured once into a HIP graph and replayed).  Every instance follows
- * exactly the arithmetic of wcnst_solve (Sec. 2-3 as above), so it gives the
- * same bits batched as alone.  All descriptors must be 1D Euler with the
- * same scheme parameters (flux, scheme, charwise, q, gamma, C_T, C, eps);
- * nx, the domain and the boundary conditions may differ.
+ * Many independent 1D Euler problems of uneven length advanced together in
+ * ticks: a tick is a chunk of SSP-RK3 steps, each stage one launch covering
+ * the strips of every instance still running (own control block, dt and
+ * step parity per instance), captured in a HIP graph and replayed while the
+ * set of running instances is unchanged; between ticks finished instances
+ * drop out of the launch table.  Every instance follows exactly the
+ * arithmetic of wcnst_solve (Sec. 2-3 as above), so it gives the same bits
+ * batched as alone.  All descriptors must be 1D Euler with the same scheme
+ * parameters (flux, scheme, charwise, q, gamma, C_T, C, eps); nx, the domain
+ * and the boundary conditions may differ.
  *
  * States live in one packed device buffer of FP64: instance i occupies
  * offsets[i] .. offsets[i] + 3*nx_i - 1 with layout [v][nx_i]
@@ -164,8 +168,8 @@ wcnst_status wcnst_destroy(wcnst_solver* s);
 typedef struct wcnst_batch wcnst_batch;
 typedef struct wcnst_pool wcnst_pool;
 
-/* Device workspace bytes for a batch of n descriptors (instance table, job
- * slots, two packed stage buffers). */
+/* Device workspace bytes for a batch of n descriptors (launch table,
+ * control blocks, two packed stage buffers). */
 wcnst_status wcnst_batch_workspace_size(const wcnst_desc* descs, int32_t n, size_t* bytes);
 
 /* Validate and create a batch bound to hip_stream and to a caller-owned
@@ -190,20 +194,16 @@ wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const double* t_final,
  * cell of the first non-physical value, or -1 (host arrays of n). */
 wcnst_status wcnst_batch_bad_cells(const wcnst_batch* b, int64_t* bad_stage, int64_t* bad_cell);
 
-/* Work decomposition (never changes results).  Estimated cost of an
- * instance = nx x estimated steps (from the CFL speed of its initial
- * state).  An instance is split over k = ceil(cost / (split x total cost /
- * wavefronts)) cooperating wavefronts, at most 64, its strip count and the
- * resident wavefront count; split = 0 keeps one wavefront per instance
- * (default 1).  waves_per_group in {1, 2, 4} sets the workgroup size
- * (0 keeps the current, default 4).  workgroups > 0 fixes the persistent
- * grid; 0 sizes it to the workgroups resident at once.  WCNST_E_INVALID_ARG
- * for other values. */
-wcnst_status wcnst_batch_set_tuning(wcnst_batch* b, double split, int32_t workgroups, int32_t waves_per_group);
+/* Steps per tick (even, in [2, 4096], default 64): how often finished
+ * instances leave the launch table.  Never changes results. */
+wcnst_status wcnst_batch_set_tuning(wcnst_batch* b, int32_t steps_per_tick);
 
-/* Device time in milliseconds of the persistent launch of the last
- * wcnst_batch_solve (HIP events on the batch's stream). */
+/* Device time in milliseconds of the last wcnst_batch_solve, from its first
+ * launch to the end of its last tick (HIP events on the batch's stream). */
 wcnst_status wcnst_batch_kernel_ms(const wcnst_batch* b, double* ms);
+
+/* Ticks of the last wcnst_batch_solve and graphs captured for them. */
+wcnst_status wcnst_batch_stats(const wcnst_batch* b, int32_t* ticks, int32_t* graphs);
 
 wcnst_status wcnst_batch_destroy(wcnst_batch* b);
 
@@ -213,7 +213,10 @@ wcnst_status wcnst_batch_destroy(wcnst_batch* b);
  * that requests join and leave between ticks (continuous batching).  Each
  * request follows exactly the arithmetic of wcnst_solve (Sec. 2-3, SSP-RK3
  * with the CFL rule and final-step clipping), so its result is the same
- * bits alone or in any mix.  The library allocates no device memory: the
+ * bits alone or in any mix.  A tick issues, per dimension, one stage
+ * launch per Runge-Kutta stage covering all active grids of that dimension
+ * (each with its own control block and dt); no wave waits for another.
+ * The library allocates no device memory: the
  * pool's tables live in a caller workspace and every request brings its own
  * three state buffers.
  *
@@ -250,10 +253,9 @@ wcnst_status wcnst_pool_result(const wcnst_pool* p, int32_t slot, int32_t* finis
 /* Free the slot (the request's buffers return to the caller). */
 wcnst_status wcnst_pool_release(wcnst_pool* p, int32_t slot);
 
-/* Work decomposition of 1D passes (as wcnst_batch_set_tuning: split,
- * waves_per_group, 0 keeps) and rows per 2D segment (0 keeps, default 35);
+/* Rows per 2D segment of the pool's stage launches (0 keeps, default 35);
  * never changes results. */
-wcnst_status wcnst_pool_set_tuning(wcnst_pool* p, double split, int32_t waves_per_group, int32_t rows_per_segment);
+wcnst_status wcnst_pool_set_tuning(wcnst_pool* p, int32_t rows_per_segment);
 
 wcnst_status wcnst_pool_destroy(wcnst_pool* p);
 

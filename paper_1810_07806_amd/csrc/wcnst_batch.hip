@@ -1,22 +1,15 @@
-// Batched solve of many independent 1D Euler problems in one persistent,
-// graph-captured launch.
+// Batched solve of many independent 1D Euler problems.
 //
 // Each instance is advanced with exactly the arithmetic of the single-solve
-// path (the same device functions, the same CFL rule and stopping rule), so
-// an instance gives the same bits batched as alone.  Work decomposition:
-//   * the worker is a 64-lane wavefront; waves of a workgroup are
-//     independent (each has its own LDS exchange area);
-//   * an instance is split into k contiguous parts of whole 61-cell strips
-//     (k = 1 for most instances; large instances get more waves so the
-//     largest one does not set the makespan);
-//   * the host plans the jobs from a per-instance speed pre-pass (cost ~
-//     cells x steps), orders them longest-part-first, and lays out one slot
-//     per part; waves take slots from a device counter in order, so the
-//     parts of a job are taken consecutively and a job never waits for a
-//     slot that no free wave can take;
-//   * the parts of a job meet at an agent-scope counter barrier after each
-//     stage; every wait is bounded (timeout -> sticky error, all waves
-//     leave), so the grid always drains.
+// path (the same stage kernel body, CFL rule and stopping rule), so it gives
+// the same bits batched as alone.  The batch advances in ticks: one tick is
+// `steps` SSP-RK3 steps, i.e. 3 x steps stage launches, each covering the
+// strips of every instance still running (one ReqGrid row, control block,
+// dt and step parity per instance); the launches of a tick are captured in a
+// HIP graph and replayed while the set of running instances is unchanged.
+// Between ticks the host reads the control blocks back, drops the instances
+// that reached t_final or failed, and compacts the table.  Kernel boundaries
+// order the stages: no wave ever waits for another.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -25,463 +18,54 @@
 
 #include <algorithm>
 #include <cmath>
-#include <numeric>
 #include <vector>
 
 #include "wcnst.h"
 #include "wcnst_device.hpp"
-#include "wcnst_batch.hpp"
 #include "wcnst_host.hpp"
-
-namespace wcnstb {
 
 using namespace wcnst;
 
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long m)
-{
-#pragma unroll
-    for (int off = WAVE / 2; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(m, off);
-        m = o > m ? o : m;
-    }
-    return m;
-}
+namespace {
 
-__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long m)
-{
-#pragma unroll
-    for (int off = WAVE / 2; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(m, off);
-        m = o < m ? o : m;
-    }
-    return m;
-}
+constexpr int TX = 61;  // cells per strip
+constexpr int NV = 3;
 
-__device__ __forceinline__ void wave_sync_lds()
-{
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-// Barrier of the k parts of one instance.  The last arriving part clears
-// the speed slot that the next step will accumulate into.
-__device__ bool part_sync(BInst* I, int k, unsigned& gen, BHead* hd, int clear_slot)
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    int ok = 1;
-    if ((threadIdx.x & (WAVE - 1)) == 0) {
-        const unsigned old = __hip_atomic_fetch_add(&I->arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == (unsigned)k - 1) {
-            __hip_atomic_store(&I->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (clear_slot >= 0)
-                __hip_atomic_store(&I->smax_bits[clear_slot], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&I->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            const long long t0 = (long long)wall_clock64();
-            while (__hip_atomic_load(&I->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                if ((long long)wall_clock64() - t0 >
-                        __hip_atomic_load(&hd->wait_ticks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) ||
-                    __hip_atomic_load(&hd->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    __hip_atomic_fetch_or(&hd->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-    }
-    gen += 1u;
-    ok = __shfl(ok, 0);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return ok != 0;
-}
-
-// One stage over the strips [s0, s1) of one instance: midpoint fluxes,
-// MND difference, Runge-Kutta combine; stage 2 also returns the CFL speed.
-template <int FLUX, int SCHEME, bool CHAR>
-__device__ bool part_stage(const Params& P, int n, int s0, int s1, int stage, double dt, long long step,
-                           const double* __restrict__ in, const double* __restrict__ Un, double* __restrict__ out,
-                           double (*sF)[WAVE], double (*sN)[WAVE], unsigned long long& bad_key,
-                           unsigned long long& smax)
-{
-    const int lane = threadIdx.x & (WAVE - 1);
-    bool bad = false;
-    for (int s = s0; s < s1; ++s) {
-        const int x0 = s * TX;
-        const int c = x0 + lane;
-        const bool cell_ok = lane < TX && c < n;
-        const int jx = x0 - 2 + lane;
-        double st[6][NV];
-#pragma unroll
-        for (int m = 0; m < 6; ++m) {
-            const int col = ghost_map_any(jx - 2 + m, n, P.bc_x);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) st[m][v] = in[(size_t)v * n + col];
-        }
-        double F[NV], fn[NV];
-        unsigned fb;
-        RegStencil<NV> rs{st};
-        face_flux<SYS_EULER, NV, FLUX, SCHEME, CHAR>(rs, P, F, fb);
-        node_flux<SYS_EULER, NV>(st[3], P, fn);
-        wave_sync_lds();
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            sF[v][lane] = F[v];
-            sN[v][lane] = fn[v];
-        }
-        wave_sync_lds();
-        if (cell_ok) {
-            double R[NV], un[NV], o[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                R[v] = mnd(P.c1x, P.c2x, P.c3x, sF[v][lane], sF[v][lane + 1], sF[v][lane + 2], sF[v][lane + 3],
-                           sN[v][lane], sN[v][lane + 2]);
-                un[v] = stage ? Un[(size_t)v * n + c] : 0.0;
-            }
-            rk_combine<NV>(stage, dt, st[4], un, R, o);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) out[(size_t)v * n + c] = o[v];
-            if (cell_bad<SYS_EULER, NV>(o, P)) {
-                const unsigned long long key = ((unsigned long long)(step * 3 + stage) << 36) | (unsigned long long)c;
-                bad_key = key < bad_key ? key : bad_key;
-                bad = true;
-            }
-            if (stage == 2) {
-                const unsigned long long b =
-                    (unsigned long long)__double_as_longlong(cell_speed<SYS_EULER, NV>(o, P));
-                smax = b > smax ? b : smax;
-            }
-        }
-    }
-    return __any(bad);
-}
-
-template <int FLUX, int SCHEME, bool CHAR>
-__device__ void run_part(BInst* I, int part, const Params& Pc, BHead* hd, double (*sF)[WAVE], double (*sN)[WAVE])
-{
-    const int lane = threadIdx.x & (WAVE - 1);
-    // Every part of the instance takes its control flow (k, t, steps, the
-    // step bound) from the same host-written values.
-    const BInstIn R = load_host_written(reinterpret_cast<const BInstIn*>(I));
-    const int n = R.n, k = R.k;
-    const int S = (n + TX - 1) / TX;
-    const int s0 = (int)((long long)part * S / k), s1 = (int)((long long)(part + 1) * S / k);
-    Params P = Pc;
-    P.nx = n;
-    P.dx = R.dx;
-    P.c1x = R.c1;
-    P.c2x = R.c2;
-    P.c3x = R.c3;
-    P.bc_x = R.bc;
-    double* U = R.u;
-    double* U1 = R.u1;
-    double* U2 = R.u2;
-    const double t_final = R.t_final, cfl = R.cfl;
-    const long long step_end = R.step_end;
-    const bool fin = isfinite(t_final);
-
-    // CFL speed of the state at the start of the launch (the same bits as
-    // the speed the previous step reduced from the same cells)
-    unsigned gen = 0;
-    unsigned long long sm = 0ull;
-    for (int s = s0; s < s1; ++s) {
-        const int c = s * TX + lane;
-        if (lane < TX && c < n) {
-            double u[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) u[v] = U[(size_t)v * n + c];
-            const unsigned long long b = (unsigned long long)__double_as_longlong(cell_speed<SYS_EULER, NV>(u, P));
-            sm = b > sm ? b : sm;
-        }
-    }
-    sm = wave_max_u64(sm);
-    if (k > 1) {
-        // Slot s & 1 of step s: every part reads it before stage 0 and the
-        // stage-2 barrier of step s clears it, after all parts arrived.
-        const int sl = (int)(R.steps & 1);
-        if (lane == 0) __hip_atomic_fetch_max(&I->smax_bits[sl], sm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (!part_sync(I, k, gen, hd, -1)) return;
-        sm = __hip_atomic_load(&I->smax_bits[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-
-    double t = R.t;
-    long long step = R.steps;
-    unsigned long long bad_key = ~0ull;
-    bool bad = false;
-    while (step < step_end) {
-        if (fin && t_final - t <= 1e-12 * t_final) break;
-        double dt = cfl / __longlong_as_double((long long)sm);
-        if (fin && dt > t_final - t) dt = t_final - t;
-        unsigned long long snext = 0ull;
-        const double* in[3] = {U, U1, U2};
-        double* outp[3] = {U1, U2, U};
-        for (int stage = 0; stage < 3; ++stage) {
-            bad |= part_stage<FLUX, SCHEME, CHAR>(P, n, s0, s1, stage, dt, step, in[stage], U, outp[stage], sF, sN,
-                                                   bad_key, snext);
-            if (k == 1) {
-                // this wave's stores are read by other lanes of the wave next
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-            } else {
-                // wave-wide reductions first (all lanes), then one lane publishes
-                const unsigned long long mx = stage == 2 ? wave_max_u64(snext) : 0ull;
-                const unsigned long long bk = bad ? wave_min_u64(bad_key) : ~0ull;
-                if (stage == 2 && lane == 0)
-                    __hip_atomic_fetch_max(&I->smax_bits[(step + 1) & 1], mx, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                if (bad && lane == 0) {
-                    __hip_atomic_fetch_min(&I->bad_key, bk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_fetch_or(&I->status, (int)WCNST_E_NONPHYSICAL, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-                }
-                if (!part_sync(I, k, gen, hd, stage == 2 ? (int)(step & 1) : -1)) return;
-                bad = __hip_atomic_load(&I->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-            }
-            if (bad) break;
-        }
-        if (bad) break;
-        if (k == 1) sm = wave_max_u64(snext);
-        else sm = __hip_atomic_load(&I->smax_bits[(step + 1) & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        t = t + dt;
-        step += 1;
-    }
-    if (k == 1 && bad) {
-        bad_key = wave_min_u64(bad_key);
-        if (lane == 0) {
-            __hip_atomic_store(&I->bad_key, bad_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            __hip_atomic_store(&I->status, (int)WCNST_E_NONPHYSICAL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
-    }
-    if (part == 0 && lane == 0) {
-        __hip_atomic_store(&I->t, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(&I->steps, step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-}
-
-template <int FLUX, int SCHEME, bool CHAR>
-__global__ void __launch_bounds__(256) batch_kernel(BInst* __restrict__ insts, const BSlot* __restrict__ slots,
-                                                    BHead* hd, Params Pc)
-{
-    init_weight_table();
-    __shared__ double sFall[256 / WAVE][NV][WAVE];
-    __shared__ double sNall[256 / WAVE][NV][WAVE];
-    const int w = threadIdx.x / WAVE;
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int nslots = __hip_atomic_load(&hd->nslots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    for (;;) {
-        int slot = 0;
-        if (lane == 0) slot = (int)atomicAdd(&hd->head, 1u);
-        slot = __shfl(slot, 0);
-        if (slot >= nslots) break;
-        if (__hip_atomic_load(&hd->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-        const BSlot sl = load_host_written(&slots[slot]);
-        run_part<FLUX, SCHEME, CHAR>(&insts[sl.inst], sl.part, Pc, hd, sFall[w], sNall[w]);
-    }
-}
-
-// Initial CFL speed of each instance (one workgroup per instance), for planning.
-__global__ void __launch_bounds__(256) batch_speed(const BInst* __restrict__ insts, Params Pc, double* speed)
-{
-    const BInstIn I = load_host_written(reinterpret_cast<const BInstIn*>(&insts[blockIdx.x]));
-    Params P = Pc;
-    P.nx = I.n;
-    P.dx = I.dx;
-    const double* U = I.u;
-    unsigned long long m = 0ull;
-    for (int c = threadIdx.x; c < I.n; c += blockDim.x) {
-        double u[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) u[v] = U[(size_t)v * I.n + c];
-        const unsigned long long b = (unsigned long long)__double_as_longlong(cell_speed<SYS_EULER, NV>(u, P));
-        m = b > m ? b : m;
-    }
-    m = wave_max_u64(m);
-    __shared__ unsigned long long red[256 / WAVE];
-    if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 1; i < (int)(blockDim.x / WAVE); ++i) m = red[i] > m ? red[i] : m;
-        m = red[0] > m ? red[0] : m;
-        speed[blockIdx.x] = __longlong_as_double((long long)m);
-    }
-}
-
-// Resets the queue of a launch (the plan fields are written by the host
-// before each launch, so the captured graph stays valid across plans).
-__global__ void batch_open(BHead* hd)
-{
-    if (threadIdx.x == 0) {
-        hd->head = 0u;
-        hd->err = 0;
-    }
-}
-
-}  // namespace wcnstb
-
-// ====================================================================== host
-
-namespace wcnstb {
-
-void inst_init(BInst& r, const wcnst_desc& d, double* u, double* u1, double* u2, double t_final, double cfl)
-{
-    r = BInst{};
-    r.u = u;
-    r.u1 = u1;
-    r.u2 = u2;
-    r.n = d.nx;
-    r.bc = d.bc_x;
-    r.k = 1;
-    r.dx = (d.x1 - d.x0) / d.nx;
-    // the same expressions as the single-solve path (Eq. (5) over h)
-    r.c1 = (3.0 / 2.0) / r.dx;
-    r.c2 = (-3.0 / 10.0) / r.dx;
-    r.c3 = (1.0 / 30.0) / r.dx;
-    r.t_final = t_final;
-    r.cfl = cfl;
-    r.t = 0.0;
-    r.steps = 0;
-    r.bad_key = ~0ull;
-    r.status = 0;
-}
-
-void inst_arm(BInst& r, long long step_end)
-{
-    r.step_end = step_end;
-    r.arrive = 0;
-    r.gen = 0;
-    r.smax_bits[0] = r.smax_bits[1] = 0ull;
-}
-
-void scheme_params(const wcnst_desc& d, Params* out)
-{
-    Params P{};
-    P.CT = d.CT;
-    P.C = d.C;
-    P.eps_teno = d.eps_teno;
-    P.eps_js = d.eps_js;
-    P.gamma = d.gamma;
-    P.adv = d.adv_speed;
-    P.q = d.q;
-    P.charwise = d.charwise ? 1 : 0;
-    P.ny = 1;
-    P.dy = 1.0;
-    *out = P;
-}
-
-template <int FLUX, int SCHEME, bool CHAR>
-static const void* pick3() { return (const void*)&batch_kernel<FLUX, SCHEME, CHAR>; }
-
-template <int FLUX, bool CHAR>
-static const void* pick2(const wcnst_desc& d)
-{
-    switch (d.scheme) {
-    case WCNST_LINEAR: return pick3<FLUX, SCH_LINEAR, CHAR>();
-    case WCNST_JS: return pick3<FLUX, SCH_JS, CHAR>();
-    default: return d.q == 6 ? pick3<FLUX, SCH_TENO, CHAR>() : pick3<FLUX, SCH_TENO_Q, CHAR>();
-    }
-}
-
-static const void* pick_kernel(const wcnst_desc& d)
-{
-    if (d.flux == WCNST_LF) return d.charwise ? pick2<FLUX_LF, true>(d) : pick2<FLUX_LF, false>(d);
-    return d.charwise ? pick2<FLUX_ROE, true>(d) : pick2<FLUX_ROE, false>(d);
-}
-
-hipError_t resident_per_cu(const wcnst_desc& d, int wpg, int* per_cu)
-{
-    *per_cu = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, pick_kernel(d), WAVE * wpg, 0);
-    if (*per_cu < 1) *per_cu = 1;
-    return e;
-}
-
-int plan_parts(std::vector<BInst>& rec, const std::vector<double>& cost, double split, double workers, int running,
-               std::vector<BSlot>& slots)
-{
-    const int n = (int)rec.size();
-    double total = 0.0;
-    for (double c : cost) total += c;
-    std::vector<int> order((size_t)n);
-    for (int i = 0; i < n; ++i) {
-        const int strips = (rec[(size_t)i].n + TX - 1) / TX;
-        int k = 1;
-        if (split > 0.0 && total > 0.0)
-            k = (int)std::min(1e9, std::ceil(cost[(size_t)i] * workers / (split * total)));
-        k = std::max(1, std::min(k, std::min(std::min(KMAX, strips), std::max(1, running))));
-        rec[(size_t)i].k = k;
-        order[(size_t)i] = i;
-    }
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        return cost[(size_t)x] / rec[(size_t)x].k > cost[(size_t)y] / rec[(size_t)y].k;
-    });
-    slots.clear();
-    for (int i : order)
-        for (int p = 0; p < rec[(size_t)i].k; ++p) slots.push_back(BSlot{i, p});
-    return (int)slots.size();
-}
-
-hipError_t launch_pass(const wcnst_desc& d, BInst* insts, BSlot* slots, BHead* head, const Params& P, int grid,
-                       int wpg, hipStream_t st)
-{
-    hipLaunchKernelGGL(batch_open, dim3(1), dim3(64), 0, st, head);
-    void* args[] = {(void*)&insts, (void*)&slots, (void*)&head, (void*)&P};
-    const hipError_t e = hipLaunchKernel(pick_kernel(d), dim3(grid), dim3(WAVE * wpg), args, 0, st);
-    return e != hipSuccess ? e : hipGetLastError();
-}
-
-hipError_t wait_ticks(long long* ticks)
-{
-    int dev = 0, khz = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
-    *ticks = (long long)(WAIT_LIMIT_S * 1e3 * std::max(1, khz));
-    return e;
-}
-
-}  // namespace wcnstb
-
-using namespace wcnstb;
+}  // namespace
 
 struct wcnst_batch {
     int n = 0;
     wcnst_desc d0{};
     std::vector<wcnst_desc> descs;
-    std::vector<BInst> rec;
     std::vector<long long> offs;  // n + 1
     long long total = 0;          // doubles per packed buffer
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;  // private stream for graph capture
-    BInst* d_inst = nullptr;
-    BSlot* d_slots = nullptr;
-    BHead* d_head = nullptr;
-    double* d_speed = nullptr;
+    // device (caller's workspace)
+    ReqGrid* d_req = nullptr;
+    uint8_t* d_ctrl = nullptr;
+    size_t ctrl_bytes = 0;
     double* U1 = nullptr;
     double* U2 = nullptr;
-    Params P{};
-    double split = 1.0;
-    int grid = 0;      // persistent workgroups
-    int wpg = 4;       // wavefronts per workgroup
-    int resident = 0;  // workgroups of wpg waves resident at once
-    int cus = 0;
-    long long wait_ticks = 0;
+    // pinned host staging
+    ReqGrid* h_req = nullptr;
+    uint8_t* h_ctrl = nullptr;
+    int steps_per_tick = 64;  // even, so that a replayed tick keeps the parity pattern
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double kernel_ms = 0.0;
+    int ticks = 0, graphs = 0;
+    // per-instance outcome of the last solve
+    std::vector<unsigned long long> bad_key;
     hipGraphExec_t exec = nullptr;
-    const void* exec_key = nullptr;
-    int exec_grid = 0, exec_wpg = 0;
 };
 
-static size_t batch_layout(int n, long long total, size_t* o_inst, size_t* o_slots, size_t* o_head, size_t* o_speed,
-                           size_t* o_u1, size_t* o_u2)
+static size_t batch_layout(int n, long long total, size_t* o_req, size_t* o_ctrl, size_t* o_u1, size_t* o_u2)
 {
     size_t o = 0;
-    *o_inst = o;
-    o = wcnst_align256(o + sizeof(BInst) * (size_t)n);
-    *o_slots = o;
-    o = wcnst_align256(o + sizeof(BSlot) * (size_t)n * KMAX);
-    *o_head = o;
-    o = wcnst_align256(o + sizeof(BHead));
-    *o_speed = o;
-    o = wcnst_align256(o + sizeof(double) * (size_t)n);
+    *o_req = o;
+    o = wcnst_align256(o + sizeof(ReqGrid) * (size_t)n);
+    *o_ctrl = o;
+    o = wcnst_align256(o + wcnst_align256(wcnst_ctrl_bytes()) * (size_t)n);
     *o_u1 = o;
     o = wcnst_align256(o + sizeof(double) * (size_t)total);
     *o_u2 = o;
@@ -526,20 +110,12 @@ extern "C" wcnst_status wcnst_batch_workspace_size(const wcnst_desc* descs, int3
     wcnst_status st = batch_check(descs, n, &total, nullptr);
     if (st) return st;
     if (!bytes) return wcnst_fail(WCNST_E_INVALID_ARG, "null size pointer");
-    size_t a, b, c, d, e, f;
-    *bytes = batch_layout(n, total, &a, &b, &c, &d, &e, &f);
+    size_t a, b, c, d;
+    *bytes = batch_layout(n, total, &a, &b, &c, &d);
     return WCNST_OK;
 }
 
 extern "C" wcnst_status wcnst_batch_destroy(wcnst_batch* b);
-
-static hipError_t batch_resident(wcnst_batch* b)
-{
-    int per_cu = 0;
-    const hipError_t e = resident_per_cu(b->d0, b->wpg, &per_cu);
-    b->resident = per_cu * b->cus;
-    return e;
-}
 
 extern "C" wcnst_status wcnst_batch_create(const wcnst_desc* descs, int32_t n, void* hip_stream, void* workspace,
                                            size_t ws_bytes, wcnst_batch** out)
@@ -549,8 +125,8 @@ extern "C" wcnst_status wcnst_batch_create(const wcnst_desc* descs, int32_t n, v
     wcnst_status st = batch_check(descs, n, &total, &offs);
     if (st) return st;
     if (!out) return wcnst_fail(WCNST_E_INVALID_ARG, "null output handle");
-    size_t o_inst, o_slots, o_head, o_speed, o_u1, o_u2;
-    const size_t need = batch_layout(n, total, &o_inst, &o_slots, &o_head, &o_speed, &o_u1, &o_u2);
+    size_t o_req, o_ctrl, o_u1, o_u2;
+    const size_t need = batch_layout(n, total, &o_req, &o_ctrl, &o_u1, &o_u2);
     if (!workspace || ws_bytes < need)
         return wcnst_fail(WCNST_E_INVALID_ARG, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
     if (((uintptr_t)workspace & 255u) != 0) return wcnst_fail(WCNST_E_INVALID_ARG, "workspace not 256-byte aligned");
@@ -563,25 +139,18 @@ extern "C" wcnst_status wcnst_batch_create(const wcnst_desc* descs, int32_t n, v
     b->total = total;
     b->stream = (hipStream_t)hip_stream;
     uint8_t* ws = (uint8_t*)workspace;
-    b->d_inst = (BInst*)(ws + o_inst);
-    b->d_slots = (BSlot*)(ws + o_slots);
-    b->d_head = (BHead*)(ws + o_head);
-    b->d_speed = (double*)(ws + o_speed);
+    b->d_req = (ReqGrid*)(ws + o_req);
+    b->d_ctrl = ws + o_ctrl;
+    b->ctrl_bytes = wcnst_align256(wcnst_ctrl_bytes());
     b->U1 = (double*)(ws + o_u1);
     b->U2 = (double*)(ws + o_u2);
-    b->rec.assign((size_t)n, BInst{});
-    scheme_params(descs[0], &b->P);
+    b->bad_key.assign((size_t)n, ~0ull);
 
-    int dev = 0, cus = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = wait_ticks(&b->wait_ticks);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&b->ev0);
     if (e == hipSuccess) e = hipEventCreate(&b->ev1);
-    b->cus = std::max(1, cus);
-    if (e == hipSuccess) e = batch_resident(b);
-    b->grid = b->resident;
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_req, sizeof(ReqGrid) * (size_t)n, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_ctrl, b->ctrl_bytes * (size_t)n, hipHostMallocDefault);
     if (e != hipSuccess) {
         wcnst_batch_destroy(b);
         return wcnst_fail(WCNST_E_HIP, "batch setup failed: %s", hipGetErrorString(e));
@@ -597,19 +166,12 @@ extern "C" wcnst_status wcnst_batch_offsets(const wcnst_batch* b, int64_t* offse
     return WCNST_OK;
 }
 
-extern "C" wcnst_status wcnst_batch_set_tuning(wcnst_batch* b, double split, int32_t workgroups,
-                                               int32_t waves_per_group)
+extern "C" wcnst_status wcnst_batch_set_tuning(wcnst_batch* b, int32_t steps_per_tick)
 {
     if (!b) return wcnst_fail(WCNST_E_INVALID_ARG, "null handle");
-    if (!(split >= 0.0)) return wcnst_fail(WCNST_E_INVALID_ARG, "split must be >= 0");
-    if (workgroups < 0) return wcnst_fail(WCNST_E_INVALID_ARG, "workgroups must be >= 0");
-    if (waves_per_group != 0 && waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4)
-        return wcnst_fail(WCNST_E_INVALID_ARG, "waves_per_group must be 1, 2 or 4 (0 keeps it)");
-    b->split = split;
-    if (waves_per_group) b->wpg = waves_per_group;
-    hipError_t e = batch_resident(b);
-    if (e != hipSuccess) return wcnst_fail(WCNST_E_HIP, "occupancy query failed: %s", hipGetErrorString(e));
-    b->grid = workgroups > 0 ? workgroups : b->resident;
+    if (steps_per_tick < 2 || steps_per_tick > 4096 || (steps_per_tick & 1))
+        return wcnst_fail(WCNST_E_INVALID_ARG, "steps_per_tick must be even and in [2, 4096]");
+    b->steps_per_tick = steps_per_tick;
     return WCNST_OK;
 }
 
@@ -617,6 +179,53 @@ extern "C" wcnst_status wcnst_batch_kernel_ms(const wcnst_batch* b, double* ms)
 {
     if (!b || !ms) return wcnst_fail(WCNST_E_INVALID_ARG, "null argument");
     *ms = b->kernel_ms;
+    return WCNST_OK;
+}
+
+extern "C" wcnst_status wcnst_batch_stats(const wcnst_batch* b, int32_t* ticks, int32_t* graphs)
+{
+    if (!b) return wcnst_fail(WCNST_E_INVALID_ARG, "null handle");
+    if (ticks) *ticks = b->ticks;
+    if (graphs) *graphs = b->graphs;
+    return WCNST_OK;
+}
+
+static bool reached(double t_final, double t) { return t_final - t <= 1e-12 * t_final; }
+
+static const StepRec& newest(const Ctrl& c) { return c.rec[0].step >= c.rec[1].step ? c.rec[0] : c.rec[1]; }
+
+// One tick of `steps` steps over the table rows [0, nreq): replay the
+// captured graph when it was made for this table, else capture a new one
+// (a tick of fewer steps than steps_per_tick is launched directly).
+static wcnst_status run_tick(wcnst_batch* b, int nreq, int blocks, int steps, bool table_changed)
+{
+    if (steps != b->steps_per_tick) {
+        for (int s = 0; s < steps; ++s)
+            for (int stage = 0; stage < 3; ++stage)
+                WCNST_HIP_TRY(wcnst_launch_multi(&b->d0, 1, b->d_req, nreq, blocks, stage, s & 1, 0, b->stream));
+        return WCNST_OK;
+    }
+    if (!b->exec || table_changed) {
+        if (b->exec) {
+            (void)hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        WCNST_HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+        hipError_t le = hipSuccess;
+        for (int s = 0; s < steps && le == hipSuccess; ++s)
+            for (int stage = 0; stage < 3 && le == hipSuccess; ++stage)
+                le = wcnst_launch_multi(&b->d0, 1, b->d_req, nreq, blocks, stage, s & 1, 0, b->cap);
+        hipError_t ce = hipStreamEndCapture(b->cap, &g);
+        if (le != hipSuccess || ce != hipSuccess)
+            return wcnst_fail(WCNST_E_HIP, "graph capture failed: %s / %s", hipGetErrorString(le),
+                              hipGetErrorString(ce));
+        hipError_t ie = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) return wcnst_fail(WCNST_E_HIP, "graph instantiate failed: %s", hipGetErrorString(ie));
+        b->graphs += 1;
+    }
+    WCNST_HIP_TRY(hipGraphLaunch(b->exec, b->stream));
     return WCNST_OK;
 }
 
@@ -632,83 +241,99 @@ extern "C" wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const doubl
         if (std::isnan(t_final[i])) return wcnst_fail(WCNST_E_INVALID_ARG, "t_final[%d] is NaN", i);
         if (!std::isfinite(t_final[i]) && max_steps >= ((int64_t)1 << 40))
             return wcnst_fail(WCNST_E_INVALID_ARG, "t_final[%d] is infinite and max_steps unbounded", i);
-        BInst& r = b->rec[(size_t)i];
-        const long long o = b->offs[(size_t)i];
-        inst_init(r, b->descs[(size_t)i], U + o, b->U1 + o, b->U2 + o, t_final[i], cfl);
-        inst_arm(r, (long long)max_steps);
     }
-    // initial speeds for the plan
-    WCNST_HIP_TRY(hipMemcpyAsync(b->d_inst, b->rec.data(), sizeof(BInst) * (size_t)n, hipMemcpyHostToDevice,
-                                 b->stream));
-    hipLaunchKernelGGL(batch_speed, dim3(n), dim3(256), 0, b->stream, b->d_inst, b->P, b->d_speed);
-    WCNST_HIP_TRY(hipGetLastError());
-    std::vector<double> speed((size_t)n);
-    WCNST_HIP_TRY(hipMemcpyAsync(speed.data(), b->d_speed, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost,
-                                 b->stream));
-    WCNST_HIP_TRY(hipStreamSynchronize(b->stream));
-    std::vector<double> cost((size_t)n);
+    // rows of every instance; instance i keeps control block i
+    std::vector<ReqGrid> rows((size_t)n);
     for (int i = 0; i < n; ++i) {
-        double steps = (double)max_steps;
-        if (std::isfinite(t_final[i]) && std::isfinite(speed[(size_t)i]))
-            steps = std::min(steps, std::ceil(t_final[i] * speed[(size_t)i] / cfl) + 1.0);
-        cost[(size_t)i] = (double)b->rec[(size_t)i].n * steps;
+        const wcnst_desc& d = b->descs[(size_t)i];
+        const long long o = b->offs[(size_t)i];
+        ReqGrid& q = rows[(size_t)i];
+        q = ReqGrid{};
+        q.U = U + o;
+        q.U1 = b->U1 + o;
+        q.U2 = b->U2 + o;
+        q.ctrl = (Ctrl*)(b->d_ctrl + b->ctrl_bytes * (size_t)i);
+        wcnst_make_params(&d, &q.P);
+        q.t_final = t_final[i];
+        q.cfl = cfl;
+        q.nstrips = (d.nx + TX - 1) / TX;
+        q.parity0 = 0;
     }
-    std::vector<BSlot> slots;
-    const int running = b->wpg * std::min(b->grid, b->resident);
-    const int nslots = plan_parts(b->rec, cost, b->split, (double)b->wpg * b->grid, running, slots);
-    BHead h{};
-    h.nslots = nslots;
-    h.wait_ticks = b->wait_ticks;
-    WCNST_HIP_TRY(hipMemcpyAsync(b->d_inst, b->rec.data(), sizeof(BInst) * (size_t)n, hipMemcpyHostToDevice,
-                                 b->stream));
-    WCNST_HIP_TRY(hipMemcpyAsync(b->d_slots, slots.data(), sizeof(BSlot) * slots.size(), hipMemcpyHostToDevice,
-                                 b->stream));
-    WCNST_HIP_TRY(hipMemcpyAsync(b->d_head, &h, sizeof(BHead), hipMemcpyHostToDevice, b->stream));
-    // the tables must be in device memory before the graph's kernels start
-    WCNST_HIP_TRY(hipStreamSynchronize(b->stream));
+    b->ticks = 0;
+    b->graphs = 0;
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    std::vector<int> active((size_t)n);
+    for (int i = 0; i < n; ++i) active[(size_t)i] = i;
+    std::vector<int> parity((size_t)n, 0);
 
-    // one persistent launch, captured once into a graph and replayed (the
-    // buffers are reached through the instance table, so the graph does
-    // not depend on U)
-    const void* key = pick_kernel(b->d0);
-    if (!b->exec || b->exec_key != key || b->exec_grid != b->grid || b->exec_wpg != b->wpg) {
-        if (b->exec) {
-            (void)hipGraphExecDestroy(b->exec);
-            b->exec = nullptr;
-        }
-        hipGraph_t g = nullptr;
-        WCNST_HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-        hipError_t le = launch_pass(b->d0, b->d_inst, b->d_slots, b->d_head, b->P, b->grid, b->wpg, b->cap);
-        hipError_t ce = hipStreamEndCapture(b->cap, &g);
-        if (le != hipSuccess || ce != hipSuccess)
-            return wcnst_fail(WCNST_E_HIP, "graph capture failed: %s / %s", hipGetErrorString(le),
-                              hipGetErrorString(ce));
-        hipError_t ie = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (ie != hipSuccess) return wcnst_fail(WCNST_E_HIP, "graph instantiate failed: %s", hipGetErrorString(ie));
-        b->exec_key = key;
-        b->exec_grid = b->grid;
-        b->exec_wpg = b->wpg;
+    // table of all rows; control blocks reset and initial speeds in one launch
+    int blocks = 0;
+    for (int i = 0; i < n; ++i) {
+        b->h_req[i] = rows[(size_t)i];
+        b->h_req[i].blk0 = blocks;
+        blocks += rows[(size_t)i].nstrips;
     }
+    WCNST_HIP_TRY(hipMemcpyAsync(b->d_req, b->h_req, sizeof(ReqGrid) * (size_t)n, hipMemcpyHostToDevice, b->stream));
     WCNST_HIP_TRY(hipEventRecord(b->ev0, b->stream));
-    WCNST_HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    WCNST_HIP_TRY(wcnst_launch_multi_init(1, b->d_req, n, b->stream));
+
+    long long launched = 0;
+    bool changed = true;
+    while (!active.empty() && launched < (long long)max_steps) {
+        const int steps = (int)std::min<long long>(b->steps_per_tick, (long long)max_steps - launched);
+        if (changed && b->ticks > 0) {
+            // compact the table to the running instances (the previous tick
+            // has completed: the host waited for its control blocks)
+            blocks = 0;
+            for (size_t j = 0; j < active.size(); ++j) {
+                const int i = active[j];
+                b->h_req[j] = rows[(size_t)i];
+                b->h_req[j].blk0 = blocks;
+                b->h_req[j].parity0 = parity[(size_t)i];
+                blocks += rows[(size_t)i].nstrips;
+            }
+            WCNST_HIP_TRY(hipMemcpyAsync(b->d_req, b->h_req, sizeof(ReqGrid) * active.size(), hipMemcpyHostToDevice,
+                                         b->stream));
+        }
+        wcnst_status st = run_tick(b, (int)active.size(), blocks, steps, changed);
+        if (st) return st;
+        launched += steps;
+        b->ticks += 1;
+        for (int i : active) parity[(size_t)i] = (parity[(size_t)i] + steps) & 1;
+        WCNST_HIP_TRY(hipMemcpyAsync(b->h_ctrl, b->d_ctrl, b->ctrl_bytes * (size_t)n, hipMemcpyDeviceToHost,
+                                     b->stream));
+        WCNST_HIP_TRY(hipStreamSynchronize(b->stream));
+        std::vector<int> still;
+        still.reserve(active.size());
+        for (int i : active) {
+            const Ctrl& c = *(const Ctrl*)(b->h_ctrl + b->ctrl_bytes * (size_t)i);
+            const bool done = c.status != 0 || c.done != 0 ||
+                              (std::isfinite(t_final[i]) && reached(t_final[i], newest(c).t));
+            if (!done) still.push_back(i);
+        }
+        changed = still.size() != active.size();
+        active.swap(still);
+    }
     WCNST_HIP_TRY(hipEventRecord(b->ev1, b->stream));
-    WCNST_HIP_TRY(hipMemcpyAsync(b->rec.data(), b->d_inst, sizeof(BInst) * (size_t)n, hipMemcpyDeviceToHost,
-                                 b->stream));
-    WCNST_HIP_TRY(hipMemcpyAsync(&h, b->d_head, sizeof(BHead), hipMemcpyDeviceToHost, b->stream));
+    WCNST_HIP_TRY(hipMemcpyAsync(b->h_ctrl, b->d_ctrl, b->ctrl_bytes * (size_t)n, hipMemcpyDeviceToHost, b->stream));
     WCNST_HIP_TRY(hipStreamSynchronize(b->stream));
     float ms = 0.0f;
     WCNST_HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1));
     b->kernel_ms = ms;
-    if (h.err) return wcnst_fail(WCNST_E_HIP, "a cooperating part waited past its limit");
+
     wcnst_status ret = WCNST_OK;
     for (int i = 0; i < n; ++i) {
-        const BInst& r = b->rec[(size_t)i];
-        int s = r.status;
-        if (s == 0 && std::isfinite(r.t_final) && !(r.t_final - r.t <= 1e-12 * r.t_final)) s = WCNST_E_MAX_STEPS;
+        const Ctrl& c = *(const Ctrl*)(b->h_ctrl + b->ctrl_bytes * (size_t)i);
+        const StepRec& r = newest(c);
+        b->bad_key[(size_t)i] = c.bad_key;
+        int s = c.status;
+        if (s == 0 && std::isfinite(t_final[i]) && !reached(t_final[i], r.t)) s = WCNST_E_MAX_STEPS;
         status[i] = s;
         if (t_out) t_out[i] = r.t;
-        if (steps_out) steps_out[i] = r.steps;
+        if (steps_out) steps_out[i] = r.step;
         if (s != 0 && ret == WCNST_OK) ret = s;
     }
     if (ret != WCNST_OK) return wcnst_fail(ret, "at least one instance did not finish (see the status array)");
@@ -719,7 +344,7 @@ extern "C" wcnst_status wcnst_batch_bad_cells(const wcnst_batch* b, int64_t* bad
 {
     if (!b || !bad_stage || !bad_cell) return wcnst_fail(WCNST_E_INVALID_ARG, "null argument");
     for (int i = 0; i < b->n; ++i) {
-        const unsigned long long key = b->rec[(size_t)i].bad_key;
+        const unsigned long long key = b->bad_key[(size_t)i];
         const bool none = key == ~0ull;
         bad_stage[i] = none ? -1 : (int64_t)(key >> 36);
         bad_cell[i] = none ? -1 : (int64_t)(key & ((1ull << 36) - 1));
@@ -735,6 +360,8 @@ extern "C" wcnst_status wcnst_batch_destroy(wcnst_batch* b)
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
+    if (b->h_req) (void)hipHostFree(b->h_req);
+    if (b->h_ctrl) (void)hipHostFree(b->h_ctrl);
     delete b;
     return WCNST_OK;
 }

@@ -66,10 +66,11 @@ struct Ctrl {
     int pad[2];
 };
 
-// One 2D grid of a multi-grid stage launch: its buffers (U holds the state
-// at t^n, U1 / U2 the stage states), control block, parameters, and its
-// first block in the launch (blocks blk0 .. blk0 + nstrips*nseg - 1).
-struct Req2D {
+// One grid (1D or 2D) of a multi-grid stage launch: its buffers (U holds
+// the state at t^n, U1 / U2 the stage states), control block, parameters,
+// and its first block in the launch (blocks blk0 .. blk0 + nstrips*nseg - 1,
+// nseg = 1 in 1D).
+struct ReqGrid {
     double* U;
     double* U1;
     double* U2;
@@ -91,12 +92,13 @@ template <class T>
 __device__ __forceinline__ T load_host_written(const T* p)
 {
     static_assert(sizeof(T) % 8 == 0 && alignof(T) >= 8, "8-byte granular entries");
-    T out;
     const unsigned long long* s = reinterpret_cast<const unsigned long long*>(p);
-    unsigned long long* d = reinterpret_cast<unsigned long long*>(&out);
+    unsigned long long words[sizeof(T) / 8];
 #pragma unroll
     for (int i = 0; i < (int)(sizeof(T) / 8); ++i)
-        d[i] = __hip_atomic_load(s + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        words[i] = __hip_atomic_load(s + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    T out;
+    __builtin_memcpy(&out, words, sizeof(T));
     return out;
 }
 

@@ -22,13 +22,16 @@ struct Params;
 // Solver parameters of a validated descriptor (spacing, Eq. (5) coefficients).
 void wcnst_make_params(const wcnst_desc* d, wcnst::Params* out);
 
-// Request pools: bytes of one 2D control block; reset it to t = 0 and
-// accumulate the CFL speed of U into its record 0; one stage of every grid
-// of a Req2D table (nblocks = total segments, ty rows per segment).
+// Multi-grid stage launches: bytes of one control block; reset it to t = 0
+// and accumulate the CFL speed of U (1D or 2D Euler grid d) into its record
+// 0; one stage of every grid of a ReqGrid table of one dimension (nblocks =
+// total strips in 1D, total segments of ty rows in 2D).
 size_t wcnst_ctrl_bytes();
-hipError_t wcnst_launch_init2d(const wcnst_desc* d, const double* U, void* ctrl, hipStream_t st);
-hipError_t wcnst_launch_multi2d(const wcnst_desc* d, const void* reqs, int nreq, int nblocks, int stage,
-                                int tick_step, int ty, hipStream_t st);
+hipError_t wcnst_launch_init_grid(const wcnst_desc* d, const double* U, void* ctrl, hipStream_t st);
+hipError_t wcnst_launch_multi(const wcnst_desc* d, int ndim, const void* reqs, int nreq, int nblocks, int stage,
+                              int tick_step, int ty, hipStream_t st);
+// wcnst_launch_init_grid for every grid of a ReqGrid table (one launch).
+hipError_t wcnst_launch_multi_init(int ndim, const void* reqs, int nreq, hipStream_t st);
 
 #define WCNST_HIP_TRY(expr)                                                                \
     do {                                                                                   \

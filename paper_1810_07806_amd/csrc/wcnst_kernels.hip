@@ -135,22 +135,23 @@ __device__ __forceinline__ void write_flags(uint8_t* fl, int nlines, int nfaces,
 
 // ------------------------------------------------------------------ 1D
 
+// Strip bx of one 1D grid.  Thread 0 of strip 0 opens the next step record.
 template <int SYS, int NV, int FLUX, int SCHEME, bool CHAR, int MODE>
-__global__ void __launch_bounds__(WAVE)
-sweep1d(const double* __restrict__ U, const double* __restrict__ Un, double* __restrict__ out,
-        uint8_t* __restrict__ flags, Ctrl* __restrict__ ctrl, Params P, StageArgs A)
+__device__ __forceinline__ void sweep1d_block(const double* __restrict__ U, const double* __restrict__ Un,
+                                              double* __restrict__ out, uint8_t* __restrict__ flags,
+                                              Ctrl* __restrict__ ctrl, const Params& P, const StageArgs& A, int bx)
 {
     double dt = 0.0;
     long long step = 0;
     if constexpr (MODE == MODE_STAGE) {
-        if (!stage_prologue(ctrl, A, dt, step, first_thread())) return;
+        if (!stage_prologue(ctrl, A, dt, step, bx == 0 && threadIdx.x == 0)) return;
     }
     __shared__ double sF[NV][WAVE];
     __shared__ double sN[NV][WAVE];
     init_weight_table();
     const int nx = P.nx;
     const int lane = threadIdx.x;
-    const int x0 = blockIdx.x * TX;
+    const int x0 = bx * TX;
     const int c = x0 + lane;
     const bool cell_ok = lane < TX && c < nx;
     const int jx = x0 - 2 + lane;
@@ -167,7 +168,7 @@ sweep1d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
     unsigned fb;
     RegStencil<NV> st{s};
     face_flux<SYS, NV, FLUX, SCHEME, CHAR>(st, P, F, fb);
-    if (flags && jx <= nx && face_owner(jx, nx, TX) == (int)blockIdx.x)
+    if (flags && jx <= nx && face_owner(jx, nx, TX) == bx)
         write_flags<NV>(flags, 1, nx + 3, 0, jx + 2, fb);
     node_flux<SYS, NV>(s[3], P, fn);
 #pragma unroll
@@ -199,6 +200,53 @@ sweep1d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
     if constexpr (MODE == MODE_STAGE) {
         if (A.stage == 2) flush_speed(ctrl, A.parity, sm);
     }
+}
+
+template <int SYS, int NV, int FLUX, int SCHEME, bool CHAR, int MODE>
+__global__ void __launch_bounds__(WAVE)
+sweep1d(const double* __restrict__ U, const double* __restrict__ Un, double* __restrict__ out,
+        uint8_t* __restrict__ flags, Ctrl* __restrict__ ctrl, Params P, StageArgs A)
+{
+    sweep1d_block<SYS, NV, FLUX, SCHEME, CHAR, MODE>(U, Un, out, flags, ctrl, P, A, (int)blockIdx.x);
+}
+
+// The table row of block b: the grid r with blk0[r] <= b < blk0[r+1]
+// (binary search, uniform per block).  The table is host-written for each
+// launch sequence: system-scope reads.
+__device__ __forceinline__ ReqGrid load_request(const ReqGrid* __restrict__ reqs, int nreq, int b)
+{
+    int lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (__hip_atomic_load(&reqs[mid].blk0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return load_host_written(&reqs[lo]);
+}
+
+__device__ __forceinline__ StageArgs request_stage(const ReqGrid& R, int stage, int tick_step)
+{
+    StageArgs A;
+    A.t_final = R.t_final;
+    A.cfl = R.cfl;
+    A.fixed_dt = 0.0;
+    A.stage = stage;
+    A.parity = (R.parity0 + tick_step) & 1;
+    return A;
+}
+
+// One stage of many independent 1D Euler grids in one launch (one strip per
+// block), each with its own parameters, buffers, control block and parity.
+template <int FLUX, int SCHEME, bool CHAR>
+__global__ void __launch_bounds__(WAVE)
+sweep1d_multi(const ReqGrid* __restrict__ reqs, int nreq, int stage, int tick_step)
+{
+    const int b = (int)blockIdx.x;
+    const ReqGrid R = load_request(reqs, nreq, b);
+    const StageArgs A = request_stage(R, stage, tick_step);
+    const double* in = stage == 0 ? R.U : (stage == 1 ? R.U1 : R.U2);
+    double* out = stage == 0 ? R.U1 : (stage == 1 ? R.U2 : R.U);
+    sweep1d_block<SYS_EULER, 3, FLUX, SCHEME, CHAR, MODE_STAGE>(in, R.U, out, nullptr, R.ctrl, R.P, A, b - R.blk0);
 }
 
 // ------------------------------------------------------------------ 2D
@@ -422,25 +470,13 @@ sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
 // the grid's own parameters, buffers, control block and step parity.
 template <int NV, int FLUX, int SCHEME, bool CHAR>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2)))
-sweep2d_multi(const Req2D* __restrict__ reqs, int nreq, int stage, int tick_step, int ty)
+sweep2d_multi(const ReqGrid* __restrict__ reqs, int nreq, int stage, int tick_step, int ty)
 {
-    // the request table is host-written for each tick: system-scope reads
     const int b = (int)blockIdx.x;
-    int lo = 0, hi = nreq - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (__hip_atomic_load(&reqs[mid].blk0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    const Req2D R = load_host_written(&reqs[lo]);
+    const ReqGrid R = load_request(reqs, nreq, b);
     const Params& P = R.P;
     const int local = b - R.blk0;
-    StageArgs A;
-    A.t_final = R.t_final;
-    A.cfl = R.cfl;
-    A.fixed_dt = 0.0;
-    A.stage = stage;
-    A.parity = (R.parity0 + tick_step) & 1;
+    const StageArgs A = request_stage(R, stage, tick_step);
     const double* in = stage == 0 ? R.U : (stage == 1 ? R.U1 : R.U2);
     double* out = stage == 0 ? R.U1 : (stage == 1 ? R.U2 : R.U);
     sweep2d_block<NV, FLUX, SCHEME, CHAR, MODE_STAGE>(in, R.U, out, nullptr, R.ctrl, P, A, ty, local % R.nstrips,
@@ -448,6 +484,42 @@ sweep2d_multi(const Req2D* __restrict__ reqs, int nreq, int stage, int tick_step
 }
 
 // ----------------------------------------------------- control kernels
+
+// Block r: reset the control block of grid r of a ReqGrid table to t = 0
+// (as ctrl_init) and accumulate the CFL speed of its state into record 0
+// (as wavespeed), for every grid of the table in one launch.
+template <int NV>
+__global__ void __launch_bounds__(256) multi_init(const ReqGrid* __restrict__ reqs)
+{
+    const ReqGrid R = load_host_written(&reqs[blockIdx.x]);
+    const size_t plane = (size_t)R.P.nx * R.P.ny;
+    unsigned long long m = 0ull;
+    for (size_t i = threadIdx.x; i < plane; i += blockDim.x) {
+        double u[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v] = R.U[(size_t)v * plane + i];
+        const unsigned long long b = (unsigned long long)__double_as_longlong(cell_speed<SYS_EULER, NV>(u, R.P));
+        m = b > m ? b : m;
+    }
+    m = wave_max_bits(m);
+    __shared__ unsigned long long red[256 / WAVE];
+    if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x / WAVE); ++i) m = red[i] > m ? red[i] : m;
+        Ctrl* ctrl = R.ctrl;
+        for (int k = 0; k < 2; ++k) {
+            ctrl->rec[k].t = 0.0;
+            ctrl->rec[k].dt = 0.0;
+            ctrl->rec[k].smax_bits = k == 0 ? m : 0ull;
+            ctrl->rec[k].step = 0;
+        }
+        ctrl->bad_key = ~0ull;
+        ctrl->call_step0 = 0;
+        ctrl->status = 0;
+        ctrl->done = 0;
+    }
+}
 
 __global__ void ctrl_init(Ctrl* ctrl, double t, long long step)
 {
@@ -972,50 +1044,77 @@ extern "C" wcnst_status wcnst_profile_read(wcnst_solver* s, double* stage_ms, in
 
 size_t wcnst_ctrl_bytes() { return sizeof(Ctrl); }
 
-hipError_t wcnst_launch_init2d(const wcnst_desc* d, const double* U, void* ctrl, hipStream_t st)
+hipError_t wcnst_launch_init_grid(const wcnst_desc* d, const double* U, void* ctrl, hipStream_t st)
 {
     Params P;
     wcnst_make_params(d, &P);
     hipLaunchKernelGGL(ctrl_init, dim3(1), dim3(64), 0, st, (Ctrl*)ctrl, 0.0, 0LL);
     const size_t cells = (size_t)d->nx * d->ny;
     const int blocks = (int)std::min<size_t>((cells + 255) / 256, 2048);
-    hipLaunchKernelGGL((wavespeed<SYS_EULER, 4>), dim3(blocks), dim3(256), 0, st, U, (Ctrl*)ctrl, P, 0);
+    if (d->ndim == 2)
+        hipLaunchKernelGGL((wavespeed<SYS_EULER, 4>), dim3(blocks), dim3(256), 0, st, U, (Ctrl*)ctrl, P, 0);
+    else
+        hipLaunchKernelGGL((wavespeed<SYS_EULER, 3>), dim3(blocks), dim3(256), 0, st, U, (Ctrl*)ctrl, P, 0);
     return hipGetLastError();
 }
 
-template <int FLUX, int SCHEME, bool CHAR>
-static void launch_multi_t(const Req2D* reqs, int nreq, int nblocks, int stage, int tick_step, int ty,
-                           hipStream_t st)
+hipError_t wcnst_launch_multi_init(int ndim, const void* reqs, int nreq, hipStream_t st)
 {
-    hipLaunchKernelGGL((sweep2d_multi<4, FLUX, SCHEME, CHAR>), dim3(nblocks), dim3(WAVE), 0, st, reqs, nreq,
-                       stage, tick_step, ty);
+    if (nreq <= 0) return hipSuccess;
+    if (ndim == 2)
+        hipLaunchKernelGGL((multi_init<4>), dim3(nreq), dim3(256), 0, st, (const ReqGrid*)reqs);
+    else
+        hipLaunchKernelGGL((multi_init<3>), dim3(nreq), dim3(256), 0, st, (const ReqGrid*)reqs);
+    return hipGetLastError();
 }
 
-template <int FLUX, bool CHAR>
-static void launch_multi_s(const wcnst_desc* d, const Req2D* reqs, int nreq, int nblocks, int stage,
+template <int NDIM, int FLUX, int SCHEME, bool CHAR>
+static void launch_multi_t(const ReqGrid* reqs, int nreq, int nblocks, int stage, int tick_step, int ty,
+                           hipStream_t st)
+{
+    if constexpr (NDIM == 2)
+        hipLaunchKernelGGL((sweep2d_multi<4, FLUX, SCHEME, CHAR>), dim3(nblocks), dim3(WAVE), 0, st, reqs, nreq,
+                           stage, tick_step, ty);
+    else
+        hipLaunchKernelGGL((sweep1d_multi<FLUX, SCHEME, CHAR>), dim3(nblocks), dim3(WAVE), 0, st, reqs, nreq, stage,
+                           tick_step);
+}
+
+template <int NDIM, int FLUX, bool CHAR>
+static void launch_multi_s(const wcnst_desc* d, const ReqGrid* reqs, int nreq, int nblocks, int stage,
                            int tick_step, int ty, hipStream_t st)
 {
     switch (d->scheme) {
-    case WCNST_LINEAR: launch_multi_t<FLUX, SCH_LINEAR, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, st); break;
-    case WCNST_JS: launch_multi_t<FLUX, SCH_JS, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, st); break;
+    case WCNST_LINEAR:
+        launch_multi_t<NDIM, FLUX, SCH_LINEAR, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, st);
+        break;
+    case WCNST_JS: launch_multi_t<NDIM, FLUX, SCH_JS, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, st); break;
     default:
-        if (d->q == 6) launch_multi_t<FLUX, SCH_TENO, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, st);
-        else launch_multi_t<FLUX, SCH_TENO_Q, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, st);
+        if (d->q == 6) launch_multi_t<NDIM, FLUX, SCH_TENO, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, st);
+        else launch_multi_t<NDIM, FLUX, SCH_TENO_Q, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, st);
         break;
     }
 }
 
-hipError_t wcnst_launch_multi2d(const wcnst_desc* d, const void* reqs, int nreq, int nblocks, int stage,
-                                int tick_step, int ty, hipStream_t st)
+template <int NDIM>
+static void launch_multi_d(const wcnst_desc* d, const ReqGrid* r, int nreq, int nblocks, int stage, int tick_step,
+                           int ty, hipStream_t st)
 {
-    const Req2D* r = (const Req2D*)reqs;
     if (d->flux == WCNST_LF) {
-        if (d->charwise) launch_multi_s<FLUX_LF, true>(d, r, nreq, nblocks, stage, tick_step, ty, st);
-        else launch_multi_s<FLUX_LF, false>(d, r, nreq, nblocks, stage, tick_step, ty, st);
+        if (d->charwise) launch_multi_s<NDIM, FLUX_LF, true>(d, r, nreq, nblocks, stage, tick_step, ty, st);
+        else launch_multi_s<NDIM, FLUX_LF, false>(d, r, nreq, nblocks, stage, tick_step, ty, st);
     } else {
-        if (d->charwise) launch_multi_s<FLUX_ROE, true>(d, r, nreq, nblocks, stage, tick_step, ty, st);
-        else launch_multi_s<FLUX_ROE, false>(d, r, nreq, nblocks, stage, tick_step, ty, st);
+        if (d->charwise) launch_multi_s<NDIM, FLUX_ROE, true>(d, r, nreq, nblocks, stage, tick_step, ty, st);
+        else launch_multi_s<NDIM, FLUX_ROE, false>(d, r, nreq, nblocks, stage, tick_step, ty, st);
     }
+}
+
+hipError_t wcnst_launch_multi(const wcnst_desc* d, int ndim, const void* reqs, int nreq, int nblocks, int stage,
+                              int tick_step, int ty, hipStream_t st)
+{
+    const ReqGrid* r = (const ReqGrid*)reqs;
+    if (ndim == 2) launch_multi_d<2>(d, r, nreq, nblocks, stage, tick_step, ty, st);
+    else launch_multi_d<1>(d, r, nreq, nblocks, stage, tick_step, ty, st);
     return hipGetLastError();
 }
 

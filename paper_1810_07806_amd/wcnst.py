@@ -24,7 +24,8 @@ EXPORTS = ("wcnst_desc_init", "wcnst_workspace_size", "wcnst_create", "wcnst_rhs
            "wcnst_solve", "wcnst_status_sync", "wcnst_reset", "wcnst_set_tuning", "wcnst_profile_enable",
            "wcnst_profile_read", "wcnst_destroy", "wcnst_last_error",
            "wcnst_batch_workspace_size", "wcnst_batch_create", "wcnst_batch_offsets", "wcnst_batch_solve",
-           "wcnst_batch_bad_cells", "wcnst_batch_set_tuning", "wcnst_batch_kernel_ms", "wcnst_batch_destroy",
+           "wcnst_batch_bad_cells", "wcnst_batch_set_tuning", "wcnst_batch_kernel_ms", "wcnst_batch_stats",
+           "wcnst_batch_destroy",
            "wcnst_pool_workspace_size", "wcnst_pool_create", "wcnst_pool_admit", "wcnst_pool_tick",
            "wcnst_pool_result", "wcnst_pool_release", "wcnst_pool_set_tuning", "wcnst_pool_destroy")
 
@@ -83,8 +84,9 @@ def lib(path: str | None = None):
     L.wcnst_batch_solve.argtypes = [vp, vp, dp, ctypes.c_double, ctypes.c_int64,
                                     ctypes.POINTER(ctypes.c_int32), dp, i64p]
     L.wcnst_batch_bad_cells.argtypes = [vp, i64p, i64p]
-    L.wcnst_batch_set_tuning.argtypes = [vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32]
+    L.wcnst_batch_set_tuning.argtypes = [vp, ctypes.c_int32]
     L.wcnst_batch_kernel_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.wcnst_batch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     L.wcnst_batch_destroy.argtypes = [vp]
     i32, i32p = ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)
     L.wcnst_pool_workspace_size.argtypes = [i32, ctypes.POINTER(ctypes.c_size_t)]
@@ -93,7 +95,7 @@ def lib(path: str | None = None):
     L.wcnst_pool_tick.argtypes = [vp, ctypes.c_int64, i32p]
     L.wcnst_pool_result.argtypes = [vp, i32, i32p, i32p, dp, i64p, i64p, i64p]
     L.wcnst_pool_release.argtypes = [vp, i32]
-    L.wcnst_pool_set_tuning.argtypes = [vp, ctypes.c_double, i32, i32]
+    L.wcnst_pool_set_tuning.argtypes = [vp, i32]
     L.wcnst_pool_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name != "wcnst_last_error":
@@ -250,7 +252,8 @@ def split_flags(desc: dict, fl):
 
 
 class Batch:
-    """Many independent 1D Euler problems advanced in one persistent launch.
+    """Many independent 1D Euler problems advanced together in graph-captured
+    ticks of multi-instance stage launches.
 
     States are packed into one device tensor (``pack``/``unpack``); instance i
     occupies ``offsets[i] : offsets[i] + 3 * nx_i`` with layout [v][nx_i]."""
@@ -292,13 +295,19 @@ class Batch:
         return [h[self.offsets[i]:self.offsets[i] + 3 * int(d["nx"])].reshape(3, 1, int(d["nx"])).copy()
                 for i, d in enumerate(self.descs)]
 
-    def set_tuning(self, split: float = 1.0, workgroups: int = 0, waves_per_group: int = 0):
-        _check(lib().wcnst_batch_set_tuning(self._h, float(split), int(workgroups), int(waves_per_group)))
+    def set_tuning(self, steps_per_tick: int = 64):
+        _check(lib().wcnst_batch_set_tuning(self._h, int(steps_per_tick)))
 
     def kernel_ms(self) -> float:
         ms = ctypes.c_double(0.0)
         _check(lib().wcnst_batch_kernel_ms(self._h, ctypes.byref(ms)))
         return ms.value
+
+    def stats(self) -> dict:
+        """Ticks of the last solve and graphs captured for them."""
+        tk, gr = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().wcnst_batch_stats(self._h, ctypes.byref(tk), ctypes.byref(gr)))
+        return dict(ticks=tk.value, graphs=gr.value)
 
     def solve(self, Ug, t_final, cfl: float = 0.5, max_steps: int = 1 << 40):
         """Returns dict(status, t, steps) arrays; raises only on HIP errors."""
@@ -396,8 +405,8 @@ class Pool:
         _check(lib().wcnst_pool_release(self._h, int(slot)))
         self._held.pop(slot, None)
 
-    def set_tuning(self, split: float = 1.0, waves_per_group: int = 0, rows_per_segment: int = 0):
-        _check(lib().wcnst_pool_set_tuning(self._h, float(split), int(waves_per_group), int(rows_per_segment)))
+    def set_tuning(self, rows_per_segment: int = 0):
+        _check(lib().wcnst_pool_set_tuning(self._h, int(rows_per_segment)))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -35,14 +35,14 @@ def _tubes(count, seed, n_min=64, n_max=600, t_final=0.05):
     return W.shock_tube_batch(count=count, seed=seed, n_min=n_min, n_max=n_max, t_final=t_final)
 
 
-@pytest.mark.parametrize("split", [0.0, 0.05])
-def test_batch_equals_alone_and_oracle(orc, torch, split):
+@pytest.mark.parametrize("spt", [64, 6])
+def test_batch_equals_alone_and_oracle(orc, torch, spt):
     from paper_1810_07806_amd.wcnst import Batch, Solver
     items = _tubes(24, seed=1)
     descs = [d for d, _ in items]
-    _say(f"batch of {len(items)} split={split}")
+    _say(f"batch of {len(items)} steps/tick={spt}")
     b = Batch(descs)
-    b.set_tuning(split, 0)
+    b.set_tuning(spt)
     Ug = b.pack([U for _, U in items])
     res = b.solve(Ug, [d["t_final"] for d in descs], cfl=0.5)
     assert (res["status"] == 0).all(), res["status"]
@@ -62,6 +62,10 @@ def test_batch_equals_alone_and_oracle(orc, torch, split):
     b.close()
 
 
+@pytest.mark.skip(reason="exercised the earlier cooperating-wave path (parts of one tube meeting at a device "
+                         "barrier), which stalled at its bounded wait on some runs without a cause found by "
+                         "reading; that path was removed and test_batch_paths_do_not_change_results covers "
+                         "the current decomposition")
 def test_batch_decomposition_does_not_change_results(orc, torch):
     """Seed 2 holds one tube (index 17, a strong double rarefaction) on which
     the Roe flux without entropy fix loses positivity; the oracle fails it at
@@ -99,9 +103,9 @@ def test_batch_fault_stays_local(orc, torch):
     bad_i = 5
     states[bad_i][0, 0, 17] = -0.5
     _say("fault isolation")
-    for split in (0.0, 0.02):
+    for spt in (64, 4):
         b = Batch(descs)
-        b.set_tuning(split, 0)
+        b.set_tuning(spt)
         Ug = b.pack(states)
         res = b.solve(Ug, 0.05, cfl=0.5)
         bs, bc = b.bad_cells()
@@ -127,3 +131,122 @@ def test_batch_fixed_steps(torch):
     res = b.solve(Ug, np.inf, cfl=0.5, max_steps=37)
     assert (res["status"] == 0).all() and (res["steps"] == 37).all()
     b.close()
+
+
+def test_batch_full_size_sampled(orc, torch):
+    """The 4096-tube batch of the benchmark (N log-uniform in [256, 8192],
+    t = 0.15) in one launch; small sampled tubes, finished and failed,
+    compared with the oracle bit for bit (the oracle is too slow for the
+    large ones, whose equality with the single solve is covered above)."""
+    from paper_1810_07806_amd.wcnst import Batch
+    items = W.shock_tube_batch(count=4096, seed=0, t_final=0.15)
+    descs = [d for d, _ in items]
+    _say("batch 4096 tubes, full size")
+    b = Batch(descs)
+    Ug = b.pack([U for _, U in items])
+    res = b.solve(Ug, 0.15, cfl=0.5)
+    bs, bc = b.bad_cells()
+    n = np.array([d["nx"] for d in descs])
+    assert set(np.unique(res["status"])) <= {0, 2}
+    assert (res["status"] == 2).mean() < 0.05
+    ok_small = [i for i in np.flatnonzero((res["status"] == 0) & (n <= 300))][:6]
+    bad_small = [i for i in np.flatnonzero((res["status"] == 2) & (n <= 600))][:2]
+    out = None
+    for i in ok_small + bad_small:
+        _say(f"oracle tube {i} n={n[i]}")
+        r = orc.solve(orc.problem(descs[i]), items[i][1], t_final=0.15, cfl=0.5)
+        assert r["status"] == res["status"][i]
+        if r["status"] == 0:
+            if out is None:
+                out = b.unpack(Ug)
+            assert r["steps"] == res["steps"][i]
+            assert np.array_equal(out[i], r["U"]), f"tube {i}"
+        else:
+            assert (bs[i], bc[i]) == (r["bad_stage"], r["bad_cell"])
+    assert len(ok_small) >= 3
+    b.close()
+
+
+def test_batch_strip_boundaries_and_minimum_size(orc, torch):
+    """Instances of 5 cells (the minimum) and at the edges of the 61-cell
+    strips, alone in a batch and mixed, split over several waves."""
+    from paper_1810_07806_amd.wcnst import Batch
+    rng = np.random.default_rng(31)
+    items = [W.random_tube(rng, nx) for nx in (5, 60, 61, 62, 121, 122, 123, 244)]
+    for d, _ in items:
+        d["t_final"] = 0.02
+    _say("single 5-cell instance")
+    b1 = Batch([items[0][0]])
+    U1 = b1.pack([items[0][1]])
+    r1 = b1.solve(U1, 0.02, cfl=0.5)
+    ro = orc.solve(orc.problem(items[0][0]), items[0][1], t_final=0.02, cfl=0.5)
+    assert r1["status"][0] == ro["status"]
+    if ro["status"] == 0:
+        assert np.array_equal(b1.unpack(U1)[0], ro["U"])
+    b1.close()
+    for spt in (64, 2):
+        _say(f"strip-boundary sizes, steps/tick={spt}")
+        b = Batch([d for d, _ in items])
+        b.set_tuning(spt)
+        Ug = b.pack([U for _, U in items])
+        res = b.solve(Ug, 0.02, cfl=0.5)
+        out = b.unpack(Ug)
+        for i, (d, U) in enumerate(items):
+            r = orc.solve(orc.problem(d), U, t_final=0.02, cfl=0.5)
+            assert r["status"] == res["status"][i]
+            if r["status"] == 0:
+                assert r["steps"] == res["steps"][i] and np.array_equal(out[i], r["U"]), f"n={d['nx']}"
+        b.close()
+
+
+@pytest.mark.parametrize("kw", [dict(flux="lf", bc_x="periodic"), dict(flux="roe", charwise=0),
+                                dict(flux="roe", scheme="linear")], ids=["lf-periodic", "componentwise", "linear"])
+def test_batch_scheme_variants(orc, torch, kw):
+    from paper_1810_07806_amd.wcnst import Batch
+    rng = np.random.default_rng(41)
+    items = [W.random_tube(rng, nx) for nx in (90, 200, 333)]
+    for d, _ in items:
+        d.update(kw)
+    _say(f"batch variant {kw}")
+    b = Batch([d for d, _ in items])
+    Ug = b.pack([U for _, U in items])
+    res = b.solve(Ug, 0.03, cfl=0.5)
+    out = b.unpack(Ug)
+    for i, (d, U) in enumerate(items):
+        r = orc.solve(orc.problem(d), U, t_final=0.03, cfl=0.5)
+        assert r["status"] == res["status"][i] == 0
+        assert r["steps"] == res["steps"][i]
+        assert (rel_inf_err(out[i], r["U"]) <= FIELD_TOL).all()
+    b.close()
+
+
+def test_batch_paths_do_not_change_results(orc, torch):
+    """The tick length (how often finished tubes leave the launch table) only
+    changes the work decomposition: statuses, failure locations, step counts
+    and states are bit-identical; every sampled tube matches the oracle."""
+    from paper_1810_07806_amd.wcnst import Batch
+    items = _tubes(36, seed=12, n_min=80, n_max=3000, t_final=0.02)
+    descs = [d for d, _ in items]
+    outs = []
+    for spt in (64, 2, 8, 1000):
+        _say(f"ticks of {spt} steps")
+        b = Batch(descs)
+        b.set_tuning(spt)
+        Ug = b.pack([U for _, U in items])
+        res = b.solve(Ug, 0.02, cfl=0.5)
+        st = b.stats()
+        assert st["ticks"] >= 1 and st["graphs"] >= (1 if spt <= int(res["steps"].max()) else 0)
+        outs.append((Ug.cpu().numpy(), res["steps"].copy(), res["status"].copy(), b.bad_cells(), b.unpack(Ug)))
+        b.close()
+    o0, st0, s0, (bs0, bc0), per0 = outs[0]
+    for o, st, s, (bs, bc), _ in outs[1:]:
+        assert np.array_equal(s, s0) and np.array_equal(bs, bs0) and np.array_equal(bc, bc0)
+        assert np.array_equal(st, st0) and np.array_equal(o, o0)
+    for i in range(0, len(items), 5):
+        d, U = items[i]
+        r = orc.solve(orc.problem(d), U, t_final=0.02, cfl=0.5)
+        assert r["status"] == s0[i]
+        if r["status"] == 0:
+            assert r["steps"] == st0[i] and np.array_equal(per0[i], r["U"])
+        else:
+            assert (bs0[i], bc0[i]) == (r["bad_stage"], r["bad_cell"])

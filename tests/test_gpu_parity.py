@@ -279,3 +279,27 @@ def test_launch_shape_does_not_change_results(torch):
         outs.append((R, Ug.cpu().numpy()))
     for R, V in outs[1:]:
         assert np.array_equal(R, outs[0][0]) and np.array_equal(V, outs[0][1])
+
+
+def test_solve_config3_full_size_2_steps(orc, torch):
+    """The 2048^2 benchmark problem in the benchmark's launch configuration:
+    two full SSP-RK3 steps compared with the oracle over the whole field."""
+    d, U = W.riemann2d_config3(2048)
+    _solve_case(orc, torch, d, U, np.inf, 2, "config3-2048-2-steps")
+
+
+def test_config3_full_size_200_steps_symmetric(torch):
+    """At the full size and step count of the benchmark, where the oracle is
+    too slow to follow, a property that holds at any size: the diagonal
+    symmetry of the initial state survives bit for bit, and the state stays
+    physical with a decreasing-or-bounded CFL speed."""
+    d, U = W.riemann2d_config3(2048)
+    _say("symmetry 2048 x 200 steps")
+    s = _solver(d)
+    Ug = s.new_state(U)
+    t, n = s.solve(Ug, t_final=np.inf, cfl=0.5, max_steps=200)
+    assert n == 200 and s.status()["status"] == 0
+    V = Ug.cpu().numpy()
+    assert np.array_equal(V[0], V[0].T) and np.array_equal(V[3], V[3].T)
+    assert np.array_equal(V[1], V[2].T)
+    assert np.isfinite(V).all() and (V[0] > 0).all()

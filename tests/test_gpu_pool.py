@@ -119,8 +119,8 @@ def test_pool_join_midway_and_tuning(torch):
     items = _mix(2, n1=6, n2=3)
     _say("pool join after 3 ticks")
     _compare(items, _run_pool(torch, items, 5, join_after=(4, 3)))
-    _say("pool with split 0.05, 1 wave/group, 17 rows/segment")
-    _compare(items, _run_pool(torch, items, 9, tuning=(0.05, 1, 17)))
+    _say("pool with 17 rows/segment")
+    _compare(items, _run_pool(torch, items, 9, tuning=(17,)))
 
 
 def test_pool_fault_stays_local(torch):
