@@ -141,20 +141,28 @@ double orc_interp_left(const orc_problem* p, const double s[5], double chi[3],
 
 /* ------------------------------------------------------- Euler system */
 
-static double euler_pressure(int nv, double gamma, const double* U)
+/* Ideal gas p = (gamma - 1) rho e, with rho e = E - kinetic energy; ir is
+ * 1 / rho.  Every divisor shared by several terms is inverted once and the
+ * terms multiply by its reciprocal (the paper fixes no evaluation order for
+ * the flux, the Roe average or the eigenvectors). */
+static double euler_pressure_r(int nv, double gamma, const double* U, double ir)
 {
     double kin;
-    if (nv == 4) kin = 0.5 * (U[1] * U[1] + U[2] * U[2]) / U[0];
-    else kin = 0.5 * U[1] * U[1] / U[0];
-    /* Ideal gas p = (gamma - 1) rho e, with rho e = E - kinetic energy. */
+    if (nv == 4) kin = 0.5 * (U[1] * U[1] + U[2] * U[2]) * ir;
+    else kin = 0.5 * U[1] * U[1] * ir;
     return (gamma - 1.0) * (U[nv - 1] - kin);
+}
+
+static double euler_pressure(int nv, double gamma, const double* U)
+{
+    return euler_pressure_r(nv, gamma, U, 1.0 / U[0]);
 }
 
 void orc_euler_flux(int nv, double gamma, const double* U, double* F)
 {
-    double rho = U[0];
-    double u = U[1] / rho;
-    double p = euler_pressure(nv, gamma, U);
+    double ir = 1.0 / U[0];
+    double u = U[1] * ir;
+    double p = euler_pressure_r(nv, gamma, U, ir);
     F[0] = U[1];
     F[1] = U[1] * u + p;
     if (nv == 4) F[2] = U[2] * u;
@@ -165,19 +173,23 @@ int orc_roe_eigen(int nv, double gamma, const double* UA, const double* UB,
                   double* L, double* R, double* lam)
 {
     double rA = UA[0], rB = UB[0];
-    double uA = UA[1] / rA, uB = UB[1] / rB;
-    double vA = nv == 4 ? UA[2] / rA : 0.0, vB = nv == 4 ? UB[2] / rB : 0.0;
-    double HA = (UA[nv - 1] + euler_pressure(nv, gamma, UA)) / rA;
-    double HB = (UB[nv - 1] + euler_pressure(nv, gamma, UB)) / rB;
+    double irA = 1.0 / rA, irB = 1.0 / rB;
+    double uA = UA[1] * irA, uB = UB[1] * irB;
+    double vA = nv == 4 ? UA[2] * irA : 0.0, vB = nv == 4 ? UB[2] * irB : 0.0;
+    double HA = (UA[nv - 1] + euler_pressure_r(nv, gamma, UA, irA)) * irA;
+    double HB = (UB[nv - 1] + euler_pressure_r(nv, gamma, UB, irB)) * irB;
     double sA = sqrt(rA), sB = sqrt(rB);
-    double u = (sA * uA + sB * uB) / (sA + sB);
-    double v = (sA * vA + sB * vB) / (sA + sB);
-    double H = (sA * HA + sB * HB) / (sA + sB);
+    double is = 1.0 / (sA + sB);
+    double u = (sA * uA + sB * uB) * is;
+    double v = (sA * vA + sB * vB) * is;
+    double H = (sA * HA + sB * HB) * is;
     double q2 = u * u + v * v;
     double c2 = (gamma - 1.0) * (H - 0.5 * q2);
     double c = sqrt(c2);
-    double b1 = (gamma - 1.0) / c2;
+    double ic = 1.0 / c;
+    double b1 = (gamma - 1.0) * (ic * ic);
     double b2 = 0.5 * q2 * b1;
+    double uc = u * ic;
     int bad = !(c2 > 0.0);
 
     if (nv == 3) {
@@ -185,9 +197,9 @@ int orc_roe_eigen(int nv, double gamma, const double* UA, const double* UB,
         double Rm[9] = {1.0, 1.0, 1.0,
                         u - c, u, u + c,
                         H - u * c, 0.5 * q2, H + u * c};
-        double Lm[9] = {0.5 * (b2 + u / c), -0.5 * (b1 * u + 1.0 / c), 0.5 * b1,
+        double Lm[9] = {0.5 * (b2 + uc), -0.5 * (b1 * u + ic), 0.5 * b1,
                         1.0 - b2, b1 * u, -b1,
-                        0.5 * (b2 - u / c), -0.5 * (b1 * u - 1.0 / c), 0.5 * b1};
+                        0.5 * (b2 - uc), -0.5 * (b1 * u - ic), 0.5 * b1};
         memcpy(R, Rm, sizeof Rm);
         memcpy(L, Lm, sizeof Lm);
         lam[0] = u - c; lam[1] = u; lam[2] = u + c;
@@ -197,10 +209,10 @@ int orc_roe_eigen(int nv, double gamma, const double* UA, const double* UB,
                          u - c, u, 0.0, u + c,
                          v, v, 1.0, v,
                          H - u * c, 0.5 * q2, v, H + u * c};
-        double Lm[16] = {0.5 * (b2 + u / c), -0.5 * (b1 * u + 1.0 / c), -0.5 * b1 * v, 0.5 * b1,
+        double Lm[16] = {0.5 * (b2 + uc), -0.5 * (b1 * u + ic), -0.5 * b1 * v, 0.5 * b1,
                          1.0 - b2, b1 * u, b1 * v, -b1,
                          -v, 0.0, 1.0, 0.0,
-                         0.5 * (b2 - u / c), -0.5 * (b1 * u - 1.0 / c), -0.5 * b1 * v, 0.5 * b1};
+                         0.5 * (b2 - uc), -0.5 * (b1 * u - ic), -0.5 * b1 * v, 0.5 * b1};
         memcpy(R, Rm, sizeof Rm);
         memcpy(L, Lm, sizeof Lm);
         lam[0] = u - c; lam[1] = u; lam[2] = u; lam[3] = u + c;
@@ -210,7 +222,8 @@ int orc_roe_eigen(int nv, double gamma, const double* UA, const double* UB,
 
 static double sound_speed(int nv, double gamma, const double* U)
 {
-    return sqrt(gamma * euler_pressure(nv, gamma, U) / U[0]);
+    double ir = 1.0 / U[0];
+    return sqrt(gamma * euler_pressure_r(nv, gamma, U, ir) * ir);
 }
 
 void orc_num_flux(const orc_problem* p, const double* UL, const double* UR, double* F)
@@ -236,8 +249,8 @@ void orc_num_flux(const orc_problem* p, const double* UL, const double* UR, doub
         orc_euler_flux(nv, p->gamma, UL, FL);
         orc_euler_flux(nv, p->gamma, UR, FR);
         if (p->flux == ORC_LF) {
-            double aL = fabs(UL[1] / UL[0]) + sound_speed(nv, p->gamma, UL);
-            double aR = fabs(UR[1] / UR[0]) + sound_speed(nv, p->gamma, UR);
+            double aL = fabs(UL[1] * (1.0 / UL[0])) + sound_speed(nv, p->gamma, UL);
+            double aR = fabs(UR[1] * (1.0 / UR[0])) + sound_speed(nv, p->gamma, UR);
             double al = fmax(aL, aR);
             for (int v = 0; v < nv; ++v) dis[v] = al * (UR[v] - UL[v]);
         } else {
@@ -451,11 +464,12 @@ double orc_max_speed(const orc_problem* p, const double* U)
         } else if (p->system == ORC_BURGERS) {
             s = fabs(U[c]) / p->dx;
         } else {
-            double cell[4];
+            double cell[4] = {0.0, 0.0, 0.0, 0.0};
             for (int v = 0; v < nv; ++v) cell[v] = U[v * plane + c];
             double a = sound_speed(nv, p->gamma, cell);
-            s = (fabs(cell[1] / cell[0]) + a) / p->dx;
-            if (nv == 4) s = s + (fabs(cell[2] / cell[0]) + a) / p->dy;
+            double ir = 1.0 / cell[0];
+            s = (fabs(cell[1] * ir) + a) / p->dx;
+            if (nv == 4) s = s + (fabs(cell[2] * ir) + a) / p->dy;
         }
         /* a NaN speed poisons the maximum for good */
         if (isnan(s) || (!isnan(smax) && s > smax)) smax = s;

@@ -246,11 +246,11 @@ WCNST_HD double interp5(double a, double b, double c, double d, double e, const 
 
 // Ideal gas p = (gamma - 1)(E - |m|^2 / (2 rho)).
 template <int NV>
-WCNST_HD double pressure(const double* U, double gamma)
+WCNST_HD double pressure(const double* U, double gamma, double ir)
 {
     double kin;
-    if constexpr (NV == 4) kin = 0.5 * (U[1] * U[1] + U[2] * U[2]) / U[0];
-    else kin = 0.5 * U[1] * U[1] / U[0];
+    if constexpr (NV == 4) kin = 0.5 * (U[1] * U[1] + U[2] * U[2]) * ir;
+    else kin = 0.5 * U[1] * U[1] * ir;
     return (gamma - 1.0) * (U[NV - 1] - kin);
 }
 
@@ -258,8 +258,9 @@ WCNST_HD double pressure(const double* U, double gamma)
 template <int NV>
 WCNST_HD void euler_flux(const double* U, double gamma, double* F)
 {
-    const double u = U[1] / U[0];
-    const double p = pressure<NV>(U, gamma);
+    const double ir = 1.0 / U[0];
+    const double u = U[1] * ir;
+    const double p = pressure<NV>(U, gamma, ir);
     F[0] = U[1];
     F[1] = U[1] * u + p;
     if constexpr (NV == 4) F[2] = U[2] * u;
@@ -336,21 +337,23 @@ template <int NV>
 WCNST_HD void roe_eigen(const double* A, const double* B, double gamma, Eigen<NV>& E)
 {
     const double rA = A[0], rB = B[0];
-    const double uA = A[1] / rA, uB = B[1] / rB;
-    const double vA = NV == 4 ? A[2] / rA : 0.0, vB = NV == 4 ? B[2] / rB : 0.0;
-    const double HA = (A[NV - 1] + pressure<NV>(A, gamma)) / rA;
-    const double HB = (B[NV - 1] + pressure<NV>(B, gamma)) / rB;
+    const double irA = 1.0 / rA, irB = 1.0 / rB;
+    const double uA = A[1] * irA, uB = B[1] * irB;
+    const double vA = NV == 4 ? A[2] * irA : 0.0, vB = NV == 4 ? B[2] * irB : 0.0;
+    const double HA = (A[NV - 1] + pressure<NV>(A, gamma, irA)) * irA;
+    const double HB = (B[NV - 1] + pressure<NV>(B, gamma, irB)) * irB;
     const double sA = sqrt(rA), sB = sqrt(rB);
-    E.u = (sA * uA + sB * uB) / (sA + sB);
-    E.v = (sA * vA + sB * vB) / (sA + sB);
-    E.H = (sA * HA + sB * HB) / (sA + sB);
+    const double is = 1.0 / (sA + sB);
+    E.u = (sA * uA + sB * uB) * is;
+    E.v = (sA * vA + sB * vB) * is;
+    E.H = (sA * HA + sB * HB) * is;
     E.q2 = E.u * E.u + E.v * E.v;
     const double c2 = (gamma - 1.0) * (E.H - 0.5 * E.q2);
     E.c = sqrt(c2);
-    E.b1 = (gamma - 1.0) / c2;
-    E.b2 = 0.5 * E.q2 * E.b1;
-    E.uc = E.u / E.c;
     E.ic = 1.0 / E.c;
+    E.b1 = (gamma - 1.0) * (E.ic * E.ic);
+    E.b2 = 0.5 * E.q2 * E.b1;
+    E.uc = E.u * E.ic;
 }
 
 // Numerical flux of the Euler equations from the interpolated states: the
@@ -364,8 +367,9 @@ WCNST_HD void euler_num_flux(const double* UL, const double* UR, double gamma, d
     euler_flux<NV>(UL, gamma, FL);
     euler_flux<NV>(UR, gamma, FR);
     if constexpr (FLUX == FLUX_LF) {
-        const double aL = fabs(UL[1] / UL[0]) + sqrt(gamma * pressure<NV>(UL, gamma) / UL[0]);
-        const double aR = fabs(UR[1] / UR[0]) + sqrt(gamma * pressure<NV>(UR, gamma) / UR[0]);
+        const double irL = 1.0 / UL[0], irR = 1.0 / UR[0];
+        const double aL = fabs(UL[1] * irL) + sqrt(gamma * pressure<NV>(UL, gamma, irL) * irL);
+        const double aR = fabs(UR[1] * irR) + sqrt(gamma * pressure<NV>(UR, gamma, irR) * irR);
         const double al = fmax(aL, aR);
 #pragma unroll
         for (int v = 0; v < NV; ++v) dis[v] = al * (UR[v] - UL[v]);
@@ -503,9 +507,10 @@ WCNST_HD double cell_speed(const double* U, const Params& P)
     if constexpr (SYS == SYS_ADV) return fabs(P.adv) / P.dx;
     else if constexpr (SYS == SYS_BURG) return fabs(U[0]) / P.dx;
     else {
-        const double a = sqrt(P.gamma * pressure<NV>(U, P.gamma) / U[0]);
-        double s = (fabs(U[1] / U[0]) + a) / P.dx;
-        if constexpr (NV == 4) s = s + (fabs(U[2] / U[0]) + a) / P.dy;
+        const double ir = 1.0 / U[0];
+        const double a = sqrt(P.gamma * pressure<NV>(U, P.gamma, ir) * ir);
+        double s = (fabs(U[1] * ir) + a) / P.dx;
+        if constexpr (NV == 4) s = s + (fabs(U[2] * ir) + a) / P.dy;
         return s;
     }
 }
@@ -517,7 +522,7 @@ WCNST_HD bool cell_bad(const double* U, const Params& P)
     bool bad = false;
 #pragma unroll
     for (int v = 0; v < NV; ++v) bad |= !isfinite(U[v]);
-    if constexpr (SYS == SYS_EULER) bad |= !(U[0] > 0.0) || !(pressure<NV>(U, P.gamma) > 0.0);
+    if constexpr (SYS == SYS_EULER) bad |= !(U[0] > 0.0) || !(pressure<NV>(U, P.gamma, 1.0 / U[0]) > 0.0);
     return bad;
 }
 
