@@ -312,27 +312,6 @@ struct Eigen {
     WCNST_HD double lam(int k) const { return k == 0 ? u - c : (k == NV - 1 ? u + c : u); }
 };
 
-// Scheduling fence between characteristic fields (no instruction emitted).
-WCNST_HD void field_fence()
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    __builtin_amdgcn_sched_barrier(0);
-#endif
-}
-
-// An empty register constraint: the compiler must treat the values as
-// changed here, so expressions built from them are formed after this point.
-template <int NV>
-WCNST_HD void opaque(Eigen<NV>& E)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    asm volatile("" : "+v"(E.u), "+v"(E.v), "+v"(E.H), "+v"(E.c), "+v"(E.q2));
-    asm volatile("" : "+v"(E.b1), "+v"(E.b2), "+v"(E.uc), "+v"(E.ic));
-#else
-    (void)E;
-#endif
-}
-
 template <int NV>
 WCNST_HD void roe_eigen(const double* A, const double* B, double gamma, Eigen<NV>& E)
 {
@@ -398,15 +377,12 @@ WCNST_HD void euler_num_flux(const double* UL, const double* UR, double gamma, d
 
 // --------------------------------------------------------- midpoint flux
 
-// Stencil accessors: st(m, v) is variable v (normal momentum first) of node
-// j-2+m.  refresh() marks the point where values are read again (a register
-// stencil ignores it; a stencil staged in LDS re-reads it per field rather
-// than holding all 6 x NV values in registers).
+// Stencil accessor: st(m, v) is variable v (normal momentum first) of node
+// j-2+m, held in registers.
 template <int NV>
 struct RegStencil {
     const double (&s)[6][NV];
     WCNST_HD double operator()(int m, int v) const { return s[m][v]; }
-    WCNST_HD void refresh() {}
 };
 
 // s: nodes j-2 .. j+3 around x_{j+1/2}.  F: flux at x_{j+1/2}.
@@ -438,13 +414,7 @@ WCNST_HD void face_flux(ST& st, const Params& P, double (&F)[NV], unsigned& fb)
             // increasing order, as in U = sum_k r_k w_k)
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
-                // keep the eigenvector entries and the stencil reads of field
-                // k local to this field (formed here, not hoisted and held for
-                // all k, and not interleaved with the next field)
-                field_fence();
-                Eigen<NV> Ek = E;
-                opaque(Ek);
-                st.refresh();
+                const Eigen<NV>& Ek = E;
                 double w[6];
 #pragma unroll
                 for (int m = 0; m < 6; ++m) {

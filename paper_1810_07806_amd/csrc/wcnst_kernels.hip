@@ -256,20 +256,6 @@ sweep1d_multi(const ReqGrid* __restrict__ reqs, int nreq, int stage, int tick_st
 constexpr int XW = WAVE + 5;
 constexpr int NSLOT = 6;  // rows j-2 .. j+3 around y-midpoint j
 
-// Stencil read from the staged rows: element (m, v) at base[off[m] + vs[v]].
-template <int NV>
-struct LdsStencil {
-    const double* base;
-    int off[6];
-    int vs[NV];
-    __device__ double operator()(int m, int v) const { return base[off[m] + vs[v]]; }
-    // re-read per characteristic field: the offsets are treated as changed
-    __device__ void refresh()
-    {
-        asm volatile("" : "+v"(off[0]), "+v"(off[1]), "+v"(off[2]), "+v"(off[3]), "+v"(off[4]), "+v"(off[5]));
-    }
-};
-
 template <int NV>
 __device__ __forceinline__ void load_row(const double* __restrict__ U, size_t plane, size_t rowoff,
                                          int colA, int colB, bool hasB, double (&ra)[NV], double (&rb)[NV])
@@ -300,6 +286,7 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
                                               Ctrl* __restrict__ ctrl, const Params& P, const StageArgs& A,
                                               int ty, int bx, int by)
 {
+    static_assert(NV == 4, "2D sweeps carry the four Euler variables");
     double dt = 0.0;
     long long step = 0;
     if constexpr (MODE == MODE_STAGE) {
@@ -355,18 +342,23 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
 #pragma unroll 1
         for (int pass = 0; pass < npass; ++pass) {
             const bool py = pass == 0;
-            LdsStencil<NV> st;
-            st.base = &ring[0][0][0];
+            // the six stencil nodes, read once into registers: node m at
+            // ring[slot][var][col] with (slot, col) = (row j-2+m, c) in the
+            // y pass and (row i, jx-2+m) in the x pass
+            const double* rb = &ring[0][0][0];
             const int slx = base + 1 < NSLOT ? base + 1 : base + 1 - NSLOT;
+            const int vs1 = py ? 2 * XW : XW, vs2 = py ? XW : 2 * XW;
+            double s[6][NV];
 #pragma unroll
             for (int m = 0; m < 6; ++m) {
                 const int sl = base + m < NSLOT ? base + m : base + m - NSLOT;
-                st.off[m] = py ? sl * NV * XW + lane + 4 : slx * NV * XW + lane + m;
+                const int off = py ? sl * NV * XW + lane + 4 : slx * NV * XW + lane + m;
+                s[m][0] = rb[off];
+                s[m][1] = rb[off + vs1];
+                s[m][2] = rb[off + vs2];
+                s[m][3] = rb[off + 3 * XW];
             }
-            st.vs[0] = 0;
-            st.vs[1] = py ? 2 * XW : XW;
-            st.vs[2] = py ? XW : 2 * XW;
-            st.vs[3] = 3 * XW;
+            RegStencil<NV> st{s};
             double F[NV];
             unsigned fb;
             face_flux<SYS_EULER, NV, FLUX, SCHEME, CHAR>(st, P, F, fb);
@@ -389,7 +381,7 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
                 // x node flux at node jx+1 of row i
                 double sn[NV], fn[NV];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) sn[v] = st(3, v);
+                for (int v = 0; v < NV; ++v) sn[v] = s[3][v];
                 node_flux<SYS_EULER, NV>(sn, P, fn);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
