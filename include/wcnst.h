@@ -53,7 +53,7 @@ enum { WCNST_ADVECTION = 0, WCNST_BURGERS = 1, WCNST_EULER = 2 };
 enum { WCNST_PERIODIC = 0, WCNST_ZERO_GRADIENT = 1 };
 enum { WCNST_ROE = 0, WCNST_LF = 1 };
 enum { WCNST_TENO = 0, WCNST_LINEAR = 1, WCNST_JS = 2 };
-enum { WCNST_MND = 0 };
+enum { WCNST_MND = 0, WCNST_MD = 1 };
 
 /* Problem descriptor.  Initialise with wcnst_desc_init(), then set fields. */
 typedef struct wcnst_desc {
@@ -63,10 +63,11 @@ typedef struct wcnst_desc {
     int32_t nx, ny;       /* unknowns per direction, >= 5 (ny = 1 in 1D) */
     double x0, x1;        /* domain; spacing dx = (x1 - x0) / nx */
     double y0, y1;        /* dy = (y1 - y0) / ny in 2D */
-    int32_t bc_x, bc_y;   /* WCNST_PERIODIC / WCNST_ZERO_GRADIENT (4 ghost cells) */
+    int32_t bc_x, bc_y;   /* WCNST_PERIODIC / WCNST_ZERO_GRADIENT (ghost cells by index remap) */
     int32_t flux;         /* WCNST_ROE (no entropy fix) / WCNST_LF (local) */
     int32_t scheme;       /* WCNST_TENO (Eqs. 16-19) / WCNST_LINEAR (Eq. 12) / WCNST_JS (Eq. 14) */
-    int32_t diff;         /* WCNST_MND (Eq. 5) */
+    int32_t diff;         /* WCNST_MND (Eq. 5, 4 ghost cells) / WCNST_MD (Eq. 3, 5 ghost cells;
+                             1D single solves only: batches and pools use MND) */
     int32_t charwise;     /* Euler: 1 = interpolate characteristic variables */
     int32_t q;            /* TENO integer power, Eq. (16); default 6 */
     double gamma;         /* ratio of specific heats, > 1; default 1.4 */
@@ -96,13 +97,16 @@ wcnst_status wcnst_create(const wcnst_desc* d, void* hip_stream, void* workspace
                           size_t ws_bytes, wcnst_solver** out);
 
 /* Discrete right-hand side R = -(dF/dx + dG/dy) of Eq. (2) for the state U
- * (Sec. 2.1 Eq. (5) on midpoint fluxes from Sec. 2.2-2.3), ghost cells
- * filled by the boundary conditions.  U and R are device arrays of
- * nvar*ny*nx doubles and must not overlap.  Asynchronous.
+ * (Sec. 2.1 Eq. (5), or Eq. (3) for WCNST_MD, on midpoint fluxes from
+ * Sec. 2.2-2.3), ghost cells filled by the boundary conditions.  U and R
+ * are device arrays of nvar*ny*nx doubles and must not overlap.
+ * Asynchronous.
  * flags (nullable, device, uint8): the stencil-cut pattern of every
  * interpolation, direction x first then y:
  *   x block [nvar][ny][nx+3][2], y block [nvar][nx][ny+3][2];
- * entry [k][line][s][side] is for the midpoint x_{j+1/2}, j = s - 2, of
+ *   with WCNST_MD (1D) the one block is [nvar][1][nx+5][2];
+ * entry [k][line][s][side] is for the midpoint x_{j+1/2}, j = s - 2 (MND)
+ * or j = s - 3 (MD), of
  * characteristic field k (conserved variable k when charwise = 0; for y
  * lines the normal momentum comes first), side 0 = u_L, side 1 = u_R
  * (mirrored stencil); bit k-1 holds delta_k of Eq. (18).  Scalar schemes

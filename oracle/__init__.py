@@ -13,7 +13,7 @@ import os
 
 import numpy as np
 
-from .build import LIB_PATH as _DEFAULT_LIB, build
+from .build import LIB_PATH as _DEFAULT_LIB, SRC as _SRC, build
 
 # a different build of the same source may be substituted for experiments
 LIB_PATH = os.environ.get("WCNST_ORACLE_LIB", _DEFAULT_LIB)
@@ -50,10 +50,13 @@ _lib = None
 
 
 def lib():
-    """Load the oracle library, compiling it first only if it is absent."""
+    """Load the oracle library, compiling it first if it is absent or older
+    than its source."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        stale = LIB_PATH == _DEFAULT_LIB and os.path.exists(LIB_PATH) and \
+            os.path.getmtime(LIB_PATH) < os.path.getmtime(_SRC)
+        if not os.path.exists(LIB_PATH) or stale:
             build()
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.POINTER(Problem)

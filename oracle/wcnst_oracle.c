@@ -80,13 +80,16 @@ void orc_candidates(const double s[5], double cand[3], double beta[3])
 {
     const double a = s[0], b = s[1], c = s[2], d = s[3], e = s[4];
     double D1[3], D2[3];
-    /* Eq. (10) times h and Eq. (11) times h^2, on the substencils of Eq. (8). */
+    /* Eq. (10) times h and Eq. (11) times h^2, on the substencils of Eq. (8).
+     * Each second difference adds its outer nodes first, (u_{m-1} + u_{m+1})
+     * - 2 u_m, so it takes the same value whichever end the stencil is read
+     * from. */
     D1[0] = (a - 4.0 * b + 3.0 * c) / 2.0;
     D1[1] = (d - b) / 2.0;
     D1[2] = (-3.0 * c + 4.0 * d - e) / 2.0;
-    D2[0] = a - 2.0 * b + c;
-    D2[1] = b - 2.0 * c + d;
-    D2[2] = c - 2.0 * d + e;
+    D2[0] = (a + c) - 2.0 * b;
+    D2[1] = (b + d) - 2.0 * c;
+    D2[2] = (c + e) - 2.0 * d;
     for (int k = 0; k < 3; ++k) {
         /* Eq. (9) with Delta x = h/2: u_i + u' h/2 + u'' h^2/8. */
         cand[k] = c + D1[k] / 2.0 + D2[k] / 8.0;

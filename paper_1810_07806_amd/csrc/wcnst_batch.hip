@@ -94,6 +94,8 @@ static wcnst_status batch_check(const wcnst_desc* descs, int32_t n, long long* t
         if (st) return wcnst_fail(st, "descriptor %d: %s", i, wcnst_last_error());
         if (d.ndim != 1 || d.system != WCNST_EULER)
             return wcnst_fail(WCNST_E_INVALID_ARG, "descriptor %d: batches hold 1D Euler problems", i);
+        if (d.diff != WCNST_MND)
+            return wcnst_fail(WCNST_E_INVALID_ARG, "descriptor %d: batches use the MND difference", i);
         if (wcnst_check_same_scheme(a, d))
             return wcnst_fail(WCNST_E_INVALID_ARG, "descriptor %d: scheme parameters differ from descriptor 0", i);
         if (offs) (*offs)[i] = off;

@@ -40,7 +40,7 @@ struct Params {
     double gamma;
     double adv;
     double dx, dy;
-    double c1x, c2x, c3x;  // MND coefficients divided by dx
+    double c1x, c2x, c3x;  // difference coefficients (MND, or MD in 1D) divided by dx
     double c1y, c2y, c3y;  // ... and by dy
     int q, charwise;
     int bc_x, bc_y;
@@ -84,22 +84,12 @@ struct ReqGrid {
 
 // ------------------------------------------------------------ helpers
 
-// A copy of a table entry that the host wrote before this launch, read with
-// system-scope loads: they are coherent with host copies whatever an L2
-// still holds of the same memory from an earlier launch (entries that
-// decide the control flow of cooperating waves must be seen alike by all).
+// A copy of a table entry.  Tables reach device memory by copies ordered
+// before the launch on its stream, so plain loads see them.
 template <class T>
-__device__ __forceinline__ T load_host_written(const T* p)
+__device__ __forceinline__ T load_table_entry(const T* p)
 {
-    static_assert(sizeof(T) % 8 == 0 && alignof(T) >= 8, "8-byte granular entries");
-    const unsigned long long* s = reinterpret_cast<const unsigned long long*>(p);
-    unsigned long long words[sizeof(T) / 8];
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(T) / 8); ++i)
-        words[i] = __hip_atomic_load(s + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    T out;
-    __builtin_memcpy(&out, words, sizeof(T));
-    return out;
+    return *p;
 }
 
 WCNST_HD int ghost_map(int g, int n, int bc)
@@ -121,15 +111,14 @@ WCNST_HD int ghost_map_any(int g, int n, int bc)
     return g >= n ? n - 1 : g;
 }
 
-// 1/x to about one ulp for the cut-off test (two Newton steps on the
-// hardware estimate); exact division on the host.
+// 1/x for the cut-off test: one Newton step on the hardware estimate
+// (about 24 correct bits) leaves a relative error below 3e-15, far inside
+// the band where the test is decided by rounding; exact division on the host.
 WCNST_HD double approx_rcp(double x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    double r = __builtin_amdgcn_rcp(x);
-    double e = __builtin_fma(-x, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-x, r, 1.0);
+    const double r = __builtin_amdgcn_rcp(x);
+    const double e = __builtin_fma(-x, r, 1.0);
     return __builtin_fma(r, e, r);
 #else
     return 1.0 / x;
@@ -185,9 +174,11 @@ WCNST_HD double interp5(double a, double b, double c, double d, double e, const 
     const double D10 = (a - 4.0 * b + 3.0 * c) / 2.0;
     const double D11 = (d - b) / 2.0;
     const double D12 = (-3.0 * c + 4.0 * d - e) / 2.0;
-    const double D20 = a - 2.0 * b + c;
-    const double D21 = b - 2.0 * c + d;
-    const double D22 = c - 2.0 * d + e;
+    // outer nodes first: the mirrored right-side interpolation of the same
+    // face forms the same second differences (shared, not recomputed)
+    const double D20 = (a + c) - 2.0 * b;
+    const double D21 = (b + d) - 2.0 * c;
+    const double D22 = (c + e) - 2.0 * d;
     // candidates, Eq. (9) with Delta x = h/2
     const double q0 = c + D10 / 2.0 + D20 / 8.0;
     const double q1 = c + D11 / 2.0 + D21 / 8.0;
@@ -279,6 +270,13 @@ template <int NV>
 struct Eigen {
     double u, v, H, c, q2, b1, b2, uc, ic;
 
+    // Structural zeros of L and R (the shear pair).  Products are summed
+    // over the other entries only, in increasing index order, starting from
+    // the first product: the sums equal the full matrix products except,
+    // at most, for the sign of a zero result.
+    WCNST_HD static constexpr bool L_zero(int k, int j) { return NV == 4 && k == 2 && (j == 1 || j == 3); }
+    WCNST_HD static constexpr bool R_zero(int j, int k) { return NV == 4 && k == 2 && (j == 0 || j == 1); }
+
     // entry (k, j) of L and (j, k) of R, each formed by the same expression
     // wherever it is used
     WCNST_HD double L(int k, int j) const
@@ -360,14 +358,22 @@ WCNST_HD void euler_num_flux(const double* UL, const double* UR, double gamma, d
         for (int k = 0; k < NV; ++k) {
             double acc = 0.0;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) acc += E.L(k, v) * (UR[v] - UL[v]);
+            for (int v = 0; v < NV; ++v) {
+                if (Eigen<NV>::L_zero(k, v)) continue;
+                const double t = E.L(k, v) * (UR[v] - UL[v]);
+                acc = v == 0 ? t : acc + t;
+            }
             alpha[k] = acc;
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             double acc = 0.0;
 #pragma unroll
-            for (int k = 0; k < NV; ++k) acc += E.R(v, k) * fabs(E.lam(k)) * alpha[k];
+            for (int k = 0; k < NV; ++k) {
+                if (Eigen<NV>::R_zero(v, k)) continue;
+                const double t = E.R(v, k) * fabs(E.lam(k)) * alpha[k];
+                acc = k == 0 ? t : acc + t;
+            }
             dis[v] = acc;
         }
     }
@@ -404,14 +410,10 @@ WCNST_HD void face_flux(ST& st, const Params& P, double (&F)[NV], unsigned& fb)
                 }
                 roe_eigen<NV>(A, B, P.gamma, E);
             }
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                UL[v] = 0.0;
-                UR[v] = 0.0;
-            }
             // one characteristic field at a time: project, interpolate both
             // sides, and add its share of the back-projection (sums over k in
-            // increasing order, as in U = sum_k r_k w_k)
+            // increasing order, as in U = sum_k r_k w_k; field 0 has no
+            // structural zero in R, so it starts every sum)
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
                 const Eigen<NV>& Ek = E;
@@ -420,7 +422,11 @@ WCNST_HD void face_flux(ST& st, const Params& P, double (&F)[NV], unsigned& fb)
                 for (int m = 0; m < 6; ++m) {
                     double acc = 0.0;
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) acc += Ek.L(k, v) * st(m, v);
+                    for (int v = 0; v < NV; ++v) {
+                        if (Eigen<NV>::L_zero(k, v)) continue;
+                        const double t = Ek.L(k, v) * st(m, v);
+                        acc = v == 0 ? t : acc + t;
+                    }
                     w[m] = acc;
                 }
                 unsigned mL, mR;
@@ -429,9 +435,15 @@ WCNST_HD void face_flux(ST& st, const Params& P, double (&F)[NV], unsigned& fb)
                 fb |= (mL | (mR << 3)) << (6 * k);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
+                    if (Eigen<NV>::R_zero(v, k)) continue;
                     const double r = Ek.R(v, k);
-                    UL[v] += r * wl;
-                    UR[v] += r * wr;
+                    if (k == 0) {
+                        UL[v] = r * wl;
+                        UR[v] = r * wr;
+                    } else {
+                        UL[v] += r * wl;
+                        UR[v] += r * wr;
+                    }
                 }
             }
         } else {
@@ -507,6 +519,15 @@ WCNST_HD void rk_combine(int stage, double dt, const double* Uk, const double* U
         else if (stage == 1) o[v] = 0.75 * Un[v] + 0.25 * (Uk[v] + dt * R[v]);
         else o[v] = (1.0 / 3.0) * Un[v] + (2.0 / 3.0) * (Uk[v] + dt * R[v]);
     }
+}
+
+// MD difference, Eq. (3): -(a1 (F_{i+1/2} - F_{i-1/2}) + a2 (F_{i+3/2} - F_{i-3/2})
+// + a3 (F_{i+5/2} - F_{i-5/2})) with a_k already divided by h.
+WCNST_HD double md(double a1, double a2, double a3, double Fm5, double Fm3, double Fm1, double Fp1, double Fp3,
+                   double Fp5)
+{
+    const double dfdx = a1 * (Fp1 - Fm1) + a2 * (Fp3 - Fm3) + a3 * (Fp5 - Fm5);
+    return -dfdx;
 }
 
 // MND difference, Eq. (5): -(c1 (F_{i+1/2} - F_{i-1/2}) + c2 (f_{i+1} - f_{i-1})

@@ -35,6 +35,16 @@ constexpr int WAVE = 64;
 constexpr int TX = WAVE - 3;  // cells per strip
 
 enum { MODE_RHS = 0, MODE_STAGE = 1 };
+enum { DIFF_MND = 0, DIFF_MD = 1 };
+
+// 1D strips: the 64 midpoints of a wavefront serve the cells whose
+// differences reach only them; MND reaches 3/2 spacings from a cell (61
+// cells per strip), MD 5/2 spacings (59 cells).
+template <int DIFF>
+constexpr int strip_cells()
+{
+    return DIFF == DIFF_MD ? WAVE - 5 : WAVE - 3;
+}
 
 struct StageArgs {
     double t_final;
@@ -55,19 +65,25 @@ __device__ __forceinline__ bool stage_prologue(Ctrl* ctrl, const StageArgs& A, d
                                                long long& step, bool lead)
 {
     const StepRec* cur = &ctrl->rec[A.parity];
-    if (ctrl->status != 0 || ctrl->done != 0) return false;
-    step = cur->step;
+    // independent reads, issued together (stage 0's lead writes the record's
+    // dt, so only stages 1-2 read it)
+    const int status = ctrl->status, done = ctrl->done;
+    const long long stp = cur->step;
+    const double t = cur->t;
+    const unsigned long long sbits = cur->smax_bits;
+    const double dt_rec = A.stage != 0 ? cur->dt : 0.0;
+    if (status != 0 || done != 0) return false;
+    step = stp;
     if (A.stage != 0) {
-        dt = cur->dt;
+        dt = dt_rec;
         return true;
     }
-    const double t = cur->t;
     const bool fin = isfinite(A.t_final);
     if (fin && A.t_final - t <= 1e-12 * A.t_final) {
         if (lead) ctrl->done = 1;
         return false;
     }
-    const double smax = __longlong_as_double((long long)cur->smax_bits);
+    const double smax = __longlong_as_double((long long)sbits);
     dt = A.fixed_dt > 0.0 ? A.fixed_dt : A.cfl / smax;
     if (fin && dt > A.t_final - t) dt = A.t_final - t;
     if (lead) {
@@ -136,11 +152,35 @@ __device__ __forceinline__ void write_flags(uint8_t* fl, int nlines, int nfaces,
 // ------------------------------------------------------------------ 1D
 
 // Strip bx of one 1D grid.  Thread 0 of strip 0 opens the next step record.
-template <int SYS, int NV, int FLUX, int SCHEME, bool CHAR, int MODE>
+// Lane l computes midpoint x0-G+l+1/2 (G = 2 for MND, 3 for MD); the grid
+// needs midpoints -G .. jmax = nx-2+G, so jmax+G+1 = nx+2G-1 flag slots.
+template <int SYS, int NV, int FLUX, int SCHEME, bool CHAR, int MODE, int DIFF = DIFF_MND>
 __device__ __forceinline__ void sweep1d_block(const double* __restrict__ U, const double* __restrict__ Un,
                                               double* __restrict__ out, uint8_t* __restrict__ flags,
                                               Ctrl* __restrict__ ctrl, const Params& P, const StageArgs& A, int bx)
 {
+    constexpr int W = strip_cells<DIFF>();
+    constexpr int G = DIFF == DIFF_MD ? 3 : 2;
+    const int nx = P.nx;
+    const int lane = threadIdx.x;
+    const int x0 = bx * W;
+    const int c = x0 + lane;
+    const bool cell_ok = lane < W && c < nx;
+    const int jx = x0 - G + lane;
+    const int jmax = nx - 2 + G;
+    const int jxl = min(jx, jmax);  // lanes past the last midpoint load in-range data
+
+    // the stencil (and U^n of this lane's cell) load while the control
+    // record is read
+    double s[6][NV], un[NV];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        const int col = ghost_map(jxl - 2 + m, nx, P.bc_x);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s[m][v] = U[(size_t)v * nx + col];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) un[v] = MODE == MODE_STAGE && A.stage && cell_ok ? Un[(size_t)v * nx + c] : 0.0;
     double dt = 0.0;
     long long step = 0;
     if constexpr (MODE == MODE_STAGE) {
@@ -149,49 +189,37 @@ __device__ __forceinline__ void sweep1d_block(const double* __restrict__ U, cons
     __shared__ double sF[NV][WAVE];
     __shared__ double sN[NV][WAVE];
     init_weight_table();
-    const int nx = P.nx;
-    const int lane = threadIdx.x;
-    const int x0 = bx * TX;
-    const int c = x0 + lane;
-    const bool cell_ok = lane < TX && c < nx;
-    const int jx = x0 - 2 + lane;
-    const int jxl = min(jx, nx);  // lanes past the last midpoint load in-range data
-
-    double s[6][NV];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-        const int col = ghost_map(jxl - 2 + m, nx, P.bc_x);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) s[m][v] = U[(size_t)v * nx + col];
-    }
     double F[NV], fn[NV];
     unsigned fb;
     RegStencil<NV> st{s};
     face_flux<SYS, NV, FLUX, SCHEME, CHAR>(st, P, F, fb);
-    if (flags && jx <= nx && face_owner(jx, nx, TX) == bx)
-        write_flags<NV>(flags, 1, nx + 3, 0, jx + 2, fb);
-    node_flux<SYS, NV>(s[3], P, fn);
+    if (flags && jx <= jmax && face_owner(jx, nx, W) == bx)
+        write_flags<NV>(flags, 1, jmax + G + 1, 0, jx + G, fb);
+    if constexpr (DIFF == DIFF_MND) node_flux<SYS, NV>(s[3], P, fn);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         sF[v][lane] = F[v];
-        sN[v][lane] = fn[v];
+        if constexpr (DIFF == DIFF_MND) sN[v][lane] = fn[v];
     }
     __syncthreads();
     unsigned long long sm = 0ull;
     if (cell_ok) {
         double R[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-            R[v] = mnd(P.c1x, P.c2x, P.c3x, sF[v][lane], sF[v][lane + 1], sF[v][lane + 2], sF[v][lane + 3],
-                       sN[v][lane], sN[v][lane + 2]);
+        for (int v = 0; v < NV; ++v) {
+            if constexpr (DIFF == DIFF_MD)
+                R[v] = md(P.c1x, P.c2x, P.c3x, sF[v][lane], sF[v][lane + 1], sF[v][lane + 2], sF[v][lane + 3],
+                          sF[v][lane + 4], sF[v][lane + 5]);
+            else
+                R[v] = mnd(P.c1x, P.c2x, P.c3x, sF[v][lane], sF[v][lane + 1], sF[v][lane + 2], sF[v][lane + 3],
+                           sN[v][lane], sN[v][lane + 2]);
+        }
         if constexpr (MODE == MODE_RHS) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) out[(size_t)v * nx + c] = R[v];
         } else {
-            double un[NV], o[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) un[v] = A.stage ? Un[(size_t)v * nx + c] : 0.0;
-            rk_combine<NV>(A.stage, dt, s[4], un, R, o);
+            double o[NV];
+            rk_combine<NV>(A.stage, dt, s[G + 2], un, R, o);
 #pragma unroll
             for (int v = 0; v < NV; ++v) out[(size_t)v * nx + c] = o[v];
             stage_epilogue<SYS, NV>(ctrl, P, A.stage, step, c, o, sm);
@@ -202,26 +230,25 @@ __device__ __forceinline__ void sweep1d_block(const double* __restrict__ U, cons
     }
 }
 
-template <int SYS, int NV, int FLUX, int SCHEME, bool CHAR, int MODE>
+template <int SYS, int NV, int FLUX, int SCHEME, bool CHAR, int MODE, int DIFF>
 __global__ void __launch_bounds__(WAVE)
 sweep1d(const double* __restrict__ U, const double* __restrict__ Un, double* __restrict__ out,
         uint8_t* __restrict__ flags, Ctrl* __restrict__ ctrl, Params P, StageArgs A)
 {
-    sweep1d_block<SYS, NV, FLUX, SCHEME, CHAR, MODE>(U, Un, out, flags, ctrl, P, A, (int)blockIdx.x);
+    sweep1d_block<SYS, NV, FLUX, SCHEME, CHAR, MODE, DIFF>(U, Un, out, flags, ctrl, P, A, (int)blockIdx.x);
 }
 
 // The table row of block b: the grid r with blk0[r] <= b < blk0[r+1]
-// (binary search, uniform per block).  The table is host-written for each
-// launch sequence: system-scope reads.
+// (binary search, uniform per block).
 __device__ __forceinline__ ReqGrid load_request(const ReqGrid* __restrict__ reqs, int nreq, int b)
 {
     int lo = 0, hi = nreq - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (__hip_atomic_load(&reqs[mid].blk0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) <= b) lo = mid;
+        if (reqs[mid].blk0 <= b) lo = mid;
         else hi = mid - 1;
     }
-    return load_host_written(&reqs[lo]);
+    return load_table_entry(&reqs[lo]);
 }
 
 __device__ __forceinline__ StageArgs request_stage(const ReqGrid& R, int stage, int tick_step)
@@ -483,7 +510,7 @@ sweep2d_multi(const ReqGrid* __restrict__ reqs, int nreq, int stage, int tick_st
 template <int NV>
 __global__ void __launch_bounds__(256) multi_init(const ReqGrid* __restrict__ reqs)
 {
-    const ReqGrid R = load_host_written(&reqs[blockIdx.x]);
+    const ReqGrid R = load_table_entry(&reqs[blockIdx.x]);
     const size_t plane = (size_t)R.P.nx * R.P.ny;
     unsigned long long m = 0ull;
     for (size_t i = threadIdx.x; i < plane; i += blockDim.x) {
@@ -625,7 +652,9 @@ wcnst_status wcnst_check_desc(const wcnst_desc* d)
             return fail(WCNST_E_INVALID_ARG, "unknown boundary condition %d", b);
     if (d->flux != WCNST_ROE && d->flux != WCNST_LF) return fail(WCNST_E_INVALID_ARG, "unknown flux");
     if (d->scheme < WCNST_TENO || d->scheme > WCNST_JS) return fail(WCNST_E_INVALID_ARG, "unknown scheme");
-    if (d->diff != WCNST_MND) return fail(WCNST_E_INVALID_ARG, "only the MND difference is built");
+    if (d->diff != WCNST_MND && d->diff != WCNST_MD) return fail(WCNST_E_INVALID_ARG, "unknown difference");
+    if (d->diff == WCNST_MD && d->ndim != 1)
+        return fail(WCNST_E_INVALID_ARG, "the MD difference is built for 1D grids");
     if (d->system == WCNST_EULER && !(d->gamma > 1.0)) return fail(WCNST_E_INVALID_ARG, "gamma must be > 1");
     if (d->q < 1 || d->q > 64) return fail(WCNST_E_INVALID_ARG, "q must be in [1, 64]");
     if (!(d->CT > 0.0 && d->CT < 1.0 / 3.0)) return fail(WCNST_E_INVALID_ARG, "C_T must be in (0, 1/3)");
@@ -690,10 +719,17 @@ void wcnst_make_params(const wcnst_desc* d, Params* out)
     P.ny = d->ny;
     P.dx = (d->x1 - d->x0) / d->nx;
     P.dy = d->ndim == 2 ? (d->y1 - d->y0) / d->ny : 1.0;
-    // Eq. (5) coefficients (3/2, -3/10, 1/30) divided by the spacing
-    P.c1x = (3.0 / 2.0) / P.dx;
-    P.c2x = (-3.0 / 10.0) / P.dx;
-    P.c3x = (1.0 / 30.0) / P.dx;
+    // Eq. (5) coefficients (3/2, -3/10, 1/30), or Eq. (3) coefficients
+    // (75/64, -25/384, 3/640) for MD, divided by the spacing
+    if (d->diff == WCNST_MD) {
+        P.c1x = (75.0 / 64.0) / P.dx;
+        P.c2x = (-25.0 / 384.0) / P.dx;
+        P.c3x = (3.0 / 640.0) / P.dx;
+    } else {
+        P.c1x = (3.0 / 2.0) / P.dx;
+        P.c2x = (-3.0 / 10.0) / P.dx;
+        P.c3x = (1.0 / 30.0) / P.dx;
+    }
     P.c1y = (3.0 / 2.0) / P.dy;
     P.c2y = (-3.0 / 10.0) / P.dy;
     P.c3y = (1.0 / 30.0) / P.dy;
@@ -773,14 +809,19 @@ template <int SYS, int NV, int FLUX, int SCHEME, bool CHAR, int MODE>
 static void launch_sweep_t(const wcnst_solver* s, const double* U, const double* Un, double* out,
                            uint8_t* flags, const StageArgs& A)
 {
-    const int nstrips = (s->d.nx + TX - 1) / TX;
     if constexpr (SYS == SYS_EULER && NV == 4) {
+        const int nstrips = (s->d.nx + TX - 1) / TX;
         const int nseg = (s->d.ny + s->ty - 1) / s->ty;
         hipLaunchKernelGGL((sweep2d<NV, FLUX, SCHEME, CHAR, MODE>), dim3(nstrips, nseg), dim3(WAVE), 0,
                            s->stream, U, Un, out, flags, s->ctrl, s->P, A, s->ty);
+    } else if (s->d.diff == WCNST_MD) {
+        constexpr int W = strip_cells<DIFF_MD>();
+        hipLaunchKernelGGL((sweep1d<SYS, NV, FLUX, SCHEME, CHAR, MODE, DIFF_MD>), dim3((s->d.nx + W - 1) / W),
+                           dim3(WAVE), 0, s->stream, U, Un, out, flags, s->ctrl, s->P, A);
     } else {
-        hipLaunchKernelGGL((sweep1d<SYS, NV, FLUX, SCHEME, CHAR, MODE>), dim3(nstrips), dim3(WAVE), 0,
-                           s->stream, U, Un, out, flags, s->ctrl, s->P, A);
+        constexpr int W = strip_cells<DIFF_MND>();
+        hipLaunchKernelGGL((sweep1d<SYS, NV, FLUX, SCHEME, CHAR, MODE, DIFF_MND>), dim3((s->d.nx + W - 1) / W),
+                           dim3(WAVE), 0, s->stream, U, Un, out, flags, s->ctrl, s->P, A);
     }
 }
 

@@ -97,6 +97,7 @@ extern "C" wcnst_status wcnst_pool_create(const wcnst_desc* scheme, int32_t capa
     wcnst_status st = wcnst_check_desc(scheme);
     if (st) return st;
     if (scheme->system != WCNST_EULER) return wcnst_fail(WCNST_E_INVALID_ARG, "pools hold Euler problems");
+    if (scheme->diff != WCNST_MND) return wcnst_fail(WCNST_E_INVALID_ARG, "pools use the MND difference");
     size_t need = 0;
     st = wcnst_pool_workspace_size(capacity, &need);
     if (st) return st;

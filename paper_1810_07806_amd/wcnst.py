@@ -18,7 +18,7 @@ _SYSTEM = {"advection": 0, "burgers": 1, "euler": 2}
 _BC = {"periodic": 0, "zero_gradient": 1}
 _FLUX = {"roe": 0, "lf": 1}
 _SCHEME = {"teno": 0, "linear": 1, "js": 2}
-_DIFF = {"mnd": 0}
+_DIFF = {"mnd": 0, "md": 1}
 
 EXPORTS = ("wcnst_desc_init", "wcnst_workspace_size", "wcnst_create", "wcnst_rhs", "wcnst_step",
            "wcnst_solve", "wcnst_status_sync", "wcnst_reset", "wcnst_set_tuning", "wcnst_profile_enable",
@@ -140,10 +140,15 @@ def nvar(desc: dict) -> int:
     return 3 if int(desc.get("ndim", 1)) == 1 else 4
 
 
+def _nfaces_1d(desc: dict) -> int:
+    """Midpoints of a 1D line: -2 .. nx for MND, -3 .. nx+1 for MD."""
+    return int(desc["nx"]) + (5 if desc.get("diff", "mnd") == "md" else 3)
+
+
 def flag_count(desc: dict) -> int:
     nv, nx = nvar(desc), int(desc["nx"])
     if int(desc.get("ndim", 1)) == 1:
-        return nv * (nx + 3) * 2
+        return nv * _nfaces_1d(desc) * 2
     ny = int(desc["ny"])
     return nv * ny * (nx + 3) * 2 + nv * nx * (ny + 3) * 2
 
@@ -245,7 +250,7 @@ def split_flags(desc: dict, fl):
     """Views of a flat flag buffer as the x (and y) blocks of ``wcnst_rhs``."""
     nv, nx = nvar(desc), int(desc["nx"])
     if int(desc.get("ndim", 1)) == 1:
-        return [fl.reshape(nv, 1, nx + 3, 2)]
+        return [fl.reshape(nv, 1, _nfaces_1d(desc), 2)]
     ny = int(desc["ny"])
     nxb = nv * ny * (nx + 3) * 2
     return [fl[:nxb].reshape(nv, ny, nx + 3, 2), fl[nxb:].reshape(nv, nx, ny + 3, 2)]

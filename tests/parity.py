@@ -58,14 +58,17 @@ def check_flags(fg_blocks, fo_blocks, chi_blocks, CT):
     return flips
 
 
-def rhs_mask_from_flips(shape, flips, ndim):
-    """Boolean mask (ny, nx) of cells whose stencil touches a flipped midpoint."""
+def rhs_mask_from_flips(shape, flips, ndim, diff="mnd"):
+    """Boolean mask (ny, nx) of cells whose stencil touches a flipped midpoint
+    (MND: midpoints within 3/2 spacings of a cell, slot s = j + 2; MD: within
+    5/2 spacings, slot s = j + 3)."""
     ny, nx = shape
+    g = 3 if diff == "md" else 2
     keep = np.ones((ny, nx), dtype=bool)
     for d, fl in enumerate(flips):
         for k, line, slot, side in fl:
-            j = slot - 2  # midpoint j + 1/2
-            lo, hi = max(0, j - 1), min((nx if d == 0 else ny) - 1, j + 2)
+            j = slot - g  # midpoint j + 1/2
+            lo, hi = max(0, j - g + 1), min((nx if d == 0 else ny) - 1, j + g)
             if d == 0:
                 keep[line, lo:hi + 1] = False
             else:

@@ -60,9 +60,11 @@ def test_workspace_size_and_validation():
     assert st == 0 and n >= 2 * 3 * 100 * 8
     st, n2 = _ws(wc, L, ndim=2, nx=2048, ny=2048)
     assert st == 0 and n2 >= 2 * 4 * 2048 * 2048 * 8
+    st, _ = _ws(wc, L, nx=100, diff="md")
+    assert st == 0
     bad = [dict(nx=4), dict(ndim=3), dict(ndim=2, system="advection", nx=8, ny=8),
            dict(ndim=2, nx=8, ny=4), dict(gamma=1.0), dict(CT=0.5), dict(q=0),
-           dict(x0=1.0, x1=1.0)]
+           dict(x0=1.0, x1=1.0), dict(ndim=2, nx=8, ny=8, diff="md")]
     for kw in bad:
         st, _ = _ws(wc, L, **kw)
         assert st == wc.E_INVALID_ARG, kw
@@ -80,3 +82,16 @@ def test_binding_refuses_a_missing_library(tmp_path):
     finally:
         wcnst._lib = saved
     importlib.reload  # keep the import used
+
+
+def test_batches_and_pools_refuse_the_md_difference():
+    """Batched and pooled solves run the MND stage kernels only; an MD
+    descriptor is refused at sizing time with a message, before any device
+    work."""
+    wc, L = _lib()
+    descs = (wc.Desc * 2)(*[wc.make_desc(dict(ndim=1, system="euler", nx=64, diff=df)) for df in ("mnd", "md")])
+    n = ctypes.c_size_t(0)
+    L.wcnst_batch_workspace_size.argtypes = [ctypes.POINTER(wc.Desc), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+    assert L.wcnst_batch_workspace_size(descs, 1, ctypes.byref(n)) == 0
+    assert L.wcnst_batch_workspace_size(descs, 2, ctypes.byref(n)) == wc.E_INVALID_ARG
+    assert b"MND" in L.wcnst_last_error()
