@@ -28,7 +28,6 @@ using namespace wcnst;
 
 namespace {
 
-constexpr int TX = 61;  // cells per strip
 constexpr int NV = 3;
 
 }  // namespace

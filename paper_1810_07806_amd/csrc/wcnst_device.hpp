@@ -34,6 +34,55 @@ enum { FLUX_ROE = 0, FLUX_LF = 1 };
 // SCH_TENO: Eq. (16) with the paper's q = 6; SCH_TENO_Q: any integer q
 enum { SCH_TENO = 0, SCH_LINEAR = 1, SCH_JS = 2, SCH_TENO_Q = 3 };
 enum { BC_PERIODIC = 0, BC_ZG = 1 };
+enum { DIFF_MND = 0, DIFF_MD = 1 };
+
+// ------------------------------------------------------ strip geometry
+
+constexpr int WAVE = 64;      // lanes per wavefront, one midpoint each
+constexpr int TX = WAVE - 3;  // cells per MND strip (1D) / columns per 2D strip
+
+// 1D strips: the 64 midpoints of a wavefront serve the cells whose
+// differences reach only them; MND reaches 3/2 spacings from a cell (61
+// cells per strip), MD 5/2 spacings (59 cells).
+template <int DIFF>
+constexpr int strip_cells()
+{
+    return DIFF == DIFF_MD ? WAVE - 5 : WAVE - 3;
+}
+
+// Owner of midpoint j (j in [-G, n-2+G]) among tiles of width w: the tile
+// of the nearest cell.
+WCNST_HD int face_owner(int j, int n, int w)
+{
+    j = j < 0 ? 0 : (j > n - 1 ? n - 1 : j);
+    return j / w;
+}
+
+// Lane `lane` of 1D strip bx on a line of nx cells.  The lane computes
+// midpoint jx+1/2, jx = x0-G+lane (G = 2 for MND, 3 for MD); the line needs
+// midpoints -G .. jmax = nx-2+G (jmax+G+1 flag slots).  Lanes past jmax
+// read the stencil of jmax (in-range data, result unused).  The lane owns
+// cell c = x0+lane when cell_ok; that cell's differences use the midpoints
+// of lanes lane .. lane+2G-1, and its own state is stencil node G+2.
+template <int DIFF>
+struct Strip1D {
+    static constexpr int W = strip_cells<DIFF>();
+    static constexpr int G = DIFF == DIFF_MD ? 3 : 2;
+    int x0, c, jx, jmax, jxl;
+    bool cell_ok;
+    WCNST_HD Strip1D(int bx, int lane, int nx)
+    {
+        x0 = bx * W;
+        c = x0 + lane;
+        cell_ok = lane < W && c < nx;
+        jx = x0 - G + lane;
+        jmax = nx - 2 + G;
+        jxl = jx < jmax ? jx : jmax;
+    }
+    // this lane reports the cut flags of its midpoint (each midpoint once)
+    WCNST_HD bool owns_face(int bx, int nx) const { return jx <= jmax && face_owner(jx, nx, W) == bx; }
+    WCNST_HD int nfaces() const { return jmax + G + 1; }
+};
 
 struct Params {
     double CT, C, eps_teno, eps_js;

@@ -31,20 +31,7 @@
 
 namespace wcnst {
 
-constexpr int WAVE = 64;
-constexpr int TX = WAVE - 3;  // cells per strip
-
 enum { MODE_RHS = 0, MODE_STAGE = 1 };
-enum { DIFF_MND = 0, DIFF_MD = 1 };
-
-// 1D strips: the 64 midpoints of a wavefront serve the cells whose
-// differences reach only them; MND reaches 3/2 spacings from a cell (61
-// cells per strip), MD 5/2 spacings (59 cells).
-template <int DIFF>
-constexpr int strip_cells()
-{
-    return DIFF == DIFF_MD ? WAVE - 5 : WAVE - 3;
-}
 
 struct StageArgs {
     double t_final;
@@ -130,13 +117,6 @@ __device__ __forceinline__ void flush_speed(Ctrl* ctrl, int parity, unsigned lon
     if (threadIdx.x == 0) atomicMax(&ctrl->rec[parity ^ 1].smax_bits, m);
 }
 
-// Owner of midpoint j (j in [-2, n]) among tiles of width w.
-__device__ __forceinline__ int face_owner(int j, int n, int w)
-{
-    j = j < 0 ? 0 : (j > n - 1 ? n - 1 : j);
-    return j / w;
-}
-
 template <int NV>
 __device__ __forceinline__ void write_flags(uint8_t* fl, int nlines, int nfaces, int line, int slot,
                                             unsigned fb)
@@ -151,24 +131,19 @@ __device__ __forceinline__ void write_flags(uint8_t* fl, int nlines, int nfaces,
 
 // ------------------------------------------------------------------ 1D
 
-// Strip bx of one 1D grid.  Thread 0 of strip 0 opens the next step record.
-// Lane l computes midpoint x0-G+l+1/2 (G = 2 for MND, 3 for MD); the grid
-// needs midpoints -G .. jmax = nx-2+G, so jmax+G+1 = nx+2G-1 flag slots.
+// Strip bx of one 1D grid (geometry in Strip1D).  Thread 0 of strip 0
+// opens the next step record.
 template <int SYS, int NV, int FLUX, int SCHEME, bool CHAR, int MODE, int DIFF = DIFF_MND>
 __device__ __forceinline__ void sweep1d_block(const double* __restrict__ U, const double* __restrict__ Un,
                                               double* __restrict__ out, uint8_t* __restrict__ flags,
                                               Ctrl* __restrict__ ctrl, const Params& P, const StageArgs& A, int bx)
 {
-    constexpr int W = strip_cells<DIFF>();
-    constexpr int G = DIFF == DIFF_MD ? 3 : 2;
+    constexpr int G = Strip1D<DIFF>::G;
     const int nx = P.nx;
     const int lane = threadIdx.x;
-    const int x0 = bx * W;
-    const int c = x0 + lane;
-    const bool cell_ok = lane < W && c < nx;
-    const int jx = x0 - G + lane;
-    const int jmax = nx - 2 + G;
-    const int jxl = min(jx, jmax);  // lanes past the last midpoint load in-range data
+    const Strip1D<DIFF> S(bx, lane, nx);
+    const int c = S.c, jx = S.jx, jxl = S.jxl;
+    const bool cell_ok = S.cell_ok;
 
     // the stencil (and U^n of this lane's cell) load while the control
     // record is read
@@ -193,8 +168,7 @@ __device__ __forceinline__ void sweep1d_block(const double* __restrict__ U, cons
     unsigned fb;
     RegStencil<NV> st{s};
     face_flux<SYS, NV, FLUX, SCHEME, CHAR>(st, P, F, fb);
-    if (flags && jx <= jmax && face_owner(jx, nx, W) == bx)
-        write_flags<NV>(flags, 1, jmax + G + 1, 0, jx + G, fb);
+    if (MODE == MODE_RHS && flags && S.owns_face(bx, nx)) write_flags<NV>(flags, 1, S.nfaces(), 0, jx + G, fb);
     if constexpr (DIFF == DIFF_MND) node_flux<SYS, NV>(s[3], P, fn);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -334,7 +308,8 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
     const int c = x0 + lane;
     const bool cell_ok = lane < TX && c < nx;
     const int jx = x0 - 2 + lane;
-    const bool own_x = flags && jx <= nx && face_owner(jx, nx, TX) == bx;
+    // cut flags are reported by right-hand-side launches only
+    const bool own_x = MODE == MODE_RHS && flags && jx <= nx && face_owner(jx, nx, TX) == bx;
     // columns this lane stages (ghost cells by index remap, any distance)
     const bool hasB = lane < XW - WAVE;
     const int colA = ghost_map_any(x0 - 4 + lane, nx, P.bc_x);
@@ -361,14 +336,16 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
     for (int j = y0 - 2; j <= y1; ++j) {
         const int i = j - 1;  // row finished once y-midpoint j is known
         const int npass = i >= y0 ? 2 : 1;
-        // pass 0: y-midpoint (c, j+1/2) from rows j-2 .. j+3 at this lane's
-        // column (normal momentum = rho v first); pass 1: x-midpoint
-        // (jx+1/2, i) from row i.  Both passes run the same instructions on
-        // different staged data (selects, no branches), so they share one
-        // set of registers.
+        // last pass: y-midpoint (c, j+1/2) from rows j-2 .. j+3 at this
+        // lane's column (normal momentum = rho v first); first pass (rows
+        // i >= y0): x-midpoint (jx+1/2, i) from row i.  Both passes run the
+        // same instructions on different staged data (selects, no branches),
+        // so they share one set of registers; the y flux is the one left in
+        // F when the loop ends.
+        double F[NV];
 #pragma unroll 1
         for (int pass = 0; pass < npass; ++pass) {
-            const bool py = pass == 0;
+            const bool py = pass == npass - 1;
             // the six stencil nodes, read once into registers: node m at
             // ring[slot][var][col] with (slot, col) = (row j-2+m, c) in the
             // y pass and (row i, jx-2+m) in the x pass
@@ -386,23 +363,15 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
                 s[m][3] = rb[off + 3 * XW];
             }
             RegStencil<NV> st{s};
-            double F[NV];
             unsigned fb;
             face_flux<SYS_EULER, NV, FLUX, SCHEME, CHAR>(st, P, F, fb);
-            if (flags) {
+            if (MODE == MODE_RHS && flags) {
                 if (py) {
                     if (cell_ok && j <= ny && face_owner(j, ny, ty) == by)
                         write_flags<NV>(flags + (size_t)NV * ny * (nx + 3) * 2, nx, ny + 3, c, j + 2, fb);
                 } else if (own_x) {
                     write_flags<NV>(flags, ny, nx + 3, i, jx + 2, fb);
                 }
-            }
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                fy[0][v] = py ? fy[1][v] : fy[0][v];
-                fy[1][v] = py ? fy[2][v] : fy[1][v];
-                fy[2][v] = py ? fy[3][v] : fy[2][v];
-                fy[3][v] = py ? F[v] : fy[3][v];
             }
             if (!py) {
                 // x node flux at node jx+1 of row i
@@ -417,7 +386,18 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
                 }
             }
         }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            fy[0][v] = fy[1][v];
+            fy[1][v] = fy[2][v];
+            fy[2][v] = fy[3][v];
+            fy[3][v] = F[v];
+        }
         __syncthreads();
+        // row j+4 travels while row i is finished (it replaces row j-2 =
+        // i-1, which the difference below still reads)
+        double ra[NV], rb[NV];
+        if (j < y1) load_row<NV>(U, plane, (size_t)ghost_map(j + 4, ny, P.bc_y) * nx, colA, colB, hasB, ra, rb);
         if (npass == 2 && cell_ok) {
             // rows i-1, i, i+1 of this lane's column are still staged
             const int s_im = base;                                  // row j-2 = i-1
@@ -458,12 +438,7 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
         }
         __syncthreads();
         // row j-2 is no longer read: its slot takes row j+4
-        if (j < y1) {
-            double ra[NV], rb[NV];
-            const size_t rowoff = (size_t)ghost_map(j + 4, ny, P.bc_y) * nx;
-            load_row<NV>(U, plane, rowoff, colA, colB, hasB, ra, rb);
-            store_row<NV>(ring[base], lane, hasB, ra, rb);
-        }
+        if (j < y1) store_row<NV>(ring[base], lane, hasB, ra, rb);
         base = base + 1 < NSLOT ? base + 1 : 0;
         __syncthreads();
     }

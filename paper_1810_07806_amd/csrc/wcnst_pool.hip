@@ -30,7 +30,6 @@ using namespace wcnst;
 
 namespace {
 
-constexpr int TX = 61;  // cells per 1D strip / columns per 2D strip
 
 struct PoolReq {
     bool used = false;

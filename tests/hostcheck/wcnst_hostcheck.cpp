@@ -86,6 +86,54 @@ void run_line(int sys, int nv, int flux, int scheme, const Params& P, int n, int
 
 }  // namespace
 
+namespace {
+
+// Index geometry of the 1D stage kernel (Strip1D) on a line of nx cells,
+// evaluated for every strip and lane of the launch.  Returns 0 when every
+// cell is owned once, every midpoint -G .. nx-2+G is reported once by a lane
+// that computed it from its own (unclamped) stencil, each owned cell finds
+// its 2G midpoints on the lanes above it and its own state at stencil node
+// G+2, and all stencil nodes lie within one line length of the line; else a
+// code naming the first violated property.
+template <int DIFF>
+static int strip_check(int nx)
+{
+    using S1 = Strip1D<DIFF>;
+    const int G = S1::G, W = S1::W;
+    const int nstrips = (nx + W - 1) / W;
+    std::vector<int> cells((size_t)nx, 0), faces((size_t)nx + 2 * G - 1, 0);
+    for (int bx = 0; bx < nstrips; ++bx)
+        for (int lane = 0; lane < WAVE; ++lane) {
+            const S1 s(bx, lane, nx);
+            if (s.nfaces() != nx + 2 * G - 1) return 1;
+            for (int m = 0; m < 6; ++m) {
+                const int node = s.jxl - 2 + m;
+                if (node < -nx || node >= 2 * nx) return 2;
+            }
+            if (s.owns_face(bx, nx)) {
+                if (s.jx < -G || s.jx > s.jmax || s.jxl != s.jx) return 3;
+                faces[(size_t)(s.jx + G)] += 1;
+            }
+            if (s.cell_ok) {
+                if (s.c < 0 || s.c >= nx) return 4;
+                cells[(size_t)s.c] += 1;
+                if (s.jxl - 2 + (G + 2) != s.c) return 5;
+                for (int k = 0; k < 2 * G; ++k) {
+                    if (lane + k >= WAVE) return 6;
+                    const S1 t(bx, lane + k, nx);
+                    if (t.jx != s.c - G + k || t.jxl != t.jx) return 7;
+                }
+            }
+        }
+    for (int v : cells)
+        if (v != 1) return 8;
+    for (int v : faces)
+        if (v != 1) return 9;
+    return 0;
+}
+
+}  // namespace
+
 extern "C" {
 
 // sys: 0 advection, 1 Burgers, 2 Euler; flux: 0 Roe, 1 LF.  U, R: [nv][ny][nx].
@@ -126,6 +174,11 @@ int hc_rhs(int ndim, int sys, int flux, int nx, int ny, double dx, double dy, in
         }
     }
     return 0;
+}
+
+int hc_strip1d_check(int nx, int diff_md)
+{
+    return diff_md ? strip_check<DIFF_MD>(nx) : strip_check<DIFF_MND>(nx);
 }
 
 }  // extern "C"

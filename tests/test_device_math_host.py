@@ -108,3 +108,15 @@ def test_state_after_steps_with_rounding_noise(orc, hc):
     d1, U1 = W.random_tube(rng, 80)
     V1 = orc.solve(orc.problem(d1), U1, cfl=0.5, max_steps=5)["U"]
     _compare(orc, hc, d1, V1)
+
+
+def test_strip_geometry_of_the_1d_kernel(hc):
+    """The index map of the 1D stage kernel (one midpoint per lane, cells
+    owned by the strip whose midpoints reach them), checked for every strip
+    and lane of the launch: each cell once, each midpoint reported once from
+    its own stencil, each cell's 2G midpoints on the lanes above it, stencils
+    inside the ghost range.  MND (G = 2, 61-cell strips) and MD (G = 3, 59)."""
+    hc.hc_strip1d_check.argtypes = [ctypes.c_int, ctypes.c_int]
+    for md in (0, 1):
+        for nx in list(range(5, 200)) + [243, 244, 245, 4096, 16384, 16385]:
+            assert hc.hc_strip1d_check(nx, md) == 0, (nx, md)
