@@ -51,7 +51,7 @@ enum {
 
 enum { WCNST_ADVECTION = 0, WCNST_BURGERS = 1, WCNST_EULER = 2 };
 enum { WCNST_PERIODIC = 0, WCNST_ZERO_GRADIENT = 1 };
-enum { WCNST_ROE = 0, WCNST_LF = 1 };
+enum { WCNST_ROE = 0, WCNST_LF = 1, WCNST_VANLEER = 2 };
 enum { WCNST_TENO = 0, WCNST_LINEAR = 1, WCNST_JS = 2 };
 enum { WCNST_MND = 0, WCNST_MD = 1 };
 
@@ -64,7 +64,8 @@ typedef struct wcnst_desc {
     double x0, x1;        /* domain; spacing dx = (x1 - x0) / nx */
     double y0, y1;        /* dy = (y1 - y0) / ny in 2D */
     int32_t bc_x, bc_y;   /* WCNST_PERIODIC / WCNST_ZERO_GRADIENT (ghost cells by index remap) */
-    int32_t flux;         /* WCNST_ROE (no entropy fix) / WCNST_LF (local) */
+    int32_t flux;         /* WCNST_ROE (no entropy fix) / WCNST_LF (local) /
+                             WCNST_VANLEER (flux-vector splitting, Euler only) */
     int32_t scheme;       /* WCNST_TENO (Eqs. 16-19) / WCNST_LINEAR (Eq. 12) / WCNST_JS (Eq. 14) */
     int32_t diff;         /* WCNST_MND (Eq. 5, 4 ghost cells) / WCNST_MD (Eq. 3, 5 ghost cells;
                              1D single solves only: batches and pools use MND) */

@@ -20,14 +20,14 @@ LIB_PATH = os.environ.get("WCNST_ORACLE_LIB", _DEFAULT_LIB)
 
 ADVECTION, BURGERS, EULER = 0, 1, 2
 PERIODIC, ZERO_GRADIENT = 0, 1
-ROE, LF = 0, 1
+ROE, LF, VANLEER = 0, 1, 2
 TENO, LINEAR, JS = 0, 1, 2
 MND, MD = 0, 1
 OK, E_INVALID, E_NONPHYSICAL, E_MAX_STEPS = 0, 1, 2, 3
 
 _SYSTEM = {"advection": ADVECTION, "burgers": BURGERS, "euler": EULER}
 _BC = {"periodic": PERIODIC, "zero_gradient": ZERO_GRADIENT}
-_FLUX = {"roe": ROE, "lf": LF}
+_FLUX = {"roe": ROE, "lf": LF, "vanleer": VANLEER}
 _SCHEME = {"teno": TENO, "linear": LINEAR, "js": JS}
 _DIFF = {"mnd": MND, "md": MD}
 

@@ -19,6 +19,8 @@
  *   characteristic-wise interpolation, ideal gas .. Sec. 3 (opening paragraph)
  *   Roe flux-difference splitting ................. Sec. 1 (named); the system
  *                                                   form of Eq. (6) with |A| = R|Lambda|L
+ *   van Leer flux-vector splitting ................ Sec. 3 (named as the flux of
+ *                                                   the paper's results; textbook form)
  * The paper does not print the difference coefficients, the Runge-Kutta
  * form, the Roe average or the eigenvectors; the readings used here are:
  *   MND: (c1, c2, c3) = (3/2, -3/10, 1/30); MD: (75/64, -25/384, 3/640),
@@ -29,6 +31,8 @@
  *   Characteristic projection uses the Roe average of the two nodes next to
  *   the midpoint and the textbook conserved-variable eigenvectors.
  *   No entropy fix in the Roe flux (Eq. (6) uses the plain |a|).
+ *   van Leer: F = F+(U_L) + F-(U_R) on the interpolated states, the
+ *        subsonic parts with mass flux +-rho c (M +- 1)^2 / 4.
  */
 #include "wcnst_oracle.h"
 
@@ -68,6 +72,7 @@ static int validate(const orc_problem* p)
     if (!(p->dx > 0) || (p->ndim == 2 && !(p->dy > 0))) return ORC_E_INVALID;
     if (p->system == ORC_EULER && !(p->gamma > 1)) return ORC_E_INVALID;
     if (p->q < 1) return ORC_E_INVALID;
+    if (p->flux == ORC_VANLEER && p->system != ORC_EULER) return ORC_E_INVALID;
     return ORC_OK;
 }
 
@@ -229,6 +234,38 @@ static double sound_speed(int nv, double gamma, const double* U)
     return sqrt(gamma * euler_pressure_r(nv, gamma, U, ir) * ir);
 }
 
+/* van Leer's split flux F+ (sign = +1) or F- (sign = -1) of the normal flux
+ * at U (normal momentum first).  Supersonic states give the whole flux to
+ * one side; subsonic, with M = u/c,
+ *   f_m = sign rho c (M + sign)^2 / 4,  w = (gamma - 1) u + sign 2 c,
+ *   F = f_m (1, w / gamma, [v], w^2 / (2 (gamma^2 - 1)) [+ v^2 / 2]). */
+static void vanleer_part(int nv, double gamma, const double* U, double sign, double* Fs)
+{
+    double ir = 1.0 / U[0];
+    double u = U[1] * ir;
+    double c = sqrt(gamma * euler_pressure_r(nv, gamma, U, ir) * ir);
+    double M = u / c;
+    if (M >= 1.0 || M <= -1.0) {
+        int whole = (M >= 1.0) == (sign > 0.0);
+        orc_euler_flux(nv, gamma, U, Fs);
+        if (!whole)
+            for (int k = 0; k < nv; ++k) Fs[k] = 0.0;
+        return;
+    }
+    double a = M + sign;
+    double fm = sign * (0.25 * U[0] * c * (a * a));
+    double w = (gamma - 1.0) * u + sign * (2.0 * c);
+    double e = (w * w) / (2.0 * (gamma * gamma - 1.0));
+    Fs[0] = fm;
+    Fs[1] = fm * (w / gamma);
+    if (nv == 4) {
+        double v = U[2] * ir;
+        Fs[2] = fm * v;
+        e = e + 0.5 * (v * v);
+    }
+    Fs[nv - 1] = fm * e;
+}
+
 void orc_num_flux(const orc_problem* p, const double* UL, const double* UR, double* F)
 {
     if (p->system == ORC_ADVECTION) {
@@ -244,6 +281,14 @@ void orc_num_flux(const orc_problem* p, const double* UL, const double* UR, doub
         double ah = p->flux == ORC_LF ? fmax(fabs(UL[0]), fabs(UR[0]))
                                       : 0.5 * (UL[0] + UR[0]);
         F[0] = 0.5 * ((fr + fl) - fabs(ah) * (UR[0] - UL[0]));
+        return;
+    }
+    if (p->flux == ORC_VANLEER) {
+        int nv = orc_nvar(p);
+        double Fp[4], Fm[4];
+        vanleer_part(nv, p->gamma, UL, 1.0, Fp);
+        vanleer_part(nv, p->gamma, UR, -1.0, Fm);
+        for (int v = 0; v < nv; ++v) F[v] = Fp[v] + Fm[v];
         return;
     }
     {

@@ -30,7 +30,7 @@ extern "C" {
 
 enum { ORC_ADVECTION = 0, ORC_BURGERS = 1, ORC_EULER = 2 };
 enum { ORC_PERIODIC = 0, ORC_ZERO_GRADIENT = 1 };
-enum { ORC_ROE = 0, ORC_LF = 1 };
+enum { ORC_ROE = 0, ORC_LF = 1, ORC_VANLEER = 2 };
 enum { ORC_TENO = 0, ORC_LINEAR = 1, ORC_JS = 2 };
 enum { ORC_MND = 0, ORC_MD = 1 };
 
@@ -47,7 +47,7 @@ typedef struct orc_problem {
     int nx, ny;      /* unknowns per direction (ny = 1 in 1D) */
     double dx, dy;   /* uniform spacing h per direction */
     int bc_x, bc_y;  /* ORC_PERIODIC / ORC_ZERO_GRADIENT */
-    int flux;        /* ORC_ROE / ORC_LF */
+    int flux;        /* ORC_ROE / ORC_LF / ORC_VANLEER (Euler only) */
     int scheme;      /* ORC_TENO / ORC_LINEAR / ORC_JS */
     int diff;        /* ORC_MND / ORC_MD */
     int charwise;    /* Euler: 1 = interpolate characteristic variables */

@@ -30,7 +30,7 @@
 namespace wcnst {
 
 enum { SYS_ADV = 0, SYS_BURG = 1, SYS_EULER = 2 };
-enum { FLUX_ROE = 0, FLUX_LF = 1 };
+enum { FLUX_ROE = 0, FLUX_LF = 1, FLUX_VL = 2 };
 // SCH_TENO: Eq. (16) with the paper's q = 6; SCH_TENO_Q: any integer q
 enum { SCH_TENO = 0, SCH_LINEAR = 1, SCH_JS = 2, SCH_TENO_Q = 3 };
 enum { BC_PERIODIC = 0, BC_ZG = 1 };
@@ -382,13 +382,56 @@ WCNST_HD void roe_eigen(const double* A, const double* B, double gamma, Eigen<NV
     E.uc = E.u * E.ic;
 }
 
+// van Leer's split normal flux (the flux named for the results of Sec. 3;
+// textbook form, not printed in the paper): F+ (sign = +1) or F- (sign =
+// -1) at U.  Supersonic states give the whole flux to one side; subsonic,
+// with M = u/c, f_m = sign rho c (M + sign)^2 / 4, w = (gamma-1) u +
+// sign 2c, and F = f_m (1, w/gamma, [v], w^2 / (2 (gamma^2 - 1)) [+ v^2/2]).
+template <int NV>
+WCNST_HD void vanleer_part(const double* U, double gamma, double sign, double* Fs)
+{
+    const double ir = 1.0 / U[0];
+    const double u = U[1] * ir;
+    const double c = sqrt(gamma * pressure<NV>(U, gamma, ir) * ir);
+    const double M = u / c;
+    if (M >= 1.0 || M <= -1.0) {
+        const bool whole = (M >= 1.0) == (sign > 0.0);
+        euler_flux<NV>(U, gamma, Fs);
+        if (!whole)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) Fs[k] = 0.0;
+        return;
+    }
+    const double a = M + sign;
+    const double fm = sign * (0.25 * U[0] * c * (a * a));
+    const double w = (gamma - 1.0) * u + sign * (2.0 * c);
+    double e = (w * w) / (2.0 * (gamma * gamma - 1.0));
+    Fs[0] = fm;
+    Fs[1] = fm * (w / gamma);
+    if constexpr (NV == 4) {
+        const double v = U[2] * ir;
+        Fs[2] = fm * v;
+        e = e + 0.5 * (v * v);
+    }
+    Fs[NV - 1] = fm * e;
+}
+
 // Numerical flux of the Euler equations from the interpolated states: the
 // system form of Eq. (6), 1/2 [(F(U_R) + F(U_L)) - |A| (U_R - U_L)], with
 // |A| = R |Lambda| L at the Roe average of U_L and U_R (no entropy fix), or
-// the local Lax-Friedrichs speed max(|u| + c).
+// the local Lax-Friedrichs speed max(|u| + c); or van Leer's F+(U_L) +
+// F-(U_R).
 template <int NV, int FLUX>
 WCNST_HD void euler_num_flux(const double* UL, const double* UR, double gamma, double* F)
 {
+    if constexpr (FLUX == FLUX_VL) {
+        double Fp[NV], Fm[NV];
+        vanleer_part<NV>(UL, gamma, 1.0, Fp);
+        vanleer_part<NV>(UR, gamma, -1.0, Fm);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) F[v] = Fp[v] + Fm[v];
+        return;
+    }
     double FL[NV], FR[NV], dis[NV];
     euler_flux<NV>(UL, gamma, FL);
     euler_flux<NV>(UR, gamma, FR);

@@ -625,7 +625,10 @@ wcnst_status wcnst_check_desc(const wcnst_desc* d)
     for (int b : {d->bc_x, d->bc_y})
         if (b != WCNST_PERIODIC && b != WCNST_ZERO_GRADIENT)
             return fail(WCNST_E_INVALID_ARG, "unknown boundary condition %d", b);
-    if (d->flux != WCNST_ROE && d->flux != WCNST_LF) return fail(WCNST_E_INVALID_ARG, "unknown flux");
+    if (d->flux != WCNST_ROE && d->flux != WCNST_LF && d->flux != WCNST_VANLEER)
+        return fail(WCNST_E_INVALID_ARG, "unknown flux");
+    if (d->flux == WCNST_VANLEER && d->system != WCNST_EULER)
+        return fail(WCNST_E_INVALID_ARG, "the van Leer splitting is for the Euler system");
     if (d->scheme < WCNST_TENO || d->scheme > WCNST_JS) return fail(WCNST_E_INVALID_ARG, "unknown scheme");
     if (d->diff != WCNST_MND && d->diff != WCNST_MD) return fail(WCNST_E_INVALID_ARG, "unknown difference");
     if (d->diff == WCNST_MD && d->ndim != 1)
@@ -826,7 +829,7 @@ template <int MODE>
 static void launch_sweep(const wcnst_solver* s, const double* U, const double* Un, double* out,
                          uint8_t* flags, const StageArgs& A)
 {
-    const bool lf = s->d.flux == WCNST_LF;
+    const bool lf = s->d.flux == WCNST_LF, vl = s->d.flux == WCNST_VANLEER;
     switch (s->kind) {
     case K_ADV1: launch_scheme<SYS_ADV, 1, FLUX_ROE, false, MODE>(s, U, Un, out, flags, A); break;
     case K_BURG1:
@@ -835,10 +838,12 @@ static void launch_sweep(const wcnst_solver* s, const double* U, const double* U
         break;
     case K_EUL1:
         if (lf) launch_char<SYS_EULER, 3, FLUX_LF, MODE>(s, U, Un, out, flags, A);
+        else if (vl) launch_char<SYS_EULER, 3, FLUX_VL, MODE>(s, U, Un, out, flags, A);
         else launch_char<SYS_EULER, 3, FLUX_ROE, MODE>(s, U, Un, out, flags, A);
         break;
     case K_EUL2:
         if (lf) launch_char<SYS_EULER, 4, FLUX_LF, MODE>(s, U, Un, out, flags, A);
+        else if (vl) launch_char<SYS_EULER, 4, FLUX_VL, MODE>(s, U, Un, out, flags, A);
         else launch_char<SYS_EULER, 4, FLUX_ROE, MODE>(s, U, Un, out, flags, A);
         break;
     }
@@ -1111,6 +1116,9 @@ static void launch_multi_d(const wcnst_desc* d, const ReqGrid* r, int nreq, int 
     if (d->flux == WCNST_LF) {
         if (d->charwise) launch_multi_s<NDIM, FLUX_LF, true>(d, r, nreq, nblocks, stage, tick_step, ty, st);
         else launch_multi_s<NDIM, FLUX_LF, false>(d, r, nreq, nblocks, stage, tick_step, ty, st);
+    } else if (d->flux == WCNST_VANLEER) {
+        if (d->charwise) launch_multi_s<NDIM, FLUX_VL, true>(d, r, nreq, nblocks, stage, tick_step, ty, st);
+        else launch_multi_s<NDIM, FLUX_VL, false>(d, r, nreq, nblocks, stage, tick_step, ty, st);
     } else {
         if (d->charwise) launch_multi_s<NDIM, FLUX_ROE, true>(d, r, nreq, nblocks, stage, tick_step, ty, st);
         else launch_multi_s<NDIM, FLUX_ROE, false>(d, r, nreq, nblocks, stage, tick_step, ty, st);

@@ -16,7 +16,7 @@ from .build import LIB_PATH
 OK, E_INVALID_ARG, E_NONPHYSICAL, E_MAX_STEPS, E_HIP = 0, 1, 2, 3, 4
 _SYSTEM = {"advection": 0, "burgers": 1, "euler": 2}
 _BC = {"periodic": 0, "zero_gradient": 1}
-_FLUX = {"roe": 0, "lf": 1}
+_FLUX = {"roe": 0, "lf": 1, "vanleer": 2}
 _SCHEME = {"teno": 0, "linear": 1, "js": 2}
 _DIFF = {"mnd": 0, "md": 1}
 

@@ -79,8 +79,10 @@ void run_line(int sys, int nv, int flux, int scheme, const Params& P, int n, int
     else if (sys == 1 && flux == 0) line_scheme<SYS_BURG, 1, FLUX_ROE>(scheme, P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
     else if (sys == 1) line_scheme<SYS_BURG, 1, FLUX_LF>(scheme, P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
     else if (nv == 3 && flux == 0) line_scheme<SYS_EULER, 3, FLUX_ROE>(scheme, P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+    else if (nv == 3 && flux == 2) line_scheme<SYS_EULER, 3, FLUX_VL>(scheme, P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
     else if (nv == 3) line_scheme<SYS_EULER, 3, FLUX_LF>(scheme, P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
     else if (flux == 0) line_scheme<SYS_EULER, 4, FLUX_ROE>(scheme, P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+    else if (flux == 2) line_scheme<SYS_EULER, 4, FLUX_VL>(scheme, P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
     else line_scheme<SYS_EULER, 4, FLUX_LF>(scheme, P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
 }
 
@@ -136,7 +138,7 @@ static int strip_check(int nx)
 
 extern "C" {
 
-// sys: 0 advection, 1 Burgers, 2 Euler; flux: 0 Roe, 1 LF.  U, R: [nv][ny][nx].
+// sys: 0 advection, 1 Burgers, 2 Euler; flux: 0 Roe, 1 LF, 2 van Leer.  U, R: [nv][ny][nx].
 // R is accumulated (the caller zeroes it).  flags: [x block][y block] like wcnst_rhs.
 int hc_rhs(int ndim, int sys, int flux, int nx, int ny, double dx, double dy, int bc_x, int bc_y,
            int scheme, int charwise, int q, double gamma, double adv, double CT, double C,

@@ -47,7 +47,7 @@ def _hc_rhs(hc, desc, U):
     dx = (desc["x1"] - desc["x0"]) / nx
     dy = (desc["y1"] - desc["y0"]) / ny if ndim == 2 else 1.0
     bc = {"periodic": 0, "zero_gradient": 1}
-    hc.hc_rhs(ndim, _SYS[desc["system"]], 0 if desc["flux"] == "roe" else 1, nx, ny, dx, dy,
+    hc.hc_rhs(ndim, _SYS[desc["system"]], {"roe": 0, "lf": 1, "vanleer": 2}[desc["flux"]], nx, ny, dx, dy,
               bc[desc["bc_x"]], bc[desc["bc_y"]], {"teno": 0, "linear": 1, "js": 2}[desc["scheme"]],
               int(desc["charwise"]), int(desc["q"]), desc["gamma"], desc["adv_speed"], desc["CT"],
               desc["C"], desc["eps_teno"], desc["eps_js"], U.ctypes.data, R.ctypes.data, fl.ctypes.data)
@@ -65,7 +65,7 @@ def _compare(orc, hc, desc, U):
     return fo
 
 
-@pytest.mark.parametrize("flux", ["roe", "lf"])
+@pytest.mark.parametrize("flux", ["roe", "lf", "vanleer"])
 @pytest.mark.parametrize("scheme", ["teno", "linear", "js"])
 @pytest.mark.parametrize("charwise", [1, 0])
 def test_euler1d_lines(orc, hc, flux, scheme, charwise):
@@ -87,7 +87,7 @@ def test_scalar_lines(orc, hc):
         _compare(orc, hc, d, rng.normal(size=(1, 1, 90)))
 
 
-@pytest.mark.parametrize("flux", ["roe", "lf"])
+@pytest.mark.parametrize("flux", ["roe", "lf", "vanleer"])
 def test_euler2d_planes(orc, hc, flux):
     rng = np.random.default_rng(41)
     d, U = W.random_euler2d(rng, 33, 27)

@@ -200,7 +200,8 @@ def test_batch_strip_boundaries_and_minimum_size(orc, torch):
 
 
 @pytest.mark.parametrize("kw", [dict(flux="lf", bc_x="periodic"), dict(flux="roe", charwise=0),
-                                dict(flux="roe", scheme="linear")], ids=["lf-periodic", "componentwise", "linear"])
+                                dict(flux="roe", scheme="linear"), dict(flux="vanleer")],
+                         ids=["lf-periodic", "componentwise", "linear", "vanleer"])
 def test_batch_scheme_variants(orc, torch, kw):
     from paper_1810_07806_amd.wcnst import Batch
     rng = np.random.default_rng(41)

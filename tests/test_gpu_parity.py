@@ -67,6 +67,8 @@ for flux in ("roe", "lf"):
 CASES_1D.append(dict(flux="roe", scheme="teno", charwise=0, bc_x="zero_gradient"))
 CASES_1D.append(dict(flux="roe", scheme="teno", charwise=1, bc_x="periodic"))
 CASES_1D.append(dict(flux="lf", scheme="teno", charwise=0, bc_x="periodic"))
+CASES_1D.append(dict(flux="vanleer", scheme="teno", charwise=1, bc_x="zero_gradient"))
+CASES_1D.append(dict(flux="vanleer", scheme="js", charwise=0, bc_x="periodic"))
 
 
 @pytest.mark.parametrize("kw", CASES_1D, ids=lambda k: "-".join(str(v) for v in k.values()))
@@ -109,7 +111,8 @@ CASES_2D = [dict(flux="roe", scheme="teno", charwise=1),
             dict(flux="lf", scheme="teno", charwise=1),
             dict(flux="roe", scheme="linear", charwise=1),
             dict(flux="roe", scheme="teno", charwise=0),
-            dict(flux="roe", scheme="js", charwise=1)]
+            dict(flux="roe", scheme="js", charwise=1),
+            dict(flux="vanleer", scheme="teno", charwise=1)]
 
 
 @pytest.mark.parametrize("kw", CASES_2D, ids=lambda k: "-".join(str(v) for v in k.values()))
@@ -163,6 +166,16 @@ def test_solve_tube_to_time(orc, torch):
     rng = np.random.default_rng(3)
     d, U = W.random_tube(rng, 257)
     _solve_case(orc, torch, d, U, 0.05, 1 << 40, "tube-to-t")
+
+
+def test_solve_vanleer_sod_and_quadrants(orc, torch):
+    """The van Leer splitting through whole solves: the Sod tube to t = 0.2
+    and 60 steps of the four-quadrant problem at 128^2."""
+    d, U = W.sod(300, flux="vanleer")
+    _solve_case(orc, torch, d, U, 0.2, 1 << 40, "sod-vanleer")
+    d, U = W.riemann2d_config3(128)
+    d["flux"] = "vanleer"
+    _solve_case(orc, torch, d, U, np.inf, 60, "quadrants-vanleer-128")
 
 
 def test_solve_config3_100_steps(orc, torch):

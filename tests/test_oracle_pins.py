@@ -533,3 +533,86 @@ def test_lax_friedrichs_closed_form(orc):
     UR = W.conserved_1d(0.5, 0.0, 2.0, 1.4)
     F = orc.num_flux(p, UL, UR)
     assert F[0] == pytest.approx(0.25 * math.sqrt(5.6), rel=1e-14)
+
+
+# ------------------------------------------- van Leer flux-vector splitting
+
+def _vl(orc, nv):
+    d = W.describe(ndim=nv - 2, system="euler", nx=8, ny=8 if nv == 4 else 1, flux="vanleer")
+    return orc.problem(d)
+
+
+def _cons(nv, rho, u, p, v=0.0, g=1.4):
+    return W.conserved_2d(rho, u, v, p, g) if nv == 4 else W.conserved_1d(rho, u, p, g)
+
+
+@pytest.mark.parametrize("nv", [3, 4])
+def test_vanleer_states_at_rest_closed_form(orc, nv):
+    """At rest (M = 0) the split fluxes reduce to F+- = (+-rho c / 4, p / 2,
+    [0], +-rho c^3 / (2 (gamma^2 - 1))), written here through p and
+    c = sqrt(gamma p / rho) rather than through the Mach form."""
+    g = 1.4
+    rl, pl, rr, pr = 1.0, 1.0, 0.5, 2.0
+    cl, cr = math.sqrt(g * pl / rl), math.sqrt(g * pr / rr)
+    F = orc.num_flux(_vl(orc, nv), _cons(nv, rl, 0.0, pl), _cons(nv, rr, 0.0, pr))
+    want = [rl * cl / 4 - rr * cr / 4, pl / 2 + pr / 2]
+    if nv == 4:
+        want.append(0.0)
+    want.append((rl * cl ** 3 - rr * cr ** 3) / (2 * (g * g - 1)))
+    assert np.allclose(F, want, rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("nv", [3, 4])
+def test_vanleer_split_is_consistent_and_mirror_symmetric(orc, nv):
+    """F+(U) + F-(U) = F(U) for subsonic states (a wrong sign or power in
+    either part breaks it), and mirroring x -> -x maps F- of a state to
+    minus the mirrored F+ of the mirrored state."""
+    g = 1.4
+    p = _vl(orc, nv)
+    rng = np.random.default_rng(4)
+    for _ in range(50):
+        rho, pr = rng.uniform(0.2, 3.0, size=2)
+        c = math.sqrt(g * pr / rho)
+        u = rng.uniform(-0.95, 0.95) * c
+        v = rng.uniform(-1, 1)
+        U = _cons(nv, rho, u, pr, v)
+        assert np.allclose(orc.num_flux(p, U, U), orc.euler_flux(nv, g, U), rtol=1e-13, atol=1e-14)
+        # F-(rho, -u, p) = -F+(rho, u, p) in mass and energy, so the flux
+        # between a state and its mirror image carries no mass or energy
+        M = U.copy()
+        M[1] = -M[1]
+        Fa = orc.num_flux(p, U, M)
+        assert abs(Fa[0]) <= 1e-14 * rho * c and abs(Fa[nv - 1]) <= 1e-13 * rho * c ** 3
+
+
+def test_vanleer_supersonic_upwinding_and_continuity(orc):
+    g = 1.4
+    p = _vl(orc, 3)
+    c = math.sqrt(g)
+    UL = W.conserved_1d(1.0, 1.5 * c, 1.0, g)
+    UR = W.conserved_1d(0.9, 1.2 * c, 0.9, g)  # c_R = c as well
+    assert np.array_equal(orc.num_flux(p, UL, UR), orc.euler_flux(3, g, UL))
+    VL = W.conserved_1d(1.0, -1.3 * c, 1.0, g)
+    VR = W.conserved_1d(0.8, -2.0 * c, 1.0, g)
+    assert np.array_equal(orc.num_flux(p, VL, VR), orc.euler_flux(3, g, VR))
+    # the subsonic parts join the supersonic ones continuously at |M| = 1
+    for eps in (1e-7, 1e-9):
+        lo = W.conserved_1d(1.0, (1 - eps) * c, 1.0, g)
+        hi = W.conserved_1d(1.0, (1 + eps) * c, 1.0, g)
+        Flo, Fhi = orc.num_flux(p, lo, lo), orc.num_flux(p, hi, hi)
+        assert np.allclose(Flo, Fhi, rtol=10 * eps)
+
+
+def test_vanleer_sod_against_exact_riemann_solution(orc):
+    from riemann_exact import sample
+    errs = []
+    for n in (100, 200, 400):
+        d, U = W.sod(n, flux="vanleer")
+        r = orc.solve(orc.problem(d), U, t_final=0.2, cfl=0.5)
+        assert r["status"] == 0
+        rho = r["U"][0].ravel()
+        ex = sample((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), W.coords(d), 0.2)
+        errs.append(np.abs(rho - ex[0]).mean())
+        assert rho.max() < 1.0 + 0.02 and rho.min() > 0.125 - 0.02
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 3e-3
