@@ -50,7 +50,7 @@ enum {
 };
 
 enum { WCNST_ADVECTION = 0, WCNST_BURGERS = 1, WCNST_EULER = 2 };
-enum { WCNST_PERIODIC = 0, WCNST_ZERO_GRADIENT = 1 };
+enum { WCNST_PERIODIC = 0, WCNST_ZERO_GRADIENT = 1, WCNST_REFLECT = 2, WCNST_FIXED = 3 };
 enum { WCNST_ROE = 0, WCNST_LF = 1, WCNST_VANLEER = 2 };
 enum { WCNST_TENO = 0, WCNST_LINEAR = 1, WCNST_JS = 2 };
 enum { WCNST_MND = 0, WCNST_MD = 1 };
@@ -63,7 +63,9 @@ typedef struct wcnst_desc {
     int32_t nx, ny;       /* unknowns per direction, >= 5 (ny = 1 in 1D) */
     double x0, x1;        /* domain; spacing dx = (x1 - x0) / nx */
     double y0, y1;        /* dy = (y1 - y0) / ny in 2D */
-    int32_t bc_x, bc_y;   /* WCNST_PERIODIC / WCNST_ZERO_GRADIENT (ghost cells by index remap) */
+    int32_t bc_x, bc_y;   /* WCNST_PERIODIC / WCNST_ZERO_GRADIENT / WCNST_REFLECT (Euler: mirror
+                             image, normal momentum reversed) / WCNST_FIXED (ghosts hold
+                             fixed_x / fixed_y) */
     int32_t flux;         /* WCNST_ROE (no entropy fix) / WCNST_LF (local) /
                              WCNST_VANLEER (flux-vector splitting, Euler only) */
     int32_t scheme;       /* WCNST_TENO (Eqs. 16-19) / WCNST_LINEAR (Eq. 12) / WCNST_JS (Eq. 14) */
@@ -77,6 +79,10 @@ typedef struct wcnst_desc {
     double C;             /* TENO constant C, Eq. (16); default 1 */
     double eps_teno;      /* TENO epsilon, Eq. (16); default 1e-40 */
     double eps_js;        /* Jiang-Shu epsilon, Eq. (14); default 1e-6 */
+    double fixed_x[2][4]; /* WCNST_FIXED ghost states at x0 / x1, conserved variables in storage
+                             order (rho, rho u, [rho v], E; scalars use [0]); default 0 */
+    double fixed_y[2][4]; /* ... at y0 / y1 (2D) */
+    double gravity;       /* 2D Euler body force in +y: R += (0, 0, rho g, rho v g); default 0 */
 } wcnst_desc;
 
 typedef struct wcnst_solver wcnst_solver;

@@ -26,7 +26,7 @@ MND, MD = 0, 1
 OK, E_INVALID, E_NONPHYSICAL, E_MAX_STEPS = 0, 1, 2, 3
 
 _SYSTEM = {"advection": ADVECTION, "burgers": BURGERS, "euler": EULER}
-_BC = {"periodic": PERIODIC, "zero_gradient": ZERO_GRADIENT}
+_BC = {"periodic": PERIODIC, "zero_gradient": ZERO_GRADIENT, "reflect": 2, "fixed": 3}
 _FLUX = {"roe": ROE, "lf": LF, "vanleer": VANLEER}
 _SCHEME = {"teno": TENO, "linear": LINEAR, "js": JS}
 _DIFF = {"mnd": MND, "md": MD}
@@ -43,6 +43,8 @@ class Problem(ctypes.Structure):
         ("gamma", ctypes.c_double), ("adv_speed", ctypes.c_double),
         ("CT", ctypes.c_double), ("C", ctypes.c_double),
         ("eps_teno", ctypes.c_double), ("eps_js", ctypes.c_double),
+        ("fixed_x", (ctypes.c_double * 4) * 2), ("fixed_y", (ctypes.c_double * 4) * 2),
+        ("gravity", ctypes.c_double),
     ]
 
 
@@ -104,7 +106,20 @@ def problem(desc: dict) -> Problem:
         adv_speed=float(desc.get("adv_speed", 1.0)), CT=float(desc.get("CT", 1e-5)),
         C=float(desc.get("C", 1.0)), eps_teno=float(desc.get("eps_teno", 1e-40)),
         eps_js=float(desc.get("eps_js", 1e-6)),
+        fixed_x=_fixed(desc.get("fixed_x")), fixed_y=_fixed(desc.get("fixed_y")),
+        gravity=float(desc.get("gravity", 0.0)),
     )
+
+
+def _fixed(states):
+    """Fixed-boundary ghost states ((lo), (hi)), conserved variables in
+    storage order, as the struct's double[2][4]."""
+    a = ((ctypes.c_double * 4) * 2)()
+    if states is not None:
+        for side in range(2):
+            for v, val in enumerate(states[side]):
+                a[side][v] = float(val)
+    return a
 
 
 def nvar(p: Problem) -> int:

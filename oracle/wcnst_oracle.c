@@ -73,6 +73,8 @@ static int validate(const orc_problem* p)
     if (p->system == ORC_EULER && !(p->gamma > 1)) return ORC_E_INVALID;
     if (p->q < 1) return ORC_E_INVALID;
     if (p->flux == ORC_VANLEER && p->system != ORC_EULER) return ORC_E_INVALID;
+    if ((p->bc_x == ORC_REFLECT || p->bc_y == ORC_REFLECT) && p->system != ORC_EULER) return ORC_E_INVALID;
+    if (p->gravity != 0.0 && p->ndim != 2) return ORC_E_INVALID;
     return ORC_OK;
 }
 
@@ -434,13 +436,35 @@ static void line_rhs(const orc_problem* p, int nv, int n, double h, const double
     }
 }
 
-/* Ghost index map: periodic wrap or zero-gradient copy of the end value. */
+/* Ghost index map: periodic wrap, mirror image across a reflecting wall
+ * (cell-centred: ghost -1-k mirrors cell k), or the nearest end cell
+ * (zero-gradient; also the unused source index of a fixed ghost). */
 static int ghost_index(int g, int n, int bc)
 {
     if (bc == ORC_PERIODIC) return ((g % n) + n) % n;
+    if (bc == ORC_REFLECT) {
+        if (g < 0) return -1 - g;
+        if (g >= n) return 2 * n - 1 - g;
+        return g;
+    }
     if (g < 0) return 0;
     if (g >= n) return n - 1;
     return g;
+}
+
+/* Variable order of x lines (storage order). */
+static const int ident[4] = {0, 1, 2, 3};
+
+/* Ghost value of line variable v (line order: normal momentum at index 1)
+ * taken from the source cell's value `val`: a reflecting wall reverses the
+ * normal momentum, a fixed boundary supplies its own state (`fixed` in
+ * line order). */
+static double ghost_value(int bc, int g, int n, int v, double val, const double fixed[2][4], const int* perm)
+{
+    if (g >= 0 && g < n) return val;
+    if (bc == ORC_REFLECT && v == 1) return -val;
+    if (bc == ORC_FIXED) return fixed[g < 0 ? 0 : 1][perm[v]];
+    return val;
 }
 
 int orc_rhs(const orc_problem* p, const double* U, double* R, uint8_t* flags, double* chi,
@@ -466,7 +490,8 @@ int orc_rhs(const orc_problem* p, const double* U, double* R, uint8_t* flags, do
             for (int g = -GHOST; g < nx + GHOST; ++g) {
                 int x = ghost_index(g, nx, p->bc_x);
                 for (int v = 0; v < nv; ++v)
-                    line[(size_t)(g + GHOST) * nv + v] = U[v * plane + (size_t)y * nx + x];
+                    line[(size_t)(g + GHOST) * nv + v] =
+                        ghost_value(p->bc_x, g, nx, v, U[v * plane + (size_t)y * nx + x], p->fixed_x, ident);
             }
             line_rhs(p, nv, nx, p->dx, line, out, flags, chi, y, ny, Ff, Fn);
             for (int x = 0; x < nx; ++x)
@@ -483,13 +508,24 @@ int orc_rhs(const orc_problem* p, const double* U, double* R, uint8_t* flags, do
                 for (int g = -GHOST; g < ny + GHOST; ++g) {
                     int y = ghost_index(g, ny, p->bc_y);
                     for (int v = 0; v < nv; ++v)
-                        line[(size_t)(g + GHOST) * nv + v] = U[perm[v] * plane + (size_t)y * nx + x];
+                        line[(size_t)(g + GHOST) * nv + v] = ghost_value(
+                            p->bc_y, g, ny, v, U[perm[v] * plane + (size_t)y * nx + x], p->fixed_y, perm);
                 }
                 line_rhs(p, nv, ny, p->dy, line, out, fy, cy, x, nx, Ff, Fn);
                 for (int y = 0; y < ny; ++y)
                     for (int v = 0; v < nv; ++v) {
                         size_t idx = perm[v] * plane + (size_t)y * nx + x;
                         R[idx] = R[idx] + out[(size_t)y * nv + v];
+                    }
+            }
+            if (p->gravity != 0.0) {
+                /* body force in +y: d(rho v)/dt += rho g, dE/dt += rho v g */
+#pragma omp for schedule(static)
+                for (int y = 0; y < ny; ++y)
+                    for (int x = 0; x < nx; ++x) {
+                        size_t c = (size_t)y * nx + x;
+                        R[2 * plane + c] = R[2 * plane + c] + U[c] * p->gravity;
+                        R[3 * plane + c] = R[3 * plane + c] + U[2 * plane + c] * p->gravity;
                     }
             }
         }

@@ -29,7 +29,7 @@ extern "C" {
 #endif
 
 enum { ORC_ADVECTION = 0, ORC_BURGERS = 1, ORC_EULER = 2 };
-enum { ORC_PERIODIC = 0, ORC_ZERO_GRADIENT = 1 };
+enum { ORC_PERIODIC = 0, ORC_ZERO_GRADIENT = 1, ORC_REFLECT = 2, ORC_FIXED = 3 };
 enum { ORC_ROE = 0, ORC_LF = 1, ORC_VANLEER = 2 };
 enum { ORC_TENO = 0, ORC_LINEAR = 1, ORC_JS = 2 };
 enum { ORC_MND = 0, ORC_MD = 1 };
@@ -46,7 +46,7 @@ typedef struct orc_problem {
     int system;      /* ORC_ADVECTION / ORC_BURGERS / ORC_EULER */
     int nx, ny;      /* unknowns per direction (ny = 1 in 1D) */
     double dx, dy;   /* uniform spacing h per direction */
-    int bc_x, bc_y;  /* ORC_PERIODIC / ORC_ZERO_GRADIENT */
+    int bc_x, bc_y;  /* ORC_PERIODIC / ORC_ZERO_GRADIENT / ORC_REFLECT (Euler) / ORC_FIXED */
     int flux;        /* ORC_ROE / ORC_LF / ORC_VANLEER (Euler only) */
     int scheme;      /* ORC_TENO / ORC_LINEAR / ORC_JS */
     int diff;        /* ORC_MND / ORC_MD */
@@ -58,6 +58,11 @@ typedef struct orc_problem {
     double C;        /* TENO constant (1) */
     double eps_teno; /* TENO epsilon (1e-40) */
     double eps_js;   /* Jiang-Shu epsilon (1e-6) */
+    /* ORC_FIXED ghost states, conserved variables in storage order (rho,
+     * rho u, [rho v], E), at the low / high end of each direction */
+    double fixed_x[2][4];
+    double fixed_y[2][4];
+    double gravity;  /* 2D Euler: source (0, 0, rho g, rho v g) added to R */
 } orc_problem;
 
 int orc_nvar(const orc_problem* p);

@@ -203,7 +203,7 @@ static wcnst_status run_tick(wcnst_batch* b, int nreq, int blocks, int steps, bo
     if (steps != b->steps_per_tick) {
         for (int s = 0; s < steps; ++s)
             for (int stage = 0; stage < 3; ++stage)
-                WCNST_HIP_TRY(wcnst_launch_multi(&b->d0, 1, b->d_req, nreq, blocks, stage, s & 1, 0, b->stream));
+                WCNST_HIP_TRY(wcnst_launch_multi(&b->d0, 1, b->d_req, nreq, blocks, stage, s & 1, 0, false, b->stream));
         return WCNST_OK;
     }
     if (!b->exec || table_changed) {
@@ -216,7 +216,7 @@ static wcnst_status run_tick(wcnst_batch* b, int nreq, int blocks, int steps, bo
         hipError_t le = hipSuccess;
         for (int s = 0; s < steps && le == hipSuccess; ++s)
             for (int stage = 0; stage < 3 && le == hipSuccess; ++stage)
-                le = wcnst_launch_multi(&b->d0, 1, b->d_req, nreq, blocks, stage, s & 1, 0, b->cap);
+                le = wcnst_launch_multi(&b->d0, 1, b->d_req, nreq, blocks, stage, s & 1, 0, false, b->cap);
         hipError_t ce = hipStreamEndCapture(b->cap, &g);
         if (le != hipSuccess || ce != hipSuccess)
             return wcnst_fail(WCNST_E_HIP, "graph capture failed: %s / %s", hipGetErrorString(le),

@@ -33,7 +33,7 @@ enum { SYS_ADV = 0, SYS_BURG = 1, SYS_EULER = 2 };
 enum { FLUX_ROE = 0, FLUX_LF = 1, FLUX_VL = 2 };
 // SCH_TENO: Eq. (16) with the paper's q = 6; SCH_TENO_Q: any integer q
 enum { SCH_TENO = 0, SCH_LINEAR = 1, SCH_JS = 2, SCH_TENO_Q = 3 };
-enum { BC_PERIODIC = 0, BC_ZG = 1 };
+enum { BC_PERIODIC = 0, BC_ZG = 1, BC_REFLECT = 2, BC_FIXED = 3 };
 enum { DIFF_MND = 0, DIFF_MD = 1 };
 
 // ------------------------------------------------------ strip geometry
@@ -94,6 +94,9 @@ struct Params {
     int q, charwise;
     int bc_x, bc_y;
     int nx, ny;
+    double fixed_x[2][4];  // fixed ghost states (storage order) at the low / high ends
+    double fixed_y[2][4];
+    double gravity;        // 2D Euler body force in +y
 };
 
 // Step records of one solve, alternating by step parity: the current
@@ -141,23 +144,63 @@ __device__ __forceinline__ T load_table_entry(const T* p)
     return *p;
 }
 
+// Source cell of (ghost) index g on a line of n cells, g in [-n, 2n):
+// periodic wrap, mirror image across a reflecting wall (cell-centred: ghost
+// -1-k mirrors cell k), else the nearest end cell (zero gradient; a fixed
+// ghost ignores the value loaded there).
 WCNST_HD int ghost_map(int g, int n, int bc)
 {
     if (bc == BC_PERIODIC) {
         g = g < 0 ? g + n : g;
         return g >= n ? g - n : g;
     }
+    if (bc == BC_REFLECT) {
+        g = g < 0 ? -1 - g : g;
+        return g >= n ? 2 * n - 1 - g : g;
+    }
     g = g < 0 ? 0 : g;
     return g >= n ? n - 1 : g;
 }
 
 // Same map for an index any distance outside [0, n) (periodic wraps as often
-// as needed); used where lanes past the last needed column stage data.
+// as needed; a mirror image that falls outside again is clamped); used
+// where lanes past the last needed column stage data.
 WCNST_HD int ghost_map_any(int g, int n, int bc)
 {
     if (bc == BC_PERIODIC) return ((g % n) + n) % n;
+    if (bc == BC_REFLECT) {
+        g = g < 0 ? -1 - g : g;
+        g = g >= n ? 2 * n - 1 - g : g;
+    }
     g = g < 0 ? 0 : g;
     return g >= n ? n - 1 : g;
+}
+
+// What a ghost holds besides its source cell's value: GH_COPY (interior
+// cells, periodic, zero gradient), GH_REVERSE (reflecting wall: the normal
+// momentum reversed), GH_FIXED_LO / GH_FIXED_HI (the fixed state of that
+// end replaces the value).
+enum { GH_COPY = 0, GH_REVERSE = 1, GH_FIXED_LO = 2, GH_FIXED_HI = 3 };
+
+WCNST_HD int ghost_kind(int g, int n, int bc)
+{
+    if (g >= 0 && g < n) return GH_COPY;
+    if (bc == BC_REFLECT) return GH_REVERSE;
+    if (bc == BC_FIXED) return g < 0 ? GH_FIXED_LO : GH_FIXED_HI;
+    return GH_COPY;
+}
+
+// Variable v (storage order) of a ghost of kind `kind` whose source cell
+// holds `val`; `normal` is the storage index of the momentum normal to the
+// boundary, `fixed` the two fixed states of that direction.
+WCNST_HD double ghost_value(int kind, int v, int normal, double val, const double (&fixed)[2][4])
+{
+    // selects, not an index computed from `kind`: the fixed states stay in
+    // registers instead of private memory
+    if (kind == GH_REVERSE) return v == normal ? -val : val;
+    if (kind == GH_FIXED_LO) return fixed[0][v];
+    if (kind == GH_FIXED_HI) return fixed[1][v];
+    return val;
 }
 
 // 1/x for the cut-off test: one Newton step on the hardware estimate

@@ -154,6 +154,16 @@ __device__ __forceinline__ void sweep1d_block(const double* __restrict__ U, cons
 #pragma unroll
         for (int v = 0; v < NV; ++v) s[m][v] = U[(size_t)v * nx + col];
     }
+    if (P.bc_x >= BC_REFLECT) {
+        // reflecting walls reverse the momentum of their ghosts; fixed ends
+        // supply their own states
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            const int kind = ghost_kind(jxl - 2 + m, nx, P.bc_x);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) s[m][v] = ghost_value(kind, v, 1, s[m][v], P.fixed_x);
+        }
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) un[v] = MODE == MODE_STAGE && A.stage && cell_ok ? Un[(size_t)v * nx + c] : 0.0;
     double dt = 0.0;
@@ -268,6 +278,28 @@ __device__ __forceinline__ void load_row(const double* __restrict__ U, size_t pl
     }
 }
 
+// Ghosts of a staged row: the row's own kind (y boundary, uniform) and each
+// lane's column kinds (x boundary).  Periodic and zero-gradient sides are
+// pure index remaps and skip this.
+template <int NV>
+__device__ __forceinline__ void fix_row(const Params& P, int ky, int kA, int kB, double (&ra)[NV], double (&rb)[NV])
+{
+    if (ky != GH_COPY) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            ra[v] = ghost_value(ky, v, 2, ra[v], P.fixed_y);
+            rb[v] = ghost_value(ky, v, 2, rb[v], P.fixed_y);
+        }
+    }
+    if (P.bc_x >= BC_REFLECT) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            ra[v] = ghost_value(kA, v, 1, ra[v], P.fixed_x);
+            rb[v] = ghost_value(kB, v, 1, rb[v], P.fixed_x);
+        }
+    }
+}
+
 template <int NV>
 __device__ __forceinline__ void store_row(double (*slot)[XW], int lane, bool hasB, const double (&ra)[NV],
                                           const double (&rb)[NV])
@@ -281,7 +313,9 @@ __device__ __forceinline__ void store_row(double (*slot)[XW], int lane, bool has
 
 // One segment (strip bx, rows by*ty ..) of one 2D grid.  Thread 0 of
 // segment (0, 0) opens the next step record.
-template <int NV, int FLUX, int SCHEME, bool CHAR, int MODE>
+// GB: general boundaries (reflecting walls, fixed ends, gravity); without
+// it only index-remap sides (periodic, zero gradient) and no source.
+template <int NV, int FLUX, int SCHEME, bool CHAR, int MODE, bool GB>
 __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, const double* __restrict__ Un,
                                               double* __restrict__ out, uint8_t* __restrict__ flags,
                                               Ctrl* __restrict__ ctrl, const Params& P, const StageArgs& A,
@@ -314,6 +348,8 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
     const bool hasB = lane < XW - WAVE;
     const int colA = ghost_map_any(x0 - 4 + lane, nx, P.bc_x);
     const int colB = ghost_map_any(x0 - 4 + WAVE + lane, nx, P.bc_x);
+    const int kA = GB ? ghost_kind(x0 - 4 + lane, nx, P.bc_x) : GH_COPY;
+    const int kB = GB ? ghost_kind(x0 - 4 + WAVE + lane, nx, P.bc_x) : GH_COPY;
 
     // y-midpoint fluxes j-3 .. j of this lane's column, in y-normal
     // variable order (rho, rho v, rho u, E)
@@ -328,6 +364,7 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
         double ra[NV], rb[NV];
         const size_t rowoff = (size_t)ghost_map(y0 - 4 + k, ny, P.bc_y) * nx;
         load_row<NV>(U, plane, rowoff, colA, colB, hasB, ra, rb);
+        if constexpr (GB) fix_row<NV>(P, ghost_kind(y0 - 4 + k, ny, P.bc_y), kA, kB, ra, rb);
         store_row<NV>(ring[k], lane, hasB, ra, rb);
     }
     __syncthreads();
@@ -422,6 +459,11 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
             R[1] = Rx[1] + Ry[2];
             R[2] = Rx[2] + Ry[1];
             R[3] = Rx[3] + Ry[3];
+            if (GB && P.gravity != 0.0) {
+                // body force in +y on the momentum and energy equations
+                R[2] = R[2] + Uc[0] * P.gravity;
+                R[3] = R[3] + Uc[2] * P.gravity;
+            }
             const size_t cell = (size_t)i * nx + c;
             if constexpr (MODE == MODE_RHS) {
 #pragma unroll
@@ -438,7 +480,10 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
         }
         __syncthreads();
         // row j-2 is no longer read: its slot takes row j+4
-        if (j < y1) store_row<NV>(ring[base], lane, hasB, ra, rb);
+        if (j < y1) {
+            if constexpr (GB) fix_row<NV>(P, ghost_kind(j + 4, ny, P.bc_y), kA, kB, ra, rb);
+            store_row<NV>(ring[base], lane, hasB, ra, rb);
+        }
         base = base + 1 < NSLOT ? base + 1 : 0;
         __syncthreads();
     }
@@ -449,12 +494,12 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
 
 // Two wavefronts per SIMD: the register budget is capped at 256 (a few
 // values spill); measured faster than one wavefront with no spills.
-template <int NV, int FLUX, int SCHEME, bool CHAR, int MODE>
+template <int NV, int FLUX, int SCHEME, bool CHAR, int MODE, bool GB>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2)))
 sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __restrict__ out,
         uint8_t* __restrict__ flags, Ctrl* __restrict__ ctrl, Params P, StageArgs A, int ty)
 {
-    sweep2d_block<NV, FLUX, SCHEME, CHAR, MODE>(U, Un, out, flags, ctrl, P, A, ty, (int)blockIdx.x,
+    sweep2d_block<NV, FLUX, SCHEME, CHAR, MODE, GB>(U, Un, out, flags, ctrl, P, A, ty, (int)blockIdx.x,
                                                 (int)blockIdx.y);
 }
 
@@ -462,7 +507,7 @@ sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
 // the request r with blk0[r] <= b < blk0[r+1] (binary search over the
 // table, uniform per block), then runs segment b - blk0[r] of that grid with
 // the grid's own parameters, buffers, control block and step parity.
-template <int NV, int FLUX, int SCHEME, bool CHAR>
+template <int NV, int FLUX, int SCHEME, bool CHAR, bool GB>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2)))
 sweep2d_multi(const ReqGrid* __restrict__ reqs, int nreq, int stage, int tick_step, int ty)
 {
@@ -473,7 +518,7 @@ sweep2d_multi(const ReqGrid* __restrict__ reqs, int nreq, int stage, int tick_st
     const StageArgs A = request_stage(R, stage, tick_step);
     const double* in = stage == 0 ? R.U : (stage == 1 ? R.U1 : R.U2);
     double* out = stage == 0 ? R.U1 : (stage == 1 ? R.U2 : R.U);
-    sweep2d_block<NV, FLUX, SCHEME, CHAR, MODE_STAGE>(in, R.U, out, nullptr, R.ctrl, P, A, ty, local % R.nstrips,
+    sweep2d_block<NV, FLUX, SCHEME, CHAR, MODE_STAGE, GB>(in, R.U, out, nullptr, R.ctrl, P, A, ty, local % R.nstrips,
                                                       local / R.nstrips);
 }
 
@@ -622,9 +667,15 @@ wcnst_status wcnst_check_desc(const wcnst_desc* d)
     if ((int64_t)d->nx * d->ny > ((int64_t)1 << 34)) return fail(WCNST_E_INVALID_ARG, "grid too large");
     if (!(d->x1 > d->x0) || (d->ndim == 2 && !(d->y1 > d->y0)))
         return fail(WCNST_E_INVALID_ARG, "empty domain");
-    for (int b : {d->bc_x, d->bc_y})
-        if (b != WCNST_PERIODIC && b != WCNST_ZERO_GRADIENT)
+    for (int b : {d->bc_x, d->bc_y}) {
+        if (b != WCNST_PERIODIC && b != WCNST_ZERO_GRADIENT && b != WCNST_REFLECT && b != WCNST_FIXED)
             return fail(WCNST_E_INVALID_ARG, "unknown boundary condition %d", b);
+        if (b == WCNST_REFLECT && d->system != WCNST_EULER)
+            return fail(WCNST_E_INVALID_ARG, "reflecting walls are for the Euler system");
+    }
+    if (!std::isfinite(d->gravity)) return fail(WCNST_E_INVALID_ARG, "gravity must be finite");
+    if (d->gravity != 0.0 && (d->ndim != 2 || d->system != WCNST_EULER))
+        return fail(WCNST_E_INVALID_ARG, "gravity is a 2D Euler source");
     if (d->flux != WCNST_ROE && d->flux != WCNST_LF && d->flux != WCNST_VANLEER)
         return fail(WCNST_E_INVALID_ARG, "unknown flux");
     if (d->flux == WCNST_VANLEER && d->system != WCNST_EULER)
@@ -639,6 +690,12 @@ wcnst_status wcnst_check_desc(const wcnst_desc* d)
     if (!(d->C > 0.0) || !(d->eps_teno > 0.0) || !(d->eps_js > 0.0))
         return fail(WCNST_E_INVALID_ARG, "C and epsilons must be positive");
     return WCNST_OK;
+}
+
+bool wcnst_general_bc(const wcnst_desc* d)
+{
+    return d->bc_x == WCNST_REFLECT || d->bc_x == WCNST_FIXED || d->bc_y == WCNST_REFLECT ||
+           d->bc_y == WCNST_FIXED || d->gravity != 0.0;
 }
 
 int wcnst_desc_nvar(const wcnst_desc* d)
@@ -715,6 +772,12 @@ void wcnst_make_params(const wcnst_desc* d, Params* out)
     P.charwise = d->charwise ? 1 : 0;
     P.bc_x = d->bc_x;
     P.bc_y = d->bc_y;
+    for (int side = 0; side < 2; ++side)
+        for (int v = 0; v < 4; ++v) {
+            P.fixed_x[side][v] = d->fixed_x[side][v];
+            P.fixed_y[side][v] = d->fixed_y[side][v];
+        }
+    P.gravity = d->gravity;
     *out = P;
 }
 
@@ -790,8 +853,12 @@ static void launch_sweep_t(const wcnst_solver* s, const double* U, const double*
     if constexpr (SYS == SYS_EULER && NV == 4) {
         const int nstrips = (s->d.nx + TX - 1) / TX;
         const int nseg = (s->d.ny + s->ty - 1) / s->ty;
-        hipLaunchKernelGGL((sweep2d<NV, FLUX, SCHEME, CHAR, MODE>), dim3(nstrips, nseg), dim3(WAVE), 0,
-                           s->stream, U, Un, out, flags, s->ctrl, s->P, A, s->ty);
+        if (wcnst_general_bc(&s->d))
+            hipLaunchKernelGGL((sweep2d<NV, FLUX, SCHEME, CHAR, MODE, true>), dim3(nstrips, nseg), dim3(WAVE), 0,
+                               s->stream, U, Un, out, flags, s->ctrl, s->P, A, s->ty);
+        else
+            hipLaunchKernelGGL((sweep2d<NV, FLUX, SCHEME, CHAR, MODE, false>), dim3(nstrips, nseg), dim3(WAVE), 0,
+                               s->stream, U, Un, out, flags, s->ctrl, s->P, A, s->ty);
     } else if (s->d.diff == WCNST_MD) {
         constexpr int W = strip_cells<DIFF_MD>();
         hipLaunchKernelGGL((sweep1d<SYS, NV, FLUX, SCHEME, CHAR, MODE, DIFF_MD>), dim3((s->d.nx + W - 1) / W),
@@ -1083,54 +1150,58 @@ hipError_t wcnst_launch_multi_init(int ndim, const void* reqs, int nreq, hipStre
 
 template <int NDIM, int FLUX, int SCHEME, bool CHAR>
 static void launch_multi_t(const ReqGrid* reqs, int nreq, int nblocks, int stage, int tick_step, int ty,
-                           hipStream_t st)
+                           bool general, hipStream_t st)
 {
-    if constexpr (NDIM == 2)
-        hipLaunchKernelGGL((sweep2d_multi<4, FLUX, SCHEME, CHAR>), dim3(nblocks), dim3(WAVE), 0, st, reqs, nreq,
-                           stage, tick_step, ty);
-    else
+    if constexpr (NDIM == 2) {
+        if (general)
+            hipLaunchKernelGGL((sweep2d_multi<4, FLUX, SCHEME, CHAR, true>), dim3(nblocks), dim3(WAVE), 0, st, reqs,
+                               nreq, stage, tick_step, ty);
+        else
+            hipLaunchKernelGGL((sweep2d_multi<4, FLUX, SCHEME, CHAR, false>), dim3(nblocks), dim3(WAVE), 0, st, reqs,
+                               nreq, stage, tick_step, ty);
+    } else
         hipLaunchKernelGGL((sweep1d_multi<FLUX, SCHEME, CHAR>), dim3(nblocks), dim3(WAVE), 0, st, reqs, nreq, stage,
                            tick_step);
 }
 
 template <int NDIM, int FLUX, bool CHAR>
 static void launch_multi_s(const wcnst_desc* d, const ReqGrid* reqs, int nreq, int nblocks, int stage,
-                           int tick_step, int ty, hipStream_t st)
+                           int tick_step, int ty, bool general, hipStream_t st)
 {
     switch (d->scheme) {
     case WCNST_LINEAR:
-        launch_multi_t<NDIM, FLUX, SCH_LINEAR, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, st);
+        launch_multi_t<NDIM, FLUX, SCH_LINEAR, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, general, st);
         break;
-    case WCNST_JS: launch_multi_t<NDIM, FLUX, SCH_JS, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, st); break;
+    case WCNST_JS: launch_multi_t<NDIM, FLUX, SCH_JS, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, general, st); break;
     default:
-        if (d->q == 6) launch_multi_t<NDIM, FLUX, SCH_TENO, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, st);
-        else launch_multi_t<NDIM, FLUX, SCH_TENO_Q, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, st);
+        if (d->q == 6) launch_multi_t<NDIM, FLUX, SCH_TENO, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, general, st);
+        else launch_multi_t<NDIM, FLUX, SCH_TENO_Q, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, general, st);
         break;
     }
 }
 
 template <int NDIM>
 static void launch_multi_d(const wcnst_desc* d, const ReqGrid* r, int nreq, int nblocks, int stage, int tick_step,
-                           int ty, hipStream_t st)
+                           int ty, bool general, hipStream_t st)
 {
     if (d->flux == WCNST_LF) {
-        if (d->charwise) launch_multi_s<NDIM, FLUX_LF, true>(d, r, nreq, nblocks, stage, tick_step, ty, st);
-        else launch_multi_s<NDIM, FLUX_LF, false>(d, r, nreq, nblocks, stage, tick_step, ty, st);
+        if (d->charwise) launch_multi_s<NDIM, FLUX_LF, true>(d, r, nreq, nblocks, stage, tick_step, ty, general, st);
+        else launch_multi_s<NDIM, FLUX_LF, false>(d, r, nreq, nblocks, stage, tick_step, ty, general, st);
     } else if (d->flux == WCNST_VANLEER) {
-        if (d->charwise) launch_multi_s<NDIM, FLUX_VL, true>(d, r, nreq, nblocks, stage, tick_step, ty, st);
-        else launch_multi_s<NDIM, FLUX_VL, false>(d, r, nreq, nblocks, stage, tick_step, ty, st);
+        if (d->charwise) launch_multi_s<NDIM, FLUX_VL, true>(d, r, nreq, nblocks, stage, tick_step, ty, general, st);
+        else launch_multi_s<NDIM, FLUX_VL, false>(d, r, nreq, nblocks, stage, tick_step, ty, general, st);
     } else {
-        if (d->charwise) launch_multi_s<NDIM, FLUX_ROE, true>(d, r, nreq, nblocks, stage, tick_step, ty, st);
-        else launch_multi_s<NDIM, FLUX_ROE, false>(d, r, nreq, nblocks, stage, tick_step, ty, st);
+        if (d->charwise) launch_multi_s<NDIM, FLUX_ROE, true>(d, r, nreq, nblocks, stage, tick_step, ty, general, st);
+        else launch_multi_s<NDIM, FLUX_ROE, false>(d, r, nreq, nblocks, stage, tick_step, ty, general, st);
     }
 }
 
 hipError_t wcnst_launch_multi(const wcnst_desc* d, int ndim, const void* reqs, int nreq, int nblocks, int stage,
-                              int tick_step, int ty, hipStream_t st)
+                              int tick_step, int ty, bool general, hipStream_t st)
 {
     const ReqGrid* r = (const ReqGrid*)reqs;
-    if (ndim == 2) launch_multi_d<2>(d, r, nreq, nblocks, stage, tick_step, ty, st);
-    else launch_multi_d<1>(d, r, nreq, nblocks, stage, tick_step, ty, st);
+    if (ndim == 2) launch_multi_d<2>(d, r, nreq, nblocks, stage, tick_step, ty, general, st);
+    else launch_multi_d<1>(d, r, nreq, nblocks, stage, tick_step, ty, general, st);
     return hipGetLastError();
 }
 

@@ -183,6 +183,7 @@ static wcnst_status issue_dim(wcnst_pool* p, int ndim, const std::vector<int>& a
     ReqGrid* tab = p->h_req[ndim - 1];
     int blocks = 0;
     int n = 0;
+    bool general = false;
     for (int i : act) {
         PoolReq& r = p->reqs[(size_t)i];
         Ctrl* ctrl = (Ctrl*)(p->d_ctrl + p->ctrl_bytes * (size_t)i);
@@ -191,6 +192,7 @@ static wcnst_status issue_dim(wcnst_pool* p, int ndim, const std::vector<int>& a
             r.init = true;
             r.parity = 0;
         }
+        general = general || wcnst_general_bc(&r.d);
         ReqGrid& q = tab[n++];
         q = ReqGrid{};
         q.U = r.U;
@@ -210,7 +212,8 @@ static wcnst_status issue_dim(wcnst_pool* p, int ndim, const std::vector<int>& a
     for (int64_t s = 0; s < steps; ++s)
         for (int stage = 0; stage < 3; ++stage)
             WCNST_HIP_TRY(
-                wcnst_launch_multi(&p->scheme, ndim, p->d_req[ndim - 1], n, blocks, stage, (int)(s & 1), p->ty, st));
+                wcnst_launch_multi(&p->scheme, ndim, p->d_req[ndim - 1], n, blocks, stage, (int)(s & 1), p->ty, general,
+                                   st));
     return WCNST_OK;
 }
 

@@ -15,7 +15,7 @@ from .build import LIB_PATH
 
 OK, E_INVALID_ARG, E_NONPHYSICAL, E_MAX_STEPS, E_HIP = 0, 1, 2, 3, 4
 _SYSTEM = {"advection": 0, "burgers": 1, "euler": 2}
-_BC = {"periodic": 0, "zero_gradient": 1}
+_BC = {"periodic": 0, "zero_gradient": 1, "reflect": 2, "fixed": 3}
 _FLUX = {"roe": 0, "lf": 1, "vanleer": 2}
 _SCHEME = {"teno": 0, "linear": 1, "js": 2}
 _DIFF = {"mnd": 0, "md": 1}
@@ -46,6 +46,8 @@ class Desc(ctypes.Structure):
         ("q", ctypes.c_int32),
         ("gamma", ctypes.c_double), ("adv_speed", ctypes.c_double), ("CT", ctypes.c_double),
         ("C", ctypes.c_double), ("eps_teno", ctypes.c_double), ("eps_js", ctypes.c_double),
+        ("fixed_x", (ctypes.c_double * 4) * 2), ("fixed_y", (ctypes.c_double * 4) * 2),
+        ("gravity", ctypes.c_double),
     ]
 
 
@@ -131,6 +133,14 @@ def make_desc(desc: dict) -> Desc:
     d.C = float(desc.get("C", 1.0))
     d.eps_teno = float(desc.get("eps_teno", 1e-40))
     d.eps_js = float(desc.get("eps_js", 1e-6))
+    for name in ("fixed_x", "fixed_y"):
+        states = desc.get(name)
+        if states is not None:
+            arr = getattr(d, name)
+            for side in range(2):
+                for v, val in enumerate(states[side]):
+                    arr[side][v] = float(val)
+    d.gravity = float(desc.get("gravity", 0.0))
     return d
 
 

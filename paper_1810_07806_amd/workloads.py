@@ -192,6 +192,28 @@ def riemann2d_config6(n: int = 1024, **kw):
     return quadrants(n, n, CONFIG6_STATES, **kw)
 
 
+def rayleigh_taylor(nx: int = 128, ny: int = 512, gamma: float = 5.0 / 3.0, **kw):
+    """Sec. 3.8 Rayleigh-Taylor instability on [0, 1/4] x [0, 1], gamma = 5/3:
+    heavy gas (rho 2, p = 1 + 2y) below y = 1/2, light gas (rho 1,
+    p = y + 3/2, the reading of the garbled "1 + 3/2") above, both at rest
+    but for v = -0.025 a cos(8 pi x) with a the local sound speed;
+    reflecting walls at x = 0 and 1/4, fixed states (2, 0, 0, 1) at y = 0 and
+    (1, 0, 0, 2.5) at y = 1; body force rho (in +y) in the momentum and
+    rho v in the energy equation."""
+    g = gamma
+    fixed_y = (tuple(conserved_2d(2.0, 0.0, 0.0, 1.0, g)), tuple(conserved_2d(1.0, 0.0, 0.0, 2.5, g)))
+    d = describe(ndim=2, system="euler", nx=nx, ny=ny, x0=0.0, x1=0.25, y0=0.0, y1=1.0, gamma=g,
+                 bc_x="reflect", bc_y="fixed", fixed_y=fixed_y, gravity=1.0, **kw)
+    x = coords(d, "x")[None, :]
+    y = coords(d, "y")[:, None]
+    low = np.broadcast_to(y < 0.5, (ny, nx))
+    rho = np.where(low, 2.0, 1.0)
+    p = np.where(low, 1.0 + 2.0 * y, y + 1.5)
+    a = np.sqrt(g * p / rho)
+    v = -0.025 * a * np.cos(8.0 * np.pi * x)
+    return d, conserved_2d(rho, np.zeros_like(rho), v, p, g)
+
+
 def random_euler2d(rng: np.random.Generator, nx: int, ny: int, gamma: float = 1.4, **kw):
     """Random four-quadrant state with smooth ripples: every parity case sees
     shocks, contacts and smooth regions, so both cut and kept stencils occur."""

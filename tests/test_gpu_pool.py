@@ -154,3 +154,20 @@ def test_server_results_equal_per_solve(torch):
         p = ps[c["rid"]]
         assert c["status"] == p["status"] == 0 and c["steps"] == p["steps"]
         assert np.array_equal(c["U"].ravel(), p["U"].ravel())
+
+
+def test_pool_mixes_general_and_plain_boundaries(torch):
+    """A Rayleigh-Taylor request (walls, fixed ends, gravity) and 1D tubes
+    with walls and fixed ends next to plain zero-gradient requests: the 2D
+    stage launches of a tick then take the general-boundary kernel for the
+    whole table, and every request still gives the bits of its single solve."""
+    items = _mix(4, n1=3, n2=2)
+    d, U = W.rayleigh_taylor(32, 128, gamma=1.4)  # a pool shares one gamma
+    items.append((d, U, 0.1))
+    rng = np.random.default_rng(9)
+    for bc in ("reflect", "fixed"):
+        d, U = W.random_tube(rng, 150)
+        d.update(bc_x=bc, fixed_x=(tuple(W.conserved_1d(1.2, 0.1, 1.0, 1.4)), tuple(W.conserved_1d(0.3, 0.0, 0.4, 1.4))))
+        items.append((d, U, 0.02))
+    _say("pool with general boundaries")
+    _compare(items, _run_pool(torch, items, 8))
