@@ -40,6 +40,7 @@ struct wcnst_batch {
     long long total = 0;          // doubles per packed buffer
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;  // private stream for graph capture
+    bool general = false;       // some instance has reflecting / fixed sides
     // device (caller's workspace)
     ReqGrid* d_req = nullptr;
     uint8_t* d_ctrl = nullptr;
@@ -203,7 +204,7 @@ static wcnst_status run_tick(wcnst_batch* b, int nreq, int blocks, int steps, bo
     if (steps != b->steps_per_tick) {
         for (int s = 0; s < steps; ++s)
             for (int stage = 0; stage < 3; ++stage)
-                WCNST_HIP_TRY(wcnst_launch_multi(&b->d0, 1, b->d_req, nreq, blocks, stage, s & 1, 0, false, b->stream));
+                WCNST_HIP_TRY(wcnst_launch_multi(&b->d0, 1, b->d_req, nreq, blocks, stage, s & 1, 0, b->general, b->stream));
         return WCNST_OK;
     }
     if (!b->exec || table_changed) {
@@ -216,7 +217,7 @@ static wcnst_status run_tick(wcnst_batch* b, int nreq, int blocks, int steps, bo
         hipError_t le = hipSuccess;
         for (int s = 0; s < steps && le == hipSuccess; ++s)
             for (int stage = 0; stage < 3 && le == hipSuccess; ++stage)
-                le = wcnst_launch_multi(&b->d0, 1, b->d_req, nreq, blocks, stage, s & 1, 0, false, b->cap);
+                le = wcnst_launch_multi(&b->d0, 1, b->d_req, nreq, blocks, stage, s & 1, 0, b->general, b->cap);
         hipError_t ce = hipStreamEndCapture(b->cap, &g);
         if (le != hipSuccess || ce != hipSuccess)
             return wcnst_fail(WCNST_E_HIP, "graph capture failed: %s / %s", hipGetErrorString(le),
@@ -245,6 +246,8 @@ extern "C" wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const doubl
     }
     // rows of every instance; instance i keeps control block i
     std::vector<ReqGrid> rows((size_t)n);
+    b->general = false;
+    for (int i = 0; i < n; ++i) b->general = b->general || wcnst_general_bc(&b->descs[(size_t)i]);
     for (int i = 0; i < n; ++i) {
         const wcnst_desc& d = b->descs[(size_t)i];
         const long long o = b->offs[(size_t)i];

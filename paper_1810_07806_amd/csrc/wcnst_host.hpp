@@ -29,7 +29,7 @@ void wcnst_make_params(const wcnst_desc* d, wcnst::Params* out);
 size_t wcnst_ctrl_bytes();
 hipError_t wcnst_launch_init_grid(const wcnst_desc* d, const double* U, void* ctrl, hipStream_t st);
 // general: some grid of the table has reflecting / fixed sides or gravity
-// (2D tables pick the stage kernel that handles them).
+// (the tables then take the stage kernels that handle them).
 hipError_t wcnst_launch_multi(const wcnst_desc* d, int ndim, const void* reqs, int nreq, int nblocks, int stage,
                               int tick_step, int ty, bool general, hipStream_t st);
 // true when d has sides other than periodic / zero gradient, or gravity

@@ -133,7 +133,9 @@ __device__ __forceinline__ void write_flags(uint8_t* fl, int nlines, int nfaces,
 
 // Strip bx of one 1D grid (geometry in Strip1D).  Thread 0 of strip 0
 // opens the next step record.
-template <int SYS, int NV, int FLUX, int SCHEME, bool CHAR, int MODE, int DIFF = DIFF_MND>
+// GB: general boundaries (reflecting walls, fixed ends); without it only
+// index-remap sides (periodic, zero gradient).
+template <int SYS, int NV, int FLUX, int SCHEME, bool CHAR, int MODE, int DIFF = DIFF_MND, bool GB = true>
 __device__ __forceinline__ void sweep1d_block(const double* __restrict__ U, const double* __restrict__ Un,
                                               double* __restrict__ out, uint8_t* __restrict__ flags,
                                               Ctrl* __restrict__ ctrl, const Params& P, const StageArgs& A, int bx)
@@ -154,7 +156,7 @@ __device__ __forceinline__ void sweep1d_block(const double* __restrict__ U, cons
 #pragma unroll
         for (int v = 0; v < NV; ++v) s[m][v] = U[(size_t)v * nx + col];
     }
-    if (P.bc_x >= BC_REFLECT) {
+    if (GB && P.bc_x >= BC_REFLECT) {
         // reflecting walls reverse the momentum of their ghosts; fixed ends
         // supply their own states
 #pragma unroll
@@ -248,7 +250,7 @@ __device__ __forceinline__ StageArgs request_stage(const ReqGrid& R, int stage, 
 
 // One stage of many independent 1D Euler grids in one launch (one strip per
 // block), each with its own parameters, buffers, control block and parity.
-template <int FLUX, int SCHEME, bool CHAR>
+template <int FLUX, int SCHEME, bool CHAR, bool GB>
 __global__ void __launch_bounds__(WAVE)
 sweep1d_multi(const ReqGrid* __restrict__ reqs, int nreq, int stage, int tick_step)
 {
@@ -257,7 +259,8 @@ sweep1d_multi(const ReqGrid* __restrict__ reqs, int nreq, int stage, int tick_st
     const StageArgs A = request_stage(R, stage, tick_step);
     const double* in = stage == 0 ? R.U : (stage == 1 ? R.U1 : R.U2);
     double* out = stage == 0 ? R.U1 : (stage == 1 ? R.U2 : R.U);
-    sweep1d_block<SYS_EULER, 3, FLUX, SCHEME, CHAR, MODE_STAGE>(in, R.U, out, nullptr, R.ctrl, R.P, A, b - R.blk0);
+    sweep1d_block<SYS_EULER, 3, FLUX, SCHEME, CHAR, MODE_STAGE, DIFF_MND, GB>(in, R.U, out, nullptr, R.ctrl, R.P, A,
+                                                                         b - R.blk0);
 }
 
 // ------------------------------------------------------------------ 2D
@@ -1159,9 +1162,13 @@ static void launch_multi_t(const ReqGrid* reqs, int nreq, int nblocks, int stage
         else
             hipLaunchKernelGGL((sweep2d_multi<4, FLUX, SCHEME, CHAR, false>), dim3(nblocks), dim3(WAVE), 0, st, reqs,
                                nreq, stage, tick_step, ty);
-    } else
-        hipLaunchKernelGGL((sweep1d_multi<FLUX, SCHEME, CHAR>), dim3(nblocks), dim3(WAVE), 0, st, reqs, nreq, stage,
-                           tick_step);
+    } else if (general) {
+        hipLaunchKernelGGL((sweep1d_multi<FLUX, SCHEME, CHAR, true>), dim3(nblocks), dim3(WAVE), 0, st, reqs, nreq,
+                           stage, tick_step);
+    } else {
+        hipLaunchKernelGGL((sweep1d_multi<FLUX, SCHEME, CHAR, false>), dim3(nblocks), dim3(WAVE), 0, st, reqs, nreq,
+                           stage, tick_step);
+    }
 }
 
 template <int NDIM, int FLUX, bool CHAR>

@@ -199,9 +199,13 @@ def test_batch_strip_boundaries_and_minimum_size(orc, torch):
         b.close()
 
 
+_FIXED = ((1.2, 0.1, 2.6), (0.3, 0.0, 1.0))
+
+
 @pytest.mark.parametrize("kw", [dict(flux="lf", bc_x="periodic"), dict(flux="roe", charwise=0),
-                                dict(flux="roe", scheme="linear"), dict(flux="vanleer")],
-                         ids=["lf-periodic", "componentwise", "linear", "vanleer"])
+                                dict(flux="roe", scheme="linear"), dict(flux="vanleer"),
+                                dict(bc_x="reflect"), dict(bc_x="fixed", fixed_x=_FIXED)],
+                         ids=["lf-periodic", "componentwise", "linear", "vanleer", "walls", "fixed-ends"])
 def test_batch_scheme_variants(orc, torch, kw):
     from paper_1810_07806_amd.wcnst import Batch
     rng = np.random.default_rng(41)
