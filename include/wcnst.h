@@ -53,7 +53,7 @@ enum { WCNST_ADVECTION = 0, WCNST_BURGERS = 1, WCNST_EULER = 2 };
 enum { WCNST_PERIODIC = 0, WCNST_ZERO_GRADIENT = 1, WCNST_REFLECT = 2, WCNST_FIXED = 3 };
 enum { WCNST_ROE = 0, WCNST_LF = 1, WCNST_VANLEER = 2 };
 enum { WCNST_TENO = 0, WCNST_LINEAR = 1, WCNST_JS = 2 };
-enum { WCNST_MND = 0, WCNST_MD = 1 };
+enum { WCNST_MND = 0, WCNST_MD = 1, WCNST_HWCNS = 2 };
 
 /* Problem descriptor.  Initialise with wcnst_desc_init(), then set fields. */
 typedef struct wcnst_desc {
@@ -69,8 +69,8 @@ typedef struct wcnst_desc {
     int32_t flux;         /* WCNST_ROE (no entropy fix) / WCNST_LF (local) /
                              WCNST_VANLEER (flux-vector splitting, Euler only) */
     int32_t scheme;       /* WCNST_TENO (Eqs. 16-19) / WCNST_LINEAR (Eq. 12) / WCNST_JS (Eq. 14) */
-    int32_t diff;         /* WCNST_MND (Eq. 5, 4 ghost cells) / WCNST_MD (Eq. 3, 5 ghost cells;
-                             1D single solves only: batches and pools use MND) */
+    int32_t diff;         /* WCNST_MND (Eq. 5) / WCNST_MD (Eq. 3) / WCNST_HWCNS (Eq. 4); MD and
+                             HWCNS: 1D single solves only (batches and pools use MND) */
     int32_t charwise;     /* Euler: 1 = interpolate characteristic variables */
     int32_t q;            /* TENO integer power, Eq. (16); default 6 */
     double gamma;         /* ratio of specific heats, > 1; default 1.4 */
@@ -111,9 +111,10 @@ wcnst_status wcnst_create(const wcnst_desc* d, void* hip_stream, void* workspace
  * flags (nullable, device, uint8): the stencil-cut pattern of every
  * interpolation, direction x first then y:
  *   x block [nvar][ny][nx+3][2], y block [nvar][nx][ny+3][2];
- *   with WCNST_MD (1D) the one block is [nvar][1][nx+5][2];
- * entry [k][line][s][side] is for the midpoint x_{j+1/2}, j = s - 2 (MND)
- * or j = s - 3 (MD), of
+ *   with WCNST_MD (1D) the one block is [nvar][1][nx+5][2], with
+ *   WCNST_HWCNS [nvar][1][nx+1][2];
+ * entry [k][line][s][side] is for the midpoint x_{j+1/2}, j = s - 2 (MND),
+ * j = s - 3 (MD) or j = s - 1 (HWCNS), of
  * characteristic field k (conserved variable k when charwise = 0; for y
  * lines the normal momentum comes first), side 0 = u_L, side 1 = u_R
  * (mirrored stencil); bit k-1 holds delta_k of Eq. (18).  Scalar schemes

@@ -22,14 +22,14 @@ ADVECTION, BURGERS, EULER = 0, 1, 2
 PERIODIC, ZERO_GRADIENT = 0, 1
 ROE, LF, VANLEER = 0, 1, 2
 TENO, LINEAR, JS = 0, 1, 2
-MND, MD = 0, 1
+MND, MD, HWCNS = 0, 1, 2
 OK, E_INVALID, E_NONPHYSICAL, E_MAX_STEPS = 0, 1, 2, 3
 
 _SYSTEM = {"advection": ADVECTION, "burgers": BURGERS, "euler": EULER}
 _BC = {"periodic": PERIODIC, "zero_gradient": ZERO_GRADIENT, "reflect": 2, "fixed": 3}
 _FLUX = {"roe": ROE, "lf": LF, "vanleer": VANLEER}
 _SCHEME = {"teno": TENO, "linear": LINEAR, "js": JS}
-_DIFF = {"mnd": MND, "md": MD}
+_DIFF = {"mnd": MND, "md": MD, "hwcns": HWCNS}
 
 
 class Problem(ctypes.Structure):

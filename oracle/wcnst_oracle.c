@@ -10,7 +10,7 @@
  * The steps and where they come from:
  *   semi-discretisation du_i/dt = -f'_i ........... Sec. 2, Eq. (2)
  *   SSP-RK3 (Shu-Osher form) ...................... Sec. 2 (cites Gottlieb et al. 2001)
- *   MND / MD flux differences ..................... Sec. 2.1, Eqs. (5) and (3)
+ *   MND / MD / HWCNS flux differences ............. Sec. 2.1, Eqs. (5), (3), (4)
  *   scalar upwind midpoint flux ................... Sec. 2.2, Eq. (6)
  *   candidate interpolants, derivatives ........... Sec. 2.2, Eqs. (9)-(11)
  *   optimal linear weights d_k .................... Sec. 2.2, Eq. (13)
@@ -23,8 +23,9 @@
  *                                                   the paper's results; textbook form)
  * The paper does not print the difference coefficients, the Runge-Kutta
  * form, the Roe average or the eigenvectors; the readings used here are:
- *   MND: (c1, c2, c3) = (3/2, -3/10, 1/30); MD: (75/64, -25/384, 3/640),
- *        the unique sixth-order solutions of the Taylor conditions.
+ *   MND: (c1, c2, c3) = (3/2, -3/10, 1/30); MD: (75/64, -25/384, 3/640);
+ *        HWCNS: (b1, b2, b3) = (64/45, -2/9, 1/180), the unique sixth-order
+ *        solutions of the Taylor conditions.
  *   h cancels in beta_k (Eq. (15)) and in the candidates (Eq. (9)); the
  *        scaled differences D1 = h u^(1), D2 = h^2 u^(2) are used directly.
  *   delta_k = 1 when chi_k == C_T ("otherwise" branch of Eq. (18)).
@@ -50,9 +51,9 @@ int orc_nvar(const orc_problem* p)
     return 1;
 }
 
-static int first_face(const orc_problem* p) { return p->diff == ORC_MD ? -3 : -2; }
+static int first_face(const orc_problem* p) { return p->diff == ORC_MD ? -3 : (p->diff == ORC_HWCNS ? -1 : -2); }
 
-int orc_nfaces(const orc_problem* p, int n) { return p->diff == ORC_MD ? n + 5 : n + 3; }
+int orc_nfaces(const orc_problem* p, int n) { return p->diff == ORC_MD ? n + 5 : (p->diff == ORC_HWCNS ? n + 1 : n + 3); }
 
 int64_t orc_flag_count(const orc_problem* p)
 {
@@ -422,6 +423,20 @@ static void line_rhs(const orc_problem* p, int nv, int n, double h, const double
                 double dfdx = c1 / h * (Fp1 - Fm1) + c2 / h * (fp - fm) + c3 / h * (Fp3 - Fm3);
                 out[(size_t)i * nv + v] = -dfdx;
             }
+    } else if (p->diff == ORC_HWCNS) {
+        /* Eq. (4): b1 (F_{i+1/2}-F_{i-1/2}) + b2 (f_{i+1}-f_{i-1}) + b3 (f_{i+2}-f_{i-2}),
+         * node fluxes f_i for i = -2 .. n+1 at Fnode[i + 2] */
+        const double b1 = 64.0 / 45.0, b2 = -2.0 / 9.0, b3 = 1.0 / 180.0;
+        for (int i = -2; i <= n + 1; ++i)
+            phys_flux(p, line + (size_t)(i + GHOST) * nv, Fnode + (size_t)(i + 2) * nv);
+        for (int i = 0; i < n; ++i)
+            for (int v = 0; v < nv; ++v) {
+                double Fp1 = Fface[(size_t)(i + 1) * nv + v], Fm1 = Fface[(size_t)i * nv + v];
+                double fp1 = Fnode[(size_t)(i + 3) * nv + v], fm1 = Fnode[(size_t)(i + 1) * nv + v];
+                double fp2 = Fnode[(size_t)(i + 4) * nv + v], fm2 = Fnode[(size_t)i * nv + v];
+                double dfdx = b1 / h * (Fp1 - Fm1) + b2 / h * (fp1 - fm1) + b3 / h * (fp2 - fm2);
+                out[(size_t)i * nv + v] = -dfdx;
+            }
     } else {
         /* Eq. (3): a1 (F_{i+1/2}-F_{i-1/2}) + a2 (F_{i+3/2}-F_{i-3/2}) + a3 (F_{i+5/2}-F_{i-5/2}) */
         const double a1 = 75.0 / 64.0, a2 = -25.0 / 384.0, a3 = 3.0 / 640.0;
@@ -484,7 +499,7 @@ int orc_rhs(const orc_problem* p, const double* U, double* R, uint8_t* flags, do
         double* line = (double*)malloc(sizeof(double) * (size_t)(nmax + 2 * GHOST) * nv);
         double* out = (double*)malloc(sizeof(double) * (size_t)nmax * nv);
         double* Ff = (double*)malloc(sizeof(double) * (size_t)(nmax + 5) * nv);
-        double* Fn = (double*)malloc(sizeof(double) * (size_t)(nmax + 2) * nv);
+        double* Fn = (double*)malloc(sizeof(double) * (size_t)(nmax + 4) * nv);
 #pragma omp for schedule(static)
         for (int y = 0; y < ny; ++y) {
             for (int g = -GHOST; g < nx + GHOST; ++g) {

@@ -32,7 +32,7 @@ enum { ORC_ADVECTION = 0, ORC_BURGERS = 1, ORC_EULER = 2 };
 enum { ORC_PERIODIC = 0, ORC_ZERO_GRADIENT = 1, ORC_REFLECT = 2, ORC_FIXED = 3 };
 enum { ORC_ROE = 0, ORC_LF = 1, ORC_VANLEER = 2 };
 enum { ORC_TENO = 0, ORC_LINEAR = 1, ORC_JS = 2 };
-enum { ORC_MND = 0, ORC_MD = 1 };
+enum { ORC_MND = 0, ORC_MD = 1, ORC_HWCNS = 2 };
 
 enum {
     ORC_OK = 0,
@@ -49,7 +49,7 @@ typedef struct orc_problem {
     int bc_x, bc_y;  /* ORC_PERIODIC / ORC_ZERO_GRADIENT / ORC_REFLECT (Euler) / ORC_FIXED */
     int flux;        /* ORC_ROE / ORC_LF / ORC_VANLEER (Euler only) */
     int scheme;      /* ORC_TENO / ORC_LINEAR / ORC_JS */
-    int diff;        /* ORC_MND / ORC_MD */
+    int diff;        /* ORC_MND / ORC_MD / ORC_HWCNS */
     int charwise;    /* Euler: 1 = interpolate characteristic variables */
     int q;           /* TENO integer power (6) */
     double gamma;    /* ratio of specific heats */

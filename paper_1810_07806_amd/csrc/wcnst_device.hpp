@@ -34,7 +34,7 @@ enum { FLUX_ROE = 0, FLUX_LF = 1, FLUX_VL = 2 };
 // SCH_TENO: Eq. (16) with the paper's q = 6; SCH_TENO_Q: any integer q
 enum { SCH_TENO = 0, SCH_LINEAR = 1, SCH_JS = 2, SCH_TENO_Q = 3 };
 enum { BC_PERIODIC = 0, BC_ZG = 1, BC_REFLECT = 2, BC_FIXED = 3 };
-enum { DIFF_MND = 0, DIFF_MD = 1 };
+enum { DIFF_MND = 0, DIFF_MD = 1, DIFF_HW = 2 };
 
 // ------------------------------------------------------ strip geometry
 
@@ -43,11 +43,13 @@ constexpr int TX = WAVE - 3;  // cells per MND strip (1D) / columns per 2D strip
 
 // 1D strips: the 64 midpoints of a wavefront serve the cells whose
 // differences reach only them; MND reaches 3/2 spacings from a cell (61
-// cells per strip), MD 5/2 spacings (59 cells).
+// cells per strip), MD 5/2 spacings (59 cells).  HWCNS reaches midpoints
+// 1/2 away and nodes 2 away; each lane also evaluates one node flux, so 64
+// node fluxes serve 60 cells.
 template <int DIFF>
 constexpr int strip_cells()
 {
-    return DIFF == DIFF_MD ? WAVE - 5 : WAVE - 3;
+    return DIFF == DIFF_MD ? WAVE - 5 : (DIFF == DIFF_HW ? WAVE - 4 : WAVE - 3);
 }
 
 // Owner of midpoint j (j in [-G, n-2+G]) among tiles of width w: the tile
@@ -59,15 +61,19 @@ WCNST_HD int face_owner(int j, int n, int w)
 }
 
 // Lane `lane` of 1D strip bx on a line of nx cells.  The lane computes
-// midpoint jx+1/2, jx = x0-G+lane (G = 2 for MND, 3 for MD); the line needs
-// midpoints -G .. jmax = nx-2+G (jmax+G+1 flag slots).  Lanes past jmax
-// read the stencil of jmax (in-range data, result unused).  The lane owns
-// cell c = x0+lane when cell_ok; that cell's differences use the midpoints
-// of lanes lane .. lane+2G-1, and its own state is stencil node G+2.
+// midpoint jx+1/2, jx = x0-G+lane (G = 2 for MND, 3 for MD, 1 for HWCNS);
+// the line needs midpoints -G .. jmax = nx-2+G (jmax+G+1 flag slots).
+// Lanes past the last stencil any lane needs read the stencil of that last
+// one (in-range data, result unused): jmax, or for HWCNS, whose lanes also
+// evaluate the node flux at their stencil node 1 (node jx-1, needed up to
+// nx+1), jmax+3.  The lane owns cell c = x0+lane when cell_ok; that cell's
+// differences use the midpoints of lanes lane .. lane+2G-1 (and for HWCNS
+// the node fluxes of lanes lane, lane+1, lane+3, lane+4), and its own state
+// is stencil node G+2.
 template <int DIFF>
 struct Strip1D {
     static constexpr int W = strip_cells<DIFF>();
-    static constexpr int G = DIFF == DIFF_MD ? 3 : 2;
+    static constexpr int G = DIFF == DIFF_MD ? 3 : (DIFF == DIFF_HW ? 1 : 2);
     int x0, c, jx, jmax, jxl;
     bool cell_ok;
     WCNST_HD Strip1D(int bx, int lane, int nx)
@@ -77,7 +83,8 @@ struct Strip1D {
         cell_ok = lane < W && c < nx;
         jx = x0 - G + lane;
         jmax = nx - 2 + G;
-        jxl = jx < jmax ? jx : jmax;
+        const int last = DIFF == DIFF_HW ? jmax + 3 : jmax;
+        jxl = jx < last ? jx : last;
     }
     // this lane reports the cut flags of its midpoint (each midpoint once)
     WCNST_HD bool owns_face(int bx, int nx) const { return jx <= jmax && face_owner(jx, nx, W) == bx; }
@@ -662,6 +669,15 @@ WCNST_HD double md(double a1, double a2, double a3, double Fm5, double Fm3, doub
                    double Fp5)
 {
     const double dfdx = a1 * (Fp1 - Fm1) + a2 * (Fp3 - Fm3) + a3 * (Fp5 - Fm5);
+    return -dfdx;
+}
+
+// HWCNS difference, Eq. (4): -(b1 (F_{i+1/2} - F_{i-1/2}) + b2 (f_{i+1} - f_{i-1})
+// + b3 (f_{i+2} - f_{i-2})) with b_k already divided by h.
+WCNST_HD double hwcns(double b1, double b2, double b3, double Fm1, double Fp1, double fm2, double fm1, double fp1,
+                      double fp2)
+{
+    const double dfdx = b1 * (Fp1 - Fm1) + b2 * (fp1 - fm1) + b3 * (fp2 - fm2);
     return -dfdx;
 }
 

@@ -152,7 +152,8 @@ __device__ __forceinline__ void sweep1d_block(const double* __restrict__ U, cons
     double s[6][NV], un[NV];
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
-        const int col = ghost_map(jxl - 2 + m, nx, P.bc_x);
+        // HWCNS lanes reach up to 5 cells past the line: any-distance map
+        const int col = DIFF == DIFF_HW ? ghost_map_any(jxl - 2 + m, nx, P.bc_x) : ghost_map(jxl - 2 + m, nx, P.bc_x);
 #pragma unroll
         for (int v = 0; v < NV; ++v) s[m][v] = U[(size_t)v * nx + col];
     }
@@ -181,11 +182,13 @@ __device__ __forceinline__ void sweep1d_block(const double* __restrict__ U, cons
     RegStencil<NV> st{s};
     face_flux<SYS, NV, FLUX, SCHEME, CHAR>(st, P, F, fb);
     if (MODE == MODE_RHS && flags && S.owns_face(bx, nx)) write_flags<NV>(flags, 1, S.nfaces(), 0, jx + G, fb);
+    // node flux: MND at node jx+1 (stencil node 3), HWCNS at node jx-1 (1)
     if constexpr (DIFF == DIFF_MND) node_flux<SYS, NV>(s[3], P, fn);
+    if constexpr (DIFF == DIFF_HW) node_flux<SYS, NV>(s[1], P, fn);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         sF[v][lane] = F[v];
-        if constexpr (DIFF == DIFF_MND) sN[v][lane] = fn[v];
+        if constexpr (DIFF != DIFF_MD) sN[v][lane] = fn[v];
     }
     __syncthreads();
     unsigned long long sm = 0ull;
@@ -196,6 +199,9 @@ __device__ __forceinline__ void sweep1d_block(const double* __restrict__ U, cons
             if constexpr (DIFF == DIFF_MD)
                 R[v] = md(P.c1x, P.c2x, P.c3x, sF[v][lane], sF[v][lane + 1], sF[v][lane + 2], sF[v][lane + 3],
                           sF[v][lane + 4], sF[v][lane + 5]);
+            else if constexpr (DIFF == DIFF_HW)
+                R[v] = hwcns(P.c1x, P.c2x, P.c3x, sF[v][lane], sF[v][lane + 1], sN[v][lane], sN[v][lane + 1],
+                             sN[v][lane + 3], sN[v][lane + 4]);
             else
                 R[v] = mnd(P.c1x, P.c2x, P.c3x, sF[v][lane], sF[v][lane + 1], sF[v][lane + 2], sF[v][lane + 3],
                            sN[v][lane], sN[v][lane + 2]);
@@ -684,9 +690,10 @@ wcnst_status wcnst_check_desc(const wcnst_desc* d)
     if (d->flux == WCNST_VANLEER && d->system != WCNST_EULER)
         return fail(WCNST_E_INVALID_ARG, "the van Leer splitting is for the Euler system");
     if (d->scheme < WCNST_TENO || d->scheme > WCNST_JS) return fail(WCNST_E_INVALID_ARG, "unknown scheme");
-    if (d->diff != WCNST_MND && d->diff != WCNST_MD) return fail(WCNST_E_INVALID_ARG, "unknown difference");
-    if (d->diff == WCNST_MD && d->ndim != 1)
-        return fail(WCNST_E_INVALID_ARG, "the MD difference is built for 1D grids");
+    if (d->diff != WCNST_MND && d->diff != WCNST_MD && d->diff != WCNST_HWCNS)
+        return fail(WCNST_E_INVALID_ARG, "unknown difference");
+    if (d->diff != WCNST_MND && d->ndim != 1)
+        return fail(WCNST_E_INVALID_ARG, "the MD and HWCNS differences are built for 1D grids");
     if (d->system == WCNST_EULER && !(d->gamma > 1.0)) return fail(WCNST_E_INVALID_ARG, "gamma must be > 1");
     if (d->q < 1 || d->q > 64) return fail(WCNST_E_INVALID_ARG, "q must be in [1, 64]");
     if (!(d->CT > 0.0 && d->CT < 1.0 / 3.0)) return fail(WCNST_E_INVALID_ARG, "C_T must be in (0, 1/3)");
@@ -763,6 +770,11 @@ void wcnst_make_params(const wcnst_desc* d, Params* out)
         P.c1x = (75.0 / 64.0) / P.dx;
         P.c2x = (-25.0 / 384.0) / P.dx;
         P.c3x = (3.0 / 640.0) / P.dx;
+    } else if (d->diff == WCNST_HWCNS) {
+        // Eq. (4): (64/45, -2/9, 1/180)
+        P.c1x = (64.0 / 45.0) / P.dx;
+        P.c2x = (-2.0 / 9.0) / P.dx;
+        P.c3x = (1.0 / 180.0) / P.dx;
     } else {
         P.c1x = (3.0 / 2.0) / P.dx;
         P.c2x = (-3.0 / 10.0) / P.dx;
@@ -865,6 +877,10 @@ static void launch_sweep_t(const wcnst_solver* s, const double* U, const double*
     } else if (s->d.diff == WCNST_MD) {
         constexpr int W = strip_cells<DIFF_MD>();
         hipLaunchKernelGGL((sweep1d<SYS, NV, FLUX, SCHEME, CHAR, MODE, DIFF_MD>), dim3((s->d.nx + W - 1) / W),
+                           dim3(WAVE), 0, s->stream, U, Un, out, flags, s->ctrl, s->P, A);
+    } else if (s->d.diff == WCNST_HWCNS) {
+        constexpr int W = strip_cells<DIFF_HW>();
+        hipLaunchKernelGGL((sweep1d<SYS, NV, FLUX, SCHEME, CHAR, MODE, DIFF_HW>), dim3((s->d.nx + W - 1) / W),
                            dim3(WAVE), 0, s->stream, U, Un, out, flags, s->ctrl, s->P, A);
     } else {
         constexpr int W = strip_cells<DIFF_MND>();

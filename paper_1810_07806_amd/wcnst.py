@@ -18,7 +18,7 @@ _SYSTEM = {"advection": 0, "burgers": 1, "euler": 2}
 _BC = {"periodic": 0, "zero_gradient": 1, "reflect": 2, "fixed": 3}
 _FLUX = {"roe": 0, "lf": 1, "vanleer": 2}
 _SCHEME = {"teno": 0, "linear": 1, "js": 2}
-_DIFF = {"mnd": 0, "md": 1}
+_DIFF = {"mnd": 0, "md": 1, "hwcns": 2}
 
 EXPORTS = ("wcnst_desc_init", "wcnst_workspace_size", "wcnst_create", "wcnst_rhs", "wcnst_step",
            "wcnst_solve", "wcnst_status_sync", "wcnst_reset", "wcnst_set_tuning", "wcnst_profile_enable",
@@ -151,8 +151,9 @@ def nvar(desc: dict) -> int:
 
 
 def _nfaces_1d(desc: dict) -> int:
-    """Midpoints of a 1D line: -2 .. nx for MND, -3 .. nx+1 for MD."""
-    return int(desc["nx"]) + (5 if desc.get("diff", "mnd") == "md" else 3)
+    """Midpoints of a 1D line: -2 .. nx for MND, -3 .. nx+1 for MD, -1 .. nx-1
+    for HWCNS."""
+    return int(desc["nx"]) + {"mnd": 3, "md": 5, "hwcns": 1}[desc.get("diff", "mnd")]
 
 
 def flag_count(desc: dict) -> int:

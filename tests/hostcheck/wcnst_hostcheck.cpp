@@ -95,8 +95,11 @@ namespace {
 // cell is owned once, every midpoint -G .. nx-2+G is reported once by a lane
 // that computed it from its own (unclamped) stencil, each owned cell finds
 // its 2G midpoints on the lanes above it and its own state at stencil node
-// G+2, and all stencil nodes lie within one line length of the line; else a
-// code naming the first violated property.
+// G+2, HWCNS cells find the node fluxes of nodes c-2, c-1, c+1, c+2 at
+// stencil node 1 of lanes lane, lane+1, lane+3, lane+4, and the stencil
+// nodes of MND / MD lanes lie within one line length of the line (HWCNS
+// loads use the any-distance map); else a code naming the first violated
+// property.
 template <int DIFF>
 static int strip_check(int nx)
 {
@@ -108,7 +111,7 @@ static int strip_check(int nx)
         for (int lane = 0; lane < WAVE; ++lane) {
             const S1 s(bx, lane, nx);
             if (s.nfaces() != nx + 2 * G - 1) return 1;
-            for (int m = 0; m < 6; ++m) {
+            for (int m = 0; m < 6 && DIFF != DIFF_HW; ++m) {
                 const int node = s.jxl - 2 + m;
                 if (node < -nx || node >= 2 * nx) return 2;
             }
@@ -124,6 +127,14 @@ static int strip_check(int nx)
                     if (lane + k >= WAVE) return 6;
                     const S1 t(bx, lane + k, nx);
                     if (t.jx != s.c - G + k || t.jxl != t.jx) return 7;
+                }
+                if (DIFF == DIFF_HW) {
+                    const int off[4] = {0, 1, 3, 4}, node[4] = {s.c - 2, s.c - 1, s.c + 1, s.c + 2};
+                    for (int k = 0; k < 4; ++k) {
+                        if (lane + off[k] >= WAVE) return 10;
+                        const S1 t(bx, lane + off[k], nx);
+                        if (t.jxl - 2 + 1 != node[k]) return 11;
+                    }
                 }
             }
         }
@@ -180,7 +191,7 @@ int hc_rhs(int ndim, int sys, int flux, int nx, int ny, double dx, double dy, in
 
 int hc_strip1d_check(int nx, int diff_md)
 {
-    return diff_md ? strip_check<DIFF_MD>(nx) : strip_check<DIFF_MND>(nx);
+    return diff_md == 2 ? strip_check<DIFF_HW>(nx) : (diff_md ? strip_check<DIFF_MD>(nx) : strip_check<DIFF_MND>(nx));
 }
 
 }  // extern "C"

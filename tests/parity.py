@@ -61,9 +61,9 @@ def check_flags(fg_blocks, fo_blocks, chi_blocks, CT):
 def rhs_mask_from_flips(shape, flips, ndim, diff="mnd"):
     """Boolean mask (ny, nx) of cells whose stencil touches a flipped midpoint
     (MND: midpoints within 3/2 spacings of a cell, slot s = j + 2; MD: within
-    5/2 spacings, slot s = j + 3)."""
+    5/2 spacings, slot s = j + 3; HWCNS: within 1/2, slot s = j + 1)."""
     ny, nx = shape
-    g = 3 if diff == "md" else 2
+    g = {"md": 3, "hwcns": 1}.get(diff, 2)
     keep = np.ones((ny, nx), dtype=bool)
     for d, fl in enumerate(flips):
         for k, line, slot, side in fl:

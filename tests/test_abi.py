@@ -65,7 +65,8 @@ def test_workspace_size_and_validation():
     bad = [dict(nx=4), dict(ndim=3), dict(ndim=2, system="advection", nx=8, ny=8),
            dict(ndim=2, nx=8, ny=4), dict(gamma=1.0), dict(CT=0.5), dict(q=0),
            dict(x0=1.0, x1=1.0), dict(ndim=2, nx=8, ny=8, diff="md"),
-           dict(system="advection", flux="vanleer")]
+           dict(system="advection", flux="vanleer"), dict(ndim=2, nx=8, ny=8, diff="hwcns"),
+           dict(system="advection", bc_x="reflect"), dict(gravity=1.0)]
     for kw in bad:
         st, _ = _ws(wc, L, **kw)
         assert st == wc.E_INVALID_ARG, kw

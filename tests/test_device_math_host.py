@@ -115,8 +115,9 @@ def test_strip_geometry_of_the_1d_kernel(hc):
     owned by the strip whose midpoints reach them), checked for every strip
     and lane of the launch: each cell once, each midpoint reported once from
     its own stencil, each cell's 2G midpoints on the lanes above it, stencils
-    inside the ghost range.  MND (G = 2, 61-cell strips) and MD (G = 3, 59)."""
+    inside the ghost range.  MND (G = 2, 61-cell strips), MD (G = 3, 59) and
+    HWCNS (G = 1, 60, node fluxes at stencil node 1)."""
     hc.hc_strip1d_check.argtypes = [ctypes.c_int, ctypes.c_int]
-    for md in (0, 1):
+    for md in (0, 1, 2):
         for nx in list(range(5, 200)) + [243, 244, 245, 4096, 16384, 16385]:
             assert hc.hc_strip1d_check(nx, md) == 0, (nx, md)

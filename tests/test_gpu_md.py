@@ -1,9 +1,9 @@
-"""The MD difference of Sec. 2.1 Eq. (3) on the GPU (1D single solves),
-against the oracle through the C ABI: RHS within 1e-12 with cut flags
-identical outside the tie band, whole trajectories bit for bit, at sizes
-spanning several 59-cell strips with ragged tails, and the paper's own
-accuracy tables (Tables 2 and 3 of Sec. 3, which use MD) reproduced by the
-GPU path."""
+"""The MD and HWCNS differences of Sec. 2.1 (Eqs. (3) and (4)) on the GPU
+(1D single solves), against the oracle through the C ABI: RHS within 1e-12
+with cut flags identical outside the tie band, whole trajectories bit for
+bit, at sizes spanning several 59- / 60-cell strips with ragged tails, and
+the paper's own accuracy tables (Tables 2 and 3 of Sec. 3, which use MD)
+reproduced by the GPU path."""
 from __future__ import annotations
 
 import os
@@ -41,7 +41,7 @@ def _solver(desc):
 
 
 def _rhs_case(orc, torch, desc, U, name):
-    _say(f"md rhs {name} {desc['system']} nx={desc['nx']} flux={desc.get('flux')} "
+    _say(f"{desc['diff']} rhs {name} {desc['system']} nx={desc['nx']} flux={desc.get('flux')} "
          f"scheme={desc.get('scheme')} charwise={desc.get('charwise')} bc={desc.get('bc_x')}")
     from paper_1810_07806_amd.wcnst import split_flags
     s = _solver(desc)
@@ -52,16 +52,17 @@ def _rhs_case(orc, torch, desc, U, name):
     fg = [b.cpu().numpy() for b in split_flags(desc, fg)]
     s.close()
     Ro, fo, co = orc.rhs(orc.problem(desc), U, flags=True, chi=True, nthreads=NTHREADS)
-    assert fg[0].shape == fo[0].shape == (Ro.shape[0], 1, desc["nx"] + 5, 2)
+    extra = {"md": 5, "hwcns": 1}[desc["diff"]]
+    assert fg[0].shape == fo[0].shape == (Ro.shape[0], 1, desc["nx"] + extra, 2)
     flips = check_flags(fg, fo, co, desc.get("CT", 1e-5))
-    keep = rhs_mask_from_flips((1, desc["nx"]), flips, 1, diff="md")
+    keep = rhs_mask_from_flips((1, desc["nx"]), flips, 1, diff=desc["diff"])
     assert_rhs_close(Rg, Ro, keep)
     if not any(len(f) for f in flips):
         assert np.array_equal(Rg, Ro)
     return fo
 
 
-def _case(system, n, rng, **kw):
+def _case(system, n, rng, diff="md", **kw):
     if system == "euler":
         d, U = W.random_tube(rng, n)
     elif system == "advection":
@@ -72,7 +73,7 @@ def _case(system, n, rng, **kw):
         d = W.describe(ndim=1, system="burgers", nx=n, bc_x="periodic")
         U = rng.normal(size=(1, 1, n))
     d.update(kw)
-    d["diff"] = "md"
+    d["diff"] = diff
     return d, U
 
 
@@ -85,26 +86,28 @@ CASES = [("euler", dict(flux="roe", scheme="teno", charwise=1, bc_x="zero_gradie
          ("burgers", dict(flux="lf", scheme="js"))]
 
 
+@pytest.mark.parametrize("diff", ["md", "hwcns"])
 @pytest.mark.parametrize("system,kw", CASES, ids=lambda v: v if isinstance(v, str) else "-".join(map(str, v.values())))
-def test_rhs_md_1d(orc, torch, system, kw):
+def test_rhs_md_1d(orc, torch, system, kw, diff):
     rng = np.random.default_rng(31)
     cut_seen = False
-    # one strip minus one, one, one plus one, two, a ragged four, the minimum
-    for n in (58, 59, 60, 118, 245, 5):
-        d, U = _case(system, n, rng, **kw)
+    # around one and two strips (59 / 60 cells), a ragged four, the minimum
+    for n in (58, 59, 60, 61, 118, 120, 245, 5, 6):
+        d, U = _case(system, n, rng, diff=diff, **kw)
         fo = _rhs_case(orc, torch, d, U, f"{system}{n}")
         cut_seen |= bool((fo[0] != 7).any())
     if kw.get("scheme") == "teno" and system != "burgers":
         assert cut_seen
 
 
-def test_solve_md_matches_oracle_bitwise(orc, torch):
+@pytest.mark.parametrize("diff", ["md", "hwcns"])
+def test_solve_md_matches_oracle_bitwise(orc, torch, diff):
     """Whole trajectories: a shock tube to t = 0.1 and 100 steps of a
     periodic advection of a square pulse."""
     rng = np.random.default_rng(8)
     d, U = W.random_tube(rng, 300)
-    d["diff"] = "md"
-    _say("md solve tube300 to t=0.1")
+    d["diff"] = diff
+    _say(f"{diff} solve tube300 to t=0.1")
     s = _solver(d)
     V = s.new_state(U)
     t, n = s.solve(V, t_final=0.1, cfl=0.5)
@@ -113,8 +116,8 @@ def test_solve_md_matches_oracle_bitwise(orc, torch):
     assert r["status"] == 0 and n == r["steps"] and t == r["t"]
     assert rel_inf_err(V.cpu().numpy(), r["U"]).max() <= FIELD_TOL
     assert np.array_equal(V.cpu().numpy(), r["U"])
-    d, U = _case("advection", 200, rng, scheme="teno")
-    _say("md solve advection200 100 steps")
+    d, U = _case("advection", 200, rng, diff=diff, scheme="teno")
+    _say(f"{diff} solve advection200 100 steps")
     s = _solver(d)
     V = s.new_state(U)
     s.solve(V, t_final=np.inf, cfl=0.5, max_steps=100)

@@ -216,12 +216,18 @@ def test_mnd_coefficients_solve_the_taylor_system():
     assert sum(2 * ak * sk for ak, sk in zip(a, s)) == 1
     for pw in (3, 5):
         assert sum(ak * sk ** pw for ak, sk in zip(a, s)) == 0
+    # HWCNS, Eq. (4): midpoints at 1/2, nodes at 1 and 2
+    b = [Fr(64, 45), Fr(-2, 9), Fr(1, 180)]
+    s = [Fr(1, 2), Fr(1), Fr(2)]
+    assert sum(2 * bk * sk for bk, sk in zip(b, s)) == 1
+    for pw in (3, 5):
+        assert sum(bk * sk ** pw for bk, sk in zip(b, s)) == 0
 
 
-@pytest.mark.parametrize("diff", ["mnd", "md"])
+@pytest.mark.parametrize("diff", ["mnd", "md", "hwcns"])
 @pytest.mark.parametrize("deg", [1, 2, 3, 4])
 def test_rhs_exact_for_polynomials(orc, diff, deg):
-    """Linear interpolation is exact to degree 4 and MND/MD to degree 6, so the
+    """Linear interpolation is exact to degree 4 and MND/MD/HWCNS to degree 6, so the
     advection RHS equals -a u'(x_i) away from the boundary ghosts."""
     n = 40
     d = W.describe(ndim=1, system="advection", nx=n, x0=0.0, x1=1.0, scheme="linear",
@@ -242,13 +248,14 @@ def _order(errs, ns):
     return [math.log(errs[i] / errs[i + 1]) / math.log(ns[i + 1] / ns[i]) for i in range(len(ns) - 1)]
 
 
-@pytest.mark.parametrize("scheme", ["teno", "linear"])
-def test_semidiscrete_order_advection(orc, scheme):
+@pytest.mark.parametrize("scheme,diff", [("teno", "mnd"), ("linear", "mnd"), ("teno", "hwcns"), ("linear", "md")])
+def test_semidiscrete_order_advection(orc, scheme, diff):
     ns = [32, 64, 128, 256]
     errs = []
     for n in ns:
         d, U = W.smooth_periodic(n)
         d["scheme"] = scheme
+        d["diff"] = diff
         R, _, _ = orc.rhs(orc.problem(d), U)
         x = W.coords(d)
         errs.append(np.abs(R.ravel() + np.pi * np.cos(np.pi * x)).max())
