@@ -2,17 +2,19 @@
 //
 // Hot path per Runge-Kutta stage: one fused kernel computes, for every cell,
 // the midpoint fluxes around it (Sec. 2.2-2.3), the MND difference of
-// Sec. 2.1 Eq. (5) in x and y, and the stage update of SSP-RK3 (Sec. 2);
-// the last stage also reduces the CFL wave speed of the new state.
+// Sec. 2.1 Eq. (5) in x and y (1D grids may also use MD, Eq. (3), or HWCNS,
+// Eq. (4)), and the stage update of SSP-RK3 (Sec. 2); the last stage also
+// reduces the CFL wave speed of the new state.
 //
 // Work decomposition.  One wavefront (64 lanes) owns a strip of TX = 61
 // columns, so one row of the strip needs exactly 64 x-midpoints (j = x0-2 ..
 // x0+61): lane l computes midpoint x0-2+l.  In 2D the wavefront marches up a
 // segment of rows; lane l owns column x0+l and computes one y-midpoint per
-// row, keeping the last four y-midpoint fluxes and three node fluxes in
-// registers, so every midpoint flux is computed once per strip.  The x-flux
-// of a row is exchanged through 1 KiB of LDS per variable.  Ghost cells are
-// an index remap at load time (no extra HBM traffic).
+// row, keeping the last four y-midpoint fluxes in registers, so every
+// midpoint flux is computed once per strip.  The x-flux of a row is
+// exchanged through 512 bytes of LDS per variable.  Ghost cells are never
+// stored: an index remap at load time, plus a sign or a fixed state for
+// reflecting and fixed sides (no extra HBM traffic).
 #include <hip/hip_runtime.h>
 
 #include <math.h>
