@@ -329,3 +329,30 @@ def test_lax_liu_configurations_to_paper_time(orc, torch, config):
     counts agree."""
     d, U = (W.riemann2d_config3 if config == 3 else W.riemann2d_config6)(256)
     _solve_case(orc, torch, d, U, 0.3, 1 << 40, f"lax-liu-{config}-t0.3")
+
+
+@pytest.mark.parametrize("bc", ["zero_gradient", "periodic", "reflect", "fixed"])
+def test_free_stream_rhs_is_exactly_zero(orc, torch, bc):
+    """Degenerate input: a uniform state (moving, except against walls) has
+    an RHS of exactly zero on every side type, in 1D and 2D, on the GPU as
+    in the oracle; with fixed sides holding the same state."""
+    g = 1.4
+    u = 0.0 if bc == "reflect" else 0.3
+    v = 0.0 if bc == "reflect" else -0.2
+    st2 = W.conserved_2d(0.9, u, v, 1.1, g)
+    st1 = W.conserved_1d(0.9, u, 1.1, g)
+    fixed2 = (tuple(st2), tuple(st2))
+    fixed1 = (tuple(st1), tuple(st1))
+    for d, U in (
+        (W.describe(ndim=2, system="euler", nx=70, ny=40, bc_x=bc, bc_y=bc, fixed_x=fixed2, fixed_y=fixed2),
+         np.broadcast_to(np.asarray(st2)[:, None, None], (4, 40, 70)).copy()),
+        (W.describe(ndim=1, system="euler", nx=130, bc_x=bc, fixed_x=fixed1),
+         np.broadcast_to(np.asarray(st1)[:, None, None], (3, 1, 130)).copy()),
+    ):
+        _say(f"free stream {d['ndim']}D {bc}")
+        s = _solver(d)
+        Rg = s.rhs(s.new_state(U)).cpu().numpy()
+        s.close()
+        Ro, _, _ = orc.rhs(orc.problem(d), U)
+        assert np.abs(Ro).max() == 0.0
+        assert np.abs(Rg).max() == 0.0
