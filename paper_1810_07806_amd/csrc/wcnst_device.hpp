@@ -15,9 +15,13 @@
 // problem).  Every operation that produces a value is therefore evaluated
 // in the plain order of its definition with IEEE division and square root
 // and without contraction (this file and the kernels are compiled with
-// -ffp-contract=off), so results are reproducible bit for bit.  Only the
-// cut-off test itself, which is decided far from its threshold except in
-// genuine ties, uses a fast reciprocal and the comparison form
+// -ffp-contract=off), so results are reproducible bit for bit.  (The
+// reciprocals and roots of the projection's Roe average use the hardware's
+// correctly rounded sequences without their range scaling, which give the
+// IEEE results bit for bit over the argument range they are used in; lanes
+// whose arguments leave it redo that average with the IEEE operations.)
+// Only the cut-off test itself, which is decided far from its threshold
+// except in genuine ties, uses a fast reciprocal and the comparison form
 // gamma_k < C_T * sum(gamma).
 #pragma once
 
@@ -224,6 +228,71 @@ WCNST_HD double approx_rcp(double x)
 #endif
 }
 
+// 1/x and sqrt(x) for positive x in [2^-767, 2^1022), where they equal the
+// IEEE operations bit for bit.  They are the hardware's own correctly
+// rounded sequences (reciprocal estimate, two Newton steps and a residual
+// correction; root estimate and Goldschmidt refinement) without the operand
+// scaling and the special-value fix-up that the general operations wrap
+// around them: in that range neither changes a result.  Callers test their
+// arguments with in_ieee_range and redo the work with the IEEE operations
+// where a lane's argument lies outside it.
+WCNST_HD bool in_ieee_range(double x)
+{
+    // sign clear and biased exponent in [256, 2044]: one unsigned compare of
+    // the high word
+    unsigned long long b;
+    __builtin_memcpy(&b, &x, sizeof b);
+    return (unsigned)(b >> 32) - (256u << 20) < (1789u << 20);
+}
+
+WCNST_HD double recip_ranged(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-x, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    const double r = __builtin_fma(-x, y, 1.0);
+    return __builtin_fma(r, y, y);
+#else
+    return 1.0 / x;
+#endif
+}
+
+WCNST_HD double sqrt_ranged(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y;
+    double h = y * 0.5;
+    const double r = __builtin_fma(-h, g, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    double d = __builtin_fma(-g, g, x);
+    g = __builtin_fma(d, h, g);
+    d = __builtin_fma(-g, g, x);
+    return __builtin_fma(d, h, g);
+#else
+    return sqrt(x);
+#endif
+}
+
+// RANGED selects the sequences above; the caller owns the range test.
+template <bool RANGED>
+WCNST_HD double recip(double x)
+{
+    if constexpr (RANGED) return recip_ranged(x);
+    else return 1.0 / x;
+}
+
+template <bool RANGED>
+WCNST_HD double root(double x)
+{
+    if constexpr (RANGED) return sqrt_ranged(x);
+    else return sqrt(x);
+}
+
 WCNST_HD double pow_q(double x, int q)
 {
     if (q == 6) {
@@ -409,27 +478,31 @@ struct Eigen {
     WCNST_HD double lam(int k) const { return k == 0 ? u - c : (k == NV - 1 ? u + c : u); }
 };
 
-template <int NV>
-WCNST_HD void roe_eigen(const double* A, const double* B, double gamma, Eigen<NV>& E)
+// With RANGED the result is exact (equal to the IEEE one) where the return
+// value is true: the densities and c^2 lie in [2^-767, 2^1022), and with
+// them every other argument of a reciprocal or root.
+template <int NV, bool RANGED = false>
+WCNST_HD bool roe_eigen(const double* A, const double* B, double gamma, Eigen<NV>& E)
 {
     const double rA = A[0], rB = B[0];
-    const double irA = 1.0 / rA, irB = 1.0 / rB;
+    const double irA = recip<RANGED>(rA), irB = recip<RANGED>(rB);
     const double uA = A[1] * irA, uB = B[1] * irB;
     const double vA = NV == 4 ? A[2] * irA : 0.0, vB = NV == 4 ? B[2] * irB : 0.0;
     const double HA = (A[NV - 1] + pressure<NV>(A, gamma, irA)) * irA;
     const double HB = (B[NV - 1] + pressure<NV>(B, gamma, irB)) * irB;
-    const double sA = sqrt(rA), sB = sqrt(rB);
-    const double is = 1.0 / (sA + sB);
+    const double sA = root<RANGED>(rA), sB = root<RANGED>(rB);
+    const double is = recip<RANGED>(sA + sB);
     E.u = (sA * uA + sB * uB) * is;
     E.v = (sA * vA + sB * vB) * is;
     E.H = (sA * HA + sB * HB) * is;
     E.q2 = E.u * E.u + E.v * E.v;
     const double c2 = (gamma - 1.0) * (E.H - 0.5 * E.q2);
-    E.c = sqrt(c2);
-    E.ic = 1.0 / E.c;
+    E.c = root<RANGED>(c2);
+    E.ic = recip<RANGED>(E.c);
     E.b1 = (gamma - 1.0) * (E.ic * E.ic);
     E.b2 = 0.5 * E.q2 * E.b1;
     E.uc = E.u * E.ic;
+    return !RANGED || (in_ieee_range(rA) && in_ieee_range(rB) && in_ieee_range(c2));
 }
 
 // van Leer's split normal flux (the flux named for the results of Sec. 3;
@@ -550,7 +623,11 @@ WCNST_HD void face_flux(ST& st, const Params& P, double (&F)[NV], unsigned& fb)
                     A[v] = st(2, v);
                     B[v] = st(3, v);
                 }
-                roe_eigen<NV>(A, B, P.gamma, E);
+                // the ranged sequences, and the IEEE operations on lanes
+                // whose arguments leave their range (the flux's own Roe
+                // average below keeps the IEEE operations: a second such
+                // test costs about what it saves)
+                if (!roe_eigen<NV, true>(A, B, P.gamma, E)) roe_eigen<NV>(A, B, P.gamma, E);
             }
             // one characteristic field at a time: project, interpolate both
             // sides, and add its share of the back-projection (sums over k in

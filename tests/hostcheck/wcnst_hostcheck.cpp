@@ -189,6 +189,12 @@ int hc_rhs(int ndim, int sys, int flux, int nx, int ny, double dx, double dy, in
     return 0;
 }
 
+// in_ieee_range of each x (1 or 0)
+void hc_in_ieee_range(const double* x, uint8_t* out, int n)
+{
+    for (int i = 0; i < n; ++i) out[i] = in_ieee_range(x[i]) ? 1 : 0;
+}
+
 int hc_strip1d_check(int nx, int diff_md)
 {
     return diff_md == 2 ? strip_check<DIFF_HW>(nx) : (diff_md ? strip_check<DIFF_MD>(nx) : strip_check<DIFF_MND>(nx));

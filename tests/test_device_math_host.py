@@ -121,3 +121,24 @@ def test_strip_geometry_of_the_1d_kernel(hc):
     for md in (0, 1, 2):
         for nx in list(range(5, 200)) + [243, 244, 245, 4096, 16384, 16385]:
             assert hc.hc_strip1d_check(nx, md) == 0, (nx, md)
+
+
+def test_ieee_range_predicate(hc):
+    """The range test that routes a lane to the ranged reciprocal and root
+    (positive x in [2^-767, 2^1022)) at its edges and on special values,
+    against the same condition on the IEEE fields of x."""
+    hc.hc_in_ieee_range.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+    lo, hi = 2.0 ** -767, 2.0 ** 1022
+    edges = [lo, np.nextafter(lo, 0), np.nextafter(lo, 1), hi, np.nextafter(hi, 0), np.nextafter(hi, np.inf),
+             1.0, 0.5, 1e-300, 1e-231, 2e-231, 3e300, 5e307, np.finfo(float).max, np.finfo(float).tiny, 5e-324,
+             0.0, -0.0, np.inf, -np.inf, np.nan, -1.0, -lo, -1e-300]
+    rng = np.random.default_rng(5)
+    bits = rng.integers(0, 2 ** 63, size=100000, dtype=np.int64).astype(np.uint64) | \
+        (rng.integers(0, 2, size=100000).astype(np.uint64) << np.uint64(63))
+    x = np.concatenate([np.array(edges, dtype=np.float64), bits.view(np.float64)])
+    out = np.zeros(x.size, dtype=np.uint8)
+    hc.hc_in_ieee_range(x.ctypes.data, out.ctypes.data, x.size)
+    with np.errstate(invalid="ignore"):
+        want = (x >= lo) & (x < hi)
+    assert np.array_equal(out.astype(bool), want)
+    assert want[:6].tolist() == [True, False, True, False, True, False]

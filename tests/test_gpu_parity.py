@@ -356,3 +356,41 @@ def test_free_stream_rhs_is_exactly_zero(orc, torch, bc):
         Ro, _, _ = orc.rhs(orc.problem(d), U)
         assert np.abs(Ro).max() == 0.0
         assert np.abs(Rg).max() == 0.0
+
+
+def _scaled_state(ndim, n, log_rho, gamma=1.4):
+    """Smooth state with density 10**log_rho(x) (and pressure of the same
+    scale, so the sound speed stays of order one)."""
+    if ndim == 1:
+        d = W.describe(ndim=1, system="euler", nx=n, bc_x="periodic")
+        x = W.coords(d)
+        rho = 10.0 ** log_rho(x)
+        return d, W.conserved_1d(rho, 0.4 + 0.2 * np.sin(4 * np.pi * x), rho * (1 + 0.3 * np.cos(2 * np.pi * x)),
+                                 gamma)[:, None, :]
+    d = W.describe(ndim=2, system="euler", nx=n, ny=45, bc_x="periodic", bc_y="periodic")
+    x, y = np.meshgrid(W.coords(d, "x"), W.coords(d, "y"))
+    rho = 10.0 ** log_rho(x + y)
+    return d, W.conserved_2d(rho, 0.4 + 0.2 * np.sin(4 * np.pi * y), -0.3 + 0.1 * np.cos(2 * np.pi * x),
+                             rho * (1 + 0.3 * np.cos(2 * np.pi * x)), gamma)
+
+
+@pytest.mark.parametrize("flux", ["roe", "lf"])
+@pytest.mark.parametrize("scale", ["crossing-2^-767", "1e-300", "1e150"])
+def test_rhs_extreme_density_scales(orc, torch, flux, scale):
+    """Densities far from order one, where the kernels' reciprocals and roots
+    of the Roe averages and fluxes switch between the hardware sequences and
+    the IEEE operations (below 2^-767 only the latter give IEEE results):
+    the RHS still equals the oracle's bit for bit, in 1D and 2D."""
+    log_rho = {"crossing-2^-767": lambda s: -230.6 + 1.5 * np.sin(2 * np.pi * s),
+               "1e-300": lambda s: -300.0 + 0.2 * np.sin(2 * np.pi * s),
+               "1e150": lambda s: 150.0 + 0.2 * np.sin(2 * np.pi * s)}[scale]
+    for ndim, n in ((1, 245), (2, 70)):
+        d, U = _scaled_state(ndim, n, log_rho)
+        d.update(flux=flux, scheme="teno", charwise=1)
+        _rhs_case(orc, torch, d, U, f"density-{scale}")
+        s = _solver(d)
+        Rg = s.rhs(s.new_state(U)).cpu().numpy()
+        s.close()
+        Ro, _, _ = orc.rhs(orc.problem(d), U, nthreads=NTHREADS)
+        assert np.isfinite(Ro).all()
+        assert np.array_equal(Rg, Ro)
