@@ -49,9 +49,11 @@ __device__ __forceinline__ bool first_thread()
 }
 
 // Reads the step record; stage 0 also decides dt (every block computes the
-// same value from the same inputs) and opens the next record.
+// same value from the same inputs) and opens the next record.  Stage 2 also
+// reads the next record's CFL speed as it stands (seen): a lower bound of
+// the value the launch leaves there, which lets flush_speed skip atomics.
 __device__ __forceinline__ bool stage_prologue(Ctrl* ctrl, const StageArgs& A, double& dt,
-                                               long long& step, bool lead)
+                                               long long& step, bool lead, unsigned long long& seen)
 {
     const StepRec* cur = &ctrl->rec[A.parity];
     // independent reads, issued together (stage 0's lead writes the record's
@@ -61,6 +63,11 @@ __device__ __forceinline__ bool stage_prologue(Ctrl* ctrl, const StageArgs& A, d
     const double t = cur->t;
     const unsigned long long sbits = cur->smax_bits;
     const double dt_rec = A.stage != 0 ? cur->dt : 0.0;
+    // (an atomic load: from L2, where the other waves' maxima arrive, not a
+    // per-CU cached copy of the launch's first read)
+    seen = A.stage == 2 ? __hip_atomic_load(&ctrl->rec[A.parity ^ 1].smax_bits, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT)
+                        : 0ull;
     if (status != 0 || done != 0) return false;
     step = stp;
     if (A.stage != 0) {
@@ -113,10 +120,16 @@ __device__ __forceinline__ void stage_epilogue(Ctrl* ctrl, const Params& P, int 
     }
 }
 
-__device__ __forceinline__ void flush_speed(Ctrl* ctrl, int parity, unsigned long long smax_loc)
+// One wave's CFL speed into the next step's record.  The record only grows
+// during the launch (stage 0 of the step cleared it in an earlier launch), so
+// a wave whose maximum it already held when the wave started (seen) skips
+// the atomic: on a long line tens of thousands of waves would otherwise queue
+// on the one address.
+__device__ __forceinline__ void flush_speed(Ctrl* ctrl, int parity, unsigned long long smax_loc,
+                                            unsigned long long seen)
 {
     const unsigned long long m = wave_max_bits(smax_loc);
-    if (threadIdx.x == 0) atomicMax(&ctrl->rec[parity ^ 1].smax_bits, m);
+    if (threadIdx.x == 0 && seen < m) atomicMax(&ctrl->rec[parity ^ 1].smax_bits, m);
 }
 
 template <int NV>
@@ -173,8 +186,9 @@ __device__ __forceinline__ void sweep1d_block(const double* __restrict__ U, cons
     for (int v = 0; v < NV; ++v) un[v] = MODE == MODE_STAGE && A.stage && cell_ok ? Un[(size_t)v * nx + c] : 0.0;
     double dt = 0.0;
     long long step = 0;
+    unsigned long long seen = 0ull;
     if constexpr (MODE == MODE_STAGE) {
-        if (!stage_prologue(ctrl, A, dt, step, bx == 0 && threadIdx.x == 0)) return;
+        if (!stage_prologue(ctrl, A, dt, step, bx == 0 && threadIdx.x == 0, seen)) return;
     }
     __shared__ double sF[NV][WAVE];
     __shared__ double sN[NV][WAVE];
@@ -220,7 +234,7 @@ __device__ __forceinline__ void sweep1d_block(const double* __restrict__ U, cons
         }
     }
     if constexpr (MODE == MODE_STAGE) {
-        if (A.stage == 2) flush_speed(ctrl, A.parity, sm);
+        if (A.stage == 2) flush_speed(ctrl, A.parity, sm, seen);
     }
 }
 
@@ -335,8 +349,9 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
     static_assert(NV == 4, "2D sweeps carry the four Euler variables");
     double dt = 0.0;
     long long step = 0;
+    unsigned long long seen = 0ull;
     if constexpr (MODE == MODE_STAGE) {
-        if (!stage_prologue(ctrl, A, dt, step, bx == 0 && by == 0 && threadIdx.x == 0)) return;
+        if (!stage_prologue(ctrl, A, dt, step, bx == 0 && by == 0 && threadIdx.x == 0, seen)) return;
     }
     // Ring of staged rows (all variables, XW columns) and the x-midpoint /
     // x node fluxes of the current row.
@@ -499,7 +514,7 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
         __syncthreads();
     }
     if constexpr (MODE == MODE_STAGE) {
-        if (A.stage == 2) flush_speed(ctrl, A.parity, smax_loc);
+        if (A.stage == 2) flush_speed(ctrl, A.parity, smax_loc, seen);
     }
 }
 

@@ -394,3 +394,37 @@ def test_rhs_extreme_density_scales(orc, torch, flux, scale):
         Ro, _, _ = orc.rhs(orc.problem(d), U, nthreads=NTHREADS)
         assert np.isfinite(Ro).all()
         assert np.array_equal(Rg, Ro)
+
+
+def _host_dt_1d(U, d, cfl):
+    """cfl / max over cells of (|u| + c)/dx, in the kernels' order of
+    operations (1/rho once; p = (gamma - 1)(E - rho u^2 / 2))."""
+    g, dx = d["gamma"], (d["x1"] - d["x0"]) / d["nx"]
+    r, m, e = U[0].ravel(), U[1].ravel(), U[2].ravel()
+    ir = 1.0 / r
+    p = (g - 1.0) * (e - 0.5 * m * m * ir)
+    a = np.sqrt(g * p * ir)
+    return cfl / ((np.abs(m * ir) + a) / dx).max()
+
+
+def test_cfl_reduction_over_many_waves(orc, torch):
+    """The fused CFL reduction of the third stage on a 2^22-cell line
+    (68 760 wavefronts on one step record): the time after two steps is
+    t1 + cfl / S(U^1), with S the maximum cell speed of the state after the
+    first step, recomputed on the host (the host formula is the oracle's
+    step rule: checked on a 2048-cell line first)."""
+    ds, Us = W.shu_osher(2048)
+    assert orc.solve(orc.problem(ds), Us, cfl=0.5, max_steps=1)["t"] == _host_dt_1d(Us, ds, 0.5)
+    d, U = W.shu_osher(1 << 22)
+    _say("cfl reduction shu-osher 2^22 cells")
+    s = _solver(d)
+    V = s.new_state(U)
+    t1, n1 = s.solve(V, t_final=np.inf, cfl=0.5, max_steps=1)
+    U1 = V.cpu().numpy()
+    V2 = s.new_state(U)
+    s.reset(0.0, 0)
+    t2, n2 = s.solve(V2, t_final=np.inf, cfl=0.5, max_steps=2)
+    s.close()
+    assert n1 == 1 and n2 == 2
+    assert t1 == _host_dt_1d(U, d, 0.5)
+    assert t2 == t1 + _host_dt_1d(U1, d, 0.5)
