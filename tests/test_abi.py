@@ -97,3 +97,6 @@ def test_batches_and_pools_refuse_the_md_difference():
     assert L.wcnst_batch_workspace_size(descs, 1, ctypes.byref(n)) == 0
     assert L.wcnst_batch_workspace_size(descs, 2, ctypes.byref(n)) == wc.E_INVALID_ARG
     assert b"MND" in L.wcnst_last_error()
+    # an empty batch is refused, not sized
+    assert L.wcnst_batch_workspace_size(descs, 0, ctypes.byref(n)) == wc.E_INVALID_ARG
+    assert L.wcnst_last_error()

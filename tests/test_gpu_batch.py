@@ -255,3 +255,32 @@ def test_batch_paths_do_not_change_results(orc, torch):
             assert r["steps"] == st0[i] and np.array_equal(per0[i], r["U"])
         else:
             assert (bs0[i], bc0[i]) == (r["bad_stage"], r["bad_cell"])
+
+
+def test_batch_with_instances_already_at_t_final(orc, torch):
+    """Instances whose t_final is zero or negative take no step and keep
+    their state bit for bit, while the others advance exactly as alone (and
+    as in the oracle); a batch where every instance is already done returns
+    at once."""
+    from paper_1810_07806_amd.wcnst import Batch
+    items = _tubes(9, seed=21, n_min=70, n_max=400, t_final=0.02)
+    descs = [d for d, _ in items]
+    tf = np.array([d["t_final"] for d in descs])
+    tf[[0, 4, 8]] = (0.0, -1.0, 0.0)
+    _say("batch with instances already at t_final")
+    b = Batch(descs)
+    Ug = b.pack([U for _, U in items])
+    res = b.solve(Ug, tf, cfl=0.5)
+    out = b.unpack(Ug)
+    for i, (d, U) in enumerate(items):
+        assert res["status"][i] == 0
+        r = orc.solve(orc.problem(d), U, t_final=tf[i], cfl=0.5)
+        assert res["steps"][i] == r["steps"] and res["t"][i] == r["t"], i
+        assert np.array_equal(out[i], r["U"]), i
+        if tf[i] <= 0.0:
+            assert res["steps"][i] == 0 and np.array_equal(out[i], U)
+    Ug2 = b.pack([U for _, U in items])
+    res = b.solve(Ug2, np.zeros(len(items)), cfl=0.5)
+    assert (res["steps"] == 0).all() and (res["status"] == 0).all()
+    assert all(np.array_equal(a, U) for a, (_, U) in zip(b.unpack(Ug2), items))
+    b.close()

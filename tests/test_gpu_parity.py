@@ -428,3 +428,41 @@ def test_cfl_reduction_over_many_waves(orc, torch):
     assert n1 == 1 and n2 == 2
     assert t1 == _host_dt_1d(U, d, 0.5)
     assert t2 == t1 + _host_dt_1d(U1, d, 0.5)
+
+
+def test_degenerate_solve_calls(orc, torch):
+    """Calls that must not advance the state: t_final already reached (zero,
+    negative, the current time), zero steps with t_final = inf; zero steps
+    short of a finite t_final report WCNST_E_MAX_STEPS; invalid cfl, t_final
+    NaN and negative max_steps are refused before any launch.  The state is
+    unchanged bit for bit, as in the oracle."""
+    from paper_1810_07806_amd.wcnst import WcnstError
+    d, U = W.sod(101)
+    _say("degenerate solve calls sod101")
+    s = _solver(d)
+    V = s.new_state(U)
+    for tf in (0.0, -1.0):
+        assert s.solve(V, t_final=tf, cfl=0.5) == (0.0, 0)
+        assert np.array_equal(V.cpu().numpy(), U)
+        r = orc.solve(orc.problem(d), U, t_final=tf, cfl=0.5)
+        assert r["steps"] == 0 and np.array_equal(r["U"], U)
+    assert s.solve(V, t_final=np.inf, cfl=0.5, max_steps=0) == (0.0, 0)
+    assert np.array_equal(V.cpu().numpy(), U)
+    with pytest.raises(WcnstError) as e:
+        s.solve(V, t_final=0.1, cfl=0.5, max_steps=0)
+    assert e.value.status == 3
+    for kw in (dict(t_final=0.1, cfl=0.0), dict(t_final=0.1, cfl=-0.5), dict(t_final=np.nan, cfl=0.5),
+               dict(t_final=0.1, cfl=0.5, max_steps=-1)):
+        with pytest.raises(WcnstError) as e:
+            s.solve(V, **kw)
+        assert e.value.status == 1, kw
+    assert np.array_equal(V.cpu().numpy(), U)
+    t, n = s.solve(V, t_final=0.05, cfl=0.5)
+    Vh = V.cpu().numpy()
+    assert n > 0 and abs(t - 0.05) <= 1e-12 * 0.05
+    # a second call to the time already reached does nothing
+    assert s.solve(V, t_final=0.05, cfl=0.5) == (t, 0)
+    assert np.array_equal(V.cpu().numpy(), Vh)
+    s.close()
+    r = orc.solve(orc.problem(d), U, t_final=0.05, cfl=0.5)
+    assert r["steps"] == n and r["t"] == t and np.array_equal(r["U"], Vh)
