@@ -16,10 +16,11 @@
 // in the plain order of its definition with IEEE division and square root
 // and without contraction (this file and the kernels are compiled with
 // -ffp-contract=off), so results are reproducible bit for bit.  (The
-// reciprocals and roots of the projection's Roe average use the hardware's
-// correctly rounded sequences without their range scaling, which give the
-// IEEE results bit for bit over the argument range they are used in; lanes
-// whose arguments leave it redo that average with the IEEE operations.)
+// reciprocals and roots of the Roe averages (the projection's; in 1D also
+// the flux's, with the physical fluxes) use the hardware's correctly rounded
+// sequences without their range scaling, which give the IEEE results bit
+// for bit over the argument range they are used in; lanes whose arguments
+// leave it redo that work with the IEEE operations.)
 // Only the cut-off test itself, which is decided far from its threshold
 // except in genuine ties, uses a fast reciprocal and the comparison form
 // gamma_k < C_T * sum(gamma).
@@ -414,10 +415,10 @@ WCNST_HD double pressure(const double* U, double gamma, double ir)
 }
 
 // Normal flux (rho u, rho u^2 + p, rho v u, u (E + p)).
-template <int NV>
+template <int NV, bool RANGED = false>
 WCNST_HD void euler_flux(const double* U, double gamma, double* F)
 {
-    const double ir = 1.0 / U[0];
+    const double ir = recip<RANGED>(U[0]);
     const double u = U[1] * ir;
     const double p = pressure<NV>(U, gamma, ir);
     F[0] = U[1];
@@ -555,9 +556,15 @@ WCNST_HD void euler_num_flux(const double* UL, const double* UR, double gamma, d
         for (int v = 0; v < NV; ++v) F[v] = Fp[v] + Fm[v];
         return;
     }
+    // 1D Roe: the physical fluxes and the Roe average with the ranged
+    // reciprocals and roots (1/rho of U_L and U_R shared by both), redone
+    // with the IEEE operations on lanes whose arguments leave their range.
+    // The 2D kernels keep the IEEE operations here: at their register limit
+    // the test's branch costs what the ranged sequences save.
+    constexpr bool RG = NV == 3 && FLUX == FLUX_ROE;
     double FL[NV], FR[NV], dis[NV];
-    euler_flux<NV>(UL, gamma, FL);
-    euler_flux<NV>(UR, gamma, FR);
+    euler_flux<NV, RG>(UL, gamma, FL);
+    euler_flux<NV, RG>(UR, gamma, FR);
     if constexpr (FLUX == FLUX_LF) {
         const double irL = 1.0 / UL[0], irR = 1.0 / UR[0];
         const double aL = fabs(UL[1] * irL) + sqrt(gamma * pressure<NV>(UL, gamma, irL) * irL);
@@ -567,7 +574,12 @@ WCNST_HD void euler_num_flux(const double* UL, const double* UR, double gamma, d
         for (int v = 0; v < NV; ++v) dis[v] = al * (UR[v] - UL[v]);
     } else {
         Eigen<NV> E;
-        roe_eigen<NV>(UL, UR, gamma, E);
+        // (the test covers rho_L and rho_R, the reciprocals' arguments)
+        if (!roe_eigen<NV, RG>(UL, UR, gamma, E)) {
+            euler_flux<NV>(UL, gamma, FL);
+            euler_flux<NV>(UR, gamma, FR);
+            roe_eigen<NV>(UL, UR, gamma, E);
+        }
         double alpha[NV];
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
@@ -624,9 +636,7 @@ WCNST_HD void face_flux(ST& st, const Params& P, double (&F)[NV], unsigned& fb)
                     B[v] = st(3, v);
                 }
                 // the ranged sequences, and the IEEE operations on lanes
-                // whose arguments leave their range (the flux's own Roe
-                // average below keeps the IEEE operations: a second such
-                // test costs about what it saves)
+                // whose arguments leave their range
                 if (!roe_eigen<NV, true>(A, B, P.gamma, E)) roe_eigen<NV>(A, B, P.gamma, E);
             }
             // one characteristic field at a time: project, interpolate both
