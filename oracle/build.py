@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 
 def build() -> str:
-    tmp = LIB_PATH + ".tmp"
+    tmp = f"{LIB_PATH}.tmp{os.getpid():x}"  # own file: parallel workers may rebuild at once
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
            "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter",
            "-o", tmp, SRC, "-lm"]

@@ -706,8 +706,16 @@ WCNST_HD void face_flux(ST& st, const Params& P, double (&F)[NV], unsigned& fb)
 template <int SYS, int NV>
 WCNST_HD void node_flux(const double* U, const Params& P, double* F)
 {
-    if constexpr (SYS == SYS_EULER) euler_flux<NV>(U, P.gamma, F);
-    else if constexpr (SYS == SYS_ADV) F[0] = P.adv * U[0];
+    if constexpr (SYS == SYS_EULER) {
+        if constexpr (NV == 3) {
+            // 1D: 1/rho by the ranged sequence, the IEEE division where rho
+            // leaves its range
+            euler_flux<NV, true>(U, P.gamma, F);
+            if (!in_ieee_range(U[0])) euler_flux<NV>(U, P.gamma, F);
+        } else {
+            euler_flux<NV>(U, P.gamma, F);
+        }
+    } else if constexpr (SYS == SYS_ADV) F[0] = P.adv * U[0];
     else F[0] = 0.5 * U[0] * U[0];
 }
 

@@ -26,10 +26,12 @@ _SYS = {"advection": 0, "burgers": 1, "euler": 2}
 def hc():
     dev = os.path.join(ROOT, "paper_1810_07806_amd", "csrc", "wcnst_device.hpp")
     if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(SRC), os.path.getmtime(dev)):
+        # a file of this process's own (parallel test workers may rebuild at once)
+        tmp = f"{LIB}.tmp{os.getpid():x}"
         cmd = ["/opt/rocm/bin/hipcc", "--offload-host-only", "-O3", "-std=c++17", "-fPIC", "-shared",
-               "-ffp-contract=off", "-I", os.path.dirname(dev), "-o", LIB + ".tmp", SRC]
+               "-ffp-contract=off", "-I", os.path.dirname(dev), "-o", tmp, SRC]
         subprocess.run(cmd, check=True, capture_output=True)
-        os.replace(LIB + ".tmp", LIB)
+        os.replace(tmp, LIB)
     L = ctypes.CDLL(LIB)
     dp = ctypes.c_void_p
     i, d = ctypes.c_int, ctypes.c_double
