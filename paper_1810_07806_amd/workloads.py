@@ -214,6 +214,27 @@ def rayleigh_taylor(nx: int = 128, ny: int = 512, gamma: float = 5.0 / 3.0, **kw
     return d, conserved_2d(rho, np.zeros_like(rho), v, p, g)
 
 
+def ripples_2d(nx: int, ny: int, gamma: float = 1.4, **kw):
+    """Analytic 2D Euler state on [0, 1]^2 for parity at any size: ripples in
+    every variable, an oblique density and pressure jump and a shear layer,
+    so that neighbouring cells differ everywhere and both cut and kept
+    stencils occur.  Built a block of rows at a time (large grids)."""
+    d = describe(ndim=2, system="euler", nx=nx, ny=ny, gamma=gamma, **kw)
+    x = coords(d, "x")[None, :]
+    y = coords(d, "y")
+    U = np.empty((4, ny, nx))
+    tp = 2.0 * np.pi
+    for r0 in range(0, ny, 512):
+        yy = y[r0:r0 + 512, None]
+        jump = (x + 0.4 * yy) > 0.55
+        rho = 1.0 + 0.2 * np.sin(tp * (3.0 * x + 2.0 * yy)) + np.where(jump, 0.8, 0.0)
+        u = 0.3 * np.cos(tp * (x - yy)) + np.where(yy > 0.7, 0.4, -0.1)
+        v = 0.2 * np.sin(tp * (2.0 * x + 5.0 * yy))
+        p = 1.0 + 0.1 * np.cos(tp * (5.0 * x + yy)) + np.where(jump, 1.5, 0.0)
+        U[:, r0:r0 + 512, :] = conserved_2d(rho, u, v, p, gamma)
+    return d, U
+
+
 def random_euler2d(rng: np.random.Generator, nx: int, ny: int, gamma: float = 1.4, **kw):
     """Random four-quadrant state with smooth ripples: every parity case sees
     shocks, contacts and smooth regions, so both cut and kept stencils occur."""

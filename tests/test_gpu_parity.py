@@ -466,3 +466,37 @@ def test_degenerate_solve_calls(orc, torch):
     s.close()
     r = orc.solve(orc.problem(d), U, t_final=0.05, cfl=0.5)
     assert r["steps"] == n and r["t"] == t and np.array_equal(r["U"], Vh)
+
+
+def test_rhs_16384_squared_sampled_windows(orc, torch):
+    """A 16384^2 grid (8.6 GB per state: variable planes start past 2^32
+    bytes): the GPU RHS on sampled 32 x 32 windows, at the corners, edges
+    and inside, against the oracle run on each window alone.  A cell's RHS
+    depends only on the four cells on each side along its x and y lines, so
+    window cells at least 4 cells from every window edge that is not a
+    domain edge must agree (same spacing, same zero-gradient sides)."""
+    n, w = 16384, 32
+    _say(f"rhs {n}^2 sampled windows")
+    d, U = W.ripples_2d(n, n)
+    s = _solver(d)
+    Ug = s.new_state(U)
+    Rg = s.rhs(Ug)
+    torch.cuda.synchronize()
+    del Ug
+    h = 1.0 / n
+    corners = [(0, 0), (0, n - w), (n - w, 0), (n - w, n - w), (8180, 8180), (12345, 3210), (16000, 9000),
+               (5000, n - w), (n - w, 7777)]
+    for y0, x0 in corners:
+        win = np.ascontiguousarray(U[:, y0:y0 + w, x0:x0 + w])
+        dw = W.describe(ndim=2, system="euler", nx=w, ny=w, x0=x0 * h, x1=(x0 + w) * h, y0=y0 * h, y1=(y0 + w) * h)
+        Ro, _, _ = orc.rhs(orc.problem(dw), win, nthreads=NTHREADS)
+        ylo = 0 if y0 == 0 else 4
+        yhi = w if y0 + w == n else w - 4
+        xlo = 0 if x0 == 0 else 4
+        xhi = w if x0 + w == n else w - 4
+        got = Rg[:, y0 + ylo:y0 + yhi, x0 + xlo:x0 + xhi].cpu().numpy()
+        want = Ro[:, ylo:yhi, xlo:xhi]
+        scale = np.abs(want).reshape(4, -1).max(axis=1)[:, None, None]
+        assert (np.abs(got - want) <= 1e-12 * scale).all(), (y0, x0)
+        assert np.array_equal(got, want), (y0, x0)
+    s.close()
