@@ -235,6 +235,23 @@ def ripples_2d(nx: int, ny: int, gamma: float = 1.4, **kw):
     return d, U
 
 
+def ripples_1d(nx: int, gamma: float = 1.4, **kw):
+    """1D counterpart of ripples_2d on [0, 1]: ripples, a density and
+    pressure jump and a velocity step, built in chunks (long lines)."""
+    d = describe(ndim=1, system="euler", nx=nx, gamma=gamma, **kw)
+    x = coords(d)
+    U = np.empty((3, 1, nx))
+    tp = 2.0 * np.pi
+    for c0 in range(0, nx, 1 << 24):
+        xx = x[c0:c0 + (1 << 24)]
+        jump = xx > 0.55
+        rho = 1.0 + 0.2 * np.sin(tp * 7.0 * xx) + np.where(jump, 0.8, 0.0)
+        u = 0.3 * np.cos(tp * 3.0 * xx) + np.where(xx > 0.7, 0.4, -0.1)
+        p = 1.0 + 0.1 * np.cos(tp * 5.0 * xx) + np.where(jump, 1.5, 0.0)
+        U[:, 0, c0:c0 + (1 << 24)] = conserved_1d(rho, u, p, gamma)
+    return d, U
+
+
 def random_euler2d(rng: np.random.Generator, nx: int, ny: int, gamma: float = 1.4, **kw):
     """Random four-quadrant state with smooth ripples: every parity case sees
     shocks, contacts and smooth regions, so both cut and kept stencils occur."""

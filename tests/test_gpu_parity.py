@@ -500,3 +500,28 @@ def test_rhs_16384_squared_sampled_windows(orc, torch):
         assert (np.abs(got - want) <= 1e-12 * scale).all(), (y0, x0)
         assert np.array_equal(got, want), (y0, x0)
     s.close()
+
+
+def test_rhs_1d_2e28_cells_sampled_windows(orc, torch):
+    """A 1D line of 2^28 cells (6.4 GB per state: the third variable plane
+    starts past 2^32 bytes): the GPU RHS on sampled 64-cell windows at both
+    ends and inside against the oracle run on each window alone, with the
+    4-cell margin at window edges that are not domain edges."""
+    n, w = 1 << 28, 64
+    _say(f"rhs 1D {n} cells sampled windows")
+    d, U = W.ripples_1d(n)
+    s = _solver(d)
+    Ug = s.new_state(U)
+    Rg = s.rhs(Ug)
+    torch.cuda.synchronize()
+    del Ug
+    h = 1.0 / n
+    for x0 in (0, n - w, n // 2 - 17, 150_000_000, int(0.55 * n) - w // 2, 3 * (n // 4) + 5):
+        win = np.ascontiguousarray(U[:, :, x0:x0 + w])
+        dw = W.describe(ndim=1, system="euler", nx=w, x0=x0 * h, x1=(x0 + w) * h)
+        Ro, _, _ = orc.rhs(orc.problem(dw), win)
+        lo = 0 if x0 == 0 else 4
+        hi = w if x0 + w == n else w - 4
+        got = Rg[:, :, x0 + lo:x0 + hi].cpu().numpy()
+        assert np.array_equal(got, Ro[:, :, lo:hi]), x0
+    s.close()
