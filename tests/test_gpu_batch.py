@@ -284,3 +284,31 @@ def test_batch_with_instances_already_at_t_final(orc, torch):
     assert (res["steps"] == 0).all() and (res["status"] == 0).all()
     assert all(np.array_equal(a, U) for a, (_, U) in zip(b.unpack(Ug2), items))
     b.close()
+
+
+def test_batch_extreme_density_scales(orc, torch):
+    """Tubes scaled to densities near 1e-241 (below 2^-767, where the
+    kernels' ranged reciprocals and roots hand over to the IEEE operations
+    on every lane) and near 1e150, solved in one batch with unscaled tubes:
+    every instance ends as in the oracle, status, step count, time and
+    first non-physical stage and cell included, and with the oracle's final
+    state bit for bit where it finishes."""
+    from paper_1810_07806_amd.wcnst import Batch
+    base = W.shock_tube_batch(count=4, seed=33, n_min=70, n_max=300, t_final=0.02)
+    items = [(d, U * sc) for d, U in base for sc in (1.0, 2.0 ** -800, 2.0 ** 500)]
+    descs = [d for d, _ in items]
+    _say("batch with extreme density scales")
+    b = Batch(descs)
+    Ug = b.pack([U for _, U in items])
+    res = b.solve(Ug, 0.02, cfl=0.5)
+    bs, bc = b.bad_cells()
+    out = b.unpack(Ug)
+    b.close()
+    for i, (d, U) in enumerate(items):
+        r = orc.solve(orc.problem(d), U, t_final=0.02, cfl=0.5)
+        assert res["status"][i] == r["status"], i
+        if r["status"] == 0:
+            assert res["steps"][i] == r["steps"] and res["t"][i] == r["t"], i
+            assert np.array_equal(out[i], r["U"]), i
+        else:
+            assert (bs[i], bc[i]) == (r["bad_stage"], r["bad_cell"]), i
