@@ -69,6 +69,9 @@ CASES_1D.append(dict(flux="roe", scheme="teno", charwise=1, bc_x="periodic"))
 CASES_1D.append(dict(flux="lf", scheme="teno", charwise=0, bc_x="periodic"))
 CASES_1D.append(dict(flux="vanleer", scheme="teno", charwise=1, bc_x="zero_gradient"))
 CASES_1D.append(dict(flux="vanleer", scheme="js", charwise=0, bc_x="periodic"))
+# Eq. (16) with other integer powers than the paper's q = 6
+CASES_1D.append(dict(flux="roe", scheme="teno", charwise=1, bc_x="zero_gradient", q=2))
+CASES_1D.append(dict(flux="lf", scheme="teno", charwise=1, bc_x="periodic", q=4))
 
 
 @pytest.mark.parametrize("kw", CASES_1D, ids=lambda k: "-".join(str(v) for v in k.values()))
@@ -112,13 +115,16 @@ CASES_2D = [dict(flux="roe", scheme="teno", charwise=1),
             dict(flux="roe", scheme="linear", charwise=1),
             dict(flux="roe", scheme="teno", charwise=0),
             dict(flux="roe", scheme="js", charwise=1),
-            dict(flux="vanleer", scheme="teno", charwise=1)]
+            dict(flux="vanleer", scheme="teno", charwise=1),
+            dict(flux="roe", scheme="teno", charwise=1, q=4)]
 
 
 @pytest.mark.parametrize("kw", CASES_2D, ids=lambda k: "-".join(str(v) for v in k.values()))
 def test_rhs_euler2d(orc, torch, kw):
     rng = np.random.default_rng(200)
-    for (nx, ny) in ((133, 97), (61, 33), (5, 5), (130, 65)):
+    # ragged strips and segments, one strip / one segment, the minimum, and
+    # exact multiples of the 61-column strip and the 35-row segment
+    for (nx, ny) in ((133, 97), (61, 33), (5, 5), (130, 65), (122, 70), (62, 36)):
         d, U = W.random_euler2d(rng, nx, ny)
         d.update(kw)
         _rhs_case(orc, torch, d, U, f"quad{nx}x{ny}")
