@@ -255,6 +255,17 @@ wcnst_status wcnst_pool_admit(wcnst_pool* p, const wcnst_desc* d, double* U, dou
  * Synchronous.  n_active (nullable) = requests that were advanced. */
 wcnst_status wcnst_pool_tick(wcnst_pool* p, int64_t steps, int32_t* n_active);
 
+/* As wcnst_pool_tick with separate step counts for the 1D and the 2D
+ * requests (their launches run side by side on two streams, so a caller
+ * can give each about the same device time per tick).  Each request's
+ * result does not depend on the step counts. */
+wcnst_status wcnst_pool_tick_split(wcnst_pool* p, int64_t steps_1d, int64_t steps_2d, int32_t* n_active);
+
+/* Device time (ms, HIP events) from the start of the last tick to the end
+ * of its 1D launches and to the end of its 2D launches; 0 for a dimension
+ * with no active request. */
+wcnst_status wcnst_pool_tick_ms(const wcnst_pool* p, double* ms_1d, double* ms_2d);
+
 /* Outcome of the request in `slot` after the last tick: finished (t_final
  * reached or failed), status (WCNST_OK or WCNST_E_NONPHYSICAL), t, steps,
  * and the global stage and cell of the first non-physical value (-1 when

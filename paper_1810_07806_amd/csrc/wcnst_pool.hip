@@ -4,8 +4,9 @@
 //
 // Each request advances with exactly the arithmetic of wcnst_solve, so its
 // result does not depend on what else is in the pool or on when it joined.
-// One tick advances every active request by up to `steps` SSP-RK3 steps
-// with 3 x steps stage launches per dimension, each covering the strips
+// One tick advances every active 1D request by up to `steps_1d` and every
+// active 2D request by up to `steps_2d` SSP-RK3 steps, with 3 x steps stage
+// launches per dimension, each covering the strips
 // (1D, caller's stream) or row segments (2D, the pool's own stream) of all
 // active grids of that dimension; a grid has its own table row, control
 // block, dt and step parity, and grids that reach t_final stop inside the
@@ -54,7 +55,8 @@ struct wcnst_pool {
     int cap = 0;
     hipStream_t s1 = nullptr;  // caller's stream: 1D launches, result copies
     hipStream_t s2 = nullptr;  // pool stream: 2D launches
-    hipEvent_t ev_start = nullptr, ev_2d = nullptr;
+    hipEvent_t ev_start = nullptr, ev_2d = nullptr, ev_1d = nullptr;
+    float ms_1d = 0.0f, ms_2d = 0.0f;  // device time of each dimension's launches in the last tick
     // device (caller's workspace): one request table per dimension, one
     // control block per slot
     ReqGrid* d_req[2] = {nullptr, nullptr};
@@ -119,8 +121,9 @@ extern "C" wcnst_status wcnst_pool_create(const wcnst_desc* scheme, int32_t capa
     p->reqs.resize((size_t)capacity);
 
     hipError_t e = hipStreamCreateWithFlags(&p->s2, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_start, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_2d, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&p->ev_start);
+    if (e == hipSuccess) e = hipEventCreate(&p->ev_2d);
+    if (e == hipSuccess) e = hipEventCreate(&p->ev_1d);
     for (int k = 0; k < 2 && e == hipSuccess; ++k)
         e = hipHostMalloc((void**)&p->h_req[k], sizeof(ReqGrid) * (size_t)capacity, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_ctrl, p->ctrl_bytes * (size_t)capacity, hipHostMallocDefault);
@@ -217,10 +220,11 @@ static wcnst_status issue_dim(wcnst_pool* p, int ndim, const std::vector<int>& a
     return WCNST_OK;
 }
 
-extern "C" wcnst_status wcnst_pool_tick(wcnst_pool* p, int64_t steps, int32_t* n_active)
+extern "C" wcnst_status wcnst_pool_tick_split(wcnst_pool* p, int64_t steps_1d, int64_t steps_2d, int32_t* n_active)
 {
     if (!p) return wcnst_fail(WCNST_E_INVALID_ARG, "null handle");
-    if (steps < 1 || steps > (1 << 20)) return wcnst_fail(WCNST_E_INVALID_ARG, "steps must be in [1, 2^20]");
+    if (steps_1d < 1 || steps_1d > (1 << 20) || steps_2d < 1 || steps_2d > (1 << 20))
+        return wcnst_fail(WCNST_E_INVALID_ARG, "steps must be in [1, 2^20]");
     std::vector<int> a1, a2;
     for (int i = 0; i < p->cap; ++i) {
         const PoolReq& r = p->reqs[(size_t)i];
@@ -233,15 +237,19 @@ extern "C" wcnst_status wcnst_pool_tick(wcnst_pool* p, int64_t steps, int32_t* n
     // 2D on the pool stream, after the caller's work (admission copies)
     WCNST_HIP_TRY(hipEventRecord(p->ev_start, p->s1));
     WCNST_HIP_TRY(hipStreamWaitEvent(p->s2, p->ev_start, 0));
-    wcnst_status st = issue_dim(p, 2, a2, steps, p->s2);
+    wcnst_status st = issue_dim(p, 2, a2, steps_2d, p->s2);
     if (st) return st;
     WCNST_HIP_TRY(hipEventRecord(p->ev_2d, p->s2));
-    st = issue_dim(p, 1, a1, steps, p->s1);
+    st = issue_dim(p, 1, a1, steps_1d, p->s1);
     if (st) return st;
+    WCNST_HIP_TRY(hipEventRecord(p->ev_1d, p->s1));
     // one copy of the control blocks of all slots, after both streams
     WCNST_HIP_TRY(hipStreamWaitEvent(p->s1, p->ev_2d, 0));
     WCNST_HIP_TRY(hipMemcpyAsync(p->h_ctrl, p->d_ctrl, p->ctrl_bytes * (size_t)p->cap, hipMemcpyDeviceToHost, p->s1));
     WCNST_HIP_TRY(hipStreamSynchronize(p->s1));
+    p->ms_1d = p->ms_2d = 0.0f;
+    if (!a1.empty()) WCNST_HIP_TRY(hipEventElapsedTime(&p->ms_1d, p->ev_start, p->ev_1d));
+    if (!a2.empty()) WCNST_HIP_TRY(hipEventElapsedTime(&p->ms_2d, p->ev_start, p->ev_2d));
 
     for (const std::vector<int>* act : {&a1, &a2})
         for (int i : *act) {
@@ -254,6 +262,19 @@ extern "C" wcnst_status wcnst_pool_tick(wcnst_pool* p, int64_t steps, int32_t* n
             r.bad_key = c.bad_key;
             r.finished = r.status != 0 || reached(r.t_final, r.t);
         }
+    return WCNST_OK;
+}
+
+extern "C" wcnst_status wcnst_pool_tick(wcnst_pool* p, int64_t steps, int32_t* n_active)
+{
+    return wcnst_pool_tick_split(p, steps, steps, n_active);
+}
+
+extern "C" wcnst_status wcnst_pool_tick_ms(const wcnst_pool* p, double* ms_1d, double* ms_2d)
+{
+    if (!p || !ms_1d || !ms_2d) return wcnst_fail(WCNST_E_INVALID_ARG, "null argument");
+    *ms_1d = p->ms_1d;
+    *ms_2d = p->ms_2d;
     return WCNST_OK;
 }
 
@@ -291,6 +312,7 @@ extern "C" wcnst_status wcnst_pool_destroy(wcnst_pool* p)
     }
     if (p->ev_start) (void)hipEventDestroy(p->ev_start);
     if (p->ev_2d) (void)hipEventDestroy(p->ev_2d);
+    if (p->ev_1d) (void)hipEventDestroy(p->ev_1d);
     for (int k = 0; k < 2; ++k)
         if (p->h_req[k]) (void)hipHostFree(p->h_req[k]);
     if (p->h_ctrl) (void)hipHostFree(p->h_ctrl);

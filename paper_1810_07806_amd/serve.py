@@ -8,8 +8,13 @@ state is copied into the arena and it joins the pool, which advances all
 resident requests together, a tick at a time.  After each tick finished
 requests are retired: the result is copied back, the slot and the memory
 are freed, and waiting requests are admitted before the next tick.  The
-tick length (steps) adapts so that a tick lasts about `tick_ms`, which
-bounds how long a new arrival waits for admission.
+1D and the 2D requests take separate step counts per tick (their launches
+run side by side on two streams): each is sized so that its launches take
+about `tick_ms`, from its measured device time per step in the last tick,
+rescaled to the cells active in the next one.  So a small 1D request that
+needs many steps is not held to the pace of large 2D ones, and a large
+arrival shortens the next tick at once, which bounds how long a new
+arrival waits for admission.
 
 `per_solve_latencies` is the comparison: the plain path, one wcnst_solve
 per request in arrival order on the same GPU.
@@ -90,6 +95,16 @@ def percentiles(lat):
                 max=float(a.max()))
 
 
+def _active_cells(active) -> list:
+    """Cells of the active 1D and 2D requests."""
+    cells = [0, 0]
+    for a in active.values():
+        d = a["req"]["desc"]
+        nd = int(d.get("ndim", 1))
+        cells[nd - 1] += int(d["nx"]) * (int(d["ny"]) if nd == 2 else 1)
+    return cells
+
+
 class Server:
     """Continuous-batching server over one Pool and one arena tensor."""
 
@@ -124,7 +139,8 @@ class Server:
         queue = deque()
         active = {}
         done = []
-        steps = 32
+        steps = [32, 32]          # per tick, for the 1D and the 2D requests
+        per_step = [None, None]   # ms per step per active cell in the last tick
         ticks = 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -150,13 +166,13 @@ class Server:
                 if pending and realtime:
                     time.sleep(max(0.0, min(0.01, pending[0]["arrival"] - (time.perf_counter() - t0))))
                 continue
-            ts = time.perf_counter()
-            self.pool.tick(steps)
+            cells = _active_cells(active)
+            steps = [self._steps_for(k, cells[k], per_step[k], steps[k]) for k in range(2)]
+            self.pool.tick(steps[0], steps[1])
             ticks += 1
-            tick_s = time.perf_counter() - ts
-            # next tick length: aim at tick_ms
-            per_step = tick_s / steps
-            steps = int(min(self.max_steps, max(self.min_steps, self.tick_ms * 1e-3 / max(per_step, 1e-7))))
+            for k, ms in enumerate(self.pool.tick_ms()):
+                if cells[k] and ms > 0.0:
+                    per_step[k] = ms / steps[k] / cells[k]
             for slot in list(active):
                 res = self.pool.result(slot)
                 if not res["finished"]:
@@ -178,6 +194,15 @@ class Server:
                         f"latency={done[-1]['latency']:.3f}s active={len(active)} queued={len(queue)}")
         self.ticks = ticks
         return done
+
+    def _steps_for(self, k, cells, per_cell, last):
+        """Steps of dimension k (0: 1D, 1: 2D) for the next tick: about
+        tick_ms of device time at the last measured cost per step and cell,
+        or the last count when nothing was measured yet."""
+        if not cells or per_cell is None:
+            return last
+        ms = per_cell * cells
+        return int(min(self.max_steps, max(self.min_steps, self.tick_ms / max(ms, 1e-6))))
 
     def close(self):
         self.pool.close()

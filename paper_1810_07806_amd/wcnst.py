@@ -27,7 +27,8 @@ EXPORTS = ("wcnst_desc_init", "wcnst_workspace_size", "wcnst_create", "wcnst_rhs
            "wcnst_batch_bad_cells", "wcnst_batch_set_tuning", "wcnst_batch_kernel_ms", "wcnst_batch_stats",
            "wcnst_batch_destroy",
            "wcnst_pool_workspace_size", "wcnst_pool_create", "wcnst_pool_admit", "wcnst_pool_tick",
-           "wcnst_pool_result", "wcnst_pool_release", "wcnst_pool_set_tuning", "wcnst_pool_destroy")
+           "wcnst_pool_result", "wcnst_pool_release", "wcnst_pool_set_tuning", "wcnst_pool_tick_split",
+           "wcnst_pool_tick_ms", "wcnst_pool_destroy")
 
 
 class WcnstError(RuntimeError):
@@ -98,6 +99,8 @@ def lib(path: str | None = None):
     L.wcnst_pool_result.argtypes = [vp, i32, i32p, i32p, dp, i64p, i64p, i64p]
     L.wcnst_pool_release.argtypes = [vp, i32]
     L.wcnst_pool_set_tuning.argtypes = [vp, i32]
+    L.wcnst_pool_tick_split.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]
+    L.wcnst_pool_tick_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.wcnst_pool_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name != "wcnst_last_error":
@@ -403,10 +406,19 @@ class Pool:
         self._held[slot.value] = (U, U1, U2)
         return slot.value
 
-    def tick(self, steps: int) -> int:
+    def tick(self, steps: int, steps_2d: int | None = None) -> int:
+        """Advance the 1D requests by up to `steps` steps and the 2D ones by
+        up to `steps_2d` (default: the same); returns the requests advanced."""
         n = ctypes.c_int32(0)
-        _check(lib().wcnst_pool_tick(self._h, int(steps), ctypes.byref(n)))
+        _check(lib().wcnst_pool_tick_split(self._h, int(steps), int(steps if steps_2d is None else steps_2d),
+                                           ctypes.byref(n)))
         return n.value
+
+    def tick_ms(self) -> tuple:
+        """Device time of the last tick's 1D and 2D launches (ms)."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(lib().wcnst_pool_tick_ms(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def result(self, slot: int) -> dict:
         f, s = ctypes.c_int32(), ctypes.c_int32()

@@ -77,7 +77,7 @@ def _run_pool(torch, items, steps_per_tick, join_after=None, tuning=None):
     ticks = 0
     joined = join_after is None
     while True:
-        n = pool.tick(steps_per_tick)
+        n = pool.tick(*steps_per_tick) if isinstance(steps_per_tick, tuple) else pool.tick(steps_per_tick)
         ticks += 1
         if not joined and (ticks == join_after[1] or n == 0):
             for j, (d, U, tf) in enumerate(later):
@@ -113,6 +113,26 @@ def test_pool_mix_equals_alone(torch, steps_per_tick):
     items = _mix(1)
     _say(f"pool mix, {steps_per_tick} steps per tick")
     _compare(items, _run_pool(torch, items, steps_per_tick))
+
+
+@pytest.mark.parametrize("split", [(40, 3), (1, 25)])
+def test_pool_split_steps_per_dimension(torch, split):
+    """Different step counts per tick for the 1D and the 2D requests
+    (wcnst_pool_tick_split) leave every result as solved alone; the per-
+    dimension device times of a tick are reported."""
+    from paper_1810_07806_amd.wcnst import Pool
+    items = _mix(4, n1=4, n2=3)
+    _say(f"pool with {split[0]} 1D / {split[1]} 2D steps per tick")
+    _compare(items, _run_pool(torch, items, split))
+    pool = Pool(capacity=4)
+    d, U, tf = items[0]
+    b = [torch.zeros(U.size, dtype=torch.float64, device="cuda") for _ in range(3)]
+    b[0].copy_(torch.from_numpy(np.ascontiguousarray(U).ravel()))
+    pool.admit(d, b[0], b[1], b[2], tf, 0.5)
+    pool.tick(3, 5)
+    ms1, ms2 = pool.tick_ms()
+    assert ms1 > 0.0 and ms2 == 0.0
+    pool.close()
 
 
 def test_pool_join_midway_and_tuning(torch):
