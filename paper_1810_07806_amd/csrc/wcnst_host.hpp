@@ -34,6 +34,13 @@ hipError_t wcnst_launch_multi(const wcnst_desc* d, int ndim, const void* reqs, i
                               int tick_step, int ty, bool general, hipStream_t st);
 // true when d has sides other than periodic / zero gradient, or gravity
 bool wcnst_general_bc(const wcnst_desc* d);
+// Wavefront slots of the current device for the 2D stage kernel (two per
+// SIMD, four SIMDs per CU).
+int wcnst_wave_slots();
+// Rows per 2D segment when the caller fixes none: the shortest segment in
+// [9, 35] whose launch over the grids (strips[i], rows[i]), i < n, still fits
+// one round of `slots` wavefronts, else 35.  Never changes results.
+int wcnst_auto_rows(const int* strips, const int* rows, int n, int slots);
 // wcnst_launch_init_grid for every grid of a ReqGrid table (one launch).
 hipError_t wcnst_launch_multi_init(int ndim, const void* reqs, int nreq, hipStream_t st);
 

@@ -839,7 +839,10 @@ extern "C" wcnst_status wcnst_create(const wcnst_desc* d, void* hip_stream, void
     s->U1 = (double*)(ws + align256(sizeof(Ctrl)));
     s->U2 = (double*)(ws + align256(sizeof(Ctrl)) + align256(state));
     s->parity = 0;
-    s->ty = 35;
+    {
+        const int strips = (d->nx + TX - 1) / TX, rows = d->ny;
+        s->ty = d->ndim == 2 ? wcnst_auto_rows(&strips, &rows, 1, wcnst_wave_slots()) : 35;
+    }
     s->prof = false;
     s->ev_used = 0;
 
@@ -1121,6 +1124,28 @@ extern "C" wcnst_status wcnst_reset(wcnst_solver* s, double t, int64_t steps)
     s->parity = 0;
     HIP_TRY(hipGetLastError());
     return WCNST_OK;
+}
+
+int wcnst_wave_slots()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    return 8 * cus;
+}
+
+int wcnst_auto_rows(const int* strips, const int* rows, int n, int slots)
+{
+    // a grid too small to fill the device runs faster as more, shorter
+    // segments (each pays 3 extra rows of y-midpoints); one that fills it
+    // keeps the longest segment
+    for (int ty = 9; ty < 35; ++ty) {
+        long long waves = 0;
+        for (int i = 0; i < n; ++i) waves += (long long)strips[i] * ((rows[i] + ty - 1) / ty);
+        if (waves <= slots) return ty;
+    }
+    return 35;
 }
 
 extern "C" wcnst_status wcnst_set_tuning(wcnst_solver* s, int32_t rows_per_segment)

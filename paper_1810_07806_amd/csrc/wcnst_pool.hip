@@ -66,7 +66,8 @@ struct wcnst_pool {
     ReqGrid* h_req[2] = {nullptr, nullptr};
     uint8_t* h_ctrl = nullptr;
     std::vector<PoolReq> reqs;
-    int ty = 35;
+    int ty = 0;     // rows per 2D segment; 0: chosen per tick (wcnst_auto_rows)
+    int slots = 0;  // wavefront slots of the device
 };
 
 static size_t pool_layout(int cap, size_t* o_req1, size_t* o_req2, size_t* o_ctrl)
@@ -119,6 +120,7 @@ extern "C" wcnst_status wcnst_pool_create(const wcnst_desc* scheme, int32_t capa
     p->d_ctrl = ws + o_ctrl;
     p->ctrl_bytes = wcnst_align256(wcnst_ctrl_bytes());
     p->reqs.resize((size_t)capacity);
+    p->slots = wcnst_wave_slots();
 
     hipError_t e = hipStreamCreateWithFlags(&p->s2, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&p->ev_start);
@@ -139,7 +141,7 @@ extern "C" wcnst_status wcnst_pool_set_tuning(wcnst_pool* p, int32_t rows_per_se
 {
     if (!p) return wcnst_fail(WCNST_E_INVALID_ARG, "null handle");
     if (rows_per_segment < 0) return wcnst_fail(WCNST_E_INVALID_ARG, "rows_per_segment must be >= 0");
-    if (rows_per_segment) p->ty = rows_per_segment;
+    p->ty = rows_per_segment;
     return WCNST_OK;
 }
 
@@ -184,6 +186,16 @@ static wcnst_status issue_dim(wcnst_pool* p, int ndim, const std::vector<int>& a
 {
     if (act.empty()) return WCNST_OK;
     ReqGrid* tab = p->h_req[ndim - 1];
+    int ty = p->ty;
+    if (ndim == 2 && ty == 0) {
+        std::vector<int> strips, rows;
+        for (int i : act) {
+            strips.push_back((p->reqs[(size_t)i].d.nx + TX - 1) / TX);
+            rows.push_back(p->reqs[(size_t)i].d.ny);
+        }
+        ty = wcnst_auto_rows(strips.data(), rows.data(), (int)act.size(), p->slots);
+    }
+    if (ty == 0) ty = 35;  // (unused in 1D)
     int blocks = 0;
     int n = 0;
     bool general = false;
@@ -208,14 +220,14 @@ static wcnst_status issue_dim(wcnst_pool* p, int ndim, const std::vector<int>& a
         q.nstrips = (r.d.nx + TX - 1) / TX;
         q.blk0 = blocks;
         q.parity0 = r.parity;
-        blocks += q.nstrips * (ndim == 2 ? (r.d.ny + p->ty - 1) / p->ty : 1);
+        blocks += q.nstrips * (ndim == 2 ? (r.d.ny + ty - 1) / ty : 1);
         r.parity = (int)((r.parity + steps) & 1);
     }
     WCNST_HIP_TRY(hipMemcpyAsync(p->d_req[ndim - 1], tab, sizeof(ReqGrid) * (size_t)n, hipMemcpyHostToDevice, st));
     for (int64_t s = 0; s < steps; ++s)
         for (int stage = 0; stage < 3; ++stage)
             WCNST_HIP_TRY(
-                wcnst_launch_multi(&p->scheme, ndim, p->d_req[ndim - 1], n, blocks, stage, (int)(s & 1), p->ty, general,
+                wcnst_launch_multi(&p->scheme, ndim, p->d_req[ndim - 1], n, blocks, stage, (int)(s & 1), ty, general,
                                    st));
     return WCNST_OK;
 }
