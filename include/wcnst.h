@@ -149,10 +149,10 @@ wcnst_status wcnst_reset(wcnst_solver* s, double t, int64_t steps);
 
 /* Launch shape of the 2D stage kernel: one 64-lane wavefront per strip of
  * 61 columns marches up a segment of rows_per_segment rows (>= 1).  The
- * default, chosen at wcnst_create, is the shortest segment in [9, 35] whose
- * launch still fits one round of the device's wavefront slots (8 per CU),
- * else 35: grids too small to fill the device get more, shorter segments.
- * Changes only the work decomposition, never the results. */
+ * default, chosen at wcnst_create from the grid and the device's CU count,
+ * is in [2, 35]: 35 rows for grids that fill the device, shorter segments
+ * (more wavefronts) for smaller ones.  Changes only the work decomposition,
+ * never the results. */
 wcnst_status wcnst_set_tuning(wcnst_solver* s, int32_t rows_per_segment);
 
 /* Kernel timing for roofline reports: when enabled, every stage kernel is
@@ -280,9 +280,8 @@ wcnst_status wcnst_pool_result(const wcnst_pool* p, int32_t slot, int32_t* finis
 wcnst_status wcnst_pool_release(wcnst_pool* p, int32_t slot);
 
 /* Rows per 2D segment of the pool's stage launches (>= 1), or 0 for the
- * default: per tick, the shortest segment in [9, 35] whose launch over all
- * active 2D requests still fits one round of the device's wavefront slots,
- * else 35.  Never changes results. */
+ * default: chosen per tick, as at wcnst_create, over all active 2D
+ * requests.  Never changes results. */
 wcnst_status wcnst_pool_set_tuning(wcnst_pool* p, int32_t rows_per_segment);
 
 wcnst_status wcnst_pool_destroy(wcnst_pool* p);

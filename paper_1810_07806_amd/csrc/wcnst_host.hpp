@@ -37,9 +37,10 @@ bool wcnst_general_bc(const wcnst_desc* d);
 // Wavefront slots of the current device for the 2D stage kernel (two per
 // SIMD, four SIMDs per CU).
 int wcnst_wave_slots();
-// Rows per 2D segment when the caller fixes none: the shortest segment in
-// [9, 35] whose launch over the grids (strips[i], rows[i]), i < n, still fits
-// one round of `slots` wavefronts, else 35.  Never changes results.
+// Rows per 2D segment in [2, 35] when the caller fixes none, for a launch
+// over the grids (strips[i], rows[i]), i < n, on a device of `slots`
+// wavefront slots (2 per SIMD): the height minimising a cost fitted to
+// measured stage times.  Never changes results.
 int wcnst_auto_rows(const int* strips, const int* rows, int n, int slots);
 // wcnst_launch_init_grid for every grid of a ReqGrid table (one launch).
 hipError_t wcnst_launch_multi_init(int ndim, const void* reqs, int nreq, hipStream_t st);

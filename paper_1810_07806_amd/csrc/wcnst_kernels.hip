@@ -1137,15 +1137,26 @@ int wcnst_wave_slots()
 
 int wcnst_auto_rows(const int* strips, const int* rows, int n, int slots)
 {
-    // a grid too small to fill the device runs faster as more, shorter
-    // segments (each pays 3 extra rows of y-midpoints); one that fills it
-    // keeps the longest segment
-    for (int ty = 9; ty < 35; ++ty) {
+    // A wavefront's time grows with its segment's rows plus a fixed cost
+    // (3 extra rows of y-midpoints and the 6-row staging prologue: about 6
+    // rows in all), and the launch lasts as long as its busiest SIMD: w
+    // wavefronts share a SIMD's issue (w >= 2), a lone one uses about two
+    // thirds of it.  The segment height minimising (rows + 6) * g(w),
+    // ties to the taller, fits measured stage times from 128^2 to 8192^2.
+    const long long simds = slots / 2 > 0 ? slots / 2 : 1;
+    int best_ty = 35;
+    double best = 1e300;
+    for (int ty = 35; ty >= 2; --ty) {
         long long waves = 0;
         for (int i = 0; i < n; ++i) waves += (long long)strips[i] * ((rows[i] + ty - 1) / ty);
-        if (waves <= slots) return ty;
+        const long long w = (waves + simds - 1) / simds;
+        const double cost = (ty + 6) * (w <= 1 ? 1.5 : (double)w);
+        if (cost < best) {
+            best = cost;
+            best_ty = ty;
+        }
     }
-    return 35;
+    return best_ty;
 }
 
 extern "C" wcnst_status wcnst_set_tuning(wcnst_solver* s, int32_t rows_per_segment)

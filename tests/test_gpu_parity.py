@@ -291,7 +291,7 @@ def test_launch_shape_does_not_change_results(torch):
     rng = np.random.default_rng(5)
     d, U = W.random_euler2d(rng, 140, 75)
     outs = []
-    for rows in (35, 1, 16, 75, 200):
+    for rows in (35, 1, 2, 3, 16, 75, 200):
         _say(f"launch shape rows={rows}")
         s = _solver(d)
         s.set_tuning(rows)
