@@ -47,9 +47,13 @@ struct wcnst_batch {
     size_t ctrl_bytes = 0;
     double* U1 = nullptr;
     double* U2 = nullptr;
-    // pinned host staging
+    // pinned host staging: two tables and two control-block snapshots, used
+    // in turn (the host prepares a tick while the previous one runs)
     ReqGrid* h_req = nullptr;
+    ReqGrid* h_req2 = nullptr;
     uint8_t* h_ctrl = nullptr;
+    uint8_t* h_ctrl2 = nullptr;
+    hipEvent_t ev_snap[2] = {nullptr, nullptr};
     int steps_per_tick = 64;  // even, so that a replayed tick keeps the parity pattern
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double kernel_ms = 0.0;
@@ -152,7 +156,10 @@ extern "C" wcnst_status wcnst_batch_create(const wcnst_desc* descs, int32_t n, v
     if (e == hipSuccess) e = hipEventCreate(&b->ev0);
     if (e == hipSuccess) e = hipEventCreate(&b->ev1);
     if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_req, sizeof(ReqGrid) * (size_t)n, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_req2, sizeof(ReqGrid) * (size_t)n, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_ctrl, b->ctrl_bytes * (size_t)n, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_ctrl2, b->ctrl_bytes * (size_t)n, hipHostMallocDefault);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&b->ev_snap[k], hipEventDisableTiming);
     if (e != hipSuccess) {
         wcnst_batch_destroy(b);
         return wcnst_fail(WCNST_E_HIP, "batch setup failed: %s", hipGetErrorString(e));
@@ -284,42 +291,60 @@ extern "C" wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const doubl
     WCNST_HIP_TRY(hipEventRecord(b->ev0, b->stream));
     WCNST_HIP_TRY(wcnst_launch_multi_init(1, b->d_req, n, b->stream));
 
+    // Ticks are pipelined: tick k+1 is queued before the host has looked at
+    // tick k, so the set of running instances is decided from the control
+    // blocks one tick old; an instance that finished in tick k runs in tick
+    // k+1 only to leave each launch at its prologue.
+    ReqGrid* tabs[2] = {b->h_req, b->h_req2};  // table uploads alternate
+    uint8_t* snaps[2] = {b->h_ctrl, b->h_ctrl2};
+    int uploads = 1;  // the initial table came from tabs[0]
     long long launched = 0;
     bool changed = true;
+    int k = 0;
     while (!active.empty() && launched < (long long)max_steps) {
         const int steps = (int)std::min<long long>(b->steps_per_tick, (long long)max_steps - launched);
         if (changed && b->ticks > 0) {
-            // compact the table to the running instances (the previous tick
-            // has completed: the host waited for its control blocks)
+            // compact the table to the running instances, in the staging
+            // buffer not used by the last upload (the one before it has
+            // completed: the host waited on a later tick's snapshot)
+            ReqGrid* tab = tabs[uploads & 1];
             blocks = 0;
             for (size_t j = 0; j < active.size(); ++j) {
                 const int i = active[j];
-                b->h_req[j] = rows[(size_t)i];
-                b->h_req[j].blk0 = blocks;
-                b->h_req[j].parity0 = parity[(size_t)i];
+                tab[j] = rows[(size_t)i];
+                tab[j].blk0 = blocks;
+                tab[j].parity0 = parity[(size_t)i];
                 blocks += rows[(size_t)i].nstrips;
             }
-            WCNST_HIP_TRY(hipMemcpyAsync(b->d_req, b->h_req, sizeof(ReqGrid) * active.size(), hipMemcpyHostToDevice,
+            WCNST_HIP_TRY(hipMemcpyAsync(b->d_req, tab, sizeof(ReqGrid) * active.size(), hipMemcpyHostToDevice,
                                          b->stream));
+            uploads += 1;
         }
         wcnst_status st = run_tick(b, (int)active.size(), blocks, steps, changed);
         if (st) return st;
         launched += steps;
         b->ticks += 1;
         for (int i : active) parity[(size_t)i] = (parity[(size_t)i] + steps) & 1;
-        WCNST_HIP_TRY(hipMemcpyAsync(b->h_ctrl, b->d_ctrl, b->ctrl_bytes * (size_t)n, hipMemcpyDeviceToHost,
+        WCNST_HIP_TRY(hipMemcpyAsync(snaps[k & 1], b->d_ctrl, b->ctrl_bytes * (size_t)n, hipMemcpyDeviceToHost,
                                      b->stream));
-        WCNST_HIP_TRY(hipStreamSynchronize(b->stream));
-        std::vector<int> still;
-        still.reserve(active.size());
-        for (int i : active) {
-            const Ctrl& c = *(const Ctrl*)(b->h_ctrl + b->ctrl_bytes * (size_t)i);
-            const bool done = c.status != 0 || c.done != 0 ||
-                              (std::isfinite(t_final[i]) && reached(t_final[i], newest(c).t));
-            if (!done) still.push_back(i);
+        WCNST_HIP_TRY(hipEventRecord(b->ev_snap[k & 1], b->stream));
+        changed = false;
+        if (k > 0) {
+            // the previous tick's snapshot (this tick is running meanwhile)
+            WCNST_HIP_TRY(hipEventSynchronize(b->ev_snap[(k - 1) & 1]));
+            const uint8_t* snap = snaps[(k - 1) & 1];
+            std::vector<int> still;
+            still.reserve(active.size());
+            for (int i : active) {
+                const Ctrl& c = *(const Ctrl*)(snap + b->ctrl_bytes * (size_t)i);
+                const bool done = c.status != 0 || c.done != 0 ||
+                                  (std::isfinite(t_final[i]) && reached(t_final[i], newest(c).t));
+                if (!done) still.push_back(i);
+            }
+            changed = still.size() != active.size();
+            active.swap(still);
         }
-        changed = still.size() != active.size();
-        active.swap(still);
+        k += 1;
     }
     WCNST_HIP_TRY(hipEventRecord(b->ev1, b->stream));
     WCNST_HIP_TRY(hipMemcpyAsync(b->h_ctrl, b->d_ctrl, b->ctrl_bytes * (size_t)n, hipMemcpyDeviceToHost, b->stream));
@@ -365,6 +390,10 @@ extern "C" wcnst_status wcnst_batch_destroy(wcnst_batch* b)
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
     if (b->h_req) (void)hipHostFree(b->h_req);
+    if (b->h_req2) (void)hipHostFree(b->h_req2);
+    if (b->h_ctrl2) (void)hipHostFree(b->h_ctrl2);
+    for (int k = 0; k < 2; ++k)
+        if (b->ev_snap[k]) (void)hipEventDestroy(b->ev_snap[k]);
     if (b->h_ctrl) (void)hipHostFree(b->h_ctrl);
     delete b;
     return WCNST_OK;
