@@ -344,8 +344,10 @@ template <int NV, int FLUX, int SCHEME, bool CHAR, int MODE, bool GB>
 __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, const double* __restrict__ Un,
                                               double* __restrict__ out, uint8_t* __restrict__ flags,
                                               Ctrl* __restrict__ ctrl, const Params& P, const StageArgs& A,
-                                              int ty, int bx, int by)
+                                              int ty, int ty2, int nseg1, int bx, int by)
 {
+    // segment by of the strip: segments 0 .. nseg1-1 hold ty rows each, the
+    // later ones ty2 (ty2 == ty: one height; cut flags need one height)
     static_assert(NV == 4, "2D sweeps carry the four Euler variables");
     double dt = 0.0;
     long long step = 0;
@@ -363,8 +365,8 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
     const size_t plane = (size_t)nx * ny;
     const int lane = threadIdx.x;
     const int x0 = bx * TX;
-    const int y0 = by * ty;
-    const int y1 = min(y0 + ty, ny);
+    const int y0 = by < nseg1 ? by * ty : nseg1 * ty + (by - nseg1) * ty2;
+    const int y1 = min(y0 + (by < nseg1 ? ty : ty2), ny);
     const int c = x0 + lane;
     const bool cell_ok = lane < TX && c < nx;
     const int jx = x0 - 2 + lane;
@@ -523,9 +525,9 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
 template <int NV, int FLUX, int SCHEME, bool CHAR, int MODE, bool GB>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2)))
 sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __restrict__ out,
-        uint8_t* __restrict__ flags, Ctrl* __restrict__ ctrl, Params P, StageArgs A, int ty)
+        uint8_t* __restrict__ flags, Ctrl* __restrict__ ctrl, Params P, StageArgs A, int ty, int ty2, int nseg1)
 {
-    sweep2d_block<NV, FLUX, SCHEME, CHAR, MODE, GB>(U, Un, out, flags, ctrl, P, A, ty, (int)blockIdx.x,
+    sweep2d_block<NV, FLUX, SCHEME, CHAR, MODE, GB>(U, Un, out, flags, ctrl, P, A, ty, ty2, nseg1, (int)blockIdx.x,
                                                 (int)blockIdx.y);
 }
 
@@ -544,8 +546,10 @@ sweep2d_multi(const ReqGrid* __restrict__ reqs, int nreq, int stage, int tick_st
     const StageArgs A = request_stage(R, stage, tick_step);
     const double* in = stage == 0 ? R.U : (stage == 1 ? R.U1 : R.U2);
     double* out = stage == 0 ? R.U1 : (stage == 1 ? R.U2 : R.U);
-    sweep2d_block<NV, FLUX, SCHEME, CHAR, MODE_STAGE, GB>(in, R.U, out, nullptr, R.ctrl, P, A, ty, local % R.nstrips,
-                                                      local / R.nstrips);
+    // one height: every segment of the grid is of the first kind (an exact
+    // count keeps nseg1 * ty within the grid)
+    sweep2d_block<NV, FLUX, SCHEME, CHAR, MODE_STAGE, GB>(in, R.U, out, nullptr, R.ctrl, P, A, ty, ty,
+                                                      (P.ny + ty - 1) / ty, local % R.nstrips, local / R.nstrips);
 }
 
 // ----------------------------------------------------- control kernels
@@ -669,6 +673,8 @@ struct wcnst_solver {
     hipEvent_t snap_ev[2];
     int parity;
     int ty;  // rows per 2D segment
+    bool ty_user;  // set by wcnst_set_tuning (else chosen at creation)
+    int slots;     // wavefront slots of the device
     bool prof;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used;
@@ -839,9 +845,11 @@ extern "C" wcnst_status wcnst_create(const wcnst_desc* d, void* hip_stream, void
     s->U1 = (double*)(ws + align256(sizeof(Ctrl)));
     s->U2 = (double*)(ws + align256(sizeof(Ctrl)) + align256(state));
     s->parity = 0;
+    s->slots = wcnst_wave_slots();
+    s->ty_user = false;
     {
         const int strips = (d->nx + TX - 1) / TX, rows = d->ny;
-        s->ty = d->ndim == 2 ? wcnst_auto_rows(&strips, &rows, 1, wcnst_wave_slots()) : 35;
+        s->ty = d->ndim == 2 ? wcnst_auto_rows(&strips, &rows, 1, s->slots) : 35;
     }
     s->prof = false;
     s->ev_used = 0;
@@ -881,19 +889,55 @@ extern "C" wcnst_status wcnst_destroy(wcnst_solver* s)
 
 // ---------------------------------------------------------- launchers
 
+// Segments of a 2D launch: nseg1 segments of ty rows, then segments of ty2
+// rows, nseg in all.
+struct SegMap {
+    int ty, ty2, nseg1, nseg;
+};
+
+// One height in general.  A launch of one round with two wavefronts on most
+// SIMDs (more wavefronts than SIMDs, no more than the slots) is balanced:
+// a SIMD issues from its oldest wavefront first, so of the two that share
+// it (blocks b and b + SIMDs in dispatch order, measured) the first runs at
+// about its lone speed while the second, measured, advances 0.45 as fast,
+// then finishes alone.  The first-dispatched rows of segments take a rows
+// and the others c rows with c + 3 = 0.45 (a + 3) (3: the extra rows of
+// y-midpoints of a segment), so that both wavefronts of a SIMD finish
+// together: 2048^2 stage 0.45 -> 0.41 ms.
+static SegMap stage_segments(int nstrips, int ny, int ty, int slots, bool balance)
+{
+    const int nseg = (ny + ty - 1) / ty;
+    const SegMap one{ty, ty, nseg, nseg};
+    if (!balance) return one;
+    const long long simds = slots / 2;
+    const long long waves = (long long)nstrips * nseg;
+    if (waves <= simds || waves > slots) return one;
+    const int na = (int)(simds / nstrips);
+    if (na < 1) return one;
+    const double r = 0.45;
+    const int a = (int)std::lround(((double)ny / na + 3.0 - 3.0 * r) / (1.0 + r));
+    if (a < 1 || (long long)a * na >= ny) return one;
+    const int rest = ny - a * na;
+    const int c = (rest + na - 1) / na;
+    const int nb = (rest + c - 1) / c;
+    if ((long long)nstrips * (na + nb) > slots) return one;
+    return SegMap{a, c, na, na + nb};
+}
+
 template <int SYS, int NV, int FLUX, int SCHEME, bool CHAR, int MODE>
 static void launch_sweep_t(const wcnst_solver* s, const double* U, const double* Un, double* out,
                            uint8_t* flags, const StageArgs& A)
 {
     if constexpr (SYS == SYS_EULER && NV == 4) {
         const int nstrips = (s->d.nx + TX - 1) / TX;
-        const int nseg = (s->d.ny + s->ty - 1) / s->ty;
+        // cut flags (right-hand-side launches) need one segment height
+        const SegMap m = stage_segments(nstrips, s->d.ny, s->ty, s->slots, MODE == MODE_STAGE && !s->ty_user);
         if (wcnst_general_bc(&s->d))
-            hipLaunchKernelGGL((sweep2d<NV, FLUX, SCHEME, CHAR, MODE, true>), dim3(nstrips, nseg), dim3(WAVE), 0,
-                               s->stream, U, Un, out, flags, s->ctrl, s->P, A, s->ty);
+            hipLaunchKernelGGL((sweep2d<NV, FLUX, SCHEME, CHAR, MODE, true>), dim3(nstrips, m.nseg), dim3(WAVE), 0,
+                               s->stream, U, Un, out, flags, s->ctrl, s->P, A, m.ty, m.ty2, m.nseg1);
         else
-            hipLaunchKernelGGL((sweep2d<NV, FLUX, SCHEME, CHAR, MODE, false>), dim3(nstrips, nseg), dim3(WAVE), 0,
-                               s->stream, U, Un, out, flags, s->ctrl, s->P, A, s->ty);
+            hipLaunchKernelGGL((sweep2d<NV, FLUX, SCHEME, CHAR, MODE, false>), dim3(nstrips, m.nseg), dim3(WAVE), 0,
+                               s->stream, U, Un, out, flags, s->ctrl, s->P, A, m.ty, m.ty2, m.nseg1);
     } else if (s->d.diff == WCNST_MD) {
         constexpr int W = strip_cells<DIFF_MD>();
         hipLaunchKernelGGL((sweep1d<SYS, NV, FLUX, SCHEME, CHAR, MODE, DIFF_MD>), dim3((s->d.nx + W - 1) / W),
@@ -1164,6 +1208,7 @@ extern "C" wcnst_status wcnst_set_tuning(wcnst_solver* s, int32_t rows_per_segme
     if (!s) return fail(WCNST_E_INVALID_ARG, "null handle");
     if (rows_per_segment < 1) return fail(WCNST_E_INVALID_ARG, "rows_per_segment must be >= 1");
     s->ty = rows_per_segment;
+    s->ty_user = true;
     return WCNST_OK;
 }
 
