@@ -439,6 +439,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     stage_ms, launches = s.profile_read()
+    shape = s.stage_shape()
     s.profile_enable(False)
     st = s.status()
     assert st["status"] == 0, st
@@ -465,7 +466,8 @@ def main():
         "config": {"workload": f"2D Euler four-quadrant Riemann (Lax-Liu 3), {args.n}x{args.n} cells, "
                                f"WCNS-T TENO C_T=1e-5, Roe, MND, SSP-RK3 CFL 0.5, {nsteps} steps",
                    "nx": args.n, "ny": args.n, "t_reached": t_end, "kernel_ms_avg": avg_launch_s * 1e3,
-                   "stage_launches": launches, "rows_per_segment": args.rows or None},
+                   "stage_launches": launches, "rows_per_segment": args.rows or None,
+                   "stage_shape": shape},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": measured_traffic(f"quadrant2d_{args.n}") if not args.rows else None,

@@ -155,6 +155,17 @@ wcnst_status wcnst_reset(wcnst_solver* s, double t, int64_t steps);
  * never the results. */
 wcnst_status wcnst_set_tuning(wcnst_solver* s, int32_t rows_per_segment);
 
+/* Launch shape of the stage kernels (wcnst_step / wcnst_solve).  2D: strips
+ * of 61 columns; segments 0 .. nseg1-1 of each strip hold rows1 rows, the
+ * later ones (to nseg in all, the last one ragged) rows2.  Two heights are
+ * used only without an explicit tuning, for a launch of one round with two
+ * wavefronts on most SIMDs: a SIMD issues from its oldest wavefront first,
+ * and the first-dispatched segments get more rows so that both wavefronts
+ * finish together.  1D: strips only (rows and segments 1).  Right-hand-side
+ * launches use one height. */
+wcnst_status wcnst_stage_shape(const wcnst_solver* s, int32_t* strips, int32_t* rows1, int32_t* rows2,
+                               int32_t* nseg1, int32_t* nseg);
+
 /* Kernel timing for roofline reports: when enabled, every stage kernel is
  * bracketed by HIP events on the solver's stream.  wcnst_profile_read
  * synchronises and returns the summed stage-kernel milliseconds and the

@@ -1212,6 +1212,27 @@ extern "C" wcnst_status wcnst_set_tuning(wcnst_solver* s, int32_t rows_per_segme
     return WCNST_OK;
 }
 
+extern "C" wcnst_status wcnst_stage_shape(const wcnst_solver* s, int32_t* strips, int32_t* rows1, int32_t* rows2,
+                                          int32_t* nseg1, int32_t* nseg)
+{
+    if (!s || !strips || !rows1 || !rows2 || !nseg1 || !nseg) return fail(WCNST_E_INVALID_ARG, "null argument");
+    if (s->d.ndim != 2) {
+        const int W = s->d.diff == WCNST_MD ? strip_cells<DIFF_MD>()
+                                            : (s->d.diff == WCNST_HWCNS ? strip_cells<DIFF_HW>() : strip_cells<DIFF_MND>());
+        *strips = (s->d.nx + W - 1) / W;
+        *rows1 = *rows2 = 1;
+        *nseg1 = *nseg = 1;
+        return WCNST_OK;
+    }
+    *strips = (s->d.nx + TX - 1) / TX;
+    const SegMap m = stage_segments(*strips, s->d.ny, s->ty, s->slots, !s->ty_user);
+    *rows1 = m.ty;
+    *rows2 = m.ty2;
+    *nseg1 = m.nseg1;
+    *nseg = m.nseg;
+    return WCNST_OK;
+}
+
 extern "C" wcnst_status wcnst_profile_enable(wcnst_solver* s, int enable)
 {
     if (!s) return fail(WCNST_E_INVALID_ARG, "null handle");

@@ -21,7 +21,8 @@ _SCHEME = {"teno": 0, "linear": 1, "js": 2}
 _DIFF = {"mnd": 0, "md": 1, "hwcns": 2}
 
 EXPORTS = ("wcnst_desc_init", "wcnst_workspace_size", "wcnst_create", "wcnst_rhs", "wcnst_step",
-           "wcnst_solve", "wcnst_status_sync", "wcnst_reset", "wcnst_set_tuning", "wcnst_profile_enable",
+           "wcnst_solve", "wcnst_status_sync", "wcnst_reset", "wcnst_set_tuning", "wcnst_stage_shape",
+           "wcnst_profile_enable",
            "wcnst_profile_read", "wcnst_destroy", "wcnst_last_error",
            "wcnst_batch_workspace_size", "wcnst_batch_create", "wcnst_batch_offsets", "wcnst_batch_solve",
            "wcnst_batch_bad_cells", "wcnst_batch_set_tuning", "wcnst_batch_kernel_ms", "wcnst_batch_stats",
@@ -77,6 +78,7 @@ def lib(path: str | None = None):
     L.wcnst_status_sync.argtypes = [vp, dp, i64p, ctypes.POINTER(ctypes.c_int32), i64p, i64p]
     L.wcnst_reset.argtypes = [vp, ctypes.c_double, ctypes.c_int64]
     L.wcnst_set_tuning.argtypes = [vp, ctypes.c_int32]
+    L.wcnst_stage_shape.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 5
     L.wcnst_profile_enable.argtypes = [vp, ctypes.c_int]
     L.wcnst_profile_read.argtypes = [vp, dp, i64p]
     L.wcnst_destroy.argtypes = [vp]
@@ -239,6 +241,13 @@ class Solver:
 
     def set_tuning(self, rows_per_segment: int):
         _check(lib().wcnst_set_tuning(self._h, int(rows_per_segment)))
+
+    def stage_shape(self) -> dict:
+        """Launch shape of the stage kernels: strips, and segments 0 ..
+        nseg1-1 of rows1 rows then rows2 rows up to nseg (2D)."""
+        v = [ctypes.c_int32() for _ in range(5)]
+        _check(lib().wcnst_stage_shape(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("strips", "rows1", "rows2", "nseg1", "nseg"), (x.value for x in v)))
 
     def profile_enable(self, on: bool = True):
         _check(lib().wcnst_profile_enable(self._h, 1 if on else 0))

@@ -531,3 +531,23 @@ def test_rhs_1d_2e28_cells_sampled_windows(orc, torch):
         got = Rg[:, :, x0 + lo:x0 + hi].cpu().numpy()
         assert np.array_equal(got, Ro[:, :, lo:hi]), x0
     s.close()
+
+
+@pytest.mark.parametrize("n", [128, 768, 1024, 1536, 2048, 4096])
+def test_stage_shape_covers_the_grid(torch, n):
+    """The stage launch shape the library reports: its segments tile the
+    rows exactly (no empty segment), its wavefronts fit the launch rules,
+    and 2048^2 takes the pair-balanced 30 x 48 + 29 x 21 rows."""
+    d, U = W.riemann2d_config3(n)
+    s = _solver(d)
+    sh = s.stage_shape()
+    s.close()
+    assert sh["strips"] == (n + 60) // 61
+    n1, r1, r2, ns = sh["nseg1"], sh["rows1"], sh["rows2"], sh["nseg"]
+    assert 1 <= n1 <= ns and r1 >= 1 and r2 >= 1
+    rows = n1 * r1
+    assert rows < n or n1 == ns
+    last_start = rows + (ns - n1 - 1) * r2 if ns > n1 else (n1 - 1) * r1
+    assert last_start < n <= (rows + (ns - n1) * r2 if ns > n1 else n1 * r1)
+    if n == 2048:
+        assert (r1, r2, n1, ns) == (48, 21, 30, 59)
