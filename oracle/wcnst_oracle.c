@@ -5,7 +5,8 @@
  * Only tests, the smoke check and the benchmark's CPU-baseline leg load it.
  * It shares no code with the HIP path.  Built with -O2 -ffp-contract=off and
  * no fast-math so every operation is rounded as written, in the order the
- * paper writes it.
+ * paper writes it; the interpolation and the characteristic projections
+ * round each product-plus-sum once, written out as fma().
  *
  * The steps and where they come from:
  *   semi-discretisation du_i/dt = -f'_i ........... Sec. 2, Eq. (2)
@@ -91,18 +92,18 @@ void orc_candidates(const double s[5], double cand[3], double beta[3])
     /* Eq. (10) times h and Eq. (11) times h^2, on the substencils of Eq. (8).
      * Each second difference adds its outer nodes first, (u_{m-1} + u_{m+1})
      * - 2 u_m, so it takes the same value whichever end the stencil is read
-     * from. */
-    D1[0] = (a - 4.0 * b + 3.0 * c) / 2.0;
+     * from.  Each x * y + z here is rounded once, as fma(x, y, z). */
+    D1[0] = fma(3.0, c, fma(-4.0, b, a)) / 2.0;
     D1[1] = (d - b) / 2.0;
-    D1[2] = (-3.0 * c + 4.0 * d - e) / 2.0;
-    D2[0] = (a + c) - 2.0 * b;
-    D2[1] = (b + d) - 2.0 * c;
-    D2[2] = (c + e) - 2.0 * d;
+    D1[2] = (fma(-3.0, c, 4.0 * d) - e) / 2.0;
+    D2[0] = fma(-2.0, b, a + c);
+    D2[1] = fma(-2.0, c, b + d);
+    D2[2] = fma(-2.0, d, c + e);
     for (int k = 0; k < 3; ++k) {
         /* Eq. (9) with Delta x = h/2: u_i + u' h/2 + u'' h^2/8. */
-        cand[k] = c + D1[k] / 2.0 + D2[k] / 8.0;
+        cand[k] = fma(D2[k], 1.0 / 8.0, fma(D1[k], 1.0 / 2.0, c));
         /* Eq. (15). */
-        beta[k] = D1[k] * D1[k] + D2[k] * D2[k];
+        beta[k] = fma(D1[k], D1[k], D2[k] * D2[k]);
     }
 }
 
@@ -147,7 +148,7 @@ double orc_interp_left(const orc_problem* p, const double s[5], double chi[3],
     if (chi) for (int k = 0; k < 3; ++k) chi[k] = chi_l[k];
     if (delta) for (int k = 0; k < 3; ++k) delta[k] = del_l[k];
     /* Eq. (12) with the (possibly nonlinear) weights. */
-    return w[0] * cand[0] + w[1] * cand[1] + w[2] * cand[2];
+    return fma(w[2], cand[2], fma(w[1], cand[1], w[0] * cand[0]));
 }
 
 /* ------------------------------------------------------- Euler system */
@@ -344,7 +345,7 @@ static void midpoint_flux(const orc_problem* p, int nv, const double* st, double
         for (int m = 0; m < 6; ++m)
             for (int k = 0; k < nv; ++k) {
                 double acc = 0.0;
-                for (int v = 0; v < nv; ++v) acc += L[k * nv + v] * st[m * nv + v];
+                for (int v = 0; v < nv; ++v) acc = fma(L[k * nv + v], st[m * nv + v], acc);
                 W[m][k] = acc;
             }
     } else {
@@ -373,8 +374,8 @@ static void midpoint_flux(const orc_problem* p, int nv, const double* st, double
         for (int v = 0; v < nv; ++v) {
             double al = 0.0, ar = 0.0;
             for (int k = 0; k < nv; ++k) {
-                al += R[v * nv + k] * wL[k];
-                ar += R[v * nv + k] * wR[k];
+                al = fma(R[v * nv + k], wL[k], al);
+                ar = fma(R[v * nv + k], wR[k], ar);
             }
             UL[v] = al;
             UR[v] = ar;

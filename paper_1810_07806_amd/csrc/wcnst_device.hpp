@@ -14,8 +14,11 @@
 // orders drift apart by ~1e-5 after 100 steps on the four-quadrant
 // problem).  Every operation that produces a value is therefore evaluated
 // in the plain order of its definition with IEEE division and square root
-// and without contraction (this file and the kernels are compiled with
-// -ffp-contract=off), so results are reproducible bit for bit.  (The
+// and without implicit contraction (this file and the kernels are compiled
+// with -ffp-contract=off), so results are reproducible bit for bit.  The
+// interpolation (Eqs. (9)-(12), (15)) and the characteristic projections
+// use explicit fused multiply-adds, written at the same places in the
+// oracle: one rounding per a * x + y, and fewer instructions.  (The
 // reciprocals and roots of the Roe averages (the projection's; in 1D also
 // the flux's, with the physical fluxes) use the hardware's correctly rounded
 // sequences without their range scaling, which give the IEEE results bit
@@ -339,19 +342,20 @@ template <int SCHEME>
 WCNST_HD double interp5(double a, double b, double c, double d, double e, const Params& P,
                         unsigned& mask)
 {
-    // h u^(1)_k and h^2 u^(2)_k of Eqs. (10)-(11)
-    const double D10 = (a - 4.0 * b + 3.0 * c) / 2.0;
+    // h u^(1)_k and h^2 u^(2)_k of Eqs. (10)-(11); every a * x + y below
+    // is one fused multiply-add (one rounding), the same in the oracle
+    const double D10 = fma(3.0, c, fma(-4.0, b, a)) / 2.0;
     const double D11 = (d - b) / 2.0;
-    const double D12 = (-3.0 * c + 4.0 * d - e) / 2.0;
+    const double D12 = (fma(-3.0, c, 4.0 * d) - e) / 2.0;
     // outer nodes first: the mirrored right-side interpolation of the same
     // face forms the same second differences (shared, not recomputed)
-    const double D20 = (a + c) - 2.0 * b;
-    const double D21 = (b + d) - 2.0 * c;
-    const double D22 = (c + e) - 2.0 * d;
-    // candidates, Eq. (9) with Delta x = h/2
-    const double q0 = c + D10 / 2.0 + D20 / 8.0;
-    const double q1 = c + D11 / 2.0 + D21 / 8.0;
-    const double q2 = c + D12 / 2.0 + D22 / 8.0;
+    const double D20 = fma(-2.0, b, a + c);
+    const double D21 = fma(-2.0, c, b + d);
+    const double D22 = fma(-2.0, d, c + e);
+    // candidates, Eq. (9) with Delta x = h/2: u + D1/2 + D2/8
+    const double q0 = fma(D20, 0.125, fma(D10, 0.5, c));
+    const double q1 = fma(D21, 0.125, fma(D11, 0.5, c));
+    const double q2 = fma(D22, 0.125, fma(D12, 0.5, c));
     double w0, w1, w2;
     if constexpr (SCHEME == SCH_LINEAR) {
         mask = 7u;
@@ -360,9 +364,9 @@ WCNST_HD double interp5(double a, double b, double c, double d, double e, const 
         w2 = 5.0 / 16.0;
     } else {
         // Eq. (15)
-        const double b0 = D10 * D10 + D20 * D20;
-        const double b1 = D11 * D11 + D21 * D21;
-        const double b2 = D12 * D12 + D22 * D22;
+        const double b0 = fma(D10, D10, D20 * D20);
+        const double b1 = fma(D11, D11, D21 * D21);
+        const double b2 = fma(D12, D12, D22 * D22);
         if constexpr (SCHEME == SCH_JS) {
             // Eq. (14)
             mask = 7u;
@@ -378,9 +382,9 @@ WCNST_HD double interp5(double a, double b, double c, double d, double e, const 
             // Eq. (16); Eqs. (17)-(18) as gamma_k < C_T * sum(gamma)
             const double tau = fabs(b0 - b2);
             const int q = SCHEME == SCH_TENO ? 6 : P.q;
-            const double g0 = pow_q(P.C + tau * approx_rcp(b0 + P.eps_teno), q);
-            const double g1 = pow_q(P.C + tau * approx_rcp(b1 + P.eps_teno), q);
-            const double g2 = pow_q(P.C + tau * approx_rcp(b2 + P.eps_teno), q);
+            const double g0 = pow_q(fma(tau, approx_rcp(b0 + P.eps_teno), P.C), q);
+            const double g1 = pow_q(fma(tau, approx_rcp(b1 + P.eps_teno), P.C), q);
+            const double g2 = pow_q(fma(tau, approx_rcp(b2 + P.eps_teno), P.C), q);
             const double thr = P.CT * (g0 + g1 + g2);
             const bool k0 = !(g0 < thr), k1 = !(g1 < thr), k2 = !(g2 < thr);
             mask = (unsigned)k0 | ((unsigned)k1 << 1) | ((unsigned)k2 << 2);
@@ -399,7 +403,7 @@ WCNST_HD double interp5(double a, double b, double c, double d, double e, const 
         }
     }
     // Eq. (12)
-    return w0 * q0 + w1 * q1 + w2 * q2;
+    return fma(w2, q2, fma(w1, q1, w0 * q0));
 }
 
 // ------------------------------------------------------------ Euler
@@ -653,8 +657,7 @@ WCNST_HD void face_flux(ST& st, const Params& P, double (&F)[NV], unsigned& fb)
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         if (Eigen<NV>::L_zero(k, v)) continue;
-                        const double t = Ek.L(k, v) * st(m, v);
-                        acc = v == 0 ? t : acc + t;
+                        acc = v == 0 ? Ek.L(k, v) * st(m, v) : fma(Ek.L(k, v), st(m, v), acc);
                     }
                     w[m] = acc;
                 }
@@ -670,8 +673,8 @@ WCNST_HD void face_flux(ST& st, const Params& P, double (&F)[NV], unsigned& fb)
                         UL[v] = r * wl;
                         UR[v] = r * wr;
                     } else {
-                        UL[v] += r * wl;
-                        UR[v] += r * wr;
+                        UL[v] = fma(r, wl, UL[v]);
+                        UR[v] = fma(r, wr, UR[v]);
                     }
                 }
             }
