@@ -5,8 +5,9 @@
  * Only tests, the smoke check and the benchmark's CPU-baseline leg load it.
  * It shares no code with the HIP path.  Built with -O2 -ffp-contract=off and
  * no fast-math so every operation is rounded as written, in the order the
- * paper writes it; the interpolation and the characteristic projections
- * round each product-plus-sum once, written out as fma().
+ * paper writes it; the interpolation, the characteristic projections and
+ * the Roe dissipation round each product-plus-sum once, written out as
+ * fma().
  *
  * The steps and where they come from:
  *   semi-discretisation du_i/dt = -f'_i ........... Sec. 2, Eq. (2)
@@ -311,11 +312,11 @@ void orc_num_flux(const orc_problem* p, const double* UL, const double* UR, doub
             orc_roe_eigen(nv, p->gamma, UL, UR, L, R, lam);
             for (int k = 0; k < nv; ++k) {
                 alpha[k] = 0.0;
-                for (int v = 0; v < nv; ++v) alpha[k] += L[k * nv + v] * (UR[v] - UL[v]);
+                for (int v = 0; v < nv; ++v) alpha[k] = fma(L[k * nv + v], UR[v] - UL[v], alpha[k]);
             }
             for (int v = 0; v < nv; ++v) {
                 dis[v] = 0.0;
-                for (int k = 0; k < nv; ++k) dis[v] += R[v * nv + k] * fabs(lam[k]) * alpha[k];
+                for (int k = 0; k < nv; ++k) dis[v] = fma(R[v * nv + k] * fabs(lam[k]), alpha[k], dis[v]);
             }
         }
         for (int v = 0; v < nv; ++v) F[v] = 0.5 * ((FR[v] + FL[v]) - dis[v]);

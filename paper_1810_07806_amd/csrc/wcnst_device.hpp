@@ -16,9 +16,10 @@
 // in the plain order of its definition with IEEE division and square root
 // and without implicit contraction (this file and the kernels are compiled
 // with -ffp-contract=off), so results are reproducible bit for bit.  The
-// interpolation (Eqs. (9)-(12), (15)) and the characteristic projections
-// use explicit fused multiply-adds, written at the same places in the
-// oracle: one rounding per a * x + y, and fewer instructions.  (The
+// interpolation (Eqs. (9)-(12), (15)), the characteristic projections and
+// the Roe dissipation R |Lambda| L (U_R - U_L) use explicit fused
+// multiply-adds, written at the same places in the oracle: one rounding
+// per a * x + y, and fewer instructions.  (The
 // reciprocals and roots of the Roe averages (the projection's; in 1D also
 // the flux's, with the physical fluxes) use the hardware's correctly rounded
 // sequences without their range scaling, which give the IEEE results bit
@@ -591,8 +592,8 @@ WCNST_HD void euler_num_flux(const double* UL, const double* UR, double gamma, d
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 if (Eigen<NV>::L_zero(k, v)) continue;
-                const double t = E.L(k, v) * (UR[v] - UL[v]);
-                acc = v == 0 ? t : acc + t;
+                const double dU = UR[v] - UL[v];
+                acc = v == 0 ? E.L(k, v) * dU : fma(E.L(k, v), dU, acc);
             }
             alpha[k] = acc;
         }
@@ -602,8 +603,8 @@ WCNST_HD void euler_num_flux(const double* UL, const double* UR, double gamma, d
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
                 if (Eigen<NV>::R_zero(v, k)) continue;
-                const double t = E.R(v, k) * fabs(E.lam(k)) * alpha[k];
-                acc = k == 0 ? t : acc + t;
+                const double rl = E.R(v, k) * fabs(E.lam(k));
+                acc = k == 0 ? rl * alpha[k] : fma(rl, alpha[k], acc);
             }
             dis[v] = acc;
         }
