@@ -211,8 +211,7 @@ wcnst_status wcnst_batch_offsets(const wcnst_batch* b, int64_t* offsets);
  * CFL rule of wcnst_solve.  Synchronous.  status, t_out, steps_out are host
  * arrays of n (t_out / steps_out nullable); status[i] is WCNST_OK,
  * WCNST_E_NONPHYSICAL or WCNST_E_MAX_STEPS and the return value is the first
- * non-zero one.  WCNST_E_HIP if a cooperating part waited past its bounded
- * limit. */
+ * non-zero one. */
 wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const double* t_final, double cfl, int64_t max_steps,
                                int32_t* status, double* t_out, int64_t* steps_out);
 

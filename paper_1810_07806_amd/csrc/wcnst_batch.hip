@@ -60,8 +60,31 @@ struct wcnst_batch {
     int ticks = 0, graphs = 0;
     // per-instance outcome of the last solve
     std::vector<unsigned long long> bad_key;
+    // The tick graph in use and the tick that last launched it.  A graph
+    // replaced while ticks are pipelined may still be running: it waits in
+    // `retired` until the host has waited on the snapshot event of a tick at
+    // or after its last launch (same stream, so that launch has completed).
     hipGraphExec_t exec = nullptr;
+    long long exec_tick = -1;
+    struct Retired {
+        hipGraphExec_t exec;
+        long long last_tick;
+    };
+    std::vector<Retired> retired;
 };
+
+// Destroys the retired tick graphs whose last launch was in tick <= done
+// (done: a tick whose snapshot event the host has waited on; -1 after a
+// stream synchronisation destroys all).
+static void reap_retired(wcnst_batch* b, long long done)
+{
+    size_t keep = 0;
+    for (size_t i = 0; i < b->retired.size(); ++i) {
+        if (done < 0 || b->retired[i].last_tick <= done) (void)hipGraphExecDestroy(b->retired[i].exec);
+        else b->retired[keep++] = b->retired[i];
+    }
+    b->retired.resize(keep);
+}
 
 static size_t batch_layout(int n, long long total, size_t* o_req, size_t* o_ctrl, size_t* o_u1, size_t* o_u2)
 {
@@ -203,10 +226,12 @@ static bool reached(double t_final, double t) { return t_final - t <= 1e-12 * t_
 
 static const StepRec& newest(const Ctrl& c) { return c.rec[0].step >= c.rec[1].step ? c.rec[0] : c.rec[1]; }
 
-// One tick of `steps` steps over the table rows [0, nreq): replay the
+// Tick `tick` of `steps` steps over the table rows [0, nreq): replay the
 // captured graph when it was made for this table, else capture a new one
-// (a tick of fewer steps than steps_per_tick is launched directly).
-static wcnst_status run_tick(wcnst_batch* b, int nreq, int blocks, int steps, bool table_changed)
+// (a tick of fewer steps than steps_per_tick is launched directly).  A
+// replaced graph is retired, not destroyed: the previous tick, which may
+// have launched it, can still be running.
+static wcnst_status run_tick(wcnst_batch* b, int nreq, int blocks, int steps, bool table_changed, long long tick)
 {
     if (steps != b->steps_per_tick) {
         for (int s = 0; s < steps; ++s)
@@ -216,7 +241,7 @@ static wcnst_status run_tick(wcnst_batch* b, int nreq, int blocks, int steps, bo
     }
     if (!b->exec || table_changed) {
         if (b->exec) {
-            (void)hipGraphExecDestroy(b->exec);
+            b->retired.push_back({b->exec, b->exec_tick});
             b->exec = nullptr;
         }
         hipGraph_t g = nullptr;
@@ -235,6 +260,7 @@ static wcnst_status run_tick(wcnst_batch* b, int nreq, int blocks, int steps, bo
         b->graphs += 1;
     }
     WCNST_HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    b->exec_tick = tick;
     return WCNST_OK;
 }
 
@@ -272,10 +298,14 @@ extern "C" wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const doubl
     }
     b->ticks = 0;
     b->graphs = 0;
+    // graphs of an earlier solve (one that stopped on an error may have
+    // left work queued)
+    WCNST_HIP_TRY(hipStreamSynchronize(b->stream));
     if (b->exec) {
         (void)hipGraphExecDestroy(b->exec);
         b->exec = nullptr;
     }
+    reap_retired(b, -1);
     std::vector<int> active((size_t)n);
     for (int i = 0; i < n; ++i) active[(size_t)i] = i;
     std::vector<int> parity((size_t)n, 0);
@@ -320,8 +350,12 @@ extern "C" wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const doubl
                                          b->stream));
             uploads += 1;
         }
-        wcnst_status st = run_tick(b, (int)active.size(), blocks, steps, changed);
-        if (st) return st;
+        wcnst_status st = run_tick(b, (int)active.size(), blocks, steps, changed, k);
+        if (st) {
+            (void)hipStreamSynchronize(b->stream);
+            reap_retired(b, -1);
+            return st;
+        }
         launched += steps;
         b->ticks += 1;
         for (int i : active) parity[(size_t)i] = (parity[(size_t)i] + steps) & 1;
@@ -332,6 +366,8 @@ extern "C" wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const doubl
         if (k > 0) {
             // the previous tick's snapshot (this tick is running meanwhile)
             WCNST_HIP_TRY(hipEventSynchronize(b->ev_snap[(k - 1) & 1]));
+            // every launch up to tick k-1 has completed
+            reap_retired(b, k - 1);
             const uint8_t* snap = snaps[(k - 1) & 1];
             std::vector<int> still;
             still.reserve(active.size());
@@ -349,6 +385,7 @@ extern "C" wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const doubl
     WCNST_HIP_TRY(hipEventRecord(b->ev1, b->stream));
     WCNST_HIP_TRY(hipMemcpyAsync(b->h_ctrl, b->d_ctrl, b->ctrl_bytes * (size_t)n, hipMemcpyDeviceToHost, b->stream));
     WCNST_HIP_TRY(hipStreamSynchronize(b->stream));
+    reap_retired(b, -1);
     float ms = 0.0f;
     WCNST_HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1));
     b->kernel_ms = ms;
@@ -386,6 +423,7 @@ extern "C" wcnst_status wcnst_batch_destroy(wcnst_batch* b)
     if (!b) return WCNST_OK;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    reap_retired(b, -1);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
