@@ -13,10 +13,7 @@ import os
 
 import numpy as np
 
-from .build import LIB_PATH as _DEFAULT_LIB, SRC as _SRC, build
-
-# a different build of the same source may be substituted for experiments
-LIB_PATH = os.environ.get("WCNST_ORACLE_LIB", _DEFAULT_LIB)
+from .build import LIB_PATH, PLAIN_LIB_PATH, SRC as _SRC, build
 
 ADVECTION, BURGERS, EULER = 0, 1, 2
 PERIODIC, ZERO_GRADIENT = 0, 1
@@ -49,39 +46,58 @@ class Problem(ctypes.Structure):
 
 
 _lib = None
+_plain_lib = None
+
+
+def _load(path: str, plain: bool):
+    """Load a build of the oracle, compiling it first if it is absent or
+    older than its source."""
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        build(plain=plain)
+    return _configure(ctypes.CDLL(path))
 
 
 def lib():
-    """Load the oracle library, compiling it first if it is absent or older
-    than its source."""
+    """The oracle library."""
     global _lib
     if _lib is None:
-        stale = LIB_PATH == _DEFAULT_LIB and os.path.exists(LIB_PATH) and \
-            os.path.getmtime(LIB_PATH) < os.path.getmtime(_SRC)
-        if not os.path.exists(LIB_PATH) or stale:
-            build()
-        L = ctypes.CDLL(LIB_PATH)
-        P = ctypes.POINTER(Problem)
-        dp = ctypes.POINTER(ctypes.c_double)
-        i64p = ctypes.POINTER(ctypes.c_int64)
-        L.orc_nvar.argtypes = [P]
-        L.orc_nfaces.argtypes = [P, ctypes.c_int]
-        L.orc_flag_count.argtypes = [P]
-        L.orc_flag_count.restype = ctypes.c_int64
-        L.orc_interp_left.argtypes = [P, dp, dp, ctypes.POINTER(ctypes.c_int)]
-        L.orc_interp_left.restype = ctypes.c_double
-        L.orc_candidates.argtypes = [dp, dp, dp]
-        L.orc_roe_eigen.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp, dp, dp, dp]
-        L.orc_euler_flux.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
-        L.orc_num_flux.argtypes = [P, dp, dp, dp]
-        L.orc_rhs.argtypes = [P, dp, dp, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
-        L.orc_max_speed.argtypes = [P, dp]
-        L.orc_max_speed.restype = ctypes.c_double
-        L.orc_rk3_step.argtypes = [P, dp, ctypes.c_double, ctypes.c_int64, i64p, i64p, ctypes.c_int]
-        L.orc_solve.argtypes = [P, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                ctypes.c_int64, dp, i64p, i64p, i64p, ctypes.c_int]
-        _lib = L
+        _lib = _load(LIB_PATH, plain=False)
     return _lib
+
+
+def plain_lib():
+    """The same source built with every explicit product-plus-sum rounded
+    twice (``-DORC_PLAIN``): used only to show that the single rounding of
+    the default build does not change results beyond the parity
+    tolerances."""
+    global _plain_lib
+    if _plain_lib is None:
+        _plain_lib = _load(PLAIN_LIB_PATH, plain=True)
+    return _plain_lib
+
+
+def _configure(L):
+    """Argument and result types of the exported functions."""
+    P = ctypes.POINTER(Problem)
+    dp = ctypes.POINTER(ctypes.c_double)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    L.orc_nvar.argtypes = [P]
+    L.orc_nfaces.argtypes = [P, ctypes.c_int]
+    L.orc_flag_count.argtypes = [P]
+    L.orc_flag_count.restype = ctypes.c_int64
+    L.orc_interp_left.argtypes = [P, dp, dp, ctypes.POINTER(ctypes.c_int)]
+    L.orc_interp_left.restype = ctypes.c_double
+    L.orc_candidates.argtypes = [dp, dp, dp]
+    L.orc_roe_eigen.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp, dp, dp, dp]
+    L.orc_euler_flux.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
+    L.orc_num_flux.argtypes = [P, dp, dp, dp]
+    L.orc_rhs.argtypes = [P, dp, dp, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+    L.orc_max_speed.argtypes = [P, dp]
+    L.orc_max_speed.restype = ctypes.c_double
+    L.orc_rk3_step.argtypes = [P, dp, ctypes.c_double, ctypes.c_int64, i64p, i64p, ctypes.c_int]
+    L.orc_solve.argtypes = [P, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                            ctypes.c_int64, dp, i64p, i64p, i64p, ctypes.c_int]
+    return L
 
 
 def _dp(a: np.ndarray):
@@ -177,17 +193,20 @@ def num_flux(p: Problem, UL, UR):
     return F
 
 
-def rhs(p: Problem, U: np.ndarray, flags: bool = False, chi: bool = False, nthreads: int = 1):
-    """R = -(dF/dx [+ dG/dy]); optionally the cut flags and chi values.
+def rhs(p: Problem, U: np.ndarray, flags: bool = False, chi: bool = False, nthreads: int = 1,
+        plain: bool = False):
+    """R = -(dF/dx [+ dG/dy]); optionally the cut flags and chi values
+    (``plain``: from the twice-rounded build, see ``plain_lib``).
 
     Returns (R, flag_blocks, chi_blocks); the block lists hold one array per
     direction (see ``flag_shapes``), or are None when not requested."""
+    L = plain_lib() if plain else lib()
     U = np.ascontiguousarray(U, dtype=np.float64)
     R = np.empty_like(U)
-    nfl = int(lib().orc_flag_count(ctypes.byref(p)))
+    nfl = int(L.orc_flag_count(ctypes.byref(p)))
     fl = np.zeros(nfl, dtype=np.uint8) if flags else None
     ch = np.zeros(nfl * 3, dtype=np.float64) if chi else None
-    st = lib().orc_rhs(ctypes.byref(p), _dp(U), _dp(R),
+    st = L.orc_rhs(ctypes.byref(p), _dp(U), _dp(R),
                        fl.ctypes.data if fl is not None else None,
                        ch.ctypes.data if ch is not None else None, int(nthreads))
     if st:

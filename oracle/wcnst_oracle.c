@@ -7,7 +7,13 @@
  * no fast-math so every operation is rounded as written, in the order the
  * paper writes it; the interpolation, the characteristic projections and
  * the Roe dissipation round each product-plus-sum once, written out as
- * fma().
+ * ORC_FMA(a, b, c) = fma(a, b, c).  Built with -DORC_PLAIN the same macro is
+ * the plain a * b + c (two roundings): the tests require the two builds to
+ * agree within the parity tolerances on every right-hand-side case, so the
+ * single rounding is a choice of evaluation order, not a different method.
+ * The arithmetic of this file is frozen: a change of evaluation order in the
+ * HIP kernels is checked against it at the stated tolerances, not followed
+ * here.
  *
  * The steps and where they come from:
  *   semi-discretisation du_i/dt = -f'_i ........... Sec. 2, Eq. (2)
@@ -44,6 +50,13 @@
 #include <string.h>
 
 #define GHOST 5
+
+/* One product-plus-sum (see the header comment). */
+#ifdef ORC_PLAIN
+#define ORC_FMA(a, b, c) ((a) * (b) + (c))
+#else
+#define ORC_FMA(a, b, c) fma((a), (b), (c))
+#endif
 
 /* ---------------------------------------------------------------- sizes */
 
@@ -88,23 +101,29 @@ static const double D_OPT[3] = {1.0 / 16.0, 10.0 / 16.0, 5.0 / 16.0};
 
 void orc_candidates(const double s[5], double cand[3], double beta[3])
 {
-    const double a = s[0], b = s[1], c = s[2], d = s[3], e = s[4];
-    double D1[3], D2[3];
-    /* Eq. (10) times h and Eq. (11) times h^2, on the substencils of Eq. (8).
-     * Each second difference adds its outer nodes first, (u_{m-1} + u_{m+1})
-     * - 2 u_m, so it takes the same value whichever end the stencil is read
-     * from.  Each x * y + z here is rounded once, as fma(x, y, z). */
-    D1[0] = fma(3.0, c, fma(-4.0, b, a)) / 2.0;
-    D1[1] = (d - b) / 2.0;
-    D1[2] = (fma(-3.0, c, 4.0 * d) - e) / 2.0;
-    D2[0] = fma(-2.0, b, a + c);
-    D2[1] = fma(-2.0, c, b + d);
-    D2[2] = fma(-2.0, d, c + e);
+    const double c = s[2];
+    double t[4], D1[3], D2[3];
+    /* Eq. (10) times h and Eq. (11) times h^2, on the substencils of Eq. (8),
+     * written with the differences of neighbouring nodes t_m = s_{m+1} - s_m:
+     *   h u'_1 = (3 t_1 - t_0)/2,  h u'_2 = (s_3 - s_1)/2,  h u'_3 = (3 t_2 - t_3)/2,
+     *   h^2 u''_k = t_k - t_{k-1}  (k = 1, 2, 3 on t_0 .. t_3).
+     * A stencil of equal values then gives exactly zero differences, so
+     * tau_5 = 0 and every candidate is kept, as Eqs. (16)-(18) prescribe
+     * for constant data; and a second difference has the same value
+     * whichever end its three nodes are read from.  Each 3 t_1 - t_0 is one
+     * ORC_FMA. */
+    for (int m = 0; m < 4; ++m) t[m] = s[m + 1] - s[m];
+    D1[0] = ORC_FMA(3.0, t[1], -t[0]) / 2.0;
+    D1[1] = (s[3] - s[1]) / 2.0;
+    D1[2] = ORC_FMA(3.0, t[2], -t[3]) / 2.0;
+    D2[0] = t[1] - t[0];
+    D2[1] = t[2] - t[1];
+    D2[2] = t[3] - t[2];
     for (int k = 0; k < 3; ++k) {
         /* Eq. (9) with Delta x = h/2: u_i + u' h/2 + u'' h^2/8. */
-        cand[k] = fma(D2[k], 1.0 / 8.0, fma(D1[k], 1.0 / 2.0, c));
+        cand[k] = ORC_FMA(D2[k], 1.0 / 8.0, ORC_FMA(D1[k], 1.0 / 2.0, c));
         /* Eq. (15). */
-        beta[k] = fma(D1[k], D1[k], D2[k] * D2[k]);
+        beta[k] = ORC_FMA(D1[k], D1[k], D2[k] * D2[k]);
     }
 }
 
@@ -149,7 +168,7 @@ double orc_interp_left(const orc_problem* p, const double s[5], double chi[3],
     if (chi) for (int k = 0; k < 3; ++k) chi[k] = chi_l[k];
     if (delta) for (int k = 0; k < 3; ++k) delta[k] = del_l[k];
     /* Eq. (12) with the (possibly nonlinear) weights. */
-    return fma(w[2], cand[2], fma(w[1], cand[1], w[0] * cand[0]));
+    return ORC_FMA(w[2], cand[2], ORC_FMA(w[1], cand[1], w[0] * cand[0]));
 }
 
 /* ------------------------------------------------------- Euler system */
@@ -312,11 +331,11 @@ void orc_num_flux(const orc_problem* p, const double* UL, const double* UR, doub
             orc_roe_eigen(nv, p->gamma, UL, UR, L, R, lam);
             for (int k = 0; k < nv; ++k) {
                 alpha[k] = 0.0;
-                for (int v = 0; v < nv; ++v) alpha[k] = fma(L[k * nv + v], UR[v] - UL[v], alpha[k]);
+                for (int v = 0; v < nv; ++v) alpha[k] = ORC_FMA(L[k * nv + v], UR[v] - UL[v], alpha[k]);
             }
             for (int v = 0; v < nv; ++v) {
                 dis[v] = 0.0;
-                for (int k = 0; k < nv; ++k) dis[v] = fma(R[v * nv + k] * fabs(lam[k]), alpha[k], dis[v]);
+                for (int k = 0; k < nv; ++k) dis[v] = ORC_FMA(R[v * nv + k] * fabs(lam[k]), alpha[k], dis[v]);
             }
         }
         for (int v = 0; v < nv; ++v) F[v] = 0.5 * ((FR[v] + FL[v]) - dis[v]);
@@ -346,7 +365,7 @@ static void midpoint_flux(const orc_problem* p, int nv, const double* st, double
         for (int m = 0; m < 6; ++m)
             for (int k = 0; k < nv; ++k) {
                 double acc = 0.0;
-                for (int v = 0; v < nv; ++v) acc = fma(L[k * nv + v], st[m * nv + v], acc);
+                for (int v = 0; v < nv; ++v) acc = ORC_FMA(L[k * nv + v], st[m * nv + v], acc);
                 W[m][k] = acc;
             }
     } else {
@@ -375,8 +394,8 @@ static void midpoint_flux(const orc_problem* p, int nv, const double* st, double
         for (int v = 0; v < nv; ++v) {
             double al = 0.0, ar = 0.0;
             for (int k = 0; k < nv; ++k) {
-                al = fma(R[v * nv + k], wL[k], al);
-                ar = fma(R[v * nv + k], wR[k], ar);
+                al = ORC_FMA(R[v * nv + k], wL[k], al);
+                ar = ORC_FMA(R[v * nv + k], wR[k], ar);
             }
             UL[v] = al;
             UR[v] = ar;

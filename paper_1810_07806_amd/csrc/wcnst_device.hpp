@@ -337,22 +337,13 @@ __device__ __forceinline__ void init_weight_table()
     __syncthreads();
 }
 
-// u_L at x_{i+1/2} from (a, b, c, d, e) = (u_{i-2} .. u_{i+2}); mask receives
-// delta_1 | delta_2 << 1 | delta_3 << 2.
+// One side's interpolated value at x_{i+1/2} from its centre node c and the
+// scaled derivatives D1_k = h u'_k, D2_k = h^2 u''_k of its three candidates
+// (Eqs. (10)-(11)); mask receives delta_1 | delta_2 << 1 | delta_3 << 2.
 template <int SCHEME>
-WCNST_HD double interp5(double a, double b, double c, double d, double e, const Params& P,
-                        unsigned& mask)
+WCNST_HD double interp_side(double c, double D10, double D11, double D12, double D20, double D21, double D22,
+                            const Params& P, unsigned& mask)
 {
-    // h u^(1)_k and h^2 u^(2)_k of Eqs. (10)-(11); every a * x + y below
-    // is one fused multiply-add (one rounding), the same in the oracle
-    const double D10 = fma(3.0, c, fma(-4.0, b, a)) / 2.0;
-    const double D11 = (d - b) / 2.0;
-    const double D12 = (fma(-3.0, c, 4.0 * d) - e) / 2.0;
-    // outer nodes first: the mirrored right-side interpolation of the same
-    // face forms the same second differences (shared, not recomputed)
-    const double D20 = fma(-2.0, b, a + c);
-    const double D21 = fma(-2.0, c, b + d);
-    const double D22 = fma(-2.0, d, c + e);
     // candidates, Eq. (9) with Delta x = h/2: u + D1/2 + D2/8
     const double q0 = fma(D20, 0.125, fma(D10, 0.5, c));
     const double q1 = fma(D21, 0.125, fma(D11, 0.5, c));
@@ -405,6 +396,30 @@ WCNST_HD double interp5(double a, double b, double c, double d, double e, const 
     }
     // Eq. (12)
     return fma(w2, q2, fma(w1, q1, w0 * q0));
+}
+
+// u_L and the mirrored u_R at x_{j+1/2} from the six nodes w0 .. w5 = u_{j-2}
+// .. u_{j+3} (u_L from w0 .. w4, u_R from w5 .. w1).  Eqs. (10)-(11) times
+// h and h^2 are written with the differences of neighbouring nodes,
+// d_m = w_{m+1} - w_m, each formed once for both sides:
+//   left:  h u'_1 = (3 d_1 - d_0)/2, h u'_2 = (w_3 - w_1)/2, h u'_3 = (3 d_2 - d_3)/2,
+//          h^2 u''_k = (d_1 - d_0, d_2 - d_1, d_3 - d_2);
+//   right: the same on the mirrored nodes, whose neighbour differences are
+//          -d_4, -d_3, -d_2, -d_1: (d_4 - 3 d_3)/2, (w_2 - w_4)/2,
+//          (d_1 - 3 d_2)/2 and (d_4 - d_3, d_3 - d_2, d_2 - d_1).
+// Equal nodes give exactly zero differences (tau_5 = 0, every candidate
+// kept, as Eqs. (16)-(18) give for constant data), and the second
+// differences are shared by the two sides.
+template <int SCHEME>
+WCNST_HD void interp_pair(double w0, double w1, double w2, double w3, double w4, double w5, const Params& P,
+                          double& uL, double& uR, unsigned& mL, unsigned& mR)
+{
+    const double d0 = w1 - w0, d1 = w2 - w1, d2 = w3 - w2, d3 = w4 - w3, d4 = w5 - w4;
+    const double s1 = d1 - d0, s2 = d2 - d1, s3 = d3 - d2, s4 = d4 - d3;
+    uL = interp_side<SCHEME>(w2, fma(3.0, d1, -d0) * 0.5, (w3 - w1) * 0.5, fma(3.0, d2, -d3) * 0.5, s1, s2, s3,
+                             P, mL);
+    uR = interp_side<SCHEME>(w3, fma(-3.0, d3, d4) * 0.5, (w2 - w4) * 0.5, fma(-3.0, d2, d1) * 0.5, s4, s3, s2,
+                             P, mR);
 }
 
 // ------------------------------------------------------------ Euler
@@ -663,8 +678,8 @@ WCNST_HD void face_flux(ST& st, const Params& P, double (&F)[NV], unsigned& fb)
                     w[m] = acc;
                 }
                 unsigned mL, mR;
-                const double wl = interp5<SCHEME>(w[0], w[1], w[2], w[3], w[4], P, mL);
-                const double wr = interp5<SCHEME>(w[5], w[4], w[3], w[2], w[1], P, mR);
+                double wl, wr;
+                interp_pair<SCHEME>(w[0], w[1], w[2], w[3], w[4], w[5], P, wl, wr, mL, mR);
                 fb |= (mL | (mR << 3)) << (6 * k);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
@@ -683,16 +698,16 @@ WCNST_HD void face_flux(ST& st, const Params& P, double (&F)[NV], unsigned& fb)
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 unsigned mL, mR;
-                UL[v] = interp5<SCHEME>(st(0, v), st(1, v), st(2, v), st(3, v), st(4, v), P, mL);
-                UR[v] = interp5<SCHEME>(st(5, v), st(4, v), st(3, v), st(2, v), st(1, v), P, mR);
+                interp_pair<SCHEME>(st(0, v), st(1, v), st(2, v), st(3, v), st(4, v), st(5, v), P, UL[v], UR[v], mL,
+                                    mR);
                 fb |= (mL | (mR << 3)) << (6 * v);
             }
         }
         euler_num_flux<NV, FLUX>(UL, UR, P.gamma, F);
     } else {
         unsigned mL, mR;
-        const double uL = interp5<SCHEME>(st(0, 0), st(1, 0), st(2, 0), st(3, 0), st(4, 0), P, mL);
-        const double uR = interp5<SCHEME>(st(5, 0), st(4, 0), st(3, 0), st(2, 0), st(1, 0), P, mR);
+        double uL, uR;
+        interp_pair<SCHEME>(st(0, 0), st(1, 0), st(2, 0), st(3, 0), st(4, 0), st(5, 0), P, uL, uR, mL, mR);
         fb = mL | (mR << 3);
         if constexpr (SYS == SYS_ADV) {
             // Eq. (6) with f = a u, a_hat = a

@@ -61,8 +61,7 @@ def lib(path: str | None = None):
     global _lib
     if _lib is not None:
         return _lib
-    # WCNST_LIB selects another build of the same sources (A/B timing)
-    path = path or os.environ.get("WCNST_LIB") or LIB_PATH
+    path = path or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library {path} is missing: build it with "
                            "`python -m paper_1810_07806_amd.build` (no CPU fallback exists)")

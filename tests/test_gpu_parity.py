@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 from paper_1810_07806_amd import workloads as W
+from cases import CASES_1D, CASES_2D, euler1d_cases, euler2d_cases, extreme_density_cases, scalar_cases
 from parity import FIELD_TOL, assert_rhs_close, check_flags, rel_inf_err, rhs_mask_from_flips
 
 pytestmark = pytest.mark.gpu
@@ -60,31 +61,11 @@ def _rhs_case(orc, torch, desc, U, name):
     return err, fo
 
 
-CASES_1D = []
-for flux in ("roe", "lf"):
-    for scheme in ("teno", "linear", "js"):
-        CASES_1D.append(dict(flux=flux, scheme=scheme, charwise=1, bc_x="zero_gradient"))
-CASES_1D.append(dict(flux="roe", scheme="teno", charwise=0, bc_x="zero_gradient"))
-CASES_1D.append(dict(flux="roe", scheme="teno", charwise=1, bc_x="periodic"))
-CASES_1D.append(dict(flux="lf", scheme="teno", charwise=0, bc_x="periodic"))
-CASES_1D.append(dict(flux="vanleer", scheme="teno", charwise=1, bc_x="zero_gradient"))
-CASES_1D.append(dict(flux="vanleer", scheme="js", charwise=0, bc_x="periodic"))
-# Eq. (16) with other integer powers than the paper's q = 6
-CASES_1D.append(dict(flux="roe", scheme="teno", charwise=1, bc_x="zero_gradient", q=2))
-CASES_1D.append(dict(flux="lf", scheme="teno", charwise=1, bc_x="periodic", q=4))
-
-
 @pytest.mark.parametrize("kw", CASES_1D, ids=lambda k: "-".join(str(v) for v in k.values()))
 def test_rhs_euler1d(orc, torch, kw):
-    rng = np.random.default_rng(100)
-    for n in (245, 61, 62, 5):
-        d, U = W.random_tube(rng, n)
-        d.update(kw)
-        _, fo = _rhs_case(orc, torch, d, U, f"tube{n}")
-    # both kept and cut stencils occurred on the large case
-    d, U = W.random_tube(np.random.default_rng(7), 300)
-    d.update(kw)
-    _, fo = _rhs_case(orc, torch, d, U, "tube300")
+    for name, d, U in euler1d_cases(kw):
+        _, fo = _rhs_case(orc, torch, d, U, name)
+    # both kept and cut stencils occurred on the last (largest) case
     if kw["scheme"] == "teno":
         assert (fo[0] == 7).any() and (fo[0] != 7).any()
 
@@ -94,43 +75,19 @@ def test_rhs_shu_osher_2048(orc, torch):
     _rhs_case(orc, torch, d, U, "shu-osher")
 
 
-@pytest.mark.parametrize("n", [200, 199, 5])
-def test_rhs_advection(orc, torch, n):
-    d, U = W.advection_sine_square(n) if n >= 8 else W.smooth_periodic(n)
-    _, fo = _rhs_case(orc, torch, d, U, f"advection{n}")
-    if n == 200:
-        assert (fo[0] != 7).any()
-
-
-@pytest.mark.parametrize("flux", ["roe", "lf"])
-def test_rhs_burgers(orc, torch, flux):
-    rng = np.random.default_rng(5)
-    d = W.describe(ndim=1, system="burgers", nx=150, bc_x="periodic", flux=flux)
-    U = rng.normal(size=(1, 1, 150))
-    _rhs_case(orc, torch, d, U, "burgers")
-
-
-CASES_2D = [dict(flux="roe", scheme="teno", charwise=1),
-            dict(flux="lf", scheme="teno", charwise=1),
-            dict(flux="roe", scheme="linear", charwise=1),
-            dict(flux="roe", scheme="teno", charwise=0),
-            dict(flux="roe", scheme="js", charwise=1),
-            dict(flux="vanleer", scheme="teno", charwise=1),
-            dict(flux="roe", scheme="teno", charwise=1, q=4)]
+def test_rhs_scalar(orc, torch):
+    """Advection (the config 1 state and a 5-cell line) and Burgers (Roe
+    speed and local Lax-Friedrichs)."""
+    for name, d, U in scalar_cases():
+        _, fo = _rhs_case(orc, torch, d, U, name)
+        if name == "advection200":
+            assert (fo[0] != 7).any()
 
 
 @pytest.mark.parametrize("kw", CASES_2D, ids=lambda k: "-".join(str(v) for v in k.values()))
 def test_rhs_euler2d(orc, torch, kw):
-    rng = np.random.default_rng(200)
-    # ragged strips and segments, one strip / one segment, the minimum, and
-    # exact multiples of the 61-column strip and the 35-row segment
-    for (nx, ny) in ((133, 97), (61, 33), (5, 5), (130, 65), (122, 70), (62, 36)):
-        d, U = W.random_euler2d(rng, nx, ny)
-        d.update(kw)
-        _rhs_case(orc, torch, d, U, f"quad{nx}x{ny}")
-    d, U = W.random_euler2d(rng, 70, 40)
-    d.update(kw, bc_x="periodic", bc_y="periodic")
-    _rhs_case(orc, torch, d, U, "quad-periodic")
+    for name, d, U in euler2d_cases(kw):
+        _rhs_case(orc, torch, d, U, name)
 
 
 def test_rhs_config3_full_size(orc, torch):
@@ -364,22 +321,6 @@ def test_free_stream_rhs_is_exactly_zero(orc, torch, bc):
         assert np.abs(Rg).max() == 0.0
 
 
-def _scaled_state(ndim, n, log_rho, gamma=1.4):
-    """Smooth state with density 10**log_rho(x) (and pressure of the same
-    scale, so the sound speed stays of order one)."""
-    if ndim == 1:
-        d = W.describe(ndim=1, system="euler", nx=n, bc_x="periodic")
-        x = W.coords(d)
-        rho = 10.0 ** log_rho(x)
-        return d, W.conserved_1d(rho, 0.4 + 0.2 * np.sin(4 * np.pi * x), rho * (1 + 0.3 * np.cos(2 * np.pi * x)),
-                                 gamma)[:, None, :]
-    d = W.describe(ndim=2, system="euler", nx=n, ny=45, bc_x="periodic", bc_y="periodic")
-    x, y = np.meshgrid(W.coords(d, "x"), W.coords(d, "y"))
-    rho = 10.0 ** log_rho(x + y)
-    return d, W.conserved_2d(rho, 0.4 + 0.2 * np.sin(4 * np.pi * y), -0.3 + 0.1 * np.cos(2 * np.pi * x),
-                             rho * (1 + 0.3 * np.cos(2 * np.pi * x)), gamma)
-
-
 @pytest.mark.parametrize("flux", ["roe", "lf"])
 @pytest.mark.parametrize("scale", ["crossing-2^-767", "1e-300", "1e150"])
 def test_rhs_extreme_density_scales(orc, torch, flux, scale):
@@ -387,13 +328,8 @@ def test_rhs_extreme_density_scales(orc, torch, flux, scale):
     of the Roe averages and fluxes switch between the hardware sequences and
     the IEEE operations (below 2^-767 only the latter give IEEE results):
     the RHS still equals the oracle's bit for bit, in 1D and 2D."""
-    log_rho = {"crossing-2^-767": lambda s: -230.6 + 1.5 * np.sin(2 * np.pi * s),
-               "1e-300": lambda s: -300.0 + 0.2 * np.sin(2 * np.pi * s),
-               "1e150": lambda s: 150.0 + 0.2 * np.sin(2 * np.pi * s)}[scale]
-    for ndim, n in ((1, 245), (2, 70)):
-        d, U = _scaled_state(ndim, n, log_rho)
-        d.update(flux=flux, scheme="teno", charwise=1)
-        _rhs_case(orc, torch, d, U, f"density-{scale}")
+    for name, d, U in extreme_density_cases(flux, scale):
+        _rhs_case(orc, torch, d, U, name)
         s = _solver(d)
         Rg = s.rhs(s.new_state(U)).cpu().numpy()
         s.close()

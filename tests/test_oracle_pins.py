@@ -180,6 +180,25 @@ def test_tau5_zero_keeps_all_stencils(orc):
     assert v == 45 / 64
 
 
+def test_constant_stencil_keeps_every_candidate(orc):
+    """Equal values on all five nodes: every beta_k is 0, so tau5 = 0,
+    gamma_k = C^q, chi_k = 1/3 >= C_T and no candidate is cut (Eqs.
+    (16)-(18)); the value is the node value up to the rounding of Eq. (12).
+    Over values of every magnitude and sign, with q = 6 and q = 2."""
+    rng = np.random.default_rng(12)
+    vals = rng.uniform(-1, 1, 400) * 10.0 ** rng.uniform(-300, 300, 400)
+    vals = np.concatenate([vals, [0.0, 1.0, -3.0, 0.1, 1e-310, 7.3e305]])
+    for q in (6, 2):
+        p = orc.problem(W.describe(ndim=1, system="advection", nx=16, q=q))
+        for v in vals:
+            val, chi, d = orc.interp_left(p, [v] * 5)
+            _, beta = orc.candidates([v] * 5)
+            assert not beta.any(), v
+            assert tuple(d) == (1, 1, 1), (v, chi)
+            assert np.all(chi == chi[0]) and abs(chi[0] - 1 / 3) <= 1e-16
+            assert abs(val - v) <= 2 * np.spacing(abs(v)), v
+
+
 def test_cutoff_threshold_is_inclusive(orc):
     """chi_k == C_T keeps the stencil (the 'otherwise' branch of Eq. (18)):
     with C_T set to the exact chi of a stencil the flag flips only below it."""
@@ -323,6 +342,55 @@ def test_free_stream_is_exactly_zero(orc):
     U1 = W.conserved_1d(np.full(12, 0.7), np.full(12, 0.3), np.full(12, 1.1), 1.4).reshape(3, 1, 12)
     R1, _, _ = orc.rhs(orc.problem(d1), U1)
     assert not R1.any()
+
+
+# ------------------------------------------------ CFL rule (Sec. 3)
+
+def _cfl_state_2d(cells, g=1.4):
+    """2D Euler state (1 row) from (rho, u, v, p) per cell."""
+    r, u, v, p = (np.array([c[k] for c in cells], dtype=np.float64)[None, :] for k in range(4))
+    return W.conserved_2d(r, u, v, p, g)
+
+
+def test_cfl_speed_hand_computed(orc):
+    """The CFL denominator max over cells of (|u| + c)/dx [+ (|v| + c)/dy],
+    with numbers worked out by hand.  rho = 1.4 and p = 1 give c = 1.
+    1D, u = 0.5, dx = 0.1: (0.5 + 1)/0.1 = 15.  2D, dx = 0.1, dy = 0.25:
+    cell A (u, v) = (0.5, -2): 15 + 3/0.25 = 27; cell B (1.9, 0): 2.9/0.1 +
+    1/0.25 = 33; the maximum is 33 (a maximum of each direction taken
+    separately would give 29 + 12 = 41, swapped spacings 1.5/0.25 + 3/0.1 =
+    36 for A, dropping c 5 + 8 = 13 for A).  Advection a = -2 on dx = 0.1:
+    20; Burgers max |u| / dx."""
+    d1 = W.describe(ndim=1, system="euler", nx=5, x0=0.0, x1=0.5)
+    U1 = W.conserved_1d(np.full(5, 1.4), np.full(5, 0.5), np.full(5, 1.0), 1.4).reshape(3, 1, 5)
+    assert abs(orc.max_speed(orc.problem(d1), U1) - 15.0) <= 1e-13 * 15
+    # dy = 0.25: five rows of the same two cells on [0, 1.25]
+    d2 = W.describe(ndim=2, system="euler", nx=2, ny=5, x0=0.0, x1=0.2, y0=0.0, y1=1.25)
+    U2 = np.repeat(_cfl_state_2d([(1.4, 0.5, -2.0, 1.0), (1.4, 1.9, 0.0, 1.0)]), 5, axis=1)
+    assert abs(orc.max_speed(orc.problem(d2), U2) - 33.0) <= 1e-13 * 33
+    U2a = np.repeat(_cfl_state_2d([(1.4, 0.5, -2.0, 1.0), (1.4, 0.5, -2.0, 1.0)]), 5, axis=1)
+    assert abs(orc.max_speed(orc.problem(d2), U2a) - 27.0) <= 1e-13 * 27
+    da = W.describe(ndim=1, system="advection", nx=10, x0=0.0, x1=1.0, adv_speed=-2.0)
+    assert orc.max_speed(orc.problem(da), np.zeros((1, 1, 10))) == 20.0
+    db = W.describe(ndim=1, system="burgers", nx=10, x0=0.0, x1=1.0)
+    Ub = np.linspace(-3.0, 1.0, 10).reshape(1, 1, 10)
+    assert orc.max_speed(orc.problem(db), Ub) == 30.0
+
+
+def test_cfl_time_step_and_final_clip(orc):
+    """A uniform 1D state keeps an RHS of exactly zero, so every step has
+    dt = CFL / 15 = 1/30 (rho = 1.4, u = 0.5, p = 1, dx = 0.1); to
+    t_final = 0.11 the solve takes 4 steps, the last clipped to 0.01, and
+    stops at 0.11 (within 1e-12 t_final)."""
+    d = W.describe(ndim=1, system="euler", nx=10, x0=0.0, x1=1.0, bc_x="periodic")
+    U = W.conserved_1d(np.full(10, 1.4), np.full(10, 0.5), np.full(10, 1.0), 1.4).reshape(3, 1, 10)
+    r = orc.solve(orc.problem(d), U, t_final=0.11, cfl=0.5)
+    assert r["status"] == 0 and r["steps"] == 4
+    assert abs(r["t"] - 0.11) <= 1e-12 * 0.11
+    one = orc.solve(orc.problem(d), U, cfl=0.5, max_steps=1)
+    assert abs(one["t"] - 1.0 / 30.0) <= 1e-15
+    three = orc.solve(orc.problem(d), U, cfl=0.5, max_steps=3)
+    assert abs(three["t"] - 0.1) <= 1e-15
 
 
 def test_config3_diagonal_symmetry_bitwise(orc):
