@@ -52,7 +52,7 @@ enum {
 enum { WCNST_ADVECTION = 0, WCNST_BURGERS = 1, WCNST_EULER = 2 };
 enum { WCNST_PERIODIC = 0, WCNST_ZERO_GRADIENT = 1, WCNST_REFLECT = 2, WCNST_FIXED = 3 };
 enum { WCNST_ROE = 0, WCNST_LF = 1, WCNST_VANLEER = 2 };
-enum { WCNST_TENO = 0, WCNST_LINEAR = 1, WCNST_JS = 2 };
+enum { WCNST_TENO = 0, WCNST_LINEAR = 1, WCNST_JS = 2, WCNST_Z = 3 };
 enum { WCNST_MND = 0, WCNST_MD = 1, WCNST_HWCNS = 2 };
 
 /* Problem descriptor.  Initialise with wcnst_desc_init(), then set fields. */
@@ -68,7 +68,9 @@ typedef struct wcnst_desc {
                              fixed_x / fixed_y) */
     int32_t flux;         /* WCNST_ROE (no entropy fix) / WCNST_LF (local) /
                              WCNST_VANLEER (flux-vector splitting, Euler only) */
-    int32_t scheme;       /* WCNST_TENO (Eqs. 16-19) / WCNST_LINEAR (Eq. 12) / WCNST_JS (Eq. 14) */
+    int32_t scheme;       /* WCNST_TENO (Eqs. 16-19) / WCNST_LINEAR (Eq. 12) / WCNST_JS (Eq. 14) /
+                             WCNST_Z (the WCNS-Z of Sec. 3: weights of Borges et al. 2008 on the
+                             indicators of Eq. 15 and tau_5 of Sec. 2.3; 1D single solves only) */
     int32_t diff;         /* WCNST_MND (Eq. 5) / WCNST_MD (Eq. 3) / WCNST_HWCNS (Eq. 4); MD and
                              HWCNS: 1D single solves only (batches and pools use MND) */
     int32_t charwise;     /* Euler: 1 = interpolate characteristic variables */
@@ -83,12 +85,16 @@ typedef struct wcnst_desc {
                              order (rho, rho u, [rho v], E; scalars use [0]); default 0 */
     double fixed_y[2][4]; /* ... at y0 / y1 (2D) */
     double gravity;       /* 2D Euler body force in +y: R += (0, 0, rho g, rho v g); default 0 */
+    int32_t z_q;          /* WCNST_Z: power p in alpha_k = d_k (1 + (tau_5/(beta_k + eps_z))^p),
+                             in [1, 8]; default 1 */
+    double eps_z;         /* WCNST_Z: epsilon, > 0; default 1e-40 */
 } wcnst_desc;
 
 typedef struct wcnst_solver wcnst_solver;
 
 /* Fill *d with the paper's defaults: 1D Euler, Roe, TENO, MND, charwise,
- * gamma 1.4, C_T 1e-5, C 1, q 6, eps 1e-40, zero-gradient, domain [0, 1]. */
+ * gamma 1.4, C_T 1e-5, C 1, q 6, eps 1e-40, zero-gradient, domain [0, 1];
+ * for WCNS-Z p = 1 and eps_z = 1e-40. */
 wcnst_status wcnst_desc_init(wcnst_desc* d);
 
 /* Device workspace bytes needed by a solver for *d (control block plus two

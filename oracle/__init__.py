@@ -18,14 +18,14 @@ from .build import LIB_PATH, PLAIN_LIB_PATH, SRC as _SRC, build
 ADVECTION, BURGERS, EULER = 0, 1, 2
 PERIODIC, ZERO_GRADIENT = 0, 1
 ROE, LF, VANLEER = 0, 1, 2
-TENO, LINEAR, JS = 0, 1, 2
+TENO, LINEAR, JS, Z = 0, 1, 2, 3
 MND, MD, HWCNS = 0, 1, 2
 OK, E_INVALID, E_NONPHYSICAL, E_MAX_STEPS = 0, 1, 2, 3
 
 _SYSTEM = {"advection": ADVECTION, "burgers": BURGERS, "euler": EULER}
 _BC = {"periodic": PERIODIC, "zero_gradient": ZERO_GRADIENT, "reflect": 2, "fixed": 3}
 _FLUX = {"roe": ROE, "lf": LF, "vanleer": VANLEER}
-_SCHEME = {"teno": TENO, "linear": LINEAR, "js": JS}
+_SCHEME = {"teno": TENO, "linear": LINEAR, "js": JS, "z": Z}
 _DIFF = {"mnd": MND, "md": MD, "hwcns": HWCNS}
 
 
@@ -42,6 +42,7 @@ class Problem(ctypes.Structure):
         ("eps_teno", ctypes.c_double), ("eps_js", ctypes.c_double),
         ("fixed_x", (ctypes.c_double * 4) * 2), ("fixed_y", (ctypes.c_double * 4) * 2),
         ("gravity", ctypes.c_double),
+        ("z_q", ctypes.c_int), ("eps_z", ctypes.c_double),
     ]
 
 
@@ -124,6 +125,7 @@ def problem(desc: dict) -> Problem:
         eps_js=float(desc.get("eps_js", 1e-6)),
         fixed_x=_fixed(desc.get("fixed_x")), fixed_y=_fixed(desc.get("fixed_y")),
         gravity=float(desc.get("gravity", 0.0)),
+        z_q=int(desc.get("z_q", 1)), eps_z=float(desc.get("eps_z", 1e-40)),
     )
 
 

@@ -23,6 +23,9 @@
  *   candidate interpolants, derivatives ........... Sec. 2.2, Eqs. (9)-(11)
  *   optimal linear weights d_k .................... Sec. 2.2, Eq. (13)
  *   Jiang-Shu weights / smoothness indicator ...... Sec. 2.2, Eqs. (14)-(15)
+ *   WCNS-Z weights (Sec. 3's comparison scheme) ... Borges, Carmona, Costa &
+ *                                                   Don (2008), with the global
+ *                                                   indicator tau_5 of Sec. 2.3
  *   TENO measure, normalisation, cut-off, weights . Sec. 2.3, Eqs. (16)-(19)
  *   characteristic-wise interpolation, ideal gas .. Sec. 3 (opening paragraph)
  *   Roe flux-difference splitting ................. Sec. 1 (named); the system
@@ -88,6 +91,7 @@ static int validate(const orc_problem* p)
     if (!(p->dx > 0) || (p->ndim == 2 && !(p->dy > 0))) return ORC_E_INVALID;
     if (p->system == ORC_EULER && !(p->gamma > 1)) return ORC_E_INVALID;
     if (p->q < 1) return ORC_E_INVALID;
+    if (p->scheme == ORC_Z && (p->z_q < 1 || !(p->eps_z > 0))) return ORC_E_INVALID;
     if (p->flux == ORC_VANLEER && p->system != ORC_EULER) return ORC_E_INVALID;
     if ((p->bc_x == ORC_REFLECT || p->bc_y == ORC_REFLECT) && p->system != ORC_EULER) return ORC_E_INVALID;
     if (p->gravity != 0.0 && p->ndim != 2) return ORC_E_INVALID;
@@ -144,6 +148,18 @@ double orc_interp_left(const orc_problem* p, const double s[5], double chi[3],
         for (int k = 0; k < 3; ++k) {
             double be = beta[k] + p->eps_js;
             alpha[k] = D_OPT[k] / (be * be);
+        }
+        sum = alpha[0] + alpha[1] + alpha[2];
+        for (int k = 0; k < 3; ++k) { w[k] = alpha[k] / sum; chi_l[k] = w[k]; }
+    } else if (p->scheme == ORC_Z) {
+        /* Z weights of Borges et al. (2008) on the indicators of Eq. (15):
+         * alpha_k = d_k (1 + (tau5 / (beta_k + eps))^p), omega = alpha / sum. */
+        double alpha[3], sum;
+        double tau5 = fabs(beta[0] - beta[2]);
+        for (int k = 0; k < 3; ++k) {
+            double x = tau5 / (beta[k] + p->eps_z), xp = 1.0;
+            for (int m = 0; m < p->z_q; ++m) xp *= x;
+            alpha[k] = D_OPT[k] * (1.0 + xp);
         }
         sum = alpha[0] + alpha[1] + alpha[2];
         for (int k = 0; k < 3; ++k) { w[k] = alpha[k] / sum; chi_l[k] = w[k]; }

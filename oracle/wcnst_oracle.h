@@ -31,7 +31,7 @@ extern "C" {
 enum { ORC_ADVECTION = 0, ORC_BURGERS = 1, ORC_EULER = 2 };
 enum { ORC_PERIODIC = 0, ORC_ZERO_GRADIENT = 1, ORC_REFLECT = 2, ORC_FIXED = 3 };
 enum { ORC_ROE = 0, ORC_LF = 1, ORC_VANLEER = 2 };
-enum { ORC_TENO = 0, ORC_LINEAR = 1, ORC_JS = 2 };
+enum { ORC_TENO = 0, ORC_LINEAR = 1, ORC_JS = 2, ORC_Z = 3 };
 enum { ORC_MND = 0, ORC_MD = 1, ORC_HWCNS = 2 };
 
 enum {
@@ -48,7 +48,7 @@ typedef struct orc_problem {
     double dx, dy;   /* uniform spacing h per direction */
     int bc_x, bc_y;  /* ORC_PERIODIC / ORC_ZERO_GRADIENT / ORC_REFLECT (Euler) / ORC_FIXED */
     int flux;        /* ORC_ROE / ORC_LF / ORC_VANLEER (Euler only) */
-    int scheme;      /* ORC_TENO / ORC_LINEAR / ORC_JS */
+    int scheme;      /* ORC_TENO / ORC_LINEAR / ORC_JS / ORC_Z */
     int diff;        /* ORC_MND / ORC_MD / ORC_HWCNS */
     int charwise;    /* Euler: 1 = interpolate characteristic variables */
     int q;           /* TENO integer power (6) */
@@ -63,6 +63,8 @@ typedef struct orc_problem {
     double fixed_x[2][4];
     double fixed_y[2][4];
     double gravity;  /* 2D Euler: source (0, 0, rho g, rho v g) added to R */
+    int z_q;         /* ORC_Z: power p of the Z weights */
+    double eps_z;    /* ORC_Z: epsilon of the Z weights */
 } orc_problem;
 
 int orc_nvar(const orc_problem* p);

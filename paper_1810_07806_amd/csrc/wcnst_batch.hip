@@ -104,7 +104,8 @@ static size_t batch_layout(int n, long long total, size_t* o_req, size_t* o_ctrl
 wcnst_status wcnst_check_same_scheme(const wcnst_desc& a, const wcnst_desc& d)
 {
     if (d.flux != a.flux || d.scheme != a.scheme || d.charwise != a.charwise || d.q != a.q || d.gamma != a.gamma ||
-        d.CT != a.CT || d.C != a.C || d.eps_teno != a.eps_teno || d.eps_js != a.eps_js || d.diff != a.diff)
+        d.CT != a.CT || d.C != a.C || d.eps_teno != a.eps_teno || d.eps_js != a.eps_js || d.diff != a.diff ||
+        d.z_q != a.z_q || d.eps_z != a.eps_z)
         return WCNST_E_INVALID_ARG;
     return WCNST_OK;
 }
@@ -123,6 +124,8 @@ static wcnst_status batch_check(const wcnst_desc* descs, int32_t n, long long* t
             return wcnst_fail(WCNST_E_INVALID_ARG, "descriptor %d: batches hold 1D Euler problems", i);
         if (d.diff != WCNST_MND)
             return wcnst_fail(WCNST_E_INVALID_ARG, "descriptor %d: batches use the MND difference", i);
+        if (d.scheme == WCNST_Z)
+            return wcnst_fail(WCNST_E_INVALID_ARG, "descriptor %d: the WCNS-Z weights are built for single solves", i);
         if (wcnst_check_same_scheme(a, d))
             return wcnst_fail(WCNST_E_INVALID_ARG, "descriptor %d: scheme parameters differ from descriptor 0", i);
         if (offs) (*offs)[i] = off;

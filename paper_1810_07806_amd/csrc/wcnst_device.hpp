@@ -40,8 +40,9 @@ namespace wcnst {
 
 enum { SYS_ADV = 0, SYS_BURG = 1, SYS_EULER = 2 };
 enum { FLUX_ROE = 0, FLUX_LF = 1, FLUX_VL = 2 };
-// SCH_TENO: Eq. (16) with the paper's q = 6; SCH_TENO_Q: any integer q
-enum { SCH_TENO = 0, SCH_LINEAR = 1, SCH_JS = 2, SCH_TENO_Q = 3 };
+// SCH_TENO: Eq. (16) with the paper's q = 6; SCH_TENO_Q: any integer q;
+// SCH_Z: the Z weights of Borges et al. (2008), the paper's WCNS-Z
+enum { SCH_TENO = 0, SCH_LINEAR = 1, SCH_JS = 2, SCH_TENO_Q = 3, SCH_Z = 4 };
 enum { BC_PERIODIC = 0, BC_ZG = 1, BC_REFLECT = 2, BC_FIXED = 3 };
 enum { DIFF_MND = 0, DIFF_MD = 1, DIFF_HW = 2 };
 
@@ -113,6 +114,8 @@ struct Params {
     double fixed_x[2][4];  // fixed ghost states (storage order) at the low / high ends
     double fixed_y[2][4];
     double gravity;        // 2D Euler body force in +y
+    double eps_z;          // WCNS-Z epsilon
+    int z_q;               // WCNS-Z power
 };
 
 // Step records of one solve, alternating by step parity: the current
@@ -309,6 +312,15 @@ WCNST_HD double pow_q(double x, int q)
     return r;
 }
 
+// x^q by q successive multiplications (a value, not only a decision, is
+// formed from it, so the order is that of the definition)
+WCNST_HD double pow_seq(double x, int q)
+{
+    double r = 1.0;
+    for (int m = 0; m < q; ++m) r *= x;
+    return r;
+}
+
 // ------------------------------------------------- Sec. 2.2-2.3 interpolation
 
 // Weight of candidate k under cut pattern mask (bit k-1 = delta_k), Eq. (19):
@@ -366,6 +378,18 @@ WCNST_HD double interp_side(double c, double D10, double D11, double D12, double
             const double a0 = (1.0 / 16.0) / (e0 * e0);
             const double a1 = (10.0 / 16.0) / (e1 * e1);
             const double a2 = (5.0 / 16.0) / (e2 * e2);
+            const double s = a0 + a1 + a2;
+            w0 = a0 / s;
+            w1 = a1 / s;
+            w2 = a2 / s;
+        } else if constexpr (SCHEME == SCH_Z) {
+            // Z weights (Borges et al. 2008) with tau_5 of Sec. 2.3:
+            // alpha_k = d_k (1 + (tau_5 / (beta_k + eps))^p)
+            mask = 7u;
+            const double tau = fabs(b0 - b2);
+            const double a0 = (1.0 / 16.0) * (1.0 + pow_seq(tau / (b0 + P.eps_z), P.z_q));
+            const double a1 = (10.0 / 16.0) * (1.0 + pow_seq(tau / (b1 + P.eps_z), P.z_q));
+            const double a2 = (5.0 / 16.0) * (1.0 + pow_seq(tau / (b2 + P.eps_z), P.z_q));
             const double s = a0 + a1 + a2;
             w0 = a0 / s;
             w1 = a1 / s;

@@ -712,7 +712,12 @@ wcnst_status wcnst_check_desc(const wcnst_desc* d)
         return fail(WCNST_E_INVALID_ARG, "unknown flux");
     if (d->flux == WCNST_VANLEER && d->system != WCNST_EULER)
         return fail(WCNST_E_INVALID_ARG, "the van Leer splitting is for the Euler system");
-    if (d->scheme < WCNST_TENO || d->scheme > WCNST_JS) return fail(WCNST_E_INVALID_ARG, "unknown scheme");
+    if (d->scheme < WCNST_TENO || d->scheme > WCNST_Z) return fail(WCNST_E_INVALID_ARG, "unknown scheme");
+    if (d->scheme == WCNST_Z) {
+        if (d->ndim != 1) return fail(WCNST_E_INVALID_ARG, "the WCNS-Z weights are built for 1D grids");
+        if (d->z_q < 1 || d->z_q > 8) return fail(WCNST_E_INVALID_ARG, "z_q must be in [1, 8]");
+        if (!(d->eps_z > 0.0)) return fail(WCNST_E_INVALID_ARG, "eps_z must be positive");
+    }
     if (d->diff != WCNST_MND && d->diff != WCNST_MD && d->diff != WCNST_HWCNS)
         return fail(WCNST_E_INVALID_ARG, "unknown difference");
     if (d->diff != WCNST_MND && d->ndim != 1)
@@ -761,6 +766,8 @@ extern "C" wcnst_status wcnst_desc_init(wcnst_desc* d)
     d->C = 1.0;
     d->eps_teno = 1e-40;
     d->eps_js = 1e-6;
+    d->z_q = 1;
+    d->eps_z = 1e-40;
     return WCNST_OK;
 }
 
@@ -816,6 +823,8 @@ void wcnst_make_params(const wcnst_desc* d, Params* out)
             P.fixed_y[side][v] = d->fixed_y[side][v];
         }
     P.gravity = d->gravity;
+    P.z_q = d->z_q;
+    P.eps_z = d->eps_z;
     *out = P;
 }
 
@@ -960,6 +969,10 @@ static void launch_scheme(const wcnst_solver* s, const double* U, const double* 
     switch (s->d.scheme) {
     case WCNST_LINEAR: launch_sweep_t<SYS, NV, FLUX, SCH_LINEAR, CHAR, MODE>(s, U, Un, out, flags, A); break;
     case WCNST_JS: launch_sweep_t<SYS, NV, FLUX, SCH_JS, CHAR, MODE>(s, U, Un, out, flags, A); break;
+    case WCNST_Z:
+        // 1D only (refused for 2D grids at creation)
+        if constexpr (NV != 4) launch_sweep_t<SYS, NV, FLUX, SCH_Z, CHAR, MODE>(s, U, Un, out, flags, A);
+        break;
     default:
         if (s->d.q == 6) launch_sweep_t<SYS, NV, FLUX, SCH_TENO, CHAR, MODE>(s, U, Un, out, flags, A);
         else launch_sweep_t<SYS, NV, FLUX, SCH_TENO_Q, CHAR, MODE>(s, U, Un, out, flags, A);

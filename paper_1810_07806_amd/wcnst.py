@@ -17,7 +17,7 @@ OK, E_INVALID_ARG, E_NONPHYSICAL, E_MAX_STEPS, E_HIP = 0, 1, 2, 3, 4
 _SYSTEM = {"advection": 0, "burgers": 1, "euler": 2}
 _BC = {"periodic": 0, "zero_gradient": 1, "reflect": 2, "fixed": 3}
 _FLUX = {"roe": 0, "lf": 1, "vanleer": 2}
-_SCHEME = {"teno": 0, "linear": 1, "js": 2}
+_SCHEME = {"teno": 0, "linear": 1, "js": 2, "z": 3}
 _DIFF = {"mnd": 0, "md": 1, "hwcns": 2}
 
 EXPORTS = ("wcnst_desc_init", "wcnst_workspace_size", "wcnst_create", "wcnst_rhs", "wcnst_step",
@@ -50,6 +50,7 @@ class Desc(ctypes.Structure):
         ("C", ctypes.c_double), ("eps_teno", ctypes.c_double), ("eps_js", ctypes.c_double),
         ("fixed_x", (ctypes.c_double * 4) * 2), ("fixed_y", (ctypes.c_double * 4) * 2),
         ("gravity", ctypes.c_double),
+        ("z_q", ctypes.c_int32), ("eps_z", ctypes.c_double),
     ]
 
 
@@ -145,6 +146,8 @@ def make_desc(desc: dict) -> Desc:
                 for v, val in enumerate(states[side]):
                     arr[side][v] = float(val)
     d.gravity = float(desc.get("gravity", 0.0))
+    d.z_q = int(desc.get("z_q", 1))
+    d.eps_z = float(desc.get("eps_z", 1e-40))
     return d
 
 

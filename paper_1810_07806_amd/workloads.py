@@ -25,7 +25,7 @@ import numpy as np
 DEFAULTS = dict(ndim=1, system="euler", nx=64, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
                 bc_x="zero_gradient", bc_y="zero_gradient", flux="roe", scheme="teno",
                 diff="mnd", charwise=1, gamma=1.4, adv_speed=1.0, CT=1e-5, C=1.0,
-                eps_teno=1e-40, eps_js=1e-6, q=6, grid="cell")
+                eps_teno=1e-40, eps_js=1e-6, q=6, z_q=1, eps_z=1e-40, grid="cell")
 
 
 def describe(**kw) -> dict:

@@ -20,6 +20,9 @@ CASES_1D.append(dict(flux="vanleer", scheme="js", charwise=0, bc_x="periodic"))
 # Eq. (16) with other integer powers than the paper's q = 6
 CASES_1D.append(dict(flux="roe", scheme="teno", charwise=1, bc_x="zero_gradient", q=2))
 CASES_1D.append(dict(flux="lf", scheme="teno", charwise=1, bc_x="periodic", q=4))
+# the WCNS-Z comparison scheme of Sec. 3 (Borges et al. 2008 weights)
+CASES_1D.append(dict(flux="roe", scheme="z", charwise=1, bc_x="zero_gradient"))
+CASES_1D.append(dict(flux="lf", scheme="z", charwise=0, bc_x="periodic", z_q=2))
 
 CASES_2D = [dict(flux="roe", scheme="teno", charwise=1),
             dict(flux="lf", scheme="teno", charwise=1),

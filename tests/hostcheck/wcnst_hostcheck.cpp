@@ -57,7 +57,8 @@ template <int SYS, int NV, int FLUX, bool CHAR>
 void line_char(int scheme, const Params& P, int n, int bc, double c1, double c2, double c3, const double* U,
                int stride, const int* perm, double* R, uint8_t* flags, int nlines, int li)
 {
-    if (scheme == SCH_LINEAR) line<SYS, NV, FLUX, SCH_LINEAR, CHAR>(P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+    if (scheme == 3) line<SYS, NV, FLUX, SCH_Z, CHAR>(P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
+    else if (scheme == SCH_LINEAR) line<SYS, NV, FLUX, SCH_LINEAR, CHAR>(P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
     else if (scheme == SCH_JS) line<SYS, NV, FLUX, SCH_JS, CHAR>(P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
     else if (P.q == 6) line<SYS, NV, FLUX, SCH_TENO, CHAR>(P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
     else line<SYS, NV, FLUX, SCH_TENO_Q, CHAR>(P, n, bc, c1, c2, c3, U, stride, perm, R, flags, nlines, li);
@@ -149,13 +150,15 @@ static int strip_check(int nx)
 
 extern "C" {
 
-// sys: 0 advection, 1 Burgers, 2 Euler; flux: 0 Roe, 1 LF, 2 van Leer.  U, R: [nv][ny][nx].
+// sys: 0 advection, 1 Burgers, 2 Euler; flux: 0 Roe, 1 LF, 2 van Leer; scheme: 0 TENO,
+// 1 linear, 2 JS, 3 Z.  U, R: [nv][ny][nx].
 // R is accumulated (the caller zeroes it).  flags: [x block][y block] like wcnst_rhs.
 int hc_rhs(int ndim, int sys, int flux, int nx, int ny, double dx, double dy, int bc_x, int bc_y,
            int scheme, int charwise, int q, double gamma, double adv, double CT, double C,
-           double eps_teno, double eps_js, const double* U, double* R, uint8_t* flags)
+           double eps_teno, double eps_js, const double* U, double* R, uint8_t* flags, int z_q, double eps_z)
 {
     Params P{};
+    P.z_q = z_q; P.eps_z = eps_z;
     P.CT = CT; P.C = C; P.eps_teno = eps_teno; P.eps_js = eps_js;
     P.gamma = gamma; P.adv = adv; P.dx = dx; P.dy = dy;
     P.q = q; P.charwise = charwise; P.bc_x = bc_x; P.bc_y = bc_y;

@@ -44,6 +44,7 @@ def test_struct_layout_matches_header():
     assert L.wcnst_desc_init(ctypes.byref(d)) == 0
     assert d.struct_size == ctypes.sizeof(wc.Desc)
     assert (d.q, d.CT, d.C, d.eps_teno, d.gamma) == (6, 1e-5, 1.0, 1e-40, 1.4)
+    assert (d.z_q, d.eps_z) == (1, 1e-40)
 
 
 def _ws(wc, L, **kw):
@@ -62,11 +63,15 @@ def test_workspace_size_and_validation():
     assert st == 0 and n2 >= 2 * 4 * 2048 * 2048 * 8
     st, _ = _ws(wc, L, nx=100, diff="md")
     assert st == 0
+    st, _ = _ws(wc, L, nx=100, diff="md", scheme="z", z_q=2)
+    assert st == 0
     bad = [dict(nx=4), dict(ndim=3), dict(ndim=2, system="advection", nx=8, ny=8),
            dict(ndim=2, nx=8, ny=4), dict(gamma=1.0), dict(CT=0.5), dict(q=0),
            dict(x0=1.0, x1=1.0), dict(ndim=2, nx=8, ny=8, diff="md"),
            dict(system="advection", flux="vanleer"), dict(ndim=2, nx=8, ny=8, diff="hwcns"),
-           dict(system="advection", bc_x="reflect"), dict(gravity=1.0)]
+           dict(system="advection", bc_x="reflect"), dict(gravity=1.0),
+           dict(ndim=2, nx=8, ny=8, scheme="z"), dict(scheme="z", z_q=0), dict(scheme="z", z_q=9),
+           dict(scheme="z", eps_z=0.0)]
     for kw in bad:
         st, _ = _ws(wc, L, **kw)
         assert st == wc.E_INVALID_ARG, kw
@@ -100,3 +105,19 @@ def test_batches_and_pools_refuse_the_md_difference():
     # an empty batch is refused, not sized
     assert L.wcnst_batch_workspace_size(descs, 0, ctypes.byref(n)) == wc.E_INVALID_ARG
     assert L.wcnst_last_error()
+
+
+def test_batches_and_pools_refuse_the_z_weights():
+    """The WCNS-Z weights run in 1D single solves only: batches refuse them
+    at sizing time and pools at creation, before any device work."""
+    wc, L = _lib()
+    descs = (wc.Desc * 2)(*[wc.make_desc(dict(ndim=1, system="euler", nx=64, scheme=sc)) for sc in ("teno", "z")])
+    n = ctypes.c_size_t(0)
+    L.wcnst_batch_workspace_size.argtypes = [ctypes.POINTER(wc.Desc), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+    assert L.wcnst_batch_workspace_size(descs, 2, ctypes.byref(n)) == wc.E_INVALID_ARG
+    assert b"WCNS-Z" in L.wcnst_last_error()
+    h = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(1 << 16)
+    assert L.wcnst_pool_create(ctypes.byref(descs[1]), 4, None, ctypes.addressof(buf), 1 << 16,
+                               ctypes.byref(h)) == wc.E_INVALID_ARG
+    assert b"WCNS-Z" in L.wcnst_last_error()

@@ -35,7 +35,7 @@ def hc():
     L = ctypes.CDLL(LIB)
     dp = ctypes.c_void_p
     i, d = ctypes.c_int, ctypes.c_double
-    L.hc_rhs.argtypes = [i, i, i, i, i, d, d, i, i, i, i, i, d, d, d, d, d, d, dp, dp, dp]
+    L.hc_rhs.argtypes = [i, i, i, i, i, d, d, i, i, i, i, i, d, d, d, d, d, d, dp, dp, dp, i, d]
     return L
 
 
@@ -50,9 +50,10 @@ def _hc_rhs(hc, desc, U):
     dy = (desc["y1"] - desc["y0"]) / ny if ndim == 2 else 1.0
     bc = {"periodic": 0, "zero_gradient": 1}
     hc.hc_rhs(ndim, _SYS[desc["system"]], {"roe": 0, "lf": 1, "vanleer": 2}[desc["flux"]], nx, ny, dx, dy,
-              bc[desc["bc_x"]], bc[desc["bc_y"]], {"teno": 0, "linear": 1, "js": 2}[desc["scheme"]],
+              bc[desc["bc_x"]], bc[desc["bc_y"]], {"teno": 0, "linear": 1, "js": 2, "z": 3}[desc["scheme"]],
               int(desc["charwise"]), int(desc["q"]), desc["gamma"], desc["adv_speed"], desc["CT"],
-              desc["C"], desc["eps_teno"], desc["eps_js"], U.ctypes.data, R.ctypes.data, fl.ctypes.data)
+              desc["C"], desc["eps_teno"], desc["eps_js"], U.ctypes.data, R.ctypes.data, fl.ctypes.data,
+              int(desc.get("z_q", 1)), float(desc.get("eps_z", 1e-40)))
     return R, [np.asarray(b) for b in split_flags(desc, fl)]
 
 
@@ -68,7 +69,7 @@ def _compare(orc, hc, desc, U):
 
 
 @pytest.mark.parametrize("flux", ["roe", "lf", "vanleer"])
-@pytest.mark.parametrize("scheme", ["teno", "linear", "js"])
+@pytest.mark.parametrize("scheme", ["teno", "linear", "js", "z"])
 @pytest.mark.parametrize("charwise", [1, 0])
 def test_euler1d_lines(orc, hc, flux, scheme, charwise):
     rng = np.random.default_rng(31)

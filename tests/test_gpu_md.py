@@ -81,7 +81,9 @@ CASES = [("euler", dict(flux="roe", scheme="teno", charwise=1, bc_x="zero_gradie
          ("euler", dict(flux="lf", scheme="js", charwise=1, bc_x="periodic")),
          ("euler", dict(flux="roe", scheme="linear", charwise=1, bc_x="zero_gradient")),
          ("euler", dict(flux="roe", scheme="teno", charwise=0, bc_x="periodic")),
+         ("euler", dict(flux="roe", scheme="z", charwise=1, bc_x="zero_gradient")),
          ("advection", dict(scheme="teno")),
+         ("advection", dict(scheme="z")),
          ("burgers", dict(flux="roe", scheme="teno")),
          ("burgers", dict(flux="lf", scheme="js"))]
 
@@ -150,9 +152,9 @@ def test_table2_gaussian_advection_on_gpu(orc, torch, n_pts):
     """Table 2 (Gaussian pulse advected once around [0, 1], node grid, MD,
     CFL 0.02): the GPU reproduces the printed L_inf errors of the linear,
     JS and TCNS schemes with the oracle's tolerances, and the oracle's
-    final state bit for bit."""
-    lin, js, _, tcns = _table("table2_advection_linf.txt")[n_pts]
-    for scheme, want, rel in (("linear", lin, 6e-3), ("js", js, 6e-3),
+    final state bit for bit; and the WCNS-Z column."""
+    lin, js, z, tcns = _table("table2_advection_linf.txt")[n_pts]
+    for scheme, want, rel in (("linear", lin, 6e-3), ("js", js, 6e-3), ("z", z, 6e-3),
                               ("teno", tcns, 1.2e-2 if n_pts == 51 else 6e-3)):
         _say(f"table2 N={n_pts} {scheme}")
         d, U = W.advection_gaussian(n_pts, scheme=scheme, diff="md")
@@ -175,8 +177,8 @@ def _burgers_exact(x, t):
 def test_table3_burgers_on_gpu(orc, torch, n_pts):
     """Table 3 (Burgers, u0 = 1/2 + sin(pi x) on [0, 2] to t = 0.2, node
     grid, MD, Roe speed): printed L_inf errors to 1 %, oracle bit for bit."""
-    lin, js, _, tcns = _table("table3_burgers_linf.txt")[n_pts]
-    for scheme, want in (("linear", lin), ("js", js), ("teno", tcns)):
+    lin, js, z, tcns = _table("table3_burgers_linf.txt")[n_pts]
+    for scheme, want in (("linear", lin), ("js", js), ("z", z), ("teno", tcns)):
         _say(f"table3 N={n_pts} {scheme}")
         d, U = W.burgers_sine(n_pts, scheme=scheme, diff="md")
         V = _gpu_solve(d, U, 0.2, 0.05)

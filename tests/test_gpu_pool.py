@@ -1,14 +1,19 @@
 """Request pool and serving loop: each request gives the same bits in the
 mix as solved alone (wcnst_solve), whenever it joins, whatever else runs,
-and under any tuning; a failing request stays local."""
+and under any tuning; a failing request stays local; pooled and served
+results match the oracle (status, steps, t, field)."""
 from __future__ import annotations
 
+import os
 import sys
 
 import numpy as np
 import pytest
 
 from paper_1810_07806_amd import workloads as W
+from parity import FIELD_TOL, rel_inf_err
+
+NTHREADS = max(1, min(16, len(os.sched_getaffinity(0))))
 
 pytestmark = pytest.mark.gpu
 
@@ -108,6 +113,31 @@ def _compare(items, res):
             assert (r["bad_stage"], r["bad_cell"]) == (st["bad_stage"], st["bad_cell"])
 
 
+def _against_oracle(orc, items, res):
+    """Every request of a pooled or served run against the oracle's solve
+    of the same problem: status (and where a failure happened), steps, t,
+    and the field within the 1e-10 field tolerance (the two agree bit for
+    bit; the tolerance is the contract)."""
+    for i, (d, U, tf) in enumerate(items):
+        got, r = res[i]
+        o = orc.solve(orc.problem(d), U, t_final=tf, cfl=0.5, nthreads=NTHREADS)
+        assert r["status"] == o["status"], (i, r, o["status"])
+        if o["status"] == 0:
+            assert r["steps"] == o["steps"] and r["t"] == o["t"], (i, r, o["steps"], o["t"])
+            assert (rel_inf_err(got, o["U"]) <= FIELD_TOL).all(), i
+        else:
+            assert (r["bad_stage"], r["bad_cell"]) == (o["bad_stage"], o["bad_cell"]), i
+
+
+def test_pool_mix_matches_oracle(orc, torch):
+    """A pooled mix of 1D tubes and 2D four-quadrant grids, one of them
+    joining after the first ticks, against the oracle request by request."""
+    items = _mix(6, n1=5, n2=3)
+    _say("pool mix against the oracle")
+    res = _run_pool(torch, items, 7, join_after=(5, 2))
+    _against_oracle(orc, items, res)
+
+
 @pytest.mark.parametrize("steps_per_tick", [1, 7, 1000])
 def test_pool_mix_equals_alone(torch, steps_per_tick):
     items = _mix(1)
@@ -159,7 +189,7 @@ def test_pool_fault_stays_local(torch):
     _compare(items, res)
 
 
-def test_server_results_equal_per_solve(torch):
+def test_server_results_equal_per_solve(orc, torch):
     from paper_1810_07806_amd.serve import Server, per_solve_service
     tr = W.serving_trace(count=10, seed=4, rate=1e9, n1_min=64, n1_max=1500, side_min=64, side_max=192,
                          t_1d=0.02, t_2d=0.01)
@@ -174,6 +204,15 @@ def test_server_results_equal_per_solve(torch):
         p = ps[c["rid"]]
         assert c["status"] == p["status"] == 0 and c["steps"] == p["steps"]
         assert np.array_equal(c["U"].ravel(), p["U"].ravel())
+    # and against the oracle
+    byid = {r["rid"]: r for r in tr}
+    items, res = [], {}
+    for k, c in enumerate(sorted(done, key=lambda c: c["rid"])):
+        r = byid[c["rid"]]
+        items.append((r["desc"], r["U0"], r["t_final"]))
+        res[k] = (c["U"].reshape(r["U0"].shape), dict(status=c["status"], steps=c["steps"], t=c["t"],
+                                                     bad_stage=-1, bad_cell=-1))
+    _against_oracle(orc, items, res)
 
 
 def test_pool_mixes_general_and_plain_boundaries(torch):

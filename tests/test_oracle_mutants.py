@@ -22,7 +22,8 @@ import test_oracle_pins as PINS
 
 # (name, text in wcnst_oracle.c, replacement, pins expected to catch it)
 MUTANTS = [
-    ("tau5-wrong-pair", "fabs(beta[0] - beta[2])", "fabs(beta[0] - beta[1])",
+    ("tau5-wrong-pair", "double tau5 = fabs(beta[0] - beta[2]);\n        for (int k = 0; k < 3; ++k) {\n            double x = p->C",
+     "double tau5 = fabs(beta[0] - beta[1]);\n        for (int k = 0; k < 3; ++k) {\n            double x = p->C",
      ["test_step_cuts_crossing_stencils", "test_tau5_zero_keeps_all_stencils"]),
     ("power-q-minus-1", "for (int m = 0; m < p->q; ++m) g[k] *= x;", "for (int m = 1; m < p->q; ++m) g[k] *= x;",
      ["test_step_cuts_crossing_stencils"]),

@@ -199,6 +199,32 @@ def test_constant_stencil_keeps_every_candidate(orc):
             assert abs(val - v) <= 2 * np.spacing(abs(v)), v
 
 
+def test_wcns_z_weights_closed_forms(orc):
+    """Z weights alpha_k = d_k (1 + tau5 / (beta_k + eps)), omega = alpha /
+    sum (Borges et al. 2008, p = 1).  A step between nodes i and i+1 has
+    beta = (0, 5/4, 13/4) and tau5 = 13/4: alpha = (1/16 (1 + 3.25e40),
+    10/16 * 3.6, 5/16 * 2), so omega_1 = 1 to 1e-38 and the value is
+    candidate 1's, 0, plus ~1e-39 of the others (3/8 and 11/8).  A one-point
+    spike has tau5 = 0: the optimal weights
+    and the linear value 45/64.  Equal nodes: the optimal weights, the node
+    value."""
+    p = orc.problem(W.describe(ndim=1, system="advection", nx=16, scheme="z"))
+    v, w, d = orc.interp_left(p, [0, 0, 0, 1, 1])
+    a = np.array([(1 + 3.25e40) / 16, 10 / 16 * 3.6, 5 / 16 * 2.0])
+    assert np.allclose(w, a / a.sum(), rtol=1e-14, atol=0)
+    assert v == pytest.approx(float(np.dot(a / a.sum(), [0.0, 3 / 8, 11 / 8])), rel=1e-14) and v < 1e-38
+    assert tuple(d) == (1, 1, 1)
+    v, w, _ = orc.interp_left(p, [0, 0, 1, 0, 0])
+    assert np.array_equal(w, [1 / 16, 10 / 16, 5 / 16]) and v == 45 / 64
+    v, w, _ = orc.interp_left(p, [2.5] * 5)
+    assert np.array_equal(w, [1 / 16, 10 / 16, 5 / 16]) and abs(v - 2.5) <= 2 * np.spacing(2.5)
+    # p = 2 squares the ratio
+    p2 = orc.problem(W.describe(ndim=1, system="advection", nx=16, scheme="z", z_q=2))
+    w2 = orc.interp_left(p2, [0, 0, 0, 1, 1])[1]
+    a2 = np.array([(1 + 3.25e40 ** 2) / 16, 10 / 16 * (1 + 2.6 ** 2), 5 / 16 * 2.0])
+    assert np.allclose(w2, a2 / a2.sum(), rtol=1e-14, atol=1e-300)
+
+
 def test_cutoff_threshold_is_inclusive(orc):
     """chi_k == C_T keeps the stencil (the 'otherwise' branch of Eq. (18)):
     with C_T set to the exact chi of a stencil the flag flips only below it."""
@@ -525,6 +551,15 @@ def test_table2_gaussian_advection(orc, n_pts):
         assert e == pytest.approx(tcns, rel=6e-3)
 
 
+@pytest.mark.parametrize("n_pts", [51, 101, 201])
+def test_table2_wcns_z_column(orc, n_pts):
+    """The WCNS-Z column of Table 2, reproduced to the printed three digits
+    by the Z weights of Borges et al. (2008) with p = 1 (with p = 2 the
+    N = 51 error would be 4.85E-02 against the printed 5.67E-02)."""
+    row = {int(r[0]): [float(v) for v in r[1:]] for r in _table("table2_advection_linf.txt")}[n_pts]
+    assert _gauss_error(orc, n_pts, "z") == pytest.approx(row[2], rel=6e-3)
+
+
 def test_table2_linear_fine_grid(orc):
     row = {int(r[0]): [float(v) for v in r[1:]] for r in _table("table2_advection_linf.txt")}[401]
     assert _gauss_error(orc, 401, "linear") == pytest.approx(row[0], rel=6e-3)
@@ -541,8 +576,8 @@ def _burgers_exact(x, t):
 @pytest.mark.parametrize("n_pts", [41, 81, 161])
 def test_table3_burgers(orc, n_pts):
     row = {int(r[0]): [float(v) for v in r[1:]] for r in _table("table3_burgers_linf.txt")}[n_pts]
-    lin, js, _, tcns = row
-    for scheme, want in (("linear", lin), ("js", js), ("teno", tcns)):
+    lin, js, z, tcns = row
+    for scheme, want in (("linear", lin), ("js", js), ("z", z), ("teno", tcns)):
         d, U = W.burgers_sine(n_pts, scheme=scheme, diff="md")
         r = orc.solve(orc.problem(d), U, t_final=0.2, cfl=0.05)
         e = np.abs(r["U"].ravel() - _burgers_exact(W.coords(d), 0.2)).max()
