@@ -143,6 +143,31 @@ wcnst_status wcnst_step(wcnst_solver* s, double* U, double dt, double cfl);
 wcnst_status wcnst_solve(wcnst_solver* s, double* U, double t_final, double cfl,
                          int64_t max_steps, double* t_out, int64_t* steps_out);
 
+/* Largest scratch (bytes) of wcnst_solve_noalloc: the control block and two
+ * stage buffers, 256 + 2 x nvar x nx x ny x 8 bytes rounded to 256 each;
+ * 64 MiB admits 2D grids up to 1024 x 1023 (about 1.05e6 cells) and 1D
+ * Euler lines up to 1.39e6 cells. */
+#define WCNST_NOALLOC_MAX_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+ * of wcnst_solve, from t = 0, on a grid described by *d, with the control
+ * block and the stage buffers in a static device array of
+ * WCNST_NOALLOC_MAX_BYTES that the library holds on each device it runs on
+ * (no handle, no workspace, no pinned host memory; nothing is allocated).
+ * U (device, [nvar][ny][nx] FP64, caller-owned) is advanced in place on
+ * hip_stream until t_final (or for max_steps steps when t_final is +inf),
+ * with the same kernels and results as wcnst_solve.  Synchronous at return.
+ * t_out / steps_out (nullable) receive the time reached and the steps taken.
+ * Returns WCNST_E_INVALID_ARG for a bad descriptor or a grid whose scratch
+ * would exceed the limit (before any device work), WCNST_E_NONPHYSICAL /
+ * WCNST_E_MAX_STEPS as wcnst_solve.  Every call on one device shares that
+ * device's array, which keeps the last call's contents (each call resets
+ * what must start at zero): calls that overlap on one device, from several
+ * host threads or streams, race. */
+wcnst_status wcnst_solve_noalloc(const wcnst_desc* d, void* hip_stream, double* U, double t_final,
+                                 double cfl, int64_t max_steps, double* t_out, int64_t* steps_out);
+
 /* Synchronise the stream and read the device counters: time, total steps,
  * sticky status, and for WCNST_E_NONPHYSICAL the global stage index
  * (3*step + stage) and the cell (y*nx + x) of the first offending value

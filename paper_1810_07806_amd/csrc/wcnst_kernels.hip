@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "wcnst.h"
@@ -1154,6 +1155,118 @@ extern "C" wcnst_status wcnst_solve(wcnst_solver* s, double* U, double t_final, 
     if (timed && !(t_final - r.t <= 1e-12 * t_final))
         return fail(WCNST_E_MAX_STEPS, "t_final not reached in %lld steps (t = %.17g)",
                     (long long)max_steps, r.t);
+    return WCNST_OK;
+}
+
+// ------------------------------------------------ allocation-free solve
+
+// Static scratch of wcnst_solve_noalloc: the control block and the two
+// Runge-Kutta stage buffers of one solve.  Each device the library runs on
+// holds its own copy until the process ends.  In host code its name is
+// only a handle for hipGetSymbolAddress: kernels get the device address
+// obtained from that call (g_scratch_ptr), never the name.
+static __device__ __align__(256) unsigned char scratch[WCNST_NOALLOC_MAX_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device with that device current.
+static wcnst_status scratch_address(void** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(WCNST_E_HIP, "device index %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(WCNST_E_HIP, "no device address for the static scratch on device %d", dev);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return WCNST_OK;
+}
+
+extern "C" wcnst_status wcnst_solve_noalloc(const wcnst_desc* d, void* hip_stream, double* U, double t_final,
+                                            double cfl, int64_t max_steps, double* t_out, int64_t* steps_out)
+{
+    wcnst_status st = wcnst_check_desc(d);
+    if (st) return st;
+    if (!U) return fail(WCNST_E_INVALID_ARG, "null state");
+    if (!(cfl > 0.0)) return fail(WCNST_E_INVALID_ARG, "cfl must be > 0");
+    if (max_steps < 0) return fail(WCNST_E_INVALID_ARG, "max_steps must be >= 0");
+    if (std::isnan(t_final)) return fail(WCNST_E_INVALID_ARG, "t_final is NaN");
+    size_t need = 0;
+    wcnst_workspace_size(d, &need);
+    if (need > (size_t)WCNST_NOALLOC_MAX_BYTES)
+        return fail(WCNST_E_INVALID_ARG, "grid needs %zu bytes of scratch; the allocation-free solve holds %zu",
+                    need, (size_t)WCNST_NOALLOC_MAX_BYTES);
+    void* ptr = nullptr;
+    st = scratch_address(&ptr);
+    if (st) return st;
+
+    // a solver on the stack over the static scratch: no pinned staging, no
+    // events (the state is polled with plain copies into host variables)
+    wcnst_solver s{};
+    s.d = *d;
+    s.nv = wcnst_desc_nvar(d);
+    s.kind = d->system == WCNST_ADVECTION ? K_ADV1
+             : d->system == WCNST_BURGERS ? K_BURG1
+             : d->ndim == 1               ? K_EUL1
+                                          : K_EUL2;
+    s.stream = (hipStream_t)hip_stream;
+    const size_t state = (size_t)s.nv * d->nx * d->ny * sizeof(double);
+    uint8_t* ws = (uint8_t*)ptr;
+    s.ctrl = (Ctrl*)ws;
+    s.U1 = (double*)(ws + align256(sizeof(Ctrl)));
+    s.U2 = (double*)(ws + align256(sizeof(Ctrl)) + align256(state));
+    s.parity = 0;
+    s.slots = wcnst_wave_slots();
+    {
+        const int strips = (d->nx + TX - 1) / TX, rows = d->ny;
+        s.ty = d->ndim == 2 ? wcnst_auto_rows(&strips, &rows, 1, s.slots) : 35;
+    }
+    wcnst_make_params(d, &s.P);
+    const bool timed = std::isfinite(t_final);
+
+    // a fresh solve from t = 0: the control block is reset by a kernel
+    hipLaunchKernelGGL(ctrl_init, dim3(1), dim3(64), 0, s.stream, s.ctrl, 0.0, 0LL);
+    hipLaunchKernelGGL(ctrl_open, dim3(1), dim3(64), 0, s.stream, s.ctrl, s.parity);
+    launch_wavespeed(&s, U);
+    HIP_TRY(hipGetLastError());
+    int64_t launched = 0, chunk = 4;
+    Ctrl c;
+    while (launched < max_steps) {
+        const int64_t k = std::min(chunk, max_steps - launched);
+        for (int64_t i = 0; i < k; ++i) launch_step(&s, U, t_final, cfl, 0.0);
+        launched += k;
+        HIP_TRY(hipGetLastError());
+        if (!timed) continue;
+        st = read_ctrl(&s, &c);
+        if (st) return st;
+        if (c.status != 0 || c.done) break;
+        const StepRec& r = newest(c);
+        const double dt = c.rec[0].step >= c.rec[1].step ? c.rec[1].dt : c.rec[0].dt;
+        int64_t est = 8;
+        if (dt > 0.0 && std::isfinite(dt)) est = (int64_t)std::ceil((t_final - r.t) / dt) + 1;
+        chunk = std::max<int64_t>(1, std::min<int64_t>(est, 512));
+    }
+    st = read_ctrl(&s, &c);
+    if (st) return st;
+    const StepRec& r = newest(c);
+    if (t_out) *t_out = r.t;
+    if (steps_out) *steps_out = r.step;
+    if (c.status != 0) {
+        const long long stg = c.bad_key == ~0ull ? -1 : (long long)(c.bad_key >> 36);
+        const long long cell = c.bad_key == ~0ull ? -1 : (long long)(c.bad_key & ((1ull << 36) - 1));
+        return fail(WCNST_E_NONPHYSICAL, "non-physical state at global stage %lld, cell %lld", stg, cell);
+    }
+    if (timed && !(t_final - r.t <= 1e-12 * t_final))
+        return fail(WCNST_E_MAX_STEPS, "t_final not reached in %lld steps (t = %.17g)", (long long)max_steps, r.t);
     return WCNST_OK;
 }
 

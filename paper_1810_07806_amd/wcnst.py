@@ -29,7 +29,7 @@ EXPORTS = ("wcnst_desc_init", "wcnst_workspace_size", "wcnst_create", "wcnst_rhs
            "wcnst_batch_destroy",
            "wcnst_pool_workspace_size", "wcnst_pool_create", "wcnst_pool_admit", "wcnst_pool_tick",
            "wcnst_pool_result", "wcnst_pool_release", "wcnst_pool_set_tuning", "wcnst_pool_tick_split",
-           "wcnst_pool_tick_ms", "wcnst_pool_destroy")
+           "wcnst_pool_tick_ms", "wcnst_pool_destroy", "wcnst_solve_noalloc")
 
 
 class WcnstError(RuntimeError):
@@ -104,6 +104,7 @@ def lib(path: str | None = None):
     L.wcnst_pool_tick_split.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]
     L.wcnst_pool_tick_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.wcnst_pool_destroy.argtypes = [vp]
+    L.wcnst_solve_noalloc.argtypes = [D, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int64, dp, i64p]
     for name in EXPORTS:
         if name != "wcnst_last_error":
             getattr(L, name).restype = ctypes.c_int32
@@ -169,6 +170,26 @@ def flag_count(desc: dict) -> int:
         return nv * _nfaces_1d(desc) * 2
     ny = int(desc["ny"])
     return nv * ny * (nx + 3) * 2 + nv * nx * (ny + 3) * 2
+
+
+def solve_noalloc(desc: dict, U, t_final: float = math.inf, cfl: float = 0.5, max_steps: int = 1 << 62,
+                  stream=None):
+    """wcnst_solve_noalloc: solve U (a contiguous float64 CUDA tensor of
+    nvar * ny * nx values) in place from t = 0 with the library's static
+    scratch (no workspace).  Returns (t, steps); raises WcnstError."""
+    import torch
+    if not (isinstance(U, torch.Tensor) and U.is_cuda and U.dtype == torch.float64 and U.is_contiguous()):
+        raise TypeError("state must be a contiguous float64 CUDA tensor")
+    ny = int(desc.get("ny", 1)) if int(desc.get("ndim", 1)) == 2 else 1
+    if U.numel() != nvar(desc) * ny * int(desc["nx"]):
+        raise ValueError("state size does not match the descriptor")
+    d = make_desc(desc)
+    st = stream if stream is not None else torch.cuda.current_stream(U.device)
+    t = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib().wcnst_solve_noalloc(ctypes.byref(d), ctypes.c_void_p(st.cuda_stream), ctypes.c_void_p(U.data_ptr()),
+                                     float(t_final), float(cfl), int(max_steps), ctypes.byref(t), ctypes.byref(n)))
+    return t.value, n.value
 
 
 class Solver:

@@ -121,3 +121,16 @@ def test_batches_and_pools_refuse_the_z_weights():
     assert L.wcnst_pool_create(ctypes.byref(descs[1]), 4, None, ctypes.addressof(buf), 1 << 16,
                                ctypes.byref(h)) == wc.E_INVALID_ARG
     assert b"WCNS-Z" in L.wcnst_last_error()
+
+
+def test_noalloc_solve_refuses_grids_beyond_its_scratch():
+    """wcnst_solve_noalloc checks the grid against its static scratch before
+    any device work: 1024 x 1024 2D Euler needs 2 x 32 MiB + 256 bytes,
+    beyond the 64 MiB limit; a bad descriptor is refused the same way."""
+    wc, L = _lib()
+    d = wc.make_desc(dict(ndim=2, system="euler", nx=1024, ny=1024))
+    U = ctypes.c_void_p(16)  # never dereferenced: the call fails first
+    assert L.wcnst_solve_noalloc(ctypes.byref(d), None, U, 1.0, 0.5, 1, None, None) == wc.E_INVALID_ARG
+    assert b"scratch" in L.wcnst_last_error()
+    bad = wc.make_desc(dict(ndim=1, system="euler", nx=4))
+    assert L.wcnst_solve_noalloc(ctypes.byref(bad), None, U, 1.0, 0.5, 1, None, None) == wc.E_INVALID_ARG
