@@ -11,7 +11,10 @@ problem (K = 200 by default, the full fixed-step run).
 Prints one JSON line.  `roofline` prices the stage kernel against the FP64
 vector peak with the algorithmic flop count per stage-cell-update (see
 `flops_per_stage_cell`); `cpu_baseline` times the CPU oracle on one full
-SSP-RK3 step of the same grid on the host cores.
+SSP-RK3 step of the same grid on the host cores.  The default line also
+carries the two systems workloads as sub-records, `tubes` and `serve`
+(below), each with its per-solve comparison on the same GPU (leave them out
+with `--no-systems`).
 
 `--workload serve`: a Poisson stream of mixed requests (70 % 1D tubes with
 N in [512, 16384] to t = 0.15, 30 % 2D random four-quadrant problems of
@@ -268,7 +271,7 @@ def bench_tubes(args):
     if not args.no_cpu_baseline:
         idx = np.random.default_rng(seed + 2).choice(count, size=min(64, count), replace=False)
         rec["cpu_baseline"] = cpu_baseline_tubes(items, idx, steps=args.cpu_steps)
-    print(json.dumps(rec), flush=True)
+    return rec
 
 
 def bench_serve(args):
@@ -347,7 +350,7 @@ def bench_serve(args):
                       "stage_cell_updates_per_s": w / ps_busy},
         "sampled_results_bitwise_equal": bool(same),
     }
-    print(json.dumps(rec), flush=True)
+    return rec
 
 
 def bench_copy(args):
@@ -384,6 +387,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--n", type=int, default=N_SIDE, help="grid side (default: the 2048^2 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-systems", action="store_true",
+                    help="default workload only: leave out the tubes and serve sub-records")
     ap.add_argument("--rows", type=int, default=0, help="rows per 2D segment (0: library default)")
     ap.add_argument("--count", type=int, default=4096, help="tubes: instances")
     ap.add_argument("--seed", type=int, default=0, help="tubes: generator seed")
@@ -407,11 +412,13 @@ def main():
         return bench_copy(args)
     if args.workload == "serve":
         args.count = 80 if args.count == 4096 else args.count
-        return bench_serve(args)
+        print(json.dumps(bench_serve(args)), flush=True)
+        return
     if args.workload == "tubes":
         args.steps = 1 if args.steps is None else args.steps
         args.warmup = 1 if args.warmup is None else args.warmup
-        return bench_tubes(args)
+        print(json.dumps(bench_tubes(args)), flush=True)
+        return
     args.steps = 200 if args.steps is None else args.steps
     args.warmup = 3 if args.warmup is None else args.warmup
 
@@ -477,7 +484,23 @@ def main():
     }
     if not args.no_cpu_baseline and args.n == N_SIDE:
         rec["cpu_baseline"] = cpu_baseline()
+    if not args.no_systems and args.n == N_SIDE:
+        # the two systems workloads on the same GPU, each beside its
+        # per-solve comparison: the batched shock tubes and the served mix
+        rec["tubes"] = systems_record(bench_tubes, args, steps=1, warmup=1, count=4096)
+        rec["serve"] = systems_record(bench_serve, args, steps=1, warmup=1, count=80)
     print(json.dumps(rec), flush=True)
+
+
+def systems_record(fn, args, steps, warmup, count):
+    """One systems workload as a sub-record of the default line (its own
+    step counts; the per-solve comparison and CPU baseline inside)."""
+    sub = argparse.Namespace(**vars(args))
+    sub.steps, sub.warmup, sub.count = steps, warmup, count
+    rec = fn(sub)
+    for k in ("n_gpus", "steps", "warmup", "higher_is_better", "scaling", "vs_baseline", "dtype"):
+        rec.pop(k, None)
+    return rec
 
 
 if __name__ == "__main__":
