@@ -43,6 +43,7 @@ struct wcnst_batch {
     bool general = false;       // some instance has reflecting / fixed sides
     // device (caller's workspace)
     ReqGrid* d_req = nullptr;
+    int* d_map = nullptr;  // table row of every block of a stage launch
     uint8_t* d_ctrl = nullptr;
     size_t ctrl_bytes = 0;
     double* U1 = nullptr;
@@ -86,11 +87,14 @@ static void reap_retired(wcnst_batch* b, long long done)
     b->retired.resize(keep);
 }
 
-static size_t batch_layout(int n, long long total, size_t* o_req, size_t* o_ctrl, size_t* o_u1, size_t* o_u2)
+static size_t batch_layout(int n, long long total, long long strips, size_t* o_req, size_t* o_map, size_t* o_ctrl,
+                           size_t* o_u1, size_t* o_u2)
 {
     size_t o = 0;
     *o_req = o;
     o = wcnst_align256(o + sizeof(ReqGrid) * (size_t)n);
+    *o_map = o;
+    o = wcnst_align256(o + sizeof(int) * (size_t)strips);
     *o_ctrl = o;
     o = wcnst_align256(o + wcnst_align256(wcnst_ctrl_bytes()) * (size_t)n);
     *o_u1 = o;
@@ -110,11 +114,12 @@ wcnst_status wcnst_check_same_scheme(const wcnst_desc& a, const wcnst_desc& d)
     return WCNST_OK;
 }
 
-static wcnst_status batch_check(const wcnst_desc* descs, int32_t n, long long* total, std::vector<long long>* offs)
+static wcnst_status batch_check(const wcnst_desc* descs, int32_t n, long long* total, std::vector<long long>* offs,
+                                long long* strips)
 {
     if (!descs || n < 1) return wcnst_fail(WCNST_E_INVALID_ARG, "need at least one descriptor");
     const wcnst_desc& a = descs[0];
-    long long off = 0;
+    long long off = 0, nstr = 0;
     if (offs) offs->assign((size_t)n + 1, 0);
     for (int i = 0; i < n; ++i) {
         const wcnst_desc& d = descs[i];
@@ -130,20 +135,22 @@ static wcnst_status batch_check(const wcnst_desc* descs, int32_t n, long long* t
             return wcnst_fail(WCNST_E_INVALID_ARG, "descriptor %d: scheme parameters differ from descriptor 0", i);
         if (offs) (*offs)[i] = off;
         off += ((long long)NV * d.nx + 63) / 64 * 64;  // 512-byte aligned instances
+        nstr += (d.nx + TX - 1) / TX;
     }
     if (offs) (*offs)[n] = off;
     if (total) *total = off;
+    if (strips) *strips = nstr;
     return WCNST_OK;
 }
 
 extern "C" wcnst_status wcnst_batch_workspace_size(const wcnst_desc* descs, int32_t n, size_t* bytes)
 {
-    long long total = 0;
-    wcnst_status st = batch_check(descs, n, &total, nullptr);
+    long long total = 0, strips = 0;
+    wcnst_status st = batch_check(descs, n, &total, nullptr, &strips);
     if (st) return st;
     if (!bytes) return wcnst_fail(WCNST_E_INVALID_ARG, "null size pointer");
-    size_t a, b, c, d;
-    *bytes = batch_layout(n, total, &a, &b, &c, &d);
+    size_t a, m, b, c, d;
+    *bytes = batch_layout(n, total, strips, &a, &m, &b, &c, &d);
     return WCNST_OK;
 }
 
@@ -152,13 +159,13 @@ extern "C" wcnst_status wcnst_batch_destroy(wcnst_batch* b);
 extern "C" wcnst_status wcnst_batch_create(const wcnst_desc* descs, int32_t n, void* hip_stream, void* workspace,
                                            size_t ws_bytes, wcnst_batch** out)
 {
-    long long total = 0;
+    long long total = 0, strips = 0;
     std::vector<long long> offs;
-    wcnst_status st = batch_check(descs, n, &total, &offs);
+    wcnst_status st = batch_check(descs, n, &total, &offs, &strips);
     if (st) return st;
     if (!out) return wcnst_fail(WCNST_E_INVALID_ARG, "null output handle");
-    size_t o_req, o_ctrl, o_u1, o_u2;
-    const size_t need = batch_layout(n, total, &o_req, &o_ctrl, &o_u1, &o_u2);
+    size_t o_req, o_map, o_ctrl, o_u1, o_u2;
+    const size_t need = batch_layout(n, total, strips, &o_req, &o_map, &o_ctrl, &o_u1, &o_u2);
     if (!workspace || ws_bytes < need)
         return wcnst_fail(WCNST_E_INVALID_ARG, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
     if (((uintptr_t)workspace & 255u) != 0) return wcnst_fail(WCNST_E_INVALID_ARG, "workspace not 256-byte aligned");
@@ -172,6 +179,7 @@ extern "C" wcnst_status wcnst_batch_create(const wcnst_desc* descs, int32_t n, v
     b->stream = (hipStream_t)hip_stream;
     uint8_t* ws = (uint8_t*)workspace;
     b->d_req = (ReqGrid*)(ws + o_req);
+    b->d_map = (int*)(ws + o_map);
     b->d_ctrl = ws + o_ctrl;
     b->ctrl_bytes = wcnst_align256(wcnst_ctrl_bytes());
     b->U1 = (double*)(ws + o_u1);
@@ -239,7 +247,8 @@ static wcnst_status run_tick(wcnst_batch* b, int nreq, int blocks, int steps, bo
     if (steps != b->steps_per_tick) {
         for (int s = 0; s < steps; ++s)
             for (int stage = 0; stage < 3; ++stage)
-                WCNST_HIP_TRY(wcnst_launch_multi(&b->d0, 1, b->d_req, nreq, blocks, stage, s & 1, 0, b->general, b->stream));
+                WCNST_HIP_TRY(wcnst_launch_multi(&b->d0, 1, b->d_req, b->d_map, nreq, blocks, stage, s & 1, 0, b->general,
+                                                 b->stream));
         return WCNST_OK;
     }
     if (!b->exec || table_changed) {
@@ -252,7 +261,8 @@ static wcnst_status run_tick(wcnst_batch* b, int nreq, int blocks, int steps, bo
         hipError_t le = hipSuccess;
         for (int s = 0; s < steps && le == hipSuccess; ++s)
             for (int stage = 0; stage < 3 && le == hipSuccess; ++stage)
-                le = wcnst_launch_multi(&b->d0, 1, b->d_req, nreq, blocks, stage, s & 1, 0, b->general, b->cap);
+                le = wcnst_launch_multi(&b->d0, 1, b->d_req, b->d_map, nreq, blocks, stage, s & 1, 0, b->general,
+                                        b->cap);
         hipError_t ce = hipStreamEndCapture(b->cap, &g);
         if (le != hipSuccess || ce != hipSuccess)
             return wcnst_fail(WCNST_E_HIP, "graph capture failed: %s / %s", hipGetErrorString(le),
@@ -323,6 +333,7 @@ extern "C" wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const doubl
     WCNST_HIP_TRY(hipMemcpyAsync(b->d_req, b->h_req, sizeof(ReqGrid) * (size_t)n, hipMemcpyHostToDevice, b->stream));
     WCNST_HIP_TRY(hipEventRecord(b->ev0, b->stream));
     WCNST_HIP_TRY(wcnst_launch_multi_init(1, b->d_req, n, b->stream));
+    WCNST_HIP_TRY(wcnst_launch_block_map(b->d_req, n, b->d_map, b->stream));
 
     // Ticks are pipelined: tick k+1 is queued before the host has looked at
     // tick k, so the set of running instances is decided from the control
@@ -351,6 +362,7 @@ extern "C" wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const doubl
             }
             WCNST_HIP_TRY(hipMemcpyAsync(b->d_req, tab, sizeof(ReqGrid) * active.size(), hipMemcpyHostToDevice,
                                          b->stream));
+            WCNST_HIP_TRY(wcnst_launch_block_map(b->d_req, (int)active.size(), b->d_map, b->stream));
             uploads += 1;
         }
         wcnst_status st = run_tick(b, (int)active.size(), blocks, steps, changed, k);

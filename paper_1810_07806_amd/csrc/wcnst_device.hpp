@@ -115,6 +115,7 @@ struct Params {
     double fixed_y[2][4];
     double gravity;        // 2D Euler body force in +y
     double eps_z;          // WCNS-Z epsilon
+    double teno_smooth;    // tau / min(beta + eps) below which every TENO candidate is kept
     int z_q;               // WCNS-Z power
 };
 
@@ -397,13 +398,21 @@ WCNST_HD double interp_side(double c, double D10, double D11, double D12, double
         } else {
             // Eq. (16); Eqs. (17)-(18) as gamma_k < C_T * sum(gamma)
             const double tau = fabs(b0 - b2);
-            const int q = SCHEME == SCH_TENO ? 6 : P.q;
-            const double g0 = pow_q(fma(tau, approx_rcp(b0 + P.eps_teno), P.C), q);
-            const double g1 = pow_q(fma(tau, approx_rcp(b1 + P.eps_teno), P.C), q);
-            const double g2 = pow_q(fma(tau, approx_rcp(b2 + P.eps_teno), P.C), q);
-            const double thr = P.CT * (g0 + g1 + g2);
-            const bool k0 = !(g0 < thr), k1 = !(g1 < thr), k2 = !(g2 < thr);
-            mask = (unsigned)k0 | ((unsigned)k1 << 1) | ((unsigned)k2 << 2);
+            const double e0 = b0 + P.eps_teno, e1 = b1 + P.eps_teno, e2 = b2 + P.eps_teno;
+            // Smooth data keep every candidate without the measure: with
+            // tau <= t e_min each C + tau/e_k lies in [C, C + t], so
+            // chi_k >= C^q / (3 (C + t)^q), which P.teno_smooth (t) keeps
+            // above C_T by a margin far beyond rounding.
+            mask = 7u;
+            if (!(tau <= P.teno_smooth * fmin(fmin(e0, e1), e2))) {
+                const int q = SCHEME == SCH_TENO ? 6 : P.q;
+                const double g0 = pow_q(fma(tau, approx_rcp(e0), P.C), q);
+                const double g1 = pow_q(fma(tau, approx_rcp(e1), P.C), q);
+                const double g2 = pow_q(fma(tau, approx_rcp(e2), P.C), q);
+                const double thr = P.CT * (g0 + g1 + g2);
+                const bool k0 = !(g0 < thr), k1 = !(g1 < thr), k2 = !(g2 < thr);
+                mask = (unsigned)k0 | ((unsigned)k1 << 1) | ((unsigned)k2 << 2);
+            }
             // Eq. (19): d_k delta_k / sum_m d_m delta_m, the exact quotient
             // for each of the seven patterns
 #if defined(__HIP_DEVICE_COMPILE__)

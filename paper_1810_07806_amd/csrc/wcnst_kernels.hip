@@ -247,10 +247,13 @@ sweep1d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
     sweep1d_block<SYS, NV, FLUX, SCHEME, CHAR, MODE, DIFF>(U, Un, out, flags, ctrl, P, A, (int)blockIdx.x);
 }
 
-// The table row of block b: the grid r with blk0[r] <= b < blk0[r+1]
-// (binary search, uniform per block).
-__device__ __forceinline__ ReqGrid load_request(const ReqGrid* __restrict__ reqs, int nreq, int b)
+// The table row of block b: the grid r with blk0[r] <= b < blk0[r+1],
+// from the block map when the launch has one (one load), else by binary
+// search over the table (uniform per block).
+__device__ __forceinline__ ReqGrid load_request(const ReqGrid* __restrict__ reqs, const int* __restrict__ map,
+                                                int nreq, int b)
 {
+    if (map) return load_table_entry(&reqs[load_table_entry(&map[b])]);
     int lo = 0, hi = nreq - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -258,6 +261,15 @@ __device__ __forceinline__ ReqGrid load_request(const ReqGrid* __restrict__ reqs
         else hi = mid - 1;
     }
     return load_table_entry(&reqs[lo]);
+}
+
+// Block map of a 1D ReqGrid table: block r writes map[blk0 + k] = r for the
+// nstrips blocks of grid r.
+__global__ void __launch_bounds__(256) block_map_fill(const ReqGrid* __restrict__ reqs, int* __restrict__ map)
+{
+    const int r = (int)blockIdx.x;
+    const int b0 = reqs[r].blk0, n = reqs[r].nstrips;
+    for (int k = (int)threadIdx.x; k < n; k += (int)blockDim.x) map[b0 + k] = r;
 }
 
 __device__ __forceinline__ StageArgs request_stage(const ReqGrid& R, int stage, int tick_step)
@@ -275,10 +287,10 @@ __device__ __forceinline__ StageArgs request_stage(const ReqGrid& R, int stage, 
 // block), each with its own parameters, buffers, control block and parity.
 template <int FLUX, int SCHEME, bool CHAR, bool GB>
 __global__ void __launch_bounds__(WAVE)
-sweep1d_multi(const ReqGrid* __restrict__ reqs, int nreq, int stage, int tick_step)
+sweep1d_multi(const ReqGrid* __restrict__ reqs, const int* __restrict__ map, int nreq, int stage, int tick_step)
 {
     const int b = (int)blockIdx.x;
-    const ReqGrid R = load_request(reqs, nreq, b);
+    const ReqGrid R = load_request(reqs, map, nreq, b);
     const StageArgs A = request_stage(R, stage, tick_step);
     const double* in = stage == 0 ? R.U : (stage == 1 ? R.U1 : R.U2);
     double* out = stage == 0 ? R.U1 : (stage == 1 ? R.U2 : R.U);
@@ -541,7 +553,7 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2)
 sweep2d_multi(const ReqGrid* __restrict__ reqs, int nreq, int stage, int tick_step, int ty)
 {
     const int b = (int)blockIdx.x;
-    const ReqGrid R = load_request(reqs, nreq, b);
+    const ReqGrid R = load_request(reqs, nullptr, nreq, b);
     const Params& P = R.P;
     const int local = b - R.blk0;
     const StageArgs A = request_stage(R, stage, tick_step);
@@ -826,6 +838,10 @@ void wcnst_make_params(const wcnst_desc* d, Params* out)
     P.gravity = d->gravity;
     P.z_q = d->z_q;
     P.eps_z = d->eps_z;
+    // TENO: tau / min(beta_k + eps) up to which every chi_k stays >= C_T:
+    // chi_k >= C^q / (3 (C + t)^q) >= C_T for t <= C ((3 C_T)^(-1/q) - 1);
+    // nine tenths of that bound
+    P.teno_smooth = 0.9 * d->C * (std::pow(3.0 * d->CT, -1.0 / d->q) - 1.0);
     *out = P;
 }
 
@@ -1413,8 +1429,8 @@ hipError_t wcnst_launch_multi_init(int ndim, const void* reqs, int nreq, hipStre
 }
 
 template <int NDIM, int FLUX, int SCHEME, bool CHAR>
-static void launch_multi_t(const ReqGrid* reqs, int nreq, int nblocks, int stage, int tick_step, int ty,
-                           bool general, hipStream_t st)
+static void launch_multi_t(const ReqGrid* reqs, const int* map, int nreq, int nblocks, int stage, int tick_step,
+                           int ty, bool general, hipStream_t st)
 {
     if constexpr (NDIM == 2) {
         if (general)
@@ -1424,52 +1440,63 @@ static void launch_multi_t(const ReqGrid* reqs, int nreq, int nblocks, int stage
             hipLaunchKernelGGL((sweep2d_multi<4, FLUX, SCHEME, CHAR, false>), dim3(nblocks), dim3(WAVE), 0, st, reqs,
                                nreq, stage, tick_step, ty);
     } else if (general) {
-        hipLaunchKernelGGL((sweep1d_multi<FLUX, SCHEME, CHAR, true>), dim3(nblocks), dim3(WAVE), 0, st, reqs, nreq,
-                           stage, tick_step);
+        hipLaunchKernelGGL((sweep1d_multi<FLUX, SCHEME, CHAR, true>), dim3(nblocks), dim3(WAVE), 0, st, reqs, map,
+                           nreq, stage, tick_step);
     } else {
-        hipLaunchKernelGGL((sweep1d_multi<FLUX, SCHEME, CHAR, false>), dim3(nblocks), dim3(WAVE), 0, st, reqs, nreq,
-                           stage, tick_step);
+        hipLaunchKernelGGL((sweep1d_multi<FLUX, SCHEME, CHAR, false>), dim3(nblocks), dim3(WAVE), 0, st, reqs, map,
+                           nreq, stage, tick_step);
     }
 }
 
 template <int NDIM, int FLUX, bool CHAR>
-static void launch_multi_s(const wcnst_desc* d, const ReqGrid* reqs, int nreq, int nblocks, int stage,
+static void launch_multi_s(const wcnst_desc* d, const ReqGrid* reqs, const int* map, int nreq, int nblocks, int stage,
                            int tick_step, int ty, bool general, hipStream_t st)
 {
     switch (d->scheme) {
     case WCNST_LINEAR:
-        launch_multi_t<NDIM, FLUX, SCH_LINEAR, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, general, st);
+        launch_multi_t<NDIM, FLUX, SCH_LINEAR, CHAR>(reqs, map, nreq, nblocks, stage, tick_step, ty, general, st);
         break;
-    case WCNST_JS: launch_multi_t<NDIM, FLUX, SCH_JS, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, general, st); break;
+    case WCNST_JS:
+        launch_multi_t<NDIM, FLUX, SCH_JS, CHAR>(reqs, map, nreq, nblocks, stage, tick_step, ty, general, st);
+        break;
     default:
-        if (d->q == 6) launch_multi_t<NDIM, FLUX, SCH_TENO, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, general, st);
-        else launch_multi_t<NDIM, FLUX, SCH_TENO_Q, CHAR>(reqs, nreq, nblocks, stage, tick_step, ty, general, st);
+        if (d->q == 6)
+            launch_multi_t<NDIM, FLUX, SCH_TENO, CHAR>(reqs, map, nreq, nblocks, stage, tick_step, ty, general, st);
+        else
+            launch_multi_t<NDIM, FLUX, SCH_TENO_Q, CHAR>(reqs, map, nreq, nblocks, stage, tick_step, ty, general, st);
         break;
     }
 }
 
 template <int NDIM>
-static void launch_multi_d(const wcnst_desc* d, const ReqGrid* r, int nreq, int nblocks, int stage, int tick_step,
-                           int ty, bool general, hipStream_t st)
+static void launch_multi_d(const wcnst_desc* d, const ReqGrid* r, const int* map, int nreq, int nblocks, int stage,
+                           int tick_step, int ty, bool general, hipStream_t st)
 {
     if (d->flux == WCNST_LF) {
-        if (d->charwise) launch_multi_s<NDIM, FLUX_LF, true>(d, r, nreq, nblocks, stage, tick_step, ty, general, st);
-        else launch_multi_s<NDIM, FLUX_LF, false>(d, r, nreq, nblocks, stage, tick_step, ty, general, st);
+        if (d->charwise) launch_multi_s<NDIM, FLUX_LF, true>(d, r, map, nreq, nblocks, stage, tick_step, ty, general, st);
+        else launch_multi_s<NDIM, FLUX_LF, false>(d, r, map, nreq, nblocks, stage, tick_step, ty, general, st);
     } else if (d->flux == WCNST_VANLEER) {
-        if (d->charwise) launch_multi_s<NDIM, FLUX_VL, true>(d, r, nreq, nblocks, stage, tick_step, ty, general, st);
-        else launch_multi_s<NDIM, FLUX_VL, false>(d, r, nreq, nblocks, stage, tick_step, ty, general, st);
+        if (d->charwise) launch_multi_s<NDIM, FLUX_VL, true>(d, r, map, nreq, nblocks, stage, tick_step, ty, general, st);
+        else launch_multi_s<NDIM, FLUX_VL, false>(d, r, map, nreq, nblocks, stage, tick_step, ty, general, st);
     } else {
-        if (d->charwise) launch_multi_s<NDIM, FLUX_ROE, true>(d, r, nreq, nblocks, stage, tick_step, ty, general, st);
-        else launch_multi_s<NDIM, FLUX_ROE, false>(d, r, nreq, nblocks, stage, tick_step, ty, general, st);
+        if (d->charwise) launch_multi_s<NDIM, FLUX_ROE, true>(d, r, map, nreq, nblocks, stage, tick_step, ty, general, st);
+        else launch_multi_s<NDIM, FLUX_ROE, false>(d, r, map, nreq, nblocks, stage, tick_step, ty, general, st);
     }
 }
 
-hipError_t wcnst_launch_multi(const wcnst_desc* d, int ndim, const void* reqs, int nreq, int nblocks, int stage,
-                              int tick_step, int ty, bool general, hipStream_t st)
+hipError_t wcnst_launch_multi(const wcnst_desc* d, int ndim, const void* reqs, const int* map, int nreq, int nblocks,
+                              int stage, int tick_step, int ty, bool general, hipStream_t st)
 {
     const ReqGrid* r = (const ReqGrid*)reqs;
-    if (ndim == 2) launch_multi_d<2>(d, r, nreq, nblocks, stage, tick_step, ty, general, st);
-    else launch_multi_d<1>(d, r, nreq, nblocks, stage, tick_step, ty, general, st);
+    if (ndim == 2) launch_multi_d<2>(d, r, nullptr, nreq, nblocks, stage, tick_step, ty, general, st);
+    else launch_multi_d<1>(d, r, map, nreq, nblocks, stage, tick_step, ty, general, st);
+    return hipGetLastError();
+}
+
+hipError_t wcnst_launch_block_map(const void* reqs, int nreq, int* map, hipStream_t st)
+{
+    if (nreq <= 0) return hipSuccess;
+    hipLaunchKernelGGL(block_map_fill, dim3(nreq), dim3(256), 0, st, (const ReqGrid*)reqs, map);
     return hipGetLastError();
 }
 

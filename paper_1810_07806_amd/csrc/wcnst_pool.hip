@@ -229,8 +229,8 @@ static wcnst_status issue_dim(wcnst_pool* p, int ndim, const std::vector<int>& a
     for (int64_t s = 0; s < steps; ++s)
         for (int stage = 0; stage < 3; ++stage)
             WCNST_HIP_TRY(
-                wcnst_launch_multi(&p->scheme, ndim, p->d_req[ndim - 1], n, blocks, stage, (int)(s & 1), ty, general,
-                                   st));
+                wcnst_launch_multi(&p->scheme, ndim, p->d_req[ndim - 1], nullptr, n, blocks, stage, (int)(s & 1), ty,
+                                   general, st));
     return WCNST_OK;
 }
 

@@ -6,6 +6,8 @@
 
 #include <stdint.h>
 
+#include <cmath>
+
 #include <vector>
 
 #include "wcnst_device.hpp"
@@ -159,6 +161,8 @@ int hc_rhs(int ndim, int sys, int flux, int nx, int ny, double dx, double dy, in
 {
     Params P{};
     P.z_q = z_q; P.eps_z = eps_z;
+    // as the library's parameters: the smooth-stencil bound of the cut test
+    P.teno_smooth = 0.9 * C * (std::pow(3.0 * CT, -1.0 / q) - 1.0);
     P.CT = CT; P.C = C; P.eps_teno = eps_teno; P.eps_js = eps_js;
     P.gamma = gamma; P.adv = adv; P.dx = dx; P.dy = dy;
     P.q = q; P.charwise = charwise; P.bc_x = bc_x; P.bc_y = bc_y;
