@@ -186,7 +186,7 @@ def bench_tubes(args):
 
     torch.cuda.set_device(0)
     count, seed, t_final = args.count, args.seed, 0.15
-    items = W.shock_tube_batch(count=count, seed=seed, t_final=t_final)
+    items = W.shock_tube_batch(count=count, seed=seed, t_final=t_final, n_min=args.n_min, n_max=args.n_max)
     descs = [d for d, _ in items]
     b = Batch(descs)
     U0 = b.pack([U for _, U in items])
@@ -194,11 +194,14 @@ def bench_tubes(args):
     log(f"tubes: {count} instances, {int(sum(d['nx'] for d in descs))} cells")
     if args.steps_per_tick:
         b.set_tuning(args.steps_per_tick)
-        tune = dict(steps_per_tick=args.steps_per_tick, cached=False, table=[])
+        b.set_persist(args.switch_strips, args.persist_waves, args.persist_group)
+        tune = dict(steps_per_tick=args.steps_per_tick, switch_strips=args.switch_strips,
+                    waves_per_group=args.persist_waves, instances_per_group=args.persist_group, cached=False, table=[])
     else:
         tune = autotune.tune_batch(b, U0, t_final, cfl=0.5, cache=args.tune_cache,
                                    device_name=torch.cuda.get_device_name(0), log=log)
-    log(f"tuning: steps/tick={tune['steps_per_tick']}")
+    log(f"tuning: steps/tick={tune['steps_per_tick']} persistent switch={tune['switch_strips']} strips "
+        f"({tune['waves_per_group']} waves x {tune['instances_per_group']} per workgroup)")
     for _ in range(args.warmup):
         Ug.copy_(U0)
         b.solve(Ug, t_final * 0.05, cfl=0.5)
@@ -255,13 +258,16 @@ def bench_tubes(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded random shock tubes)",
-        "config": {"workload": f"batched 1D Euler shock tubes: {count} instances, N log-uniform in [256, 8192], "
+        "config": {"workload": f"batched 1D Euler shock tubes: {count} instances, N log-uniform in "
+                               f"[{args.n_min}, {args.n_max}], "
                                f"t = {t_final}, WCNS-T TENO C_T=1e-5, Roe, MND, SSP-RK3 CFL 0.5, seed {seed}",
                    "instances": count, "cells": int(sum(d["nx"] for d in descs)),
                    "stage_cell_updates_per_solve": units_per_solve, "failed_instances": failed,
                    "kernel_ms_avg": avg_kernel_s * 1e3, "steps_per_tick": tune["steps_per_tick"],
                    "tuning_cached": tune.get("cached", False), "ticks": stats["ticks"],
-                   "graphs_captured": stats["graphs"]},
+                   "graphs_captured": stats["graphs"], "persistent_switch_strips": tune["switch_strips"],
+                   "persistent_shape": [tune["waves_per_group"], tune["instances_per_group"]],
+                   "persistent_instances": stats["persist_instances"]},
         "per_solve": {"value": ps_units / ps_wall, "unit": "stage-cell-updates/s", "instances": int(len(sub)),
                       "wall_s": ps_wall, "speedup_batched": (units / wall) / (ps_units / ps_wall)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
@@ -394,6 +400,12 @@ def main():
     ap.add_argument("--seed", type=int, default=0, help="tubes: generator seed")
     ap.add_argument("--steps-per-tick", type=int, default=0, help="tubes: fixed tick length (default: autotune)")
     ap.add_argument("--tune-cache", default=None, help="tubes: JSON autotune cache")
+    ap.add_argument("--n-min", type=int, default=256, help="tubes: smallest N")
+    ap.add_argument("--n-max", type=int, default=8192, help="tubes: largest N")
+    ap.add_argument("--switch-strips", type=int, default=0,
+                    help="tubes with --steps-per-tick: persistent finish below this many running strips")
+    ap.add_argument("--persist-waves", type=int, default=16, help="tubes: waves per persistent workgroup")
+    ap.add_argument("--persist-group", type=int, default=1, help="tubes: instances per persistent workgroup")
     ap.add_argument("--per-solve", type=int, default=32, help="tubes: instances timed on the per-solve path")
     ap.add_argument("--cpu-steps", type=int, default=200, help="tubes: oracle steps per sampled tube")
     ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / measured capacity")

@@ -254,12 +254,24 @@ wcnst_status wcnst_batch_bad_cells(const wcnst_batch* b, int64_t* bad_stage, int
  * instances leave the launch table.  Never changes results. */
 wcnst_status wcnst_batch_set_tuning(wcnst_batch* b, int32_t steps_per_tick);
 
+/* Persistent finish (Sec. 2 arithmetic unchanged): once the instances still
+ * running hold at most switch_strips strips of 61 cells, the batch stops
+ * issuing ticks and runs them to their final times in one persistent launch:
+ * each workgroup of waves_per_group wavefronts (1..16) owns
+ * instances_per_group instances (1..8), keeps their step control in LDS and
+ * shares their strips among its waves stage by stage, ordered by workgroup
+ * barriers only (no workgroup waits for another).  switch_strips = 0 (the
+ * default) keeps ticks to the end.  Never changes results. */
+wcnst_status wcnst_batch_set_persist(wcnst_batch* b, int32_t switch_strips, int32_t waves_per_group,
+                                     int32_t instances_per_group);
+
 /* Device time in milliseconds of the last wcnst_batch_solve, from its first
  * launch to the end of its last tick (HIP events on the batch's stream). */
 wcnst_status wcnst_batch_kernel_ms(const wcnst_batch* b, double* ms);
 
-/* Ticks of the last wcnst_batch_solve and graphs captured for them. */
-wcnst_status wcnst_batch_stats(const wcnst_batch* b, int32_t* ticks, int32_t* graphs);
+/* Ticks of the last wcnst_batch_solve, graphs captured for them, and the
+ * instances it finished in a persistent launch (all nullable). */
+wcnst_status wcnst_batch_stats(const wcnst_batch* b, int32_t* ticks, int32_t* graphs, int32_t* persist_instances);
 
 wcnst_status wcnst_batch_destroy(wcnst_batch* b);
 

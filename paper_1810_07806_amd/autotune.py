@@ -1,12 +1,27 @@
-"""Autotuner for the batched solver's tick length.
+"""Autotuner for the batched solver's launch decomposition.
 
-The tick length (steps between the host's retirement of finished instances
-from the launch table) never changes results, only time: short ticks retire
-finished instances sooner, long ticks replay one captured graph longer
-between host round trips.  Candidates are timed on a proxy of the real
-batch: the same instances run to a fraction of their final times.  Step
-counts scale with t_final, so the proxy keeps the relative lengths of the
-instances while costing a few percent of the real run.
+Three choices never change results, only time:
+
+* the tick length (steps between the host's retirement of finished
+  instances from the launch table): short ticks retire finished instances
+  sooner, long ticks replay one captured graph longer between host round
+  trips;
+* the switch to the persistent finish: once the running instances hold at
+  most `switch_strips` strips, one persistent launch runs them to their
+  final times with no kernel boundary between stages (0 = never);
+* the persistent launch's workgroup shape: waves per workgroup (which
+  share the strips of a stage) and instances per workgroup.
+
+Candidates are timed on a proxy of the real batch: the same instances run
+to a fraction of their final times.  Step counts scale with t_final, so the
+proxy keeps the relative lengths of the instances while costing a few
+percent of the real run.  The search is greedy: the tick length first
+(stage launches only), then the switch point at 16 waves x 1 instance, then
+the workgroup shape at the best switch point (skipped when stage launches
+to the end win).  A persistent winner is confirmed on a longer proxy
+against stage launches to the end: on the short one its share of the run
+(the tail) is larger than on the real run, and measured batches of shock
+tubes (N in [256, 8192] and in [64, 512]) ran slower with it.
 
 The winner can be cached in a JSON file keyed by device name and a
 signature of the batch (instance count, total cells, largest instance).
@@ -18,6 +33,8 @@ import os
 import time
 
 DEFAULT_TICKS = (16, 32, 64, 128, 256)
+DEFAULT_SWITCH = (0, 64, 256, 1024)
+DEFAULT_SHAPES = ((16, 1), (8, 1), (16, 2), (4, 4))
 
 
 def signature(descs, t_final) -> str:
@@ -34,37 +51,69 @@ def _load(path):
         return json.load(f)
 
 
+def _apply(batch, cfg):
+    batch.set_tuning(cfg["steps_per_tick"])
+    batch.set_persist(cfg["switch_strips"], cfg["waves_per_group"], cfg["instances_per_group"])
+
+
 def tune_batch(batch, Ug_init, t_final, cfl: float = 0.5, proxy: float = 0.05, ticks=DEFAULT_TICKS,
-               cache: str | None = None, device_name: str = "", log=None):
-    """Time every steps-per-tick candidate on the proxy run and set the
-    fastest on `batch`.  `Ug_init` (packed initial states) is not modified.
-    Returns dict(steps_per_tick, ms, table, cached)."""
+               switches=DEFAULT_SWITCH, shapes=DEFAULT_SHAPES, confirm: float = 0.25, cache: str | None = None,
+               device_name: str = "", log=None):
+    """Time the candidates on the proxy run and set the fastest on `batch`.
+    `Ug_init` (packed initial states) is not modified.  Returns dict(
+    steps_per_tick, switch_strips, waves_per_group, instances_per_group, ms,
+    table, cached)."""
     import numpy as np
     import torch
-    key = f"{device_name}|{signature(batch.descs, t_final)}|cfl={cfl}"
+    key = f"{device_name}|{signature(batch.descs, t_final)}|cfl={cfl}|persist"
     db = _load(cache)
     if key in db:
         best = db[key]
-        batch.set_tuning(best["steps_per_tick"])
+        _apply(batch, best)
         return dict(best, cached=True, table=[])
     tf = np.broadcast_to(np.asarray(t_final, dtype=float), (batch.n,)) * proxy
     U = torch.empty_like(Ug_init)
     table = []
-    for spt in ticks:
-        batch.set_tuning(spt)
+
+    def trial(cfg):
+        _apply(batch, cfg)
         U.copy_(Ug_init)
         torch.cuda.synchronize()
         batch.solve(U, tf, cfl=cfl)
-        ms = batch.kernel_ms()
-        table.append(dict(steps_per_tick=spt, ms=ms))
+        row = dict(cfg, ms=batch.kernel_ms(), proxy=float(tf.max() / max(1e-300, float(np.max(t_final)))))
+        table.append(row)
         if log:
-            log(f"tune steps/tick={spt}: {ms:.2f} ms")
-    best = min(table, key=lambda r: r["ms"])
-    batch.set_tuning(best["steps_per_tick"])
+            log("tune " + ", ".join(f"{k}={v}" for k, v in cfg.items()) + f": {row['ms']:.2f} ms")
+        return row
+
+    base = dict(steps_per_tick=ticks[0], switch_strips=0, waves_per_group=16, instances_per_group=1)
+    best = min([trial(dict(base, steps_per_tick=spt)) for spt in ticks], key=lambda r: r["ms"])
+    for sw in switches:
+        if sw > 0:
+            cfg = {k: best[k] for k in ("steps_per_tick", "waves_per_group", "instances_per_group")}
+            r = trial(dict(cfg, switch_strips=sw, waves_per_group=16, instances_per_group=1))
+            best = r if r["ms"] < best["ms"] else best
+    if best["switch_strips"] > 0:
+        for w, g in shapes:
+            if (w, g) != (best["waves_per_group"], best["instances_per_group"]):
+                cfg = {k: best[k] for k in ("steps_per_tick", "switch_strips")}
+                r = trial(dict(cfg, waves_per_group=w, instances_per_group=g))
+                best = r if r["ms"] < best["ms"] else best
+        # the short proxy favours the persistent finish (its tail is a larger
+        # share of the run): confirm against stage launches to the end on a
+        # proxy of `confirm` of the final times
+        tf_short = tf
+        tf = tf_short / proxy * confirm
+        ticks_only = trial(dict({k: best[k] for k in ("steps_per_tick", "waves_per_group", "instances_per_group")},
+                                switch_strips=0))
+        persistent = trial({k: best[k] for k in ("steps_per_tick", "switch_strips", "waves_per_group",
+                                                 "instances_per_group")})
+        best = persistent if persistent["ms"] < ticks_only["ms"] else ticks_only
+    best = {k: best[k] for k in ("steps_per_tick", "switch_strips", "waves_per_group", "instances_per_group", "ms")}
+    _apply(batch, best)
     if cache:
         db = _load(cache)
-        db[key] = dict(steps_per_tick=best["steps_per_tick"], ms=best["ms"], proxy=proxy,
-                       when=time.strftime("%Y-%m-%d %H:%M:%S"))
+        db[key] = dict(best, proxy=proxy, when=time.strftime("%Y-%m-%d %H:%M:%S"))
         os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
         with open(cache, "w") as f:
             json.dump(db, f, indent=1, sort_keys=True)

@@ -56,6 +56,12 @@ struct wcnst_batch {
     uint8_t* h_ctrl2 = nullptr;
     hipEvent_t ev_snap[2] = {nullptr, nullptr};
     int steps_per_tick = 64;  // even, so that a replayed tick keeps the parity pattern
+    // persistent finish: once the running instances hold at most
+    // persist_strips strips, one persistent launch (persist_waves waves per
+    // workgroup, persist_group instances each) runs them to their final
+    // times; 0 keeps stage launches to the end
+    int persist_strips = 0, persist_waves = 16, persist_group = 1;
+    int persist_instances = 0;  // instances the last solve finished in the persistent launch
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double kernel_ms = 0.0;
     int ticks = 0, graphs = 0;
@@ -218,6 +224,21 @@ extern "C" wcnst_status wcnst_batch_set_tuning(wcnst_batch* b, int32_t steps_per
     return WCNST_OK;
 }
 
+extern "C" wcnst_status wcnst_batch_set_persist(wcnst_batch* b, int32_t switch_strips, int32_t waves_per_group,
+                                                int32_t instances_per_group)
+{
+    if (!b) return wcnst_fail(WCNST_E_INVALID_ARG, "null handle");
+    if (switch_strips < 0) return wcnst_fail(WCNST_E_INVALID_ARG, "switch_strips must be >= 0");
+    if (waves_per_group < 1 || waves_per_group > 16)
+        return wcnst_fail(WCNST_E_INVALID_ARG, "waves_per_group must be in [1, 16]");
+    if (instances_per_group < 1 || instances_per_group > 8)
+        return wcnst_fail(WCNST_E_INVALID_ARG, "instances_per_group must be in [1, 8]");
+    b->persist_strips = switch_strips;
+    b->persist_waves = waves_per_group;
+    b->persist_group = instances_per_group;
+    return WCNST_OK;
+}
+
 extern "C" wcnst_status wcnst_batch_kernel_ms(const wcnst_batch* b, double* ms)
 {
     if (!b || !ms) return wcnst_fail(WCNST_E_INVALID_ARG, "null argument");
@@ -225,11 +246,13 @@ extern "C" wcnst_status wcnst_batch_kernel_ms(const wcnst_batch* b, double* ms)
     return WCNST_OK;
 }
 
-extern "C" wcnst_status wcnst_batch_stats(const wcnst_batch* b, int32_t* ticks, int32_t* graphs)
+extern "C" wcnst_status wcnst_batch_stats(const wcnst_batch* b, int32_t* ticks, int32_t* graphs,
+                                          int32_t* persist_instances)
 {
     if (!b) return wcnst_fail(WCNST_E_INVALID_ARG, "null handle");
     if (ticks) *ticks = b->ticks;
     if (graphs) *graphs = b->graphs;
+    if (persist_instances) *persist_instances = b->persist_instances;
     return WCNST_OK;
 }
 
@@ -311,6 +334,7 @@ extern "C" wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const doubl
     }
     b->ticks = 0;
     b->graphs = 0;
+    b->persist_instances = 0;
     // graphs of an earlier solve (one that stopped on an error may have
     // left work queued)
     WCNST_HIP_TRY(hipStreamSynchronize(b->stream));
@@ -394,6 +418,28 @@ extern "C" wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const doubl
             }
             changed = still.size() != active.size();
             active.swap(still);
+            long long strips = 0;
+            for (int i : active) strips += rows[(size_t)i].nstrips;
+            if (b->persist_strips > 0 && !active.empty() && strips <= b->persist_strips &&
+                launched < (long long)max_steps) {
+                // the rest in one persistent launch, after the ticks queued
+                // so far (same stream), from the table of the running ones
+                ReqGrid* tab = tabs[uploads & 1];
+                for (size_t j = 0; j < active.size(); ++j) {
+                    const int i = active[j];
+                    tab[j] = rows[(size_t)i];
+                    tab[j].blk0 = 0;
+                    tab[j].parity0 = parity[(size_t)i];
+                }
+                WCNST_HIP_TRY(hipMemcpyAsync(b->d_req, tab, sizeof(ReqGrid) * active.size(), hipMemcpyHostToDevice,
+                                             b->stream));
+                uploads += 1;
+                WCNST_HIP_TRY(wcnst_launch_persist(&b->d0, b->d_req, (int)active.size(), b->persist_group,
+                                                   b->persist_waves, (long long)max_steps - launched, b->general,
+                                                   b->stream));
+                b->persist_instances = (int)active.size();
+                break;
+            }
         }
         k += 1;
     }

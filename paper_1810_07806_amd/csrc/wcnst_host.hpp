@@ -34,6 +34,11 @@ hipError_t wcnst_launch_init_grid(const wcnst_desc* d, const double* U, void* ct
 // without one each block searches the table.
 hipError_t wcnst_launch_multi(const wcnst_desc* d, int ndim, const void* reqs, const int* map, int nreq, int nblocks,
                               int stage, int tick_step, int ty, bool general, hipStream_t st);
+// One persistent launch that runs the nreq 1D grids of a table to their
+// final times (or max_steps more steps): per_group grids per workgroup of
+// `waves` wavefronts (at most 8 and 16).
+hipError_t wcnst_launch_persist(const wcnst_desc* d, const void* reqs, int nreq, int per_group, int waves,
+                                long long max_steps, bool general, hipStream_t st);
 // Fill the block map of a 1D table of nreq rows (map: total strips ints).
 hipError_t wcnst_launch_block_map(const void* reqs, int nreq, int* map, hipStream_t st);
 // true when d has sides other than periodic / zero gradient, or gravity

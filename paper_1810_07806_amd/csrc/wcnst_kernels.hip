@@ -298,6 +298,248 @@ sweep1d_multi(const ReqGrid* __restrict__ reqs, const int* __restrict__ map, int
                                                                          b - R.blk0);
 }
 
+// ------------------------------------------- persistent batched 1D solves
+
+// One launch runs a set of 1D Euler grids to completion (t_final, a
+// non-physical state, or a step budget) with no kernel boundary between
+// stages: workgroup b owns grids b*I .. b*I+I-1 of its table, keeps their
+// step control (t, dt, step, CFL speed, status) in LDS, and its W waves
+// share the strips of every stage, ordered by workgroup barriers only (no
+// wave waits for another workgroup).  Every strip runs the single-solve
+// arithmetic (face flux, node flux, MND difference, Runge-Kutta combine,
+// non-physical check, CFL speed) with the grid's own dt, and the step rule
+// of stage_prologue (clipped dt, stop within 1e-12 t_final, the next record
+// opened at stage 0), so each grid gives the same bits as alone.
+constexpr int PERSIST_MAX_WAVES = 16;
+constexpr int PERSIST_MAX_GRIDS = 8;
+
+// Orders the LDS writes of a wave before reads of them by other lanes of
+// the same wave.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ unsigned long long wave_min_bits(unsigned long long m)
+{
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(m, off);
+        m = o < m ? o : m;
+    }
+    return m;
+}
+
+// Strip bx of one stage of a 1D Euler grid with the given dt: writes the
+// stage output of the strip's cells and returns, per lane, the key of a
+// non-physical output (~0 if none) and (stage 2) the CFL speed bits.
+template <int FLUX, int SCHEME, bool CHAR, bool GB>
+__device__ __forceinline__ void strip1d_stage(const double* __restrict__ U, const double* __restrict__ Un,
+                                              double* __restrict__ out, const Params& P, int stage, double dt,
+                                              long long step, int bx, double (*sF)[WAVE], double (*sN)[WAVE],
+                                              unsigned long long& bad, unsigned long long& speed)
+{
+    constexpr int NV = 3;
+    const int nx = P.nx;
+    const int lane = (int)threadIdx.x & (WAVE - 1);
+    const Strip1D<DIFF_MND> S(bx, lane, nx);
+    double s[6][NV], un[NV];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        const int col = ghost_map(S.jxl - 2 + m, nx, P.bc_x);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s[m][v] = U[(size_t)v * nx + col];
+    }
+    if (GB && P.bc_x >= BC_REFLECT) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            const int kind = ghost_kind(S.jxl - 2 + m, nx, P.bc_x);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) s[m][v] = ghost_value(kind, v, 1, s[m][v], P.fixed_x);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) un[v] = stage && S.cell_ok ? Un[(size_t)v * nx + S.c] : 0.0;
+    double F[NV], fn[NV];
+    unsigned fb;
+    RegStencil<NV> st{s};
+    face_flux<SYS_EULER, NV, FLUX, SCHEME, CHAR>(st, P, F, fb);
+    node_flux<SYS_EULER, NV>(s[3], P, fn);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        sF[v][lane] = F[v];
+        sN[v][lane] = fn[v];
+    }
+    wave_sync();
+    bad = ~0ull;
+    speed = 0ull;
+    if (S.cell_ok) {
+        double R[NV], o[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            R[v] = mnd(P.c1x, P.c2x, P.c3x, sF[v][lane], sF[v][lane + 1], sF[v][lane + 2], sF[v][lane + 3],
+                       sN[v][lane], sN[v][lane + 2]);
+        rk_combine<NV>(stage, dt, s[4], un, R, o);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) out[(size_t)v * nx + S.c] = o[v];
+        if (cell_bad<SYS_EULER, NV>(o, P))
+            bad = ((unsigned long long)(step * 3 + stage) << 36) | (unsigned long long)S.c;
+        if (stage == 2) speed = (unsigned long long)__double_as_longlong(cell_speed<SYS_EULER, NV>(o, P));
+    }
+    // the strip's fluxes are read; the wave's next strip may overwrite them
+    wave_sync();
+}
+
+template <int FLUX, int SCHEME, bool CHAR, bool GB>
+__global__ void __launch_bounds__(WAVE * PERSIST_MAX_WAVES)
+sweep1d_persist(const ReqGrid* __restrict__ reqs, int nreq, int per_group, long long max_steps)
+{
+    constexpr int MG = PERSIST_MAX_GRIDS;
+    const int W = (int)blockDim.x / WAVE;
+    const int wave = (int)threadIdx.x / WAVE;
+    const int lane = (int)threadIdx.x & (WAVE - 1);
+    const int q0 = (int)blockIdx.x * per_group;
+    const int nq = min(per_group, nreq - q0);
+    __shared__ double sF_all[PERSIST_MAX_WAVES][3][WAVE];
+    __shared__ double sN_all[PERSIST_MAX_WAVES][3][WAVE];
+    __shared__ ReqGrid g_req[MG];
+    __shared__ double g_t[MG], g_dt[MG], g_tn[MG];
+    __shared__ unsigned long long g_smax[MG], g_next[MG], g_bad[MG];
+    __shared__ long long g_step[MG];
+    __shared__ int g_status[MG], g_done[MG], g_active[MG], g_opened[MG], g_parity[MG], g_touched[MG];
+    __shared__ int g_any;
+    init_weight_table();
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < nq; ++q) {
+            const ReqGrid R = load_table_entry(&reqs[q0 + q]);
+            g_req[q] = R;
+            const Ctrl* c = R.ctrl;
+            // the record of the current state is the newest one (a grid
+            // that finished inside the last ticks stopped flipping parity)
+            const int p = c->rec[0].step >= c->rec[1].step ? 0 : 1;
+            g_parity[q] = p;
+            g_t[q] = c->rec[p].t;
+            g_step[q] = c->rec[p].step;
+            g_smax[q] = c->rec[p].smax_bits;
+            g_status[q] = c->status;
+            g_done[q] = c->done;
+            g_bad[q] = c->bad_key;
+            g_opened[q] = 0;
+            g_touched[q] = 0;
+            g_dt[q] = 0.0;
+        }
+    }
+    __syncthreads();
+    for (long long it = 0; it < max_steps; ++it) {
+        // stage 0 prologue of every grid (stage_prologue's rule)
+        if (threadIdx.x == 0) {
+            int any = 0;
+            for (int q = 0; q < nq; ++q) {
+                int act = g_status[q] == 0 && g_done[q] == 0;
+                const double tf = g_req[q].t_final;
+                if (act && isfinite(tf) && tf - g_t[q] <= 1e-12 * tf) {
+                    g_done[q] = 1;
+                    g_touched[q] = 1;
+                    act = 0;
+                }
+                double dt = 0.0;
+                if (act) {
+                    dt = g_req[q].cfl / __longlong_as_double((long long)g_smax[q]);
+                    if (isfinite(tf) && dt > tf - g_t[q]) dt = tf - g_t[q];
+                    // a step that cannot advance t (an infinite CFL speed)
+                    // leaves the grid unfinished instead of looping; a NaN
+                    // dt runs the stage, which reports the state as the
+                    // stage launches do
+                    if (dt == 0.0) act = 0;
+                }
+                if (act) {
+                    g_touched[q] = 1;
+                    g_dt[q] = dt;
+                    g_tn[q] = g_t[q] + dt;
+                    g_next[q] = 0ull;
+                    g_opened[q] = 1;
+                }
+                g_active[q] = act;
+                any |= act;
+            }
+            g_any = any;
+        }
+        __syncthreads();
+        if (!g_any) break;
+        for (int stage = 0; stage < 3; ++stage) {
+            int total = 0;
+            for (int q = 0; q < nq; ++q) total += g_active[q] ? g_req[q].nstrips : 0;
+            for (int task = wave; task < total; task += W) {
+                int q = 0, bx = task;
+                while (!g_active[q] || bx >= g_req[q].nstrips) {
+                    if (g_active[q]) bx -= g_req[q].nstrips;
+                    ++q;
+                }
+                const ReqGrid& R = g_req[q];
+                const double* in = stage == 0 ? R.U : (stage == 1 ? R.U1 : R.U2);
+                double* out = stage == 0 ? R.U1 : (stage == 1 ? R.U2 : R.U);
+                unsigned long long bad, speed;
+                strip1d_stage<FLUX, SCHEME, CHAR, GB>(in, R.U, out, R.P, stage, g_dt[q], g_step[q], bx,
+                                                      sF_all[wave], sN_all[wave], bad, speed);
+                bad = wave_min_bits(bad);
+                speed = wave_max_bits(speed);
+                if (lane == 0) {
+                    if (bad != ~0ull) atomicMin(&g_bad[q], bad);
+                    if (stage == 2) atomicMax(&g_next[q], speed);
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                for (int q = 0; q < nq; ++q)
+                    if (g_active[q] && g_bad[q] != ~0ull) {
+                        g_status[q] = (int)WCNST_E_NONPHYSICAL;
+                        g_active[q] = 0;
+                    }
+            }
+            __syncthreads();
+        }
+        // a completed step: its new state is current
+        if (threadIdx.x == 0) {
+            for (int q = 0; q < nq; ++q)
+                if (g_active[q]) {
+                    g_t[q] = g_tn[q];
+                    g_step[q] = g_step[q] + 1;
+                    g_smax[q] = g_next[q];
+                    g_parity[q] ^= 1;
+                    g_opened[q] = 0;
+                }
+        }
+        __syncthreads();
+    }
+    // control blocks in the layout the stage launches leave: the record of
+    // the current state (and the one a failed step had opened) is the
+    // newest; grids this launch neither advanced nor finished keep theirs
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < nq; ++q) {
+            if (!g_touched[q]) continue;
+            Ctrl* c = g_req[q].ctrl;
+            const int p = g_parity[q];
+            c->status = g_status[q];
+            c->done = g_done[q];
+            c->bad_key = g_bad[q];
+            c->rec[p].t = g_t[q];
+            c->rec[p].step = g_step[q];
+            c->rec[p].smax_bits = g_smax[q];
+            c->rec[p].dt = g_opened[q] ? g_dt[q] : 0.0;
+            if (g_opened[q]) {
+                c->rec[p ^ 1].t = g_tn[q];
+                c->rec[p ^ 1].dt = 0.0;
+                c->rec[p ^ 1].step = g_step[q] + 1;
+                c->rec[p ^ 1].smax_bits = g_next[q];
+            } else {
+                c->rec[p ^ 1].step = g_step[q] - 1;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ 2D
 
 // Width of a staged row: columns x0-4 .. x0+64 cover the x-stencils of the
@@ -1490,6 +1732,55 @@ hipError_t wcnst_launch_multi(const wcnst_desc* d, int ndim, const void* reqs, c
     const ReqGrid* r = (const ReqGrid*)reqs;
     if (ndim == 2) launch_multi_d<2>(d, r, nullptr, nreq, nblocks, stage, tick_step, ty, general, st);
     else launch_multi_d<1>(d, r, map, nreq, nblocks, stage, tick_step, ty, general, st);
+    return hipGetLastError();
+}
+
+template <int FLUX, int SCHEME, bool CHAR>
+static void launch_persist_t(const ReqGrid* reqs, int nreq, int per_group, int waves, long long max_steps,
+                             bool general, hipStream_t st)
+{
+    const dim3 grid((unsigned)((nreq + per_group - 1) / per_group)), block((unsigned)(waves * WAVE));
+    if (general)
+        hipLaunchKernelGGL((sweep1d_persist<FLUX, SCHEME, CHAR, true>), grid, block, 0, st, reqs, nreq, per_group,
+                           max_steps);
+    else
+        hipLaunchKernelGGL((sweep1d_persist<FLUX, SCHEME, CHAR, false>), grid, block, 0, st, reqs, nreq, per_group,
+                           max_steps);
+}
+
+template <int FLUX, bool CHAR>
+static void launch_persist_s(const wcnst_desc* d, const ReqGrid* reqs, int nreq, int per_group, int waves,
+                             long long max_steps, bool general, hipStream_t st)
+{
+    switch (d->scheme) {
+    case WCNST_LINEAR:
+        launch_persist_t<FLUX, SCH_LINEAR, CHAR>(reqs, nreq, per_group, waves, max_steps, general, st);
+        break;
+    case WCNST_JS: launch_persist_t<FLUX, SCH_JS, CHAR>(reqs, nreq, per_group, waves, max_steps, general, st); break;
+    default:
+        if (d->q == 6) launch_persist_t<FLUX, SCH_TENO, CHAR>(reqs, nreq, per_group, waves, max_steps, general, st);
+        else launch_persist_t<FLUX, SCH_TENO_Q, CHAR>(reqs, nreq, per_group, waves, max_steps, general, st);
+        break;
+    }
+}
+
+hipError_t wcnst_launch_persist(const wcnst_desc* d, const void* reqs, int nreq, int per_group, int waves,
+                                long long max_steps, bool general, hipStream_t st)
+{
+    if (nreq <= 0) return hipSuccess;
+    if (per_group < 1 || per_group > PERSIST_MAX_GRIDS || waves < 1 || waves > PERSIST_MAX_WAVES)
+        return hipErrorInvalidValue;
+    const ReqGrid* r = (const ReqGrid*)reqs;
+    if (d->flux == WCNST_LF) {
+        if (d->charwise) launch_persist_s<FLUX_LF, true>(d, r, nreq, per_group, waves, max_steps, general, st);
+        else launch_persist_s<FLUX_LF, false>(d, r, nreq, per_group, waves, max_steps, general, st);
+    } else if (d->flux == WCNST_VANLEER) {
+        if (d->charwise) launch_persist_s<FLUX_VL, true>(d, r, nreq, per_group, waves, max_steps, general, st);
+        else launch_persist_s<FLUX_VL, false>(d, r, nreq, per_group, waves, max_steps, general, st);
+    } else {
+        if (d->charwise) launch_persist_s<FLUX_ROE, true>(d, r, nreq, per_group, waves, max_steps, general, st);
+        else launch_persist_s<FLUX_ROE, false>(d, r, nreq, per_group, waves, max_steps, general, st);
+    }
     return hipGetLastError();
 }
 

@@ -1,9 +1,11 @@
 """Serving loop with continuous batching over the request pool.
 
 Requests (1D or 2D Euler solves of any size) arrive over time.  The server
-keeps an HBM arena of a fixed byte budget; a request is admitted, in
-arrival order, as soon as its three state buffers (U, U1, U2: 3 x nvar x
-cells x 8 bytes) fit in the arena and a pool slot is free.  Its initial
+keeps an HBM arena of a fixed byte budget; a request is admitted as soon as
+its three state buffers (U, U1, U2: 3 x nvar x cells x 8 bytes) fit in the
+arena and a pool slot is free, in arrival order except that a request that
+does not fit yet lets later ones that fit pass it (a bounded number of
+times, after which it holds the queue until memory frees up).  Its initial
 state is copied into the arena and it joins the pool, which advances all
 resident requests together, a tick at a time.  After each tick finished
 requests are retired: the result is copied back, the slot and the memory
@@ -95,6 +97,33 @@ def percentiles(lat):
                 max=float(a.max()))
 
 
+def plan_admissions(queue, arena, free_slots: int, skips: dict, max_skips: int):
+    """One admission round over `queue` (a deque of requests by arrival,
+    modified in place): requests are placed in the arena in order while
+    slots are free; one that does not fit stays queued and lets later ones
+    pass, until it has been passed max_skips times (counted in `skips` by
+    rid), after which nothing passes it.  Returns [(request, arena offset)]
+    of the admitted requests, plus (request, None) for a request that does
+    not fit at all while the queue holds nothing else that could run (the
+    caller decides whether that is an error)."""
+    admitted, waiting = [], deque()
+    while queue and free_slots > 0:
+        r = queue.popleft()
+        off = arena.alloc(request_bytes(r["desc"]))
+        if off is None:
+            skips[r["rid"]] = skips.get(r["rid"], 0) + 1
+            waiting.append(r)
+            if skips[r["rid"]] > max_skips:
+                break  # it has waited long enough: nothing passes it
+            continue
+        admitted.append((r, off))
+        free_slots -= 1
+    queue.extendleft(reversed(waiting))
+    if not admitted and waiting and arena.used_bytes == 0:
+        admitted.append((waiting[0], None))
+    return admitted
+
+
 def _active_cells(active) -> list:
     """Cells of the active 1D and 2D requests."""
     cells = [0, 0]
@@ -109,7 +138,8 @@ class Server:
     """Continuous-batching server over one Pool and one arena tensor."""
 
     def __init__(self, budget_bytes: int, capacity: int = 256, cfl: float = 0.5, tick_ms: float = 25.0,
-                 min_steps: int = 4, max_steps: int = 2048, device: str = "cuda", scheme: dict | None = None):
+                 min_steps: int = 4, max_steps: int = 2048, device: str = "cuda", scheme: dict | None = None,
+                 max_skips: int = 8):
         import torch
 
         from .wcnst import Pool
@@ -121,6 +151,10 @@ class Server:
         self.cfl = cfl
         self.tick_ms = tick_ms
         self.min_steps, self.max_steps = min_steps, max_steps
+        # admission backfills: a request that does not fit the arena yet lets
+        # later ones that fit go first, at most max_skips times; then it
+        # holds the queue until memory frees up for it
+        self.max_skips = max_skips
 
     def _views(self, off: int, nvals: int):
         per = Arena._round(8 * nvals) // 8
@@ -139,6 +173,7 @@ class Server:
         queue = deque()
         active = {}
         done = []
+        skips = {}                # rid -> admissions it let later requests pass
         steps = [32, 32]          # per tick, for the 1D and the 2D requests
         per_step = [None, None]   # ms per step per active cell in the last tick
         ticks = 0
@@ -148,20 +183,17 @@ class Server:
             now = time.perf_counter() - t0
             while pending and (not realtime or pending[0]["arrival"] <= now):
                 queue.append(pending.popleft())
-            while queue and len(active) < self.capacity:
-                r = queue[0]
-                nvals = request_values(r["desc"])
-                off = self.arena.alloc(request_bytes(r["desc"]))
+            for r, off in plan_admissions(queue, self.arena, self.capacity - len(active), skips, self.max_skips):
                 if off is None:
                     if not active:
                         raise RuntimeError(f"request {r['rid']} needs {request_bytes(r['desc'])} bytes, more than "
                                            f"the arena's {self.arena.size}")
-                    break
+                    continue
+                nvals = request_values(r["desc"])
                 U, U1, U2 = self._views(off, nvals)
                 U.copy_(torch.from_numpy(np.ascontiguousarray(r["U0"], dtype=np.float64).ravel()))
                 slot = self.pool.admit(r["desc"], U, U1, U2, r["t_final"], self.cfl)
                 active[slot] = dict(req=r, off=off, U=U, admitted=time.perf_counter() - t0)
-                queue.popleft()
             if not active:
                 if pending and realtime:
                     time.sleep(max(0.0, min(0.01, pending[0]["arrival"] - (time.perf_counter() - t0))))

@@ -26,6 +26,7 @@ EXPORTS = ("wcnst_desc_init", "wcnst_workspace_size", "wcnst_create", "wcnst_rhs
            "wcnst_profile_read", "wcnst_destroy", "wcnst_last_error",
            "wcnst_batch_workspace_size", "wcnst_batch_create", "wcnst_batch_offsets", "wcnst_batch_solve",
            "wcnst_batch_bad_cells", "wcnst_batch_set_tuning", "wcnst_batch_kernel_ms", "wcnst_batch_stats",
+           "wcnst_batch_set_persist",
            "wcnst_batch_destroy",
            "wcnst_pool_workspace_size", "wcnst_pool_create", "wcnst_pool_admit", "wcnst_pool_tick",
            "wcnst_pool_result", "wcnst_pool_release", "wcnst_pool_set_tuning", "wcnst_pool_tick_split",
@@ -91,7 +92,8 @@ def lib(path: str | None = None):
     L.wcnst_batch_bad_cells.argtypes = [vp, i64p, i64p]
     L.wcnst_batch_set_tuning.argtypes = [vp, ctypes.c_int32]
     L.wcnst_batch_kernel_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
-    L.wcnst_batch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    L.wcnst_batch_stats.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 3
+    L.wcnst_batch_set_persist.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.wcnst_batch_destroy.argtypes = [vp]
     i32, i32p = ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)
     L.wcnst_pool_workspace_size.argtypes = [i32, ctypes.POINTER(ctypes.c_size_t)]
@@ -354,11 +356,18 @@ class Batch:
         _check(lib().wcnst_batch_kernel_ms(self._h, ctypes.byref(ms)))
         return ms.value
 
+    def set_persist(self, switch_strips: int = 0, waves_per_group: int = 16, instances_per_group: int = 1):
+        """Persistent finish once the running instances hold at most
+        switch_strips strips (0: stage launches to the end)."""
+        _check(lib().wcnst_batch_set_persist(self._h, int(switch_strips), int(waves_per_group),
+                                             int(instances_per_group)))
+
     def stats(self) -> dict:
-        """Ticks of the last solve and graphs captured for them."""
-        tk, gr = ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().wcnst_batch_stats(self._h, ctypes.byref(tk), ctypes.byref(gr)))
-        return dict(ticks=tk.value, graphs=gr.value)
+        """Ticks of the last solve, graphs captured for them and instances
+        finished in the persistent launch."""
+        tk, gr, pi = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().wcnst_batch_stats(self._h, ctypes.byref(tk), ctypes.byref(gr), ctypes.byref(pi)))
+        return dict(ticks=tk.value, graphs=gr.value, persist_instances=pi.value)
 
     def solve(self, Ug, t_final, cfl: float = 0.5, max_steps: int = 1 << 40):
         """Returns dict(status, t, steps) arrays; raises only on HIP errors."""

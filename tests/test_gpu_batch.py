@@ -313,3 +313,74 @@ def test_batch_extreme_density_scales(orc, torch):
             assert np.array_equal(out[i], r["U"]), i
         else:
             assert (bs[i], bc[i]) == (r["bad_stage"], r["bad_cell"]), i
+
+
+@pytest.mark.parametrize("waves,group", [(16, 1), (4, 3), (1, 8), (7, 2)])
+def test_batch_persistent_finish_equals_ticks(orc, torch, waves, group):
+    """The persistent finish (one launch that runs the remaining tubes to
+    their final times, waves of a workgroup sharing the strips of its tubes
+    stage by stage) gives the bits of the stage-launch path: statuses, the
+    failing tube's stage and cell (seed 2, tube 17), step counts, times and
+    states, for several workgroup shapes, switching after the first tick
+    and late; sampled tubes against the oracle."""
+    from paper_1810_07806_amd.wcnst import Batch
+    items = _tubes(40, seed=2, n_min=100, n_max=2000, t_final=0.03)
+    descs = [d for d, _ in items]
+    outs = []
+    for switch in (0, 1 << 30, 200):
+        _say(f"persistent finish after {switch} strips, {waves} waves x {group} tubes per workgroup")
+        b = Batch(descs)
+        b.set_tuning(16)
+        b.set_persist(switch, waves, group)
+        Ug = b.pack([U for _, U in items])
+        res = b.solve(Ug, 0.03, cfl=0.5)
+        st = b.stats()
+        if switch == 1 << 30:
+            assert st["persist_instances"] > 0
+        outs.append((b.unpack(Ug), res["steps"].copy(), res["status"].copy(), res["t"].copy(), b.bad_cells()))
+        b.close()
+    o0, st0, s0, t0, (bs0, bc0) = outs[0]
+    assert list(np.flatnonzero(s0)) == [17]
+    for o, st, s, t, (bs, bc) in outs[1:]:
+        assert np.array_equal(s, s0) and np.array_equal(bs, bs0) and np.array_equal(bc, bc0)
+        assert np.array_equal(st, st0) and np.array_equal(t, t0)
+        for a, c in zip(o, o0):
+            assert np.array_equal(a, c)
+    for i in (0, 17, 23):
+        r = orc.solve(orc.problem(descs[i]), items[i][1], t_final=0.03, cfl=0.5)
+        assert r["status"] == s0[i] and (r["bad_stage"], r["bad_cell"]) == (bs0[i], bc0[i])
+        if r["status"] == 0:
+            assert r["steps"] == st0[i] and np.array_equal(o0[i], r["U"])
+
+
+def test_batch_persistent_finish_step_budget_and_boundaries(orc, torch):
+    """The persistent launch keeps the step budget (t_final = inf, exactly
+    max_steps steps) and the general-boundary arithmetic (walls, fixed
+    ends): the same bits as the stage launches and as the oracle."""
+    from paper_1810_07806_amd.wcnst import Batch
+    rng = np.random.default_rng(41)
+    items = [W.random_tube(rng, nx) for nx in (90, 200, 333, 61, 5)]
+    items[1][0].update(bc_x="reflect")
+    items[2][0].update(bc_x="fixed", fixed_x=_FIXED)
+    descs = [d for d, _ in items]
+    for tf, ms in ((np.inf, 37), (0.03, 1 << 40)):
+        outs = []
+        for switch in (0, 1 << 30):
+            _say(f"persistent finish, t_final={tf}, max_steps={ms}, switch={switch}")
+            b = Batch(descs)
+            b.set_tuning(4)
+            b.set_persist(switch, 8, 2)
+            Ug = b.pack([U for _, U in items])
+            res = b.solve(Ug, tf, cfl=0.5, max_steps=ms)
+            outs.append((b.unpack(Ug), res["steps"].copy(), res["status"].copy()))
+            b.close()
+        (o0, st0, s0), (o1, st1, s1) = outs
+        assert np.array_equal(st0, st1) and np.array_equal(s0, s1)
+        assert all(np.array_equal(a, c) for a, c in zip(o0, o1))
+        if np.isinf(tf):
+            assert (st1 == ms).all()
+        for i, (d, U) in enumerate(items):
+            r = orc.solve(orc.problem(d), U, t_final=tf, cfl=0.5, max_steps=ms)
+            assert r["status"] == s1[i] and r["steps"] == st1[i]
+            if r["status"] == 0:
+                assert np.array_equal(o1[i], r["U"]), i

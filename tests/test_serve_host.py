@@ -78,3 +78,42 @@ def test_serving_trace_mix_and_sizes():
     r = two[0]
     assert request_bytes(r["desc"]) == 3 * 4 * r["desc"]["nx"] ** 2 * 8
     assert r["U0"].shape == (4, r["desc"]["ny"], r["desc"]["nx"])
+
+
+def test_admission_backfills_and_bounds_skips():
+    """A request that does not fit yet lets later ones that fit pass it, at
+    most max_skips times; after that nothing passes it until memory frees."""
+    from collections import deque
+
+    from paper_1810_07806_amd.serve import Arena, plan_admissions, request_bytes
+
+    def req(rid, n):
+        return dict(rid=rid, desc=dict(ndim=1, nx=n))
+    small, big = request_bytes(req(0, 100)["desc"]), request_bytes(req(0, 4000)["desc"])
+    arena = Arena(big)                              # room for one big or several small
+    held = arena.alloc(small)                       # part of the arena in use: the big one waits
+    queue = deque([req(1, 4000), req(2, 100), req(3, 100), req(4, 100)])
+    skips = {}
+    got = plan_admissions(queue, arena, 10, skips, max_skips=2)
+    assert [r["rid"] for r, off in got] == [2, 3, 4] and all(off is not None for _, off in got)
+    assert [r["rid"] for r in queue] == [1] and skips == {1: 1}
+    for _, off in got:
+        arena.free(off)
+    queue.extend([req(5, 100), req(6, 100)])
+    assert [r["rid"] for r, _ in plan_admissions(queue, arena, 10, skips, max_skips=2)] == [5, 6]
+    for r in list(arena._used):
+        if r != held:
+            arena.free(r)
+    queue.extend([req(7, 100)])
+    # third skip: over the limit, request 1 now holds the queue
+    assert plan_admissions(queue, arena, 10, skips, max_skips=2) == []
+    assert [r["rid"] for r in queue] == [1, 7]
+    arena.free(held)
+    got = plan_admissions(queue, arena, 10, skips, max_skips=2)
+    assert [r["rid"] for r, _ in got] == [1] and [r["rid"] for r in queue] == [7]  # 1 fills the arena
+    # slot limit
+    queue.extend([req(8, 10), req(9, 10)])
+    for _, off in got:
+        arena.free(off)
+    assert [r["rid"] for r, _ in plan_admissions(queue, arena, 1, skips, max_skips=2)] == [7]
+    assert [r["rid"] for r in queue] == [8, 9]
