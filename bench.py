@@ -396,6 +396,7 @@ def main():
     ap.add_argument("--no-systems", action="store_true",
                     help="default workload only: leave out the tubes and serve sub-records")
     ap.add_argument("--rows", type=int, default=0, help="rows per 2D segment (0: library default)")
+    ap.add_argument("--tune-rows", action="store_true", help="2D: autotune the rows per segment first")
     ap.add_argument("--count", type=int, default=4096, help="tubes: instances")
     ap.add_argument("--seed", type=int, default=0, help="tubes: generator seed")
     ap.add_argument("--steps-per-tick", type=int, default=0, help="tubes: fixed tick length (default: autotune)")
@@ -445,6 +446,16 @@ def main():
     if args.rows > 0:
         s.set_tuning(args.rows)
     U0g = s.new_state(U0)
+    tuned = None
+    if args.tune_rows and args.rows == 0:
+        from paper_1810_07806_amd import autotune
+
+        def log(msg):
+            print(msg, file=sys.stderr, flush=True)
+
+        tuned = autotune.tune_rows(s, U0g, cache=args.tune_cache, device_name=torch.cuda.get_device_name(0),
+                                   log=log)
+        args.rows = tuned["rows"]
     U = U0g.clone()
     if args.warmup > 0:
         s.solve(U, t_final=math.inf, cfl=0.5, max_steps=args.warmup)
@@ -486,7 +497,7 @@ def main():
                                f"WCNS-T TENO C_T=1e-5, Roe, MND, SSP-RK3 CFL 0.5, {nsteps} steps",
                    "nx": args.n, "ny": args.n, "t_reached": t_end, "kernel_ms_avg": avg_launch_s * 1e3,
                    "stage_launches": launches, "rows_per_segment": args.rows or None,
-                   "stage_shape": shape},
+                   "rows_autotuned": tuned is not None, "stage_shape": shape},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": measured_traffic(f"quadrant2d_{args.n}") if not args.rows else None,

@@ -182,8 +182,8 @@ wcnst_status wcnst_reset(wcnst_solver* s, double t, int64_t steps);
  * 61 columns marches up a segment of rows_per_segment rows (>= 1).  The
  * default, chosen at wcnst_create from the grid and the device's CU count,
  * is in [2, 35]: 35 rows for grids that fill the device, shorter segments
- * (more wavefronts) for smaller ones.  Changes only the work decomposition,
- * never the results. */
+ * (more wavefronts) for smaller ones; 0 restores it.  Changes only the work
+ * decomposition, never the results.  Negative values: WCNST_E_INVALID_ARG. */
 wcnst_status wcnst_set_tuning(wcnst_solver* s, int32_t rows_per_segment);
 
 /* Launch shape of the stage kernels (wcnst_step / wcnst_solve).  2D: strips

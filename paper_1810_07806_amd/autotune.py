@@ -1,6 +1,14 @@
-"""Autotuner for the batched solver's launch decomposition.
+"""Autotuners for the launch decomposition of 2D solves and batched solves.
 
-Three choices never change results, only time:
+2D solves (`tune_rows`): the height of the row segment that one 64-lane
+wavefront marches up in a strip of 61 columns.  Taller segments compute
+fewer halo y-midpoints (3 per segment and column), shorter ones give more
+wavefronts; the default two-height shape (0) balances the two wavefronts
+that share a SIMD.  Each candidate runs a few steps with a fixed dt on a
+copy of the state; the solver's step record is restored afterwards.
+
+Batched solves (`tune_batch`): three choices never change results, only
+time:
 
 * the tick length (steps between the host's retirement of finished
   instances from the launch table): short ticks retire finished instances
@@ -49,6 +57,51 @@ def _load(path):
         return {}
     with open(path) as f:
         return json.load(f)
+
+
+DEFAULT_ROWS = (0, 12, 16, 21, 24, 28, 32, 35, 40, 48, 64)
+
+
+def tune_rows(solver, U, steps: int = 2, dt: float = 1e-9, rows=DEFAULT_ROWS, cache: str | None = None,
+              device_name: str = "", log=None):
+    """Time each segment height (0: the default shape) over `steps` stage
+    steps with a fixed dt on a copy of U and set the fastest on `solver`.
+    U is not modified.  Returns dict(rows, ms_per_launch, table, cached)."""
+    import torch
+    d = solver.desc
+    key = f"{device_name}|2d|nx={int(d['nx'])},ny={int(d['ny'])}|rows"
+    db = _load(cache)
+    if key in db:
+        solver.set_tuning(int(db[key]["rows"]))
+        return dict(db[key], cached=True, table=[])
+    st = solver.status()
+    Ut = torch.empty_like(U)
+    table = []
+    for r in rows:
+        solver.set_tuning(int(r))
+        Ut.copy_(U)
+        solver.step(Ut, dt=dt)  # untimed: first launch of this shape
+        solver.profile_enable(True)
+        for _ in range(steps):
+            solver.step(Ut, dt=dt)
+        ms, n = solver.profile_read()
+        solver.profile_enable(False)
+        row = dict(rows=int(r), ms_per_launch=ms / max(1, n), shape=solver.stage_shape())
+        table.append(row)
+        if log:
+            log(f"tune rows={r}: {row['ms_per_launch'] * 1e3:.1f} us per stage launch {row['shape']}")
+    solver.reset(st["t"], st["steps"])
+    torch.cuda.synchronize()
+    best = min(table, key=lambda x: x["ms_per_launch"])
+    solver.set_tuning(best["rows"])
+    out = dict(rows=best["rows"], ms_per_launch=best["ms_per_launch"])
+    if cache:
+        db = _load(cache)
+        db[key] = dict(out, when=time.strftime("%Y-%m-%d %H:%M:%S"))
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+        with open(cache, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+    return dict(out, cached=False, table=table)
 
 
 def _apply(batch, cfg):

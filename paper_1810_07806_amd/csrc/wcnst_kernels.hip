@@ -714,8 +714,16 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
             fy[3][v] = F[v];
         }
         __syncthreads();
-        // row j+4 travels while row i is finished (it replaces row j-2 =
-        // i-1, which the difference below still reads)
+        // U^n of row i first, then row j+4, which travels while row i is
+        // finished (it replaces row j-2 = i-1, which the difference below
+        // still reads): the wait for U^n leaves row j+4 in flight
+        double un[NV];
+        {
+            const size_t cell = (size_t)(i < 0 ? 0 : i) * nx + (cell_ok ? c : 0);
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                un[v] = MODE == MODE_STAGE && A.stage && npass == 2 && cell_ok ? Un[(size_t)v * plane + cell] : 0.0;
+        }
         double ra[NV], rb[NV];
         if (j < y1) load_row<NV>(U, plane, (size_t)ghost_map(j + 4, ny, P.bc_y) * nx, colA, colB, hasB, ra, rb);
         if (npass == 2 && cell_ok) {
@@ -752,9 +760,7 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
 #pragma unroll
                 for (int v = 0; v < NV; ++v) out[(size_t)v * plane + cell] = R[v];
             } else {
-                double un[NV], o[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) un[v] = A.stage ? Un[(size_t)v * plane + cell] : 0.0;
+                double o[NV];
                 rk_combine<NV>(A.stage, dt, Uc, un, R, o);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) out[(size_t)v * plane + cell] = o[v];
@@ -1590,7 +1596,14 @@ int wcnst_auto_rows(const int* strips, const int* rows, int n, int slots)
 extern "C" wcnst_status wcnst_set_tuning(wcnst_solver* s, int32_t rows_per_segment)
 {
     if (!s) return fail(WCNST_E_INVALID_ARG, "null handle");
-    if (rows_per_segment < 1) return fail(WCNST_E_INVALID_ARG, "rows_per_segment must be >= 1");
+    if (rows_per_segment < 0) return fail(WCNST_E_INVALID_ARG, "rows_per_segment must be >= 0");
+    if (rows_per_segment == 0) {
+        // the shape chosen at creation
+        const int strips = (s->d.nx + TX - 1) / TX, rows = s->d.ny;
+        s->ty = s->d.ndim == 2 ? wcnst_auto_rows(&strips, &rows, 1, s->slots) : 35;
+        s->ty_user = false;
+        return WCNST_OK;
+    }
     s->ty = rows_per_segment;
     s->ty_user = true;
     return WCNST_OK;

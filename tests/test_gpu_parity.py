@@ -268,6 +268,31 @@ def test_launch_shape_does_not_change_results(torch):
         assert np.array_equal(R, outs[0][0]) and np.array_equal(V, outs[0][1])
 
 
+def test_rows_autotuner_keeps_state_and_results(torch):
+    """The 2D segment-height autotuner times its candidates on a copy of the
+    state and restores the solver's step record; the tuned solve gives the
+    bits of the default shape, and set_tuning(0) restores that shape."""
+    from paper_1810_07806_amd import autotune
+    d, U = W.riemann2d_config3(300)
+    s = _solver(d)
+    default = s.stage_shape()
+    Ug = s.new_state(U)
+    U_in = Ug.clone()
+    _say("rows autotuner on 300^2")
+    res = autotune.tune_rows(s, Ug, steps=1, rows=(0, 8, 24, 300))
+    assert [r["rows"] for r in res["table"]] == [0, 8, 24, 300]
+    assert res["rows"] in (0, 8, 24, 300) and torch.equal(Ug, U_in)
+    st = s.status()
+    assert st["t"] == 0.0 and st["steps"] == 0 and st["status"] == 0
+    s.solve(Ug, t_final=np.inf, cfl=0.5, max_steps=6)
+    ref = _solver(d)
+    V = ref.new_state(U)
+    ref.solve(V, t_final=np.inf, cfl=0.5, max_steps=6)
+    assert torch.equal(Ug, V)
+    s.set_tuning(0)
+    assert s.stage_shape() == default
+
+
 def test_solve_config3_full_size_100_steps(orc, torch):
     """The 2048^2 benchmark problem in the benchmark's launch configuration:
     100 SSP-RK3 steps against the oracle (run on the host cores) over the
