@@ -4,8 +4,13 @@
 wavefront marches up in a strip of 61 columns.  Taller segments compute
 fewer halo y-midpoints (3 per segment and column), shorter ones give more
 wavefronts; the default two-height shape (0) balances the two wavefronts
-that share a SIMD.  Each candidate runs a few steps with a fixed dt on a
-copy of the state; the solver's step record is restored afterwards.
+that share a SIMD.  A copy of the state is first advanced by `pre_steps`
+steps with the default shape (the ranking of the shapes changes as the
+solution develops: timed at the initial state alone, 35-row segments beat
+the default by 3 % and then lose by 5 % over 200 steps of the 2048^2
+benchmark); each candidate then runs a few steps with a fixed,
+tiny dt on that state, and a candidate replaces the default only when it
+is faster by `margin`.  The solver's step record is restored afterwards.
 
 Batched solves (`tune_batch`): three choices never change results, only
 time:
@@ -62,11 +67,13 @@ def _load(path):
 DEFAULT_ROWS = (0, 12, 16, 21, 24, 28, 32, 35, 40, 48, 64)
 
 
-def tune_rows(solver, U, steps: int = 2, dt: float = 1e-9, rows=DEFAULT_ROWS, cache: str | None = None,
-              device_name: str = "", log=None):
-    """Time each segment height (0: the default shape) over `steps` stage
-    steps with a fixed dt on a copy of U and set the fastest on `solver`.
-    U is not modified.  Returns dict(rows, ms_per_launch, table, cached)."""
+def tune_rows(solver, U, steps: int = 3, pre_steps: int = 60, dt: float = 1e-9, margin: float = 0.02,
+              rows=DEFAULT_ROWS, cfl: float = 0.5, cache: str | None = None, device_name: str = "", log=None):
+    """Time each segment height (0: the default shape) over `steps` steps
+    with a fixed dt on a copy of U advanced by `pre_steps` CFL steps, and
+    set the fastest on `solver` (the default unless another is faster by
+    `margin`).  U is not modified.  Returns dict(rows, ms_per_launch, table,
+    cached)."""
     import torch
     d = solver.desc
     key = f"{device_name}|2d|nx={int(d['nx'])},ny={int(d['ny'])}|rows"
@@ -75,11 +82,16 @@ def tune_rows(solver, U, steps: int = 2, dt: float = 1e-9, rows=DEFAULT_ROWS, ca
         solver.set_tuning(int(db[key]["rows"]))
         return dict(db[key], cached=True, table=[])
     st = solver.status()
+    base = U.clone()
+    if pre_steps > 0:
+        solver.set_tuning(0)
+        solver.reset(0.0, 0)
+        solver.solve(base, cfl=cfl, max_steps=pre_steps)
     Ut = torch.empty_like(U)
     table = []
     for r in rows:
         solver.set_tuning(int(r))
-        Ut.copy_(U)
+        Ut.copy_(base)
         solver.step(Ut, dt=dt)  # untimed: first launch of this shape
         solver.profile_enable(True)
         for _ in range(steps):
@@ -93,6 +105,9 @@ def tune_rows(solver, U, steps: int = 2, dt: float = 1e-9, rows=DEFAULT_ROWS, ca
     solver.reset(st["t"], st["steps"])
     torch.cuda.synchronize()
     best = min(table, key=lambda x: x["ms_per_launch"])
+    default = next((x for x in table if x["rows"] == 0), None)
+    if default is not None and best["ms_per_launch"] > (1.0 - margin) * default["ms_per_launch"]:
+        best = default
     solver.set_tuning(best["rows"])
     out = dict(rows=best["rows"], ms_per_launch=best["ms_per_launch"])
     if cache:
