@@ -405,7 +405,7 @@ def main():
     ap.add_argument("--n-max", type=int, default=8192, help="tubes: largest N")
     ap.add_argument("--switch-strips", type=int, default=0,
                     help="tubes with --steps-per-tick: persistent finish below this many running strips")
-    ap.add_argument("--persist-waves", type=int, default=16, help="tubes: waves per persistent workgroup")
+    ap.add_argument("--persist-waves", type=int, default=8, help="tubes: waves per persistent workgroup")
     ap.add_argument("--persist-group", type=int, default=1, help="tubes: instances per persistent workgroup")
     ap.add_argument("--per-solve", type=int, default=32, help="tubes: instances timed on the per-solve path")
     ap.add_argument("--cpu-steps", type=int, default=200, help="tubes: oracle steps per sampled tube")

@@ -257,7 +257,7 @@ wcnst_status wcnst_batch_set_tuning(wcnst_batch* b, int32_t steps_per_tick);
 /* Persistent finish (Sec. 2 arithmetic unchanged): once the instances still
  * running hold at most switch_strips strips of 61 cells, the batch stops
  * issuing ticks and runs them to their final times in one persistent launch:
- * each workgroup of waves_per_group wavefronts (1..16) owns
+ * each workgroup of waves_per_group wavefronts (1..8) owns
  * instances_per_group instances (1..8), keeps their step control in LDS and
  * shares their strips among its waves stage by stage, ordered by workgroup
  * barriers only (no workgroup waits for another).  switch_strips = 0 (the

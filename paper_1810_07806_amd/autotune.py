@@ -29,7 +29,7 @@ Candidates are timed on a proxy of the real batch: the same instances run
 to a fraction of their final times.  Step counts scale with t_final, so the
 proxy keeps the relative lengths of the instances while costing a few
 percent of the real run.  The search is greedy: the tick length first
-(stage launches only), then the switch point at 16 waves x 1 instance, then
+(stage launches only), then the switch point at 8 waves x 1 instance, then
 the workgroup shape at the best switch point (skipped when stage launches
 to the end win).  A persistent winner is confirmed on a longer proxy
 against stage launches to the end: on the short one its share of the run
@@ -47,7 +47,7 @@ import time
 
 DEFAULT_TICKS = (16, 32, 64, 128, 256)
 DEFAULT_SWITCH = (0, 64, 256, 1024)
-DEFAULT_SHAPES = ((16, 1), (8, 1), (16, 2), (4, 4))
+DEFAULT_SHAPES = ((8, 1), (4, 1), (8, 2), (4, 4))
 
 
 def signature(descs, t_final) -> str:
@@ -154,12 +154,12 @@ def tune_batch(batch, Ug_init, t_final, cfl: float = 0.5, proxy: float = 0.05, t
             log("tune " + ", ".join(f"{k}={v}" for k, v in cfg.items()) + f": {row['ms']:.2f} ms")
         return row
 
-    base = dict(steps_per_tick=ticks[0], switch_strips=0, waves_per_group=16, instances_per_group=1)
+    base = dict(steps_per_tick=ticks[0], switch_strips=0, waves_per_group=8, instances_per_group=1)
     best = min([trial(dict(base, steps_per_tick=spt)) for spt in ticks], key=lambda r: r["ms"])
     for sw in switches:
         if sw > 0:
             cfg = {k: best[k] for k in ("steps_per_tick", "waves_per_group", "instances_per_group")}
-            r = trial(dict(cfg, switch_strips=sw, waves_per_group=16, instances_per_group=1))
+            r = trial(dict(cfg, switch_strips=sw, waves_per_group=8, instances_per_group=1))
             best = r if r["ms"] < best["ms"] else best
     if best["switch_strips"] > 0:
         for w, g in shapes:

@@ -229,8 +229,8 @@ extern "C" wcnst_status wcnst_batch_set_persist(wcnst_batch* b, int32_t switch_s
 {
     if (!b) return wcnst_fail(WCNST_E_INVALID_ARG, "null handle");
     if (switch_strips < 0) return wcnst_fail(WCNST_E_INVALID_ARG, "switch_strips must be >= 0");
-    if (waves_per_group < 1 || waves_per_group > 16)
-        return wcnst_fail(WCNST_E_INVALID_ARG, "waves_per_group must be in [1, 16]");
+    if (waves_per_group < 1 || waves_per_group > 8)
+        return wcnst_fail(WCNST_E_INVALID_ARG, "waves_per_group must be in [1, 8]");
     if (instances_per_group < 1 || instances_per_group > 8)
         return wcnst_fail(WCNST_E_INVALID_ARG, "instances_per_group must be in [1, 8]");
     b->persist_strips = switch_strips;

@@ -310,7 +310,9 @@ sweep1d_multi(const ReqGrid* __restrict__ reqs, const int* __restrict__ map, int
 // non-physical check, CFL speed) with the grid's own dt, and the step rule
 // of stage_prologue (clipped dt, stop within 1e-12 t_final, the next record
 // opened at stage 0), so each grid gives the same bits as alone.
-constexpr int PERSIST_MAX_WAVES = 16;
+// 8 wavefronts (2 per SIMD) leave the kernel the registers it needs: at 16
+// (4 per SIMD, 128 registers) it spilled 292 bytes per lane and ran 2x slower.
+constexpr int PERSIST_MAX_WAVES = 8;
 constexpr int PERSIST_MAX_GRIDS = 8;
 
 // Orders the LDS writes of a wave before reads of them by other lanes of

@@ -356,7 +356,7 @@ class Batch:
         _check(lib().wcnst_batch_kernel_ms(self._h, ctypes.byref(ms)))
         return ms.value
 
-    def set_persist(self, switch_strips: int = 0, waves_per_group: int = 16, instances_per_group: int = 1):
+    def set_persist(self, switch_strips: int = 0, waves_per_group: int = 8, instances_per_group: int = 1):
         """Persistent finish once the running instances hold at most
         switch_strips strips (0: stage launches to the end)."""
         _check(lib().wcnst_batch_set_persist(self._h, int(switch_strips), int(waves_per_group),

@@ -315,7 +315,7 @@ def test_batch_extreme_density_scales(orc, torch):
             assert (bs[i], bc[i]) == (r["bad_stage"], r["bad_cell"]), i
 
 
-@pytest.mark.parametrize("waves,group", [(16, 1), (4, 3), (1, 8), (7, 2)])
+@pytest.mark.parametrize("waves,group", [(8, 1), (4, 3), (1, 8), (7, 2)])
 def test_batch_persistent_finish_equals_ticks(orc, torch, waves, group):
     """The persistent finish (one launch that runs the remaining tubes to
     their final times, waves of a workgroup sharing the strips of its tubes
