@@ -70,7 +70,7 @@ typedef struct wcnst_desc {
                              WCNST_VANLEER (flux-vector splitting, Euler only) */
     int32_t scheme;       /* WCNST_TENO (Eqs. 16-19) / WCNST_LINEAR (Eq. 12) / WCNST_JS (Eq. 14) /
                              WCNST_Z (the WCNS-Z of Sec. 3: weights of Borges et al. 2008 on the
-                             indicators of Eq. 15 and tau_5 of Sec. 2.3; 1D single solves only) */
+                             indicators of Eq. 15 and tau_5 of Sec. 2.3) */
     int32_t diff;         /* WCNST_MND (Eq. 5) / WCNST_MD (Eq. 3) / WCNST_HWCNS (Eq. 4); MD and
                              HWCNS: 1D single solves only (batches and pools use MND) */
     int32_t charwise;     /* Euler: 1 = interpolate characteristic variables */

@@ -135,8 +135,6 @@ static wcnst_status batch_check(const wcnst_desc* descs, int32_t n, long long* t
             return wcnst_fail(WCNST_E_INVALID_ARG, "descriptor %d: batches hold 1D Euler problems", i);
         if (d.diff != WCNST_MND)
             return wcnst_fail(WCNST_E_INVALID_ARG, "descriptor %d: batches use the MND difference", i);
-        if (d.scheme == WCNST_Z)
-            return wcnst_fail(WCNST_E_INVALID_ARG, "descriptor %d: the WCNS-Z weights are built for single solves", i);
         if (wcnst_check_same_scheme(a, d))
             return wcnst_fail(WCNST_E_INVALID_ARG, "descriptor %d: scheme parameters differ from descriptor 0", i);
         if (offs) (*offs)[i] = off;

@@ -977,7 +977,6 @@ wcnst_status wcnst_check_desc(const wcnst_desc* d)
         return fail(WCNST_E_INVALID_ARG, "the van Leer splitting is for the Euler system");
     if (d->scheme < WCNST_TENO || d->scheme > WCNST_Z) return fail(WCNST_E_INVALID_ARG, "unknown scheme");
     if (d->scheme == WCNST_Z) {
-        if (d->ndim != 1) return fail(WCNST_E_INVALID_ARG, "the WCNS-Z weights are built for 1D grids");
         if (d->z_q < 1 || d->z_q > 8) return fail(WCNST_E_INVALID_ARG, "z_q must be in [1, 8]");
         if (!(d->eps_z > 0.0)) return fail(WCNST_E_INVALID_ARG, "eps_z must be positive");
     }
@@ -1236,10 +1235,7 @@ static void launch_scheme(const wcnst_solver* s, const double* U, const double* 
     switch (s->d.scheme) {
     case WCNST_LINEAR: launch_sweep_t<SYS, NV, FLUX, SCH_LINEAR, CHAR, MODE>(s, U, Un, out, flags, A); break;
     case WCNST_JS: launch_sweep_t<SYS, NV, FLUX, SCH_JS, CHAR, MODE>(s, U, Un, out, flags, A); break;
-    case WCNST_Z:
-        // 1D only (refused for 2D grids at creation)
-        if constexpr (NV != 4) launch_sweep_t<SYS, NV, FLUX, SCH_Z, CHAR, MODE>(s, U, Un, out, flags, A);
-        break;
+    case WCNST_Z: launch_sweep_t<SYS, NV, FLUX, SCH_Z, CHAR, MODE>(s, U, Un, out, flags, A); break;
     default:
         if (s->d.q == 6) launch_sweep_t<SYS, NV, FLUX, SCH_TENO, CHAR, MODE>(s, U, Un, out, flags, A);
         else launch_sweep_t<SYS, NV, FLUX, SCH_TENO_Q, CHAR, MODE>(s, U, Un, out, flags, A);
@@ -1716,6 +1712,9 @@ static void launch_multi_s(const wcnst_desc* d, const ReqGrid* reqs, const int* 
     case WCNST_JS:
         launch_multi_t<NDIM, FLUX, SCH_JS, CHAR>(reqs, map, nreq, nblocks, stage, tick_step, ty, general, st);
         break;
+    case WCNST_Z:
+        launch_multi_t<NDIM, FLUX, SCH_Z, CHAR>(reqs, map, nreq, nblocks, stage, tick_step, ty, general, st);
+        break;
     default:
         if (d->q == 6)
             launch_multi_t<NDIM, FLUX, SCH_TENO, CHAR>(reqs, map, nreq, nblocks, stage, tick_step, ty, general, st);
@@ -1772,6 +1771,7 @@ static void launch_persist_s(const wcnst_desc* d, const ReqGrid* reqs, int nreq,
         launch_persist_t<FLUX, SCH_LINEAR, CHAR>(reqs, nreq, per_group, waves, max_steps, general, st);
         break;
     case WCNST_JS: launch_persist_t<FLUX, SCH_JS, CHAR>(reqs, nreq, per_group, waves, max_steps, general, st); break;
+    case WCNST_Z: launch_persist_t<FLUX, SCH_Z, CHAR>(reqs, nreq, per_group, waves, max_steps, general, st); break;
     default:
         if (d->q == 6) launch_persist_t<FLUX, SCH_TENO, CHAR>(reqs, nreq, per_group, waves, max_steps, general, st);
         else launch_persist_t<FLUX, SCH_TENO_Q, CHAR>(reqs, nreq, per_group, waves, max_steps, general, st);

@@ -100,8 +100,6 @@ extern "C" wcnst_status wcnst_pool_create(const wcnst_desc* scheme, int32_t capa
     if (st) return st;
     if (scheme->system != WCNST_EULER) return wcnst_fail(WCNST_E_INVALID_ARG, "pools hold Euler problems");
     if (scheme->diff != WCNST_MND) return wcnst_fail(WCNST_E_INVALID_ARG, "pools use the MND difference");
-    if (scheme->scheme == WCNST_Z)
-        return wcnst_fail(WCNST_E_INVALID_ARG, "the WCNS-Z weights are built for single solves");
     size_t need = 0;
     st = wcnst_pool_workspace_size(capacity, &need);
     if (st) return st;

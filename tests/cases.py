@@ -30,7 +30,9 @@ CASES_2D = [dict(flux="roe", scheme="teno", charwise=1),
             dict(flux="roe", scheme="teno", charwise=0),
             dict(flux="roe", scheme="js", charwise=1),
             dict(flux="vanleer", scheme="teno", charwise=1),
-            dict(flux="roe", scheme="teno", charwise=1, q=4)]
+            dict(flux="roe", scheme="teno", charwise=1, q=4),
+            dict(flux="roe", scheme="z", charwise=1),
+            dict(flux="lf", scheme="z", charwise=0, z_q=2)]
 
 # ragged strips and segments, one strip / one segment, the minimum, and exact
 # multiples of the 61-column strip and the 35-row segment

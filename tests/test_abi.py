@@ -70,7 +70,7 @@ def test_workspace_size_and_validation():
            dict(x0=1.0, x1=1.0), dict(ndim=2, nx=8, ny=8, diff="md"),
            dict(system="advection", flux="vanleer"), dict(ndim=2, nx=8, ny=8, diff="hwcns"),
            dict(system="advection", bc_x="reflect"), dict(gravity=1.0),
-           dict(ndim=2, nx=8, ny=8, scheme="z"), dict(scheme="z", z_q=0), dict(scheme="z", z_q=9),
+           dict(scheme="z", z_q=0), dict(scheme="z", z_q=9),
            dict(scheme="z", eps_z=0.0)]
     for kw in bad:
         st, _ = _ws(wc, L, **kw)
@@ -107,20 +107,19 @@ def test_batches_and_pools_refuse_the_md_difference():
     assert L.wcnst_last_error()
 
 
-def test_batches_and_pools_refuse_the_z_weights():
-    """The WCNS-Z weights run in 1D single solves only: batches refuse them
-    at sizing time and pools at creation, before any device work."""
+def test_batches_and_pools_take_the_z_weights_with_one_scheme():
+    """Batches take the WCNS-Z weights like the other schemes; a batch that
+    mixes schemes, or Z powers, is refused at sizing time."""
     wc, L = _lib()
-    descs = (wc.Desc * 2)(*[wc.make_desc(dict(ndim=1, system="euler", nx=64, scheme=sc)) for sc in ("teno", "z")])
     n = ctypes.c_size_t(0)
     L.wcnst_batch_workspace_size.argtypes = [ctypes.POINTER(wc.Desc), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
-    assert L.wcnst_batch_workspace_size(descs, 2, ctypes.byref(n)) == wc.E_INVALID_ARG
-    assert b"WCNS-Z" in L.wcnst_last_error()
-    h = ctypes.c_void_p()
-    buf = ctypes.create_string_buffer(1 << 16)
-    assert L.wcnst_pool_create(ctypes.byref(descs[1]), 4, None, ctypes.addressof(buf), 1 << 16,
-                               ctypes.byref(h)) == wc.E_INVALID_ARG
-    assert b"WCNS-Z" in L.wcnst_last_error()
+    same = (wc.Desc * 2)(*[wc.make_desc(dict(ndim=1, system="euler", nx=64, scheme="z")) for _ in range(2)])
+    assert L.wcnst_batch_workspace_size(same, 2, ctypes.byref(n)) == 0 and n.value > 0
+    mixed = (wc.Desc * 2)(*[wc.make_desc(dict(ndim=1, system="euler", nx=64, scheme=sc)) for sc in ("teno", "z")])
+    assert L.wcnst_batch_workspace_size(mixed, 2, ctypes.byref(n)) == wc.E_INVALID_ARG
+    assert b"differ" in L.wcnst_last_error()
+    other_q = (wc.Desc * 2)(*[wc.make_desc(dict(ndim=1, system="euler", nx=64, scheme="z", z_q=zq)) for zq in (1, 2)])
+    assert L.wcnst_batch_workspace_size(other_q, 2, ctypes.byref(n)) == wc.E_INVALID_ARG
 
 
 def test_noalloc_solve_refuses_grids_beyond_its_scratch():

@@ -205,8 +205,10 @@ _FIXED = ((1.2, 0.1, 2.6), (0.3, 0.0, 1.0))
 
 @pytest.mark.parametrize("kw", [dict(flux="lf", bc_x="periodic"), dict(flux="roe", charwise=0),
                                 dict(flux="roe", scheme="linear"), dict(flux="vanleer"),
-                                dict(bc_x="reflect"), dict(bc_x="fixed", fixed_x=_FIXED)],
-                         ids=["lf-periodic", "componentwise", "linear", "vanleer", "walls", "fixed-ends"])
+                                dict(bc_x="reflect"), dict(bc_x="fixed", fixed_x=_FIXED),
+                                dict(scheme="z"), dict(flux="lf", charwise=0, scheme="z", z_q=2)],
+                         ids=["lf-periodic", "componentwise", "linear", "vanleer", "walls", "fixed-ends", "wcns-z",
+                              "wcns-z-p2"])
 def test_batch_scheme_variants(orc, torch, kw):
     from paper_1810_07806_amd.wcnst import Batch
     rng = np.random.default_rng(41)
@@ -384,3 +386,32 @@ def test_batch_persistent_finish_step_budget_and_boundaries(orc, torch):
             assert r["status"] == s1[i] and r["steps"] == st1[i]
             if r["status"] == 0:
                 assert np.array_equal(o1[i], r["U"]), i
+
+
+def test_batch_wcns_z_persistent_equals_ticks(orc, torch):
+    """WCNS-Z tubes through the persistent launch from the start give the
+    bits of the stage launches and of the oracle."""
+    from paper_1810_07806_amd.wcnst import Batch
+    rng = np.random.default_rng(43)
+    items = [W.random_tube(rng, nx) for nx in (90, 200, 61, 333)]
+    for d, _ in items:
+        d.update(scheme="z")
+    descs = [d for d, _ in items]
+    outs = []
+    for switch in (0, 1 << 30):
+        _say(f"WCNS-Z batch, persistent switch {switch}")
+        b = Batch(descs)
+        b.set_tuning(8)
+        b.set_persist(switch, 4, 2)
+        Ug = b.pack([U for _, U in items])
+        res = b.solve(Ug, 0.03, cfl=0.5)
+        outs.append((b.unpack(Ug), res["steps"].copy(), res["status"].copy()))
+        b.close()
+    (o0, st0, s0), (o1, st1, s1) = outs
+    assert np.array_equal(st0, st1) and np.array_equal(s0, s1)
+    assert all(np.array_equal(a, c) for a, c in zip(o0, o1))
+    for i, (d, U) in enumerate(items):
+        r = orc.solve(orc.problem(d), U, t_final=0.03, cfl=0.5)
+        assert r["status"] == s1[i] and r["steps"] == st1[i]
+        if r["status"] == 0:
+            assert np.array_equal(o1[i], r["U"]), i

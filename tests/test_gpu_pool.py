@@ -61,9 +61,9 @@ def _alone(d, U, tf):
     return out, st
 
 
-def _run_pool(torch, items, steps_per_tick, join_after=None, tuning=None):
+def _run_pool(torch, items, steps_per_tick, join_after=None, tuning=None, scheme=None):
     from paper_1810_07806_amd.wcnst import Pool
-    pool = Pool(capacity=16)
+    pool = Pool(scheme=scheme, capacity=16)
     if tuning:
         pool.set_tuning(*tuning)
     bufs = {}
@@ -136,6 +136,19 @@ def test_pool_mix_matches_oracle(orc, torch):
     _say("pool mix against the oracle")
     res = _run_pool(torch, items, 7, join_after=(5, 2))
     _against_oracle(orc, items, res)
+
+
+def test_pool_wcns_z_mix_matches_oracle(orc, torch):
+    """A pool built for the WCNS-Z weights (Sec. 3's comparison scheme):
+    1D tubes and 2D four-quadrant grids against the oracle and against
+    single solves."""
+    items = _mix(8, n1=3, n2=2)
+    for d, _, _ in items:
+        d.update(scheme="z")
+    _say("WCNS-Z pool mix against the oracle")
+    res = _run_pool(torch, items, 9, scheme=dict(scheme="z"))
+    _against_oracle(orc, items, res)
+    _compare(items, res)
 
 
 @pytest.mark.parametrize("steps_per_tick", [1, 7, 1000])
