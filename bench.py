@@ -63,17 +63,24 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per launch of the dominant kernel from FETCH_SIZE and
-    WRITE_SIZE counter runs, scaled by the same counters on a plain copy of
-    known size; None when the record was taken on other kernel sources."""
+def counter_record(workload: str):
+    """Counter figures of the dominant kernel (HBM bytes per launch from
+    FETCH_SIZE and WRITE_SIZE runs scaled by the same counters on a plain
+    copy of known size; VALU busy fraction from SQ counters), or None when
+    they were taken on other kernel sources."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
         rec = json.load(f).get(workload)
     if not rec or rec.get("source_hash") != kernel_source_hash():
         return None
-    return rec["hbm_bytes_per_launch"]
+    return rec
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the dominant kernel (see counter_record)."""
+    rec = counter_record(workload)
+    return rec["hbm_bytes_per_launch"] if rec else None
 
 
 def flops_per_stage_cell() -> dict:
@@ -505,6 +512,11 @@ def main():
                      "bytes_per_launch_algorithmic": bytes_per_stage_cell() * cells,
                      "hbm_GBs_algorithmic": bytes_per_stage_cell() * cells / avg_launch_s / 1e9},
     }
+    crec = counter_record(f"quadrant2d_{args.n}") if not args.rows else None
+    if crec:
+        # counter-measured figures of the same kernel (profiles/ summaries)
+        rec["roofline"]["hbm_GBs_measured"] = crec["hbm_bytes_per_launch"] / avg_launch_s / 1e9
+        rec["roofline"]["valu_busy_counters"] = crec.get("valu_busy_frac")
     if not args.no_cpu_baseline and args.n == N_SIDE:
         rec["cpu_baseline"] = cpu_baseline()
     if not args.no_systems and args.n == N_SIDE:
@@ -512,7 +524,47 @@ def main():
         # per-solve comparison: the batched shock tubes and the served mix
         rec["tubes"] = systems_record(bench_tubes, args, steps=1, warmup=1, count=4096)
         rec["serve"] = systems_record(bench_serve, args, steps=1, warmup=1, count=80)
+        rec["singles"] = bench_singles()
     print(json.dumps(rec), flush=True)
+
+
+def bench_singles() -> dict:
+    """Time-to-solution of the two 1D single-solve workloads on the
+    single-solve path (wcnst_solve, inputs resident, one synchronising call):
+    linear advection of a sine plus a square pulse (N = 200, periodic, to
+    t = 2) and the Shu-Osher problem (N = 2048, zero gradient, to t = 1.8),
+    both WCNS-T TENO with MND and SSP-RK3 at CFL 0.5.  One grid fills a
+    handful of CUs, so there is no roofline claim: each stage costs about
+    one wavefront's latency."""
+    import torch
+
+    from paper_1810_07806_amd import workloads as W
+    from paper_1810_07806_amd.wcnst import Solver
+    out = {}
+    for name, (d, U0), tf in (("advection_sine_square_200", W.advection_sine_square(200), 2.0),
+                              ("shu_osher_2048", W.shu_osher(2048), 1.8)):
+        s = Solver(d)
+        U = s.new_state(U0)
+        s.solve(U.clone(), t_final=math.inf, cfl=0.5, max_steps=20)  # warm-up
+        # the time to solution without per-launch events, then the kernel
+        # time of the same solve with them
+        s.reset(0.0, 0)
+        V = U.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t, n = s.solve(V, t_final=tf, cfl=0.5)
+        wall = time.perf_counter() - t0
+        s.reset(0.0, 0)
+        s.profile_enable(True)
+        s.solve(U, t_final=tf, cfl=0.5)
+        stage_ms, launches = s.profile_read()
+        s.profile_enable(False)
+        units = 3.0 * n * int(d["nx"])
+        out[name] = {"time_to_solution_s": wall, "steps": n, "t_final": t, "cells": int(d["nx"]),
+                     "stage_cell_updates_per_s": units / wall,
+                     "kernel_us_per_stage": stage_ms * 1e3 / max(1, launches)}
+        s.close()
+    return out
 
 
 def systems_record(fn, args, steps, warmup, count):
