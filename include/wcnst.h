@@ -123,8 +123,8 @@ wcnst_status wcnst_create(const wcnst_desc* d, void* hip_stream, void* workspace
  * j = s - 3 (MD) or j = s - 1 (HWCNS), of
  * characteristic field k (conserved variable k when charwise = 0; for y
  * lines the normal momentum comes first), side 0 = u_L, side 1 = u_R
- * (mirrored stencil); bit k-1 holds delta_k of Eq. (18).  Scalar schemes
- * without a cut (LINEAR, JS) report 7. */
+ * (mirrored stencil); bit k-1 holds delta_k of Eq. (18).  Schemes without
+ * a cut (LINEAR, JS, Z) report 7. */
 wcnst_status wcnst_rhs(wcnst_solver* s, const double* U, double* R, uint8_t* flags);
 
 /* One SSP-RK3 step of U in place (Sec. 2, Shu-Osher form).  dt > 0 is used

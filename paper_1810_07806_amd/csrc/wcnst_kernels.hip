@@ -290,7 +290,10 @@ __global__ void __launch_bounds__(WAVE)
 sweep1d_multi(const ReqGrid* __restrict__ reqs, const int* __restrict__ map, int nreq, int stage, int tick_step)
 {
     const int b = (int)blockIdx.x;
-    const ReqGrid R = load_request(reqs, map, nreq, b);
+    ReqGrid R = load_request(reqs, map, nreq, b);
+    // every field the strip geometry and the stencil loads need, loaded in
+    // one round trip before any of them is used
+    asm volatile("" : "+s"(R.U), "+s"(R.U1), "+s"(R.U2), "+s"(R.ctrl), "+s"(R.P.nx), "+s"(R.P.bc_x), "+s"(R.blk0));
     const StageArgs A = request_stage(R, stage, tick_step);
     const double* in = stage == 0 ? R.U : (stage == 1 ? R.U1 : R.U2);
     double* out = stage == 0 ? R.U1 : (stage == 1 ? R.U2 : R.U);
