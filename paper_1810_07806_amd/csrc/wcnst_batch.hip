@@ -355,7 +355,7 @@ extern "C" wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const doubl
     WCNST_HIP_TRY(hipMemcpyAsync(b->d_req, b->h_req, sizeof(ReqGrid) * (size_t)n, hipMemcpyHostToDevice, b->stream));
     WCNST_HIP_TRY(hipEventRecord(b->ev0, b->stream));
     WCNST_HIP_TRY(wcnst_launch_multi_init(1, b->d_req, n, b->stream));
-    WCNST_HIP_TRY(wcnst_launch_block_map(b->d_req, n, b->d_map, b->stream));
+    WCNST_HIP_TRY(wcnst_launch_block_map(b->d_req, n, blocks, b->d_map, b->stream));
 
     // Ticks are pipelined: tick k+1 is queued before the host has looked at
     // tick k, so the set of running instances is decided from the control
@@ -384,7 +384,7 @@ extern "C" wcnst_status wcnst_batch_solve(wcnst_batch* b, double* U, const doubl
             }
             WCNST_HIP_TRY(hipMemcpyAsync(b->d_req, tab, sizeof(ReqGrid) * active.size(), hipMemcpyHostToDevice,
                                          b->stream));
-            WCNST_HIP_TRY(wcnst_launch_block_map(b->d_req, (int)active.size(), b->d_map, b->stream));
+            WCNST_HIP_TRY(wcnst_launch_block_map(b->d_req, (int)active.size(), blocks, b->d_map, b->stream));
             uploads += 1;
         }
         wcnst_status st = run_tick(b, (int)active.size(), blocks, steps, changed, k);

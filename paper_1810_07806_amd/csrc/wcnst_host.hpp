@@ -30,17 +30,18 @@ size_t wcnst_ctrl_bytes();
 hipError_t wcnst_launch_init_grid(const wcnst_desc* d, const double* U, void* ctrl, hipStream_t st);
 // general: some grid of the table has reflecting / fixed sides or gravity
 // (the tables then take the stage kernels that handle them).
-// map (1D tables, nullable): the table row of every block (wcnst_launch_block_map);
+// map (nullable): the table row of every block (wcnst_launch_block_map);
 // without one each block searches the table.
 hipError_t wcnst_launch_multi(const wcnst_desc* d, int ndim, const void* reqs, const int* map, int nreq, int nblocks,
                               int stage, int tick_step, int ty, bool general, hipStream_t st);
 // One persistent launch that runs the nreq 1D grids of a table to their
 // final times (or max_steps more steps): per_group grids per workgroup of
-// `waves` wavefronts (at most 8 and 16).
+// `waves` wavefronts (at most 8 each).
 hipError_t wcnst_launch_persist(const wcnst_desc* d, const void* reqs, int nreq, int per_group, int waves,
                                 long long max_steps, bool general, hipStream_t st);
-// Fill the block map of a 1D table of nreq rows (map: total strips ints).
-hipError_t wcnst_launch_block_map(const void* reqs, int nreq, int* map, hipStream_t st);
+// Fill the block map of a table of nreq rows and `total` blocks (map: total
+// ints; the rows' blk0 ascending from 0).
+hipError_t wcnst_launch_block_map(const void* reqs, int nreq, int total, int* map, hipStream_t st);
 // true when d has sides other than periodic / zero gradient, or gravity
 bool wcnst_general_bc(const wcnst_desc* d);
 // Wavefront slots of the current device for the 2D stage kernel (two per

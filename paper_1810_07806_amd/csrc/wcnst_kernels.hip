@@ -263,13 +263,15 @@ __device__ __forceinline__ ReqGrid load_request(const ReqGrid* __restrict__ reqs
     return load_table_entry(&reqs[lo]);
 }
 
-// Block map of a 1D ReqGrid table: block r writes map[blk0 + k] = r for the
-// nstrips blocks of grid r.
-__global__ void __launch_bounds__(256) block_map_fill(const ReqGrid* __restrict__ reqs, int* __restrict__ map)
+// Block map of a ReqGrid table of nreq rows and `total` blocks: block r
+// writes map[k] = r for the blocks blk0[r] <= k < blk0[r+1] (total for the
+// last row) of grid r, in 1D (strips) and 2D (strips x segments) alike.
+__global__ void __launch_bounds__(256) block_map_fill(const ReqGrid* __restrict__ reqs, int nreq, int total,
+                                                      int* __restrict__ map)
 {
     const int r = (int)blockIdx.x;
-    const int b0 = reqs[r].blk0, n = reqs[r].nstrips;
-    for (int k = (int)threadIdx.x; k < n; k += (int)blockDim.x) map[b0 + k] = r;
+    const int b0 = reqs[r].blk0, b1 = r + 1 < nreq ? reqs[r + 1].blk0 : total;
+    for (int k = b0 + (int)threadIdx.x; k < b1; k += (int)blockDim.x) map[k] = r;
 }
 
 __device__ __forceinline__ StageArgs request_stage(const ReqGrid& R, int stage, int tick_step)
@@ -803,10 +805,15 @@ sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
 // the grid's own parameters, buffers, control block and step parity.
 template <int NV, int FLUX, int SCHEME, bool CHAR, bool GB>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2)))
-sweep2d_multi(const ReqGrid* __restrict__ reqs, int nreq, int stage, int tick_step, int ty)
+sweep2d_multi(const ReqGrid* __restrict__ reqs, const int* __restrict__ map, int nreq, int stage, int tick_step,
+              int ty)
 {
     const int b = (int)blockIdx.x;
-    const ReqGrid R = load_request(reqs, nullptr, nreq, b);
+    ReqGrid R = load_request(reqs, map, nreq, b);
+    // the fields the segment geometry and the first row loads need, loaded
+    // in one round trip before any of them is used
+    asm volatile("" : "+s"(R.U), "+s"(R.U1), "+s"(R.U2), "+s"(R.ctrl), "+s"(R.P.nx), "+s"(R.P.ny), "+s"(R.blk0),
+                 "+s"(R.nstrips));
     const Params& P = R.P;
     const int local = b - R.blk0;
     const StageArgs A = request_stage(R, stage, tick_step);
@@ -1691,10 +1698,10 @@ static void launch_multi_t(const ReqGrid* reqs, const int* map, int nreq, int nb
     if constexpr (NDIM == 2) {
         if (general)
             hipLaunchKernelGGL((sweep2d_multi<4, FLUX, SCHEME, CHAR, true>), dim3(nblocks), dim3(WAVE), 0, st, reqs,
-                               nreq, stage, tick_step, ty);
+                               map, nreq, stage, tick_step, ty);
         else
             hipLaunchKernelGGL((sweep2d_multi<4, FLUX, SCHEME, CHAR, false>), dim3(nblocks), dim3(WAVE), 0, st, reqs,
-                               nreq, stage, tick_step, ty);
+                               map, nreq, stage, tick_step, ty);
     } else if (general) {
         hipLaunchKernelGGL((sweep1d_multi<FLUX, SCHEME, CHAR, true>), dim3(nblocks), dim3(WAVE), 0, st, reqs, map,
                            nreq, stage, tick_step);
@@ -1747,7 +1754,7 @@ hipError_t wcnst_launch_multi(const wcnst_desc* d, int ndim, const void* reqs, c
                               int stage, int tick_step, int ty, bool general, hipStream_t st)
 {
     const ReqGrid* r = (const ReqGrid*)reqs;
-    if (ndim == 2) launch_multi_d<2>(d, r, nullptr, nreq, nblocks, stage, tick_step, ty, general, st);
+    if (ndim == 2) launch_multi_d<2>(d, r, map, nreq, nblocks, stage, tick_step, ty, general, st);
     else launch_multi_d<1>(d, r, map, nreq, nblocks, stage, tick_step, ty, general, st);
     return hipGetLastError();
 }
@@ -1802,10 +1809,10 @@ hipError_t wcnst_launch_persist(const wcnst_desc* d, const void* reqs, int nreq,
     return hipGetLastError();
 }
 
-hipError_t wcnst_launch_block_map(const void* reqs, int nreq, int* map, hipStream_t st)
+hipError_t wcnst_launch_block_map(const void* reqs, int nreq, int total, int* map, hipStream_t st)
 {
     if (nreq <= 0) return hipSuccess;
-    hipLaunchKernelGGL(block_map_fill, dim3(nreq), dim3(256), 0, st, (const ReqGrid*)reqs, map);
+    hipLaunchKernelGGL(block_map_fill, dim3(nreq), dim3(256), 0, st, (const ReqGrid*)reqs, nreq, total, map);
     return hipGetLastError();
 }
 

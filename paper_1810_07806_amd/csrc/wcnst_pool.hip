@@ -57,9 +57,10 @@ struct wcnst_pool {
     hipStream_t s2 = nullptr;  // pool stream: 2D launches
     hipEvent_t ev_start = nullptr, ev_2d = nullptr, ev_1d = nullptr;
     float ms_1d = 0.0f, ms_2d = 0.0f;  // device time of each dimension's launches in the last tick
-    // device (caller's workspace): one request table per dimension, one
-    // control block per slot
+    // device (caller's workspace): one request table and one block map per
+    // dimension, one control block per slot
     ReqGrid* d_req[2] = {nullptr, nullptr};
+    int* d_map[2] = {nullptr, nullptr};
     uint8_t* d_ctrl = nullptr;
     size_t ctrl_bytes = 0;
     // pinned host staging
@@ -70,7 +71,11 @@ struct wcnst_pool {
     int slots = 0;  // wavefront slots of the device
 };
 
-static size_t pool_layout(int cap, size_t* o_req1, size_t* o_req2, size_t* o_ctrl)
+// Blocks a pool launch can map (one int each, per dimension); a launch over
+// more searches the table instead.
+constexpr int POOL_MAP_BLOCKS = 1 << 18;
+
+static size_t pool_layout(int cap, size_t* o_req1, size_t* o_req2, size_t* o_ctrl, size_t* o_map)
 {
     size_t o = 0;
     *o_req1 = o;
@@ -79,6 +84,8 @@ static size_t pool_layout(int cap, size_t* o_req1, size_t* o_req2, size_t* o_ctr
     o = wcnst_align256(o + sizeof(ReqGrid) * (size_t)cap);
     *o_ctrl = o;
     o = wcnst_align256(o + wcnst_align256(wcnst_ctrl_bytes()) * (size_t)cap);
+    *o_map = o;
+    o = wcnst_align256(o + 2 * sizeof(int) * (size_t)POOL_MAP_BLOCKS);
     return o;
 }
 
@@ -86,8 +93,8 @@ extern "C" wcnst_status wcnst_pool_workspace_size(int32_t capacity, size_t* byte
 {
     if (capacity < 1 || capacity > (1 << 20)) return wcnst_fail(WCNST_E_INVALID_ARG, "capacity must be in [1, 2^20]");
     if (!bytes) return wcnst_fail(WCNST_E_INVALID_ARG, "null size pointer");
-    size_t a, b, c;
-    *bytes = pool_layout(capacity, &a, &b, &c);
+    size_t a, b, c, m;
+    *bytes = pool_layout(capacity, &a, &b, &c, &m);
     return WCNST_OK;
 }
 
@@ -107,8 +114,8 @@ extern "C" wcnst_status wcnst_pool_create(const wcnst_desc* scheme, int32_t capa
     if (!workspace || ws_bytes < need)
         return wcnst_fail(WCNST_E_INVALID_ARG, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
     if (((uintptr_t)workspace & 255u) != 0) return wcnst_fail(WCNST_E_INVALID_ARG, "workspace not 256-byte aligned");
-    size_t o_req1, o_req2, o_ctrl;
-    pool_layout(capacity, &o_req1, &o_req2, &o_ctrl);
+    size_t o_req1, o_req2, o_ctrl, o_map;
+    pool_layout(capacity, &o_req1, &o_req2, &o_ctrl, &o_map);
 
     wcnst_pool* p = new wcnst_pool();
     p->scheme = *scheme;
@@ -118,6 +125,8 @@ extern "C" wcnst_status wcnst_pool_create(const wcnst_desc* scheme, int32_t capa
     p->d_req[0] = (ReqGrid*)(ws + o_req1);
     p->d_req[1] = (ReqGrid*)(ws + o_req2);
     p->d_ctrl = ws + o_ctrl;
+    p->d_map[0] = (int*)(ws + o_map);
+    p->d_map[1] = p->d_map[0] + POOL_MAP_BLOCKS;
     p->ctrl_bytes = wcnst_align256(wcnst_ctrl_bytes());
     p->reqs.resize((size_t)capacity);
     p->slots = wcnst_wave_slots();
@@ -224,11 +233,17 @@ static wcnst_status issue_dim(wcnst_pool* p, int ndim, const std::vector<int>& a
         r.parity = (int)((r.parity + steps) & 1);
     }
     WCNST_HIP_TRY(hipMemcpyAsync(p->d_req[ndim - 1], tab, sizeof(ReqGrid) * (size_t)n, hipMemcpyHostToDevice, st));
+    // each block finds its table row in one load (a search over the table
+    // for launches beyond the map)
+    const int* map = nullptr;
+    if (blocks <= POOL_MAP_BLOCKS) {
+        WCNST_HIP_TRY(wcnst_launch_block_map(p->d_req[ndim - 1], n, blocks, p->d_map[ndim - 1], st));
+        map = p->d_map[ndim - 1];
+    }
     for (int64_t s = 0; s < steps; ++s)
         for (int stage = 0; stage < 3; ++stage)
-            WCNST_HIP_TRY(
-                wcnst_launch_multi(&p->scheme, ndim, p->d_req[ndim - 1], nullptr, n, blocks, stage, (int)(s & 1), ty,
-                                   general, st));
+            WCNST_HIP_TRY(wcnst_launch_multi(&p->scheme, ndim, p->d_req[ndim - 1], map, n, blocks, stage, (int)(s & 1),
+                                             ty, general, st));
     return WCNST_OK;
 }
 
