@@ -70,6 +70,11 @@ MUTANTS = [
      ["test_gravity_balances_a_hydrostatic_column"]),
     ("wall-reverses-density", "if (bc == ORC_REFLECT && v == 1) return -val;",
      "if (bc == ORC_REFLECT && v == 0) return -val;", ["test_wall_and_fixed_ghosts_match_explicit_extension"]),
+    ("wcns-z-ratio-inverted", "double x = tau5 / (beta[k] + p->eps_z), xp = 1.0;",
+     "double x = (beta[k] + p->eps_z) / (tau5 + p->eps_z), xp = 1.0;",
+     ["test_wcns_z_weights_closed_forms", "test_table2_wcns_z_column"]),
+    ("wcns-z-drops-constant-term", "alpha[k] = D_OPT[k] * (1.0 + xp);", "alpha[k] = D_OPT[k] * xp;",
+     ["test_wcns_z_weights_closed_forms", "test_table2_wcns_z_column"]),
 ]
 
 
