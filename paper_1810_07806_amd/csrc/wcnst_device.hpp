@@ -671,6 +671,59 @@ struct RegStencil {
     WCNST_HD double operator()(int m, int v) const { return s[m][v]; }
 };
 
+// Characteristic basis at x_{j+1/2}: the Roe average of nodes j, j+1
+// (stencil nodes 2 and 3) by the ranged sequences, and the IEEE operations
+// on lanes whose arguments leave their range.
+template <int NV, class ST>
+WCNST_HD void midpoint_eigen(ST& st, const Params& P, Eigen<NV>& E)
+{
+    double A[NV], B[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        A[v] = st(2, v);
+        B[v] = st(3, v);
+    }
+    if (!roe_eigen<NV, true>(A, B, P.gamma, E)) roe_eigen<NV>(A, B, P.gamma, E);
+}
+
+// Characteristic field k of the six stencil nodes, w_m = l_k . U_m (sums
+// over the conserved variables in increasing order, structural zeros
+// skipped).
+template <int NV, class ST>
+WCNST_HD void project_field(ST& st, const Eigen<NV>& E, int k, double (&w)[6])
+{
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        double acc = 0.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if (Eigen<NV>::L_zero(k, v)) continue;
+            acc = v == 0 ? E.L(k, v) * st(m, v) : fma(E.L(k, v), st(m, v), acc);
+        }
+        w[m] = acc;
+    }
+}
+
+// Field k's share of the back-projection U = sum_k r_k w_k (k in increasing
+// order; field 0 has no structural zero in R, so it starts every sum).
+template <int NV>
+WCNST_HD void back_project_field(const Eigen<NV>& E, int k, double wl, double wr, double (&UL)[NV],
+                                 double (&UR)[NV])
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (Eigen<NV>::R_zero(v, k)) continue;
+        const double r = E.R(v, k);
+        if (k == 0) {
+            UL[v] = r * wl;
+            UR[v] = r * wr;
+        } else {
+            UL[v] = fma(r, wl, UL[v]);
+            UR[v] = fma(r, wr, UR[v]);
+        }
+    }
+}
+
 // s: nodes j-2 .. j+3 around x_{j+1/2}.  F: flux at x_{j+1/2}.
 // fb: 6 flag bits per field (left mask | right mask << 3).
 template <int SYS, int NV, int FLUX, int SCHEME, bool CHAR, class ST>
@@ -681,51 +734,18 @@ WCNST_HD void face_flux(ST& st, const Params& P, double (&F)[NV], unsigned& fb)
         double UL[NV], UR[NV];
         if constexpr (CHAR) {
             Eigen<NV> E;
-            {
-                double A[NV], B[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    A[v] = st(2, v);
-                    B[v] = st(3, v);
-                }
-                // the ranged sequences, and the IEEE operations on lanes
-                // whose arguments leave their range
-                if (!roe_eigen<NV, true>(A, B, P.gamma, E)) roe_eigen<NV>(A, B, P.gamma, E);
-            }
+            midpoint_eigen<NV>(st, P, E);
             // one characteristic field at a time: project, interpolate both
-            // sides, and add its share of the back-projection (sums over k in
-            // increasing order, as in U = sum_k r_k w_k; field 0 has no
-            // structural zero in R, so it starts every sum)
+            // sides, and add its share of the back-projection
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
-                const Eigen<NV>& Ek = E;
                 double w[6];
-#pragma unroll
-                for (int m = 0; m < 6; ++m) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        if (Eigen<NV>::L_zero(k, v)) continue;
-                        acc = v == 0 ? Ek.L(k, v) * st(m, v) : fma(Ek.L(k, v), st(m, v), acc);
-                    }
-                    w[m] = acc;
-                }
+                project_field<NV>(st, E, k, w);
                 unsigned mL, mR;
                 double wl, wr;
                 interp_pair<SCHEME>(w[0], w[1], w[2], w[3], w[4], w[5], P, wl, wr, mL, mR);
                 fb |= (mL | (mR << 3)) << (6 * k);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    if (Eigen<NV>::R_zero(v, k)) continue;
-                    const double r = Ek.R(v, k);
-                    if (k == 0) {
-                        UL[v] = r * wl;
-                        UR[v] = r * wr;
-                    } else {
-                        UL[v] = fma(r, wl, UL[v]);
-                        UR[v] = fma(r, wr, UR[v]);
-                    }
-                }
+                back_project_field<NV>(E, k, wl, wr, UL, UR);
             }
         } else {
 #pragma unroll

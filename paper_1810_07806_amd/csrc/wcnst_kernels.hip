@@ -247,6 +247,140 @@ sweep1d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
     sweep1d_block<SYS, NV, FLUX, SCHEME, CHAR, MODE, DIFF>(U, Un, out, flags, ctrl, P, A, (int)blockIdx.x);
 }
 
+// ------------------------------------------------------ 1D latency mode
+
+// A stage over a few strips cannot fill the chip, and each launch then
+// lasts about one wavefront's dependent chain.  In the latency mode a strip
+// of a 1D Euler grid gets a workgroup of three wavefronts: wavefront k
+// interpolates characteristic field k (conserved component k when not
+// characteristic-wise) at the strip's 64 midpoints; the interpolated values
+// meet in LDS; wavefront 0 forms the back-projection and the midpoint flux
+// while wavefront 1 forms the node flux; wavefront 0 finishes the MND
+// difference, the stage update, the non-physical check and the CFL speed.
+// Each value is formed by the operations of the one-wavefront kernel in the
+// same order, so the results are the same bits.
+constexpr int SPLIT_WAVES = 3;
+// Strips up to which single 1D Euler solves use it (three wavefronts per
+// strip on the 1024 SIMDs of the chip).
+constexpr int SPLIT_STRIPS = 256;
+
+template <int FLUX, int SCHEME, bool CHAR, bool GB>
+__device__ __forceinline__ void strip1d_split(const double* __restrict__ U, const double* __restrict__ Un,
+                                              double* __restrict__ out, Ctrl* __restrict__ ctrl, const Params& P,
+                                              const StageArgs& A, int bx)
+{
+    constexpr int NV = 3;
+    const int wave = (int)threadIdx.x / WAVE;
+    const int lane = (int)threadIdx.x & (WAVE - 1);
+    const int nx = P.nx;
+    const Strip1D<DIFF_MND> S(bx, lane, nx);
+    __shared__ double sW[NV][2][WAVE];
+    __shared__ double sF[NV][WAVE];
+    __shared__ double sN[NV][WAVE];
+    __shared__ double s_dt;
+    __shared__ long long s_step;
+    __shared__ unsigned long long s_seen;
+    __shared__ int s_go;
+
+    double s[6][NV], un[NV];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        const int col = ghost_map(S.jxl - 2 + m, nx, P.bc_x);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s[m][v] = U[(size_t)v * nx + col];
+    }
+    if (GB && P.bc_x >= BC_REFLECT) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            const int kind = ghost_kind(S.jxl - 2 + m, nx, P.bc_x);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) s[m][v] = ghost_value(kind, v, 1, s[m][v], P.fixed_x);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) un[v] = wave == 0 && A.stage && S.cell_ok ? Un[(size_t)v * nx + S.c] : 0.0;
+    // the step record, read once for the workgroup
+    if (threadIdx.x == 0) {
+        double dt = 0.0;
+        long long step = 0;
+        unsigned long long seen = 0ull;
+        s_go = stage_prologue(ctrl, A, dt, step, bx == 0, seen) ? 1 : 0;
+        s_dt = dt;
+        s_step = step;
+        s_seen = seen;
+    }
+    init_weight_table();  // (its barrier also publishes the record)
+    if (!s_go) return;    // one value for the whole workgroup
+
+    RegStencil<NV> st{s};
+    Eigen<NV> E;
+    {
+        double wl, wr;
+        unsigned mL, mR;
+        if constexpr (CHAR) {
+            midpoint_eigen<NV>(st, P, E);
+            double w[6];
+            if (wave == 0) project_field<NV>(st, E, 0, w);
+            else if (wave == 1) project_field<NV>(st, E, 1, w);
+            else project_field<NV>(st, E, 2, w);
+            interp_pair<SCHEME>(w[0], w[1], w[2], w[3], w[4], w[5], P, wl, wr, mL, mR);
+        } else if (wave == 0) {
+            interp_pair<SCHEME>(s[0][0], s[1][0], s[2][0], s[3][0], s[4][0], s[5][0], P, wl, wr, mL, mR);
+        } else if (wave == 1) {
+            interp_pair<SCHEME>(s[0][1], s[1][1], s[2][1], s[3][1], s[4][1], s[5][1], P, wl, wr, mL, mR);
+        } else {
+            interp_pair<SCHEME>(s[0][2], s[1][2], s[2][2], s[3][2], s[4][2], s[5][2], P, wl, wr, mL, mR);
+        }
+        sW[wave][0][lane] = wl;
+        sW[wave][1][lane] = wr;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        double UL[NV], UR[NV], F[NV];
+        if constexpr (CHAR) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) back_project_field<NV>(E, k, sW[k][0][lane], sW[k][1][lane], UL, UR);
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                UL[v] = sW[v][0][lane];
+                UR[v] = sW[v][1][lane];
+            }
+        }
+        euler_num_flux<NV, FLUX>(UL, UR, P.gamma, F);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sF[v][lane] = F[v];
+    } else if (wave == 1) {
+        double fn[NV];
+        node_flux<SYS_EULER, NV>(s[3], P, fn);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sN[v][lane] = fn[v];
+    }
+    __syncthreads();
+    if (wave != 0) return;
+    unsigned long long sm = 0ull;
+    if (S.cell_ok) {
+        double R[NV], o[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            R[v] = mnd(P.c1x, P.c2x, P.c3x, sF[v][lane], sF[v][lane + 1], sF[v][lane + 2], sF[v][lane + 3],
+                       sN[v][lane], sN[v][lane + 2]);
+        rk_combine<NV>(A.stage, s_dt, s[4], un, R, o);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) out[(size_t)v * nx + S.c] = o[v];
+        stage_epilogue<SYS_EULER, NV>(ctrl, P, A.stage, s_step, S.c, o, sm);
+    }
+    if (A.stage == 2) flush_speed(ctrl, A.parity, sm, s_seen);
+}
+
+template <int FLUX, int SCHEME, bool CHAR, bool GB>
+__global__ void __launch_bounds__(WAVE * SPLIT_WAVES)
+sweep1d_split(const double* __restrict__ U, const double* __restrict__ Un, double* __restrict__ out,
+              Ctrl* __restrict__ ctrl, Params P, StageArgs A)
+{
+    strip1d_split<FLUX, SCHEME, CHAR, GB>(U, Un, out, ctrl, P, A, (int)blockIdx.x);
+}
+
 // The table row of block b: the grid r with blk0[r] <= b < blk0[r+1],
 // from the block map when the launch has one (one load), else by binary
 // search over the table (uniform per block).
@@ -947,6 +1081,7 @@ struct wcnst_solver {
     int parity;
     int ty;  // rows per 2D segment
     bool ty_user;  // set by wcnst_set_tuning (else chosen at creation)
+    int split_strips;  // 1D Euler stages over at most this many strips run in the latency mode
     int slots;     // wavefront slots of the device
     bool prof;
     std::vector<hipEvent_t> ev_pool;
@@ -1132,6 +1267,7 @@ extern "C" wcnst_status wcnst_create(const wcnst_desc* d, void* hip_stream, void
     s->parity = 0;
     s->slots = wcnst_wave_slots();
     s->ty_user = false;
+    s->split_strips = SPLIT_STRIPS;
     {
         const int strips = (d->nx + TX - 1) / TX, rows = d->ny;
         s->ty = d->ndim == 2 ? wcnst_auto_rows(&strips, &rows, 1, s->slots) : 35;
@@ -1233,8 +1369,21 @@ static void launch_sweep_t(const wcnst_solver* s, const double* U, const double*
                            dim3(WAVE), 0, s->stream, U, Un, out, flags, s->ctrl, s->P, A);
     } else {
         constexpr int W = strip_cells<DIFF_MND>();
-        hipLaunchKernelGGL((sweep1d<SYS, NV, FLUX, SCHEME, CHAR, MODE, DIFF_MND>), dim3((s->d.nx + W - 1) / W),
-                           dim3(WAVE), 0, s->stream, U, Un, out, flags, s->ctrl, s->P, A);
+        const int nstrips = (s->d.nx + W - 1) / W;
+        if constexpr (MODE == MODE_STAGE && SYS == SYS_EULER && NV == 3) {
+            // few strips: the latency mode (three wavefronts per strip)
+            if (nstrips <= s->split_strips) {
+                if (wcnst_general_bc(&s->d))
+                    hipLaunchKernelGGL((sweep1d_split<FLUX, SCHEME, CHAR, true>), dim3(nstrips),
+                                       dim3(WAVE * SPLIT_WAVES), 0, s->stream, U, Un, out, s->ctrl, s->P, A);
+                else
+                    hipLaunchKernelGGL((sweep1d_split<FLUX, SCHEME, CHAR, false>), dim3(nstrips),
+                                       dim3(WAVE * SPLIT_WAVES), 0, s->stream, U, Un, out, s->ctrl, s->P, A);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((sweep1d<SYS, NV, FLUX, SCHEME, CHAR, MODE, DIFF_MND>), dim3(nstrips), dim3(WAVE), 0,
+                           s->stream, U, Un, out, flags, s->ctrl, s->P, A);
     }
 }
 
@@ -1502,6 +1651,7 @@ extern "C" wcnst_status wcnst_solve_noalloc(const wcnst_desc* d, void* hip_strea
         const int strips = (d->nx + TX - 1) / TX, rows = d->ny;
         s.ty = d->ndim == 2 ? wcnst_auto_rows(&strips, &rows, 1, s.slots) : 35;
     }
+    s.split_strips = SPLIT_STRIPS;
     wcnst_make_params(d, &s.P);
     const bool timed = std::isfinite(t_final);
 

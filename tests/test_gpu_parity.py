@@ -136,6 +136,21 @@ def test_solve_shu_osher_to_final_time(orc, torch):
     _solve_case(orc, torch, d, U, 1.8, 1 << 40, "shu-osher-t1.8")
 
 
+@pytest.mark.parametrize("kw", [dict(), dict(flux="lf", charwise=0, bc_x="periodic"), dict(flux="vanleer"),
+                                dict(scheme="js"), dict(scheme="z", z_q=2), dict(bc_x="reflect")],
+                         ids=["roe-teno", "lf-componentwise-periodic", "vanleer", "js", "wcns-z", "walls"])
+def test_solve_1d_latency_mode_and_wide_lines(orc, torch, kw):
+    """1D Euler stages over at most 256 strips run three wavefronts per
+    strip (the latency mode), longer lines one: both through whole solves
+    against the oracle, at 5 and 61 cells (one strip), 1000 cells (17
+    strips) and 16000 cells (263 strips, the one-wavefront kernel)."""
+    rng = np.random.default_rng(11)
+    for n, steps in ((5, 40), (61, 40), (1000, 40), (16000, 12)):
+        d, U = W.random_tube(rng, n)
+        d.update(kw)
+        _solve_case(orc, torch, d, U, np.inf, steps, f"tube{n}-{kw}")
+
+
 def test_solve_tube_to_time(orc, torch):
     rng = np.random.default_rng(3)
     d, U = W.random_tube(rng, 257)
