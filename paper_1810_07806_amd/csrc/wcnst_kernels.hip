@@ -934,9 +934,10 @@ sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
 }
 
 // One stage of many independent 2D grids in one launch: block b belongs to
-// the request r with blk0[r] <= b < blk0[r+1] (binary search over the
-// table, uniform per block), then runs segment b - blk0[r] of that grid with
-// the grid's own parameters, buffers, control block and step parity.
+// the request r with blk0[r] <= b < blk0[r+1] (from the block map, else by
+// a search over the table, uniform per block), then runs segment
+// b - blk0[r] of that grid with the grid's own parameters, buffers, control
+// block and step parity.
 template <int NV, int FLUX, int SCHEME, bool CHAR, bool GB>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2)))
 sweep2d_multi(const ReqGrid* __restrict__ reqs, const int* __restrict__ map, int nreq, int stage, int tick_step,
