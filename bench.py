@@ -417,7 +417,7 @@ def main():
     ap.add_argument("--per-solve", type=int, default=32, help="tubes: instances timed on the per-solve path")
     ap.add_argument("--cpu-steps", type=int, default=200, help="tubes: oracle steps per sampled tube")
     ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / measured capacity")
-    ap.add_argument("--tick-ms", type=float, default=25.0, help="serve: target tick duration")
+    ap.add_argument("--tick-ms", type=float, default=10.0, help="serve: target tick duration")
     ap.add_argument("--capacity", type=int, default=256, help="serve: pool slots")
     ap.add_argument("--budget-gb", type=float, default=0.0, help="serve: arena GiB (0: 75 %% of free)")
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy: bytes copied per launch (MiB)")

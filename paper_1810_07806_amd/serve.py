@@ -137,7 +137,7 @@ def _active_cells(active) -> list:
 class Server:
     """Continuous-batching server over one Pool and one arena tensor."""
 
-    def __init__(self, budget_bytes: int, capacity: int = 256, cfl: float = 0.5, tick_ms: float = 25.0,
+    def __init__(self, budget_bytes: int, capacity: int = 256, cfl: float = 0.5, tick_ms: float = 10.0,
                  min_steps: int = 4, max_steps: int = 2048, device: str = "cuda", scheme: dict | None = None,
                  max_skips: int = 8):
         import torch
