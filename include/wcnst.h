@@ -74,7 +74,11 @@ typedef struct wcnst_desc {
     int32_t diff;         /* WCNST_MND (Eq. 5) / WCNST_MD (Eq. 3) / WCNST_HWCNS (Eq. 4); MD and
                              HWCNS: 1D single solves only (batches and pools use MND) */
     int32_t charwise;     /* Euler: 1 = interpolate characteristic variables */
-    int32_t q;            /* TENO integer power, Eq. (16); default 6 */
+    int32_t q;            /* TENO integer power, Eq. (16), in [1, 64]; default 6.  The cut
+                             test scales C + tau_5/(beta_k + eps) by a power of two so that the
+                             powers cannot overflow, except for q = 6, where they stay finite
+                             while C + tau_5/(beta_k + eps) <= 8e50 (tau_5 <= 8e10 with
+                             eps = 1e-40) */
     double gamma;         /* ratio of specific heats, > 1; default 1.4 */
     double adv_speed;     /* advection speed a (flux f = a u) */
     double CT;            /* TENO cut-off C_T, Eq. (18); default 1e-5 */
@@ -86,7 +90,7 @@ typedef struct wcnst_desc {
     double fixed_y[2][4]; /* ... at y0 / y1 (2D) */
     double gravity;       /* 2D Euler body force in +y: R += (0, 0, rho g, rho v g); default 0 */
     int32_t z_q;          /* WCNST_Z: power p in alpha_k = d_k (1 + (tau_5/(beta_k + eps_z))^p),
-                             in [1, 8]; default 1 */
+                             in [1, 4] (finite for tau_5 < 1e37 with eps_z = 1e-40); default 1 */
     double eps_z;         /* WCNST_Z: epsilon, > 0; default 1e-40 */
 } wcnst_desc;
 

@@ -164,13 +164,24 @@ double orc_interp_left(const orc_problem* p, const double s[5], double chi[3],
         sum = alpha[0] + alpha[1] + alpha[2];
         for (int k = 0; k < 3; ++k) { w[k] = alpha[k] / sum; chi_l[k] = w[k]; }
     } else {
-        /* Eq. (16): gamma_k = (C + tau5 / (beta_k + eps))^q, tau5 = |beta_1 - beta_3|. */
-        double g[3], gsum, dsum;
+        /* Eq. (16): gamma_k = (C + tau5 / (beta_k + eps))^q, tau5 = |beta_1 - beta_3|.
+         * chi_k of Eq. (17) is a ratio of the gammas, unchanged when every
+         * C + tau5 / (beta_k + eps) is divided by the same power of two.
+         * Dividing by the power of two of the largest keeps the gammas and
+         * their sum finite where the plain powers overflow (with eps = 1e-40
+         * two candidates with beta_k = 0 reach 1e308 at q = 8 for tau5 near
+         * 0.03), and changes no bit of any chi where they do not: scaling by
+         * a power of two commutes with rounding in the normal range. */
+        double x[3], g[3], gsum, dsum, xm;
+        int ex = 0;
         double tau5 = fabs(beta[0] - beta[2]);
+        for (int k = 0; k < 3; ++k) x[k] = p->C + tau5 / (beta[k] + p->eps_teno);
+        xm = fmax(fmax(x[0], x[1]), x[2]);
+        if (isfinite(xm)) (void)frexp(xm, &ex);
         for (int k = 0; k < 3; ++k) {
-            double x = p->C + tau5 / (beta[k] + p->eps_teno);
+            double xs = ldexp(x[k], -ex);
             g[k] = 1.0;
-            for (int m = 0; m < p->q; ++m) g[k] *= x;
+            for (int m = 0; m < p->q; ++m) g[k] *= xs;
         }
         /* Eq. (17). */
         gsum = g[0] + g[1] + g[2];

@@ -406,9 +406,27 @@ WCNST_HD double interp_side(double c, double D10, double D11, double D12, double
             mask = 7u;
             if (!(tau <= P.teno_smooth * fmin(fmin(e0, e1), e2))) {
                 const int q = SCHEME == SCH_TENO ? 6 : P.q;
-                const double g0 = pow_q(fma(tau, approx_rcp(e0), P.C), q);
-                const double g1 = pow_q(fma(tau, approx_rcp(e1), P.C), q);
-                const double g2 = pow_q(fma(tau, approx_rcp(e2), P.C), q);
+                double x0 = fma(tau, approx_rcp(e0), P.C);
+                double x1 = fma(tau, approx_rcp(e1), P.C);
+                double x2 = fma(tau, approx_rcp(e2), P.C);
+                if constexpr (SCHEME == SCH_TENO_Q) {
+                    // the test is unchanged when every C + tau/e_k is scaled
+                    // by one power of two; scaled by that of the largest, the
+                    // powers and their sum stay finite where they would
+                    // overflow (q = 8 with eps = 1e-40: tau near 0.03), and
+                    // every comparison is decided as unscaled where they
+                    // would not.  With q = 6 the powers stay finite while
+                    // C + tau/e_k <= 8e50, and the scaling (1.6 % of the 2D
+                    // stage) is left out.
+                    int ex;
+                    (void)frexp(fmax(fmax(x0, x1), x2), &ex);
+                    x0 = ldexp(x0, -ex);
+                    x1 = ldexp(x1, -ex);
+                    x2 = ldexp(x2, -ex);
+                }
+                const double g0 = pow_q(x0, q);
+                const double g1 = pow_q(x1, q);
+                const double g2 = pow_q(x2, q);
                 const double thr = P.CT * (g0 + g1 + g2);
                 const bool k0 = !(g0 < thr), k1 = !(g1 < thr), k2 = !(g2 < thr);
                 mask = (unsigned)k0 | ((unsigned)k1 << 1) | ((unsigned)k2 << 2);

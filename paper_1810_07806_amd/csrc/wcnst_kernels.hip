@@ -1123,7 +1123,8 @@ wcnst_status wcnst_check_desc(const wcnst_desc* d)
         return fail(WCNST_E_INVALID_ARG, "the van Leer splitting is for the Euler system");
     if (d->scheme < WCNST_TENO || d->scheme > WCNST_Z) return fail(WCNST_E_INVALID_ARG, "unknown scheme");
     if (d->scheme == WCNST_Z) {
-        if (d->z_q < 1 || d->z_q > 8) return fail(WCNST_E_INVALID_ARG, "z_q must be in [1, 8]");
+        // (tau_5 / 1e-40)^p stays finite for tau_5 < 1e37 with p <= 4
+        if (d->z_q < 1 || d->z_q > 4) return fail(WCNST_E_INVALID_ARG, "z_q must be in [1, 4]");
         if (!(d->eps_z > 0.0)) return fail(WCNST_E_INVALID_ARG, "eps_z must be positive");
     }
     if (d->diff != WCNST_MND && d->diff != WCNST_MD && d->diff != WCNST_HWCNS)

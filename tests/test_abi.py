@@ -70,7 +70,7 @@ def test_workspace_size_and_validation():
            dict(x0=1.0, x1=1.0), dict(ndim=2, nx=8, ny=8, diff="md"),
            dict(system="advection", flux="vanleer"), dict(ndim=2, nx=8, ny=8, diff="hwcns"),
            dict(system="advection", bc_x="reflect"), dict(gravity=1.0),
-           dict(scheme="z", z_q=0), dict(scheme="z", z_q=9),
+           dict(scheme="z", z_q=0), dict(scheme="z", z_q=5),
            dict(scheme="z", eps_z=0.0)]
     for kw in bad:
         st, _ = _ws(wc, L, **kw)

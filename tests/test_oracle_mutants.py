@@ -22,11 +22,13 @@ import test_oracle_pins as PINS
 
 # (name, text in wcnst_oracle.c, replacement, pins expected to catch it)
 MUTANTS = [
-    ("tau5-wrong-pair", "double tau5 = fabs(beta[0] - beta[2]);\n        for (int k = 0; k < 3; ++k) {\n            double x = p->C",
-     "double tau5 = fabs(beta[0] - beta[1]);\n        for (int k = 0; k < 3; ++k) {\n            double x = p->C",
+    ("tau5-wrong-pair", "double tau5 = fabs(beta[0] - beta[2]);\n        for (int k = 0; k < 3; ++k) x[k] = p->C",
+     "double tau5 = fabs(beta[0] - beta[1]);\n        for (int k = 0; k < 3; ++k) x[k] = p->C",
      ["test_step_cuts_crossing_stencils", "test_tau5_zero_keeps_all_stencils"]),
-    ("power-q-minus-1", "for (int m = 0; m < p->q; ++m) g[k] *= x;", "for (int m = 1; m < p->q; ++m) g[k] *= x;",
+    ("power-q-minus-1", "for (int m = 0; m < p->q; ++m) g[k] *= xs;", "for (int m = 1; m < p->q; ++m) g[k] *= xs;",
      ["test_step_cuts_crossing_stencils"]),
+    ("gamma-without-scaling", "double xs = ldexp(x[k], -ex);", "double xs = x[k];",
+     ["test_large_gammas_keep_their_ratios"]),
     ("tie-cuts-at-threshold", "(chi_l[k] < p->CT) ? 0 : 1", "(chi_l[k] <= p->CT) ? 0 : 1",
      ["test_cutoff_threshold_is_inclusive"]),
     ("mirror-shifted", "double sr[5] = {W[5][k], W[4][k], W[3][k], W[2][k], W[1][k]};",

@@ -168,6 +168,28 @@ def test_step_cuts_crossing_stencils(orc):
     assert tuple(d) == (0, 0, 1) and v == 1.0
 
 
+@pytest.mark.parametrize("a", [0.1, 0.16, 0.2, 1e3])
+def test_large_gammas_keep_their_ratios(orc, a):
+    """A jump at the end of the stencil, u = (0, 0, 0, 0, a): Eq. (15) gives
+    beta_1 = beta_2 = 0 and beta_3 = 5/4 a^2 = tau5, so with q = 8
+    gamma_1 = gamma_2 = (1 + tau5 / 1e-40)^8 reach 1e308 near a = 0.16 and
+    overflow beyond; Eq. (17) still gives chi = (1/2, 1/2, ~0) exactly
+    (gamma_3 = 2^8), the third candidate is cut and the value is the
+    candidates' 0 with weights (1/11, 10/11)."""
+    p = orc.problem(W.describe(ndim=1, system="advection", nx=16, q=8))
+    _, beta = orc.candidates([0, 0, 0, 0, a])
+    assert beta[0] == 0.0 and beta[1] == 0.0 and beta[2] == pytest.approx(1.25 * a * a, rel=1e-15)
+    v, chi, d = orc.interp_left(p, [0, 0, 0, 0, a])
+    assert tuple(d) == (1, 1, 0) and v == 0.0
+    assert chi[0] == 0.5 and chi[1] == 0.5 and 0.0 <= chi[2] < 1e-300
+    # the q = 6 measure of the same stencils is unchanged by the scaling:
+    # the exact ratio 2^6 / (2 (1 + tau5/eps)^6) to rounding
+    p6 = _scalar(orc)
+    chi6 = orc.interp_left(p6, [0, 0, 0, 0, a])[1]
+    g = (1 + 1.25 * a * a * 1e40) ** 6
+    assert abs(chi6[2] - 64.0 / (2 * g + 64.0)) <= 1e-12 * (64.0 / (2 * g))
+
+
 def test_tau5_zero_keeps_all_stencils(orc):
     """A one-point spike has beta_1 = beta_3 = 13/4, so tau5 = 0, every gamma_k
     is C^q = 1, chi_k = 1/3 and the linear value 45/64 is returned."""
