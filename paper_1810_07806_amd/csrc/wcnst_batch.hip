@@ -60,7 +60,7 @@ struct wcnst_batch {
     // persist_strips strips, one persistent launch (persist_waves waves per
     // workgroup, persist_group instances each) runs them to their final
     // times; 0 keeps stage launches to the end
-    int persist_strips = 0, persist_waves = 16, persist_group = 1;
+    int persist_strips = 0, persist_waves = 8, persist_group = 1;
     int persist_instances = 0;  // instances the last solve finished in the persistent launch
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double kernel_ms = 0.0;
