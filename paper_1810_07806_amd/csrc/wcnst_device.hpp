@@ -70,6 +70,20 @@ WCNST_HD int face_owner(int j, int n, int w)
     return j / w;
 }
 
+// Work index of launch index L inside a group of n consecutive launch
+// indices [base, base + n).  Consecutive workgroups of a launch go to the 8
+// XCDs in turn (workgroup L to XCD L mod 8), and each XCD has its own L2.
+// The workgroups of a group that land on one XCD take one contiguous run of
+// the group's work indices, so work items that are neighbours in the
+// index order share an L2.  A bijection of [base, base + n): the launch
+// order, and with it which workgroups share a SIMD, is unchanged.
+WCNST_HD int xcd_order(int L, int base, int n)
+{
+    const int l = L - base;
+    const int k = l & 7, per = n >> 3, extra = n & 7;
+    return base + k * per + (k < extra ? k : extra) + (l >> 3);
+}
+
 // Lane `lane` of 1D strip bx on a line of nx cells.  The lane computes
 // midpoint jx+1/2, jx = x0-G+lane (G = 2 for MND, 3 for MD, 1 for HWCNS);
 // the line needs midpoints -G .. jmax = nx-2+G (jmax+G+1 flag slots).

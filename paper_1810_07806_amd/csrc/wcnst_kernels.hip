@@ -929,8 +929,15 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2)
 sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __restrict__ out,
         uint8_t* __restrict__ flags, Ctrl* __restrict__ ctrl, Params P, StageArgs A, int ty, int ty2, int nseg1)
 {
-    sweep2d_block<NV, FLUX, SCHEME, CHAR, MODE, GB>(U, Un, out, flags, ctrl, P, A, ty, ty2, nseg1, (int)blockIdx.x,
-                                                (int)blockIdx.y);
+    // Segments in strip-fastest order, each height group in its own XCD
+    // runs: the strips on either side of a strip, which stage the same halo
+    // columns and the same partly used 128-byte lines of every row, read
+    // them through the same L2 at about the same time.
+    const int ns = (int)gridDim.x;
+    const int L = (int)blockIdx.x + ns * (int)blockIdx.y;
+    const int n1 = ns * nseg1;
+    const int w = L < n1 ? xcd_order(L, 0, n1) : xcd_order(L, n1, ns * (int)gridDim.y - n1);
+    sweep2d_block<NV, FLUX, SCHEME, CHAR, MODE, GB>(U, Un, out, flags, ctrl, P, A, ty, ty2, nseg1, w % ns, w / ns);
 }
 
 // One stage of many independent 2D grids in one launch: block b belongs to

@@ -202,6 +202,12 @@ void hc_in_ieee_range(const double* x, uint8_t* out, int n)
     for (int i = 0; i < n; ++i) out[i] = in_ieee_range(x[i]) ? 1 : 0;
 }
 
+// work index of each launch index of the group [base, base + n)
+void hc_xcd_order(int base, int n, int* out)
+{
+    for (int i = 0; i < n; ++i) out[i] = xcd_order(base + i, base, n);
+}
+
 int hc_strip1d_check(int nx, int diff_md)
 {
     return diff_md == 2 ? strip_check<DIFF_HW>(nx) : (diff_md ? strip_check<DIFF_MD>(nx) : strip_check<DIFF_MND>(nx));

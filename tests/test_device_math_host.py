@@ -126,6 +126,29 @@ def test_strip_geometry_of_the_1d_kernel(hc):
             assert hc.hc_strip1d_check(nx, md) == 0, (nx, md)
 
 
+def test_xcd_order_of_2d_segments(hc):
+    """The 2D stage launch's workgroup-to-segment order: within each group of
+    equal-height segments a permutation of the group's indices, in which the
+    workgroups that share an XCD (launch index mod 8) take one contiguous run
+    in launch order.  Group sizes of the 2048^2 launch (34 strips x 30 long
+    and x 29 short segments) and others, with every start modulo 8."""
+    hc.hc_xcd_order.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    sizes = list(range(0, 40)) + [34 * 30, 34 * 29, 1024, 2006, 4097]
+    for n in sizes:
+        for base in (0, 1, 5, 7, 1020, 34 * 30):
+            out = np.zeros(n, dtype=np.int32)
+            hc.hc_xcd_order(base, n, out.ctypes.data)
+            assert sorted(out.tolist()) == list(range(base, base + n)), (base, n)
+            L = np.arange(base, base + n)
+            for x in range(8):
+                w = out[L % 8 == x]
+                if w.size:
+                    assert np.all(np.diff(w) == 1), (base, n, x)
+            # runs follow the order of the XCDs' first workgroups
+            firsts = [out[L % 8 == (base + k) % 8][0] for k in range(min(n, 8))]
+            assert firsts == sorted(firsts), (base, n)
+
+
 def test_ieee_range_predicate(hc):
     """The range test that routes a lane to the ranged reciprocal and root
     (positive x in [2^-767, 2^1022)) at its edges and on special values,
