@@ -425,7 +425,8 @@ template <int FLUX, int SCHEME, bool CHAR, bool GB>
 __global__ void __launch_bounds__(WAVE)
 sweep1d_multi(const ReqGrid* __restrict__ reqs, const int* __restrict__ map, int nreq, int stage, int tick_step)
 {
-    const int b = (int)blockIdx.x;
+    // the strips of one XCD are one contiguous run of the table's strips
+    const int b = xcd_order((int)blockIdx.x, 0, (int)gridDim.x);
     ReqGrid R = load_request(reqs, map, nreq, b);
     // every field the strip geometry and the stencil loads need, loaded in
     // one round trip before any of them is used
@@ -950,7 +951,8 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2)
 sweep2d_multi(const ReqGrid* __restrict__ reqs, const int* __restrict__ map, int nreq, int stage, int tick_step,
               int ty)
 {
-    const int b = (int)blockIdx.x;
+    // the segments of one XCD are one contiguous run of the table's segments
+    const int b = xcd_order((int)blockIdx.x, 0, (int)gridDim.x);
     ReqGrid R = load_request(reqs, map, nreq, b);
     // the fields the segment geometry and the first row loads need, loaded
     // in one round trip before any of them is used
