@@ -1331,11 +1331,11 @@ struct SegMap {
 // SIMDs (more wavefronts than SIMDs, no more than the slots) is balanced:
 // a SIMD issues from its oldest wavefront first, so of the two that share
 // it (blocks b and b + SIMDs in dispatch order, measured) the first runs at
-// about its lone speed while the second, measured, advances 0.45 as fast,
-// then finishes alone.  The first-dispatched rows of segments take a rows
-// and the others c rows with c + 3 = 0.45 (a + 3) (3: the extra rows of
-// y-midpoints of a segment), so that both wavefronts of a SIMD finish
-// together: 2048^2 stage 0.45 -> 0.41 ms.
+// about its lone speed while the second, measured, advances about 0.48 as
+// fast, then finishes alone.  The first-dispatched rows of segments take a
+// rows and the others c rows with c + 3 = 0.48 (a + 3) (3: the extra rows
+// of y-midpoints of a segment), so that both wavefronts of a SIMD finish
+// together: 2048^2 stage 0.45 -> 0.41 ms (47 and 22 rows).
 static SegMap stage_segments(int nstrips, int ny, int ty, int slots, bool balance)
 {
     const int nseg = (ny + ty - 1) / ty;
@@ -1346,7 +1346,7 @@ static SegMap stage_segments(int nstrips, int ny, int ty, int slots, bool balanc
     if (waves <= simds || waves > slots) return one;
     const int na = (int)(simds / nstrips);
     if (na < 1) return one;
-    const double r = 0.45;
+    const double r = 0.48;
     const int a = (int)std::lround(((double)ny / na + 3.0 - 3.0 * r) / (1.0 + r));
     if (a < 1 || (long long)a * na >= ny) return one;
     const int rest = ny - a * na;
