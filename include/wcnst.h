@@ -101,8 +101,9 @@ typedef struct wcnst_solver wcnst_solver;
  * for WCNS-Z p = 1 and eps_z = 1e-40. */
 wcnst_status wcnst_desc_init(wcnst_desc* d);
 
-/* Device workspace bytes needed by a solver for *d (control block plus two
- * Runge-Kutta stage buffers).  Returns WCNST_E_INVALID_ARG for a bad desc. */
+/* Device workspace bytes needed by a solver for *d (control block, two
+ * Runge-Kutta stage buffers and, in 2D, 33 KB of segment-layout tables).
+ * Returns WCNST_E_INVALID_ARG for a bad desc. */
 wcnst_status wcnst_workspace_size(const wcnst_desc* d, size_t* bytes);
 
 /* Validate *d and create a handle bound to hip_stream (a hipStream_t; NULL is
@@ -200,6 +201,19 @@ wcnst_status wcnst_set_tuning(wcnst_solver* s, int32_t rows_per_segment);
  * launches use one height. */
 wcnst_status wcnst_stage_shape(const wcnst_solver* s, int32_t* strips, int32_t* rows1, int32_t* rows2,
                                int32_t* nseg1, int32_t* nseg);
+
+/* Rows of the first-height segments in the next two-height 2D stage launch.
+ * Those segments do not keep rows1 rows each: every launch records how long
+ * each took, and the launch after next moves rows from the segments that
+ * took longer (where the stencil-cut test of Sec. 2.3 runs in full, near
+ * discontinuities) to the others, so that all wavefronts finish about
+ * together; the first nseg1 * rows1 rows of a strip stay theirs.  Only the
+ * decomposition changes, never the results.  On return *count is strips *
+ * (nseg1 + 1), the boundaries [strip][0 .. nseg1] (row 0 up to nseg1 *
+ * rows1), or 0 where stage launches use fixed heights (1D, one height, a
+ * tuning set, the allocation-free solve).  rows (host, nullable): filled
+ * when cap >= *count, after the solver's stream has drained. */
+wcnst_status wcnst_stage_layout(wcnst_solver* s, int32_t* rows, int32_t cap, int32_t* count);
 
 /* Kernel timing for roofline reports: when enabled, every stage kernel is
  * bracketed by HIP events on the solver's stream.  wcnst_profile_read

@@ -84,6 +84,54 @@ WCNST_HD int xcd_order(int L, int base, int n)
     return base + k * per + (k < extra ? k : extra) + (l >> 3);
 }
 
+// Rows of the n segments of one strip for the next stage launch, from the
+// rows they had (boundaries b[0] = 0 < b[1] < .. < b[n]) and what each took
+// (d[i] > 0, any unit).  A segment of r rows also computes about H rows of
+// y-midpoints before its first row, so its cost per row is d[i] / (r + H);
+// the new boundaries cut the strip's cost, so read, into n equal parts,
+// each moved half way from the old boundary (the costs move with the flow
+// and are measured one launch late), and keep every segment at least minr
+// rows (b[n] >= n * minr).  With a zero duration the layout is kept.  out
+// must not alias b or d.
+WCNST_HD void plan_strip(const int* b, const unsigned* d, int n, int minr, int* out)
+{
+    constexpr float H = 3.0f;
+    float total = 0.0f;
+    bool ok = true;
+    for (int i = 0; i < n; ++i) {
+        const int rows = b[i + 1] - b[i];
+        ok = ok && d[i] > 0u && rows > 0;
+        total += (float)d[i] * (float)rows / ((float)rows + H);
+    }
+    out[0] = b[0];
+    out[n] = b[n];
+    if (!ok) {
+        for (int k = 1; k < n; ++k) out[k] = b[k];
+        return;
+    }
+    const float target = total / (float)n;
+    int k = 1;
+    float acc = 0.0f;
+    for (int i = 0; i < n && k < n; ++i) {
+        const int rows = b[i + 1] - b[i];
+        const float rho = (float)d[i] / ((float)rows + H);
+        const float c = rho * (float)rows;
+        while (k < n && acc + c >= target * (float)k) {
+            const float pos = (float)b[i] + (target * (float)k - acc) / rho;
+            int nb = (int)floorf(0.5f * ((float)b[k] + pos) + 0.5f);
+            const int lo = out[k - 1] + minr, hi = b[n] - (n - k) * minr;
+            out[k] = nb < lo ? lo : (nb > hi ? hi : nb);
+            ++k;
+        }
+        acc += c;
+    }
+    // boundaries that rounding left unplaced keep their rows
+    for (; k < n; ++k) {
+        const int lo = out[k - 1] + minr, hi = b[n] - (n - k) * minr;
+        out[k] = b[k] < lo ? lo : (b[k] > hi ? hi : b[k]);
+    }
+}
+
 // Lane `lane` of 1D strip bx on a line of nx cells.  The lane computes
 // midpoint jx+1/2, jx = x0-G+lane (G = 2 for MND, 3 for MD, 1 for HWCNS);
 // the line needs midpoints -G .. jmax = nx-2+G (jmax+G+1 flag slots).

@@ -733,15 +733,78 @@ __device__ __forceinline__ void store_row(double (*slot)[XW], int lane, bool has
     }
 }
 
+// Adaptive rows of the first-height segments of a balanced 2D stage launch
+// (the older wavefront of each SIMD pair runs at its lone speed, so its
+// segment's cost sets when the SIMD is done; where the stencil-cut test
+// runs in full, near discontinuities, a segment of equal rows costs more).
+// In a launch of parity p (alternating, set by the host), strip s's
+// first-height segment i takes rows [tab[p][s][i], tab[p][s][i+1]).  Each
+// such wavefront records what it took in cost[p]; the first wavefront of
+// the launch to finish re-plans tab[1-p] (the previous launch's layout)
+// from cost[1-p] (the previous launch's durations) for the next launch.
+// So no launch reads a table that it or a running launch writes, and every
+// table is a partition of the rows (plan_strip keeps it one).  The layout
+// moves only work between wavefronts: every cell's arithmetic, and so
+// every result, is the same.  The block sits in the padding after the
+// solver's control block (no kernel argument holds registers through the
+// sweep); on == 0 there: fixed heights.
+struct SegCtl {
+    int* tab[2];        // [strips][nseg1 + 1] boundaries
+    unsigned* cost[2];  // [strips][nseg1] durations (10 ns ticks)
+    unsigned* ctr;      // wavefronts of the running launch that have finished (0 between launches)
+    int minr;           // fewest rows of a segment
+    int on;
+};
+constexpr size_t SEGCTL_OFFSET = 128;
+static_assert(sizeof(Ctrl) <= SEGCTL_OFFSET && SEGCTL_OFFSET + sizeof(SegCtl) <= 256,
+              "the layout block must fit the control block's 256-byte slot");
+
+__host__ __device__ inline SegCtl* seg_ctl_of(Ctrl* ctrl)
+{
+    return reinterpret_cast<SegCtl*>(reinterpret_cast<char*>(ctrl) + SEGCTL_OFFSET);
+}
+
+// Records the duration of first-height segment cost_idx (-1: a
+// second-height one), counts the wavefront, and, in the launch's first
+// finisher, plans
+// every strip of the next launch, staging each strip's boundaries and
+// durations in LDS the wavefront no longer needs (lds: strips * (2 nseg1 +
+// 1) ints, checked by the host).  The launch's last finisher clears the
+// count (as does the start of every solve call).
+__device__ __forceinline__ void seg_finish(SegCtl* __restrict__ seg, int par, int cost_idx, unsigned ticks, int nseg1,
+                                           int* lds)
+{
+    const int ns = (int)gridDim.x, total = (int)(gridDim.x * gridDim.y);
+    unsigned old = 0u;
+    if (threadIdx.x == 0) {
+        if (cost_idx >= 0) seg->cost[par][cost_idx] = ticks > 0u ? ticks : 1u;
+        old = __hip_atomic_fetch_add(seg->ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the last to finish: every wavefront has counted
+        if (old == (unsigned)total - 1u) __hip_atomic_store(seg->ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    old = __shfl(old, 0);
+    if (old != 0u) return;
+    const int n = nseg1;
+    int* tab = seg->tab[par ^ 1];
+    const unsigned* cost = seg->cost[par ^ 1];
+    for (int st = (int)threadIdx.x; st < ns; st += WAVE) {
+        int* b = lds + (size_t)st * (2 * n + 1);
+        unsigned* d = reinterpret_cast<unsigned*>(b + n + 1);
+        for (int i = 0; i <= n; ++i) b[i] = tab[(size_t)st * (n + 1) + i];
+        for (int i = 0; i < n; ++i) d[i] = cost[(size_t)st * n + i];
+        plan_strip(b, d, n, seg->minr, tab + (size_t)st * (n + 1));
+    }
+}
+
 // One segment (strip bx, rows by*ty ..) of one 2D grid.  Thread 0 of
 // segment (0, 0) opens the next step record.
 // GB: general boundaries (reflecting walls, fixed ends, gravity); without
 // it only index-remap sides (periodic, zero gradient) and no source.
-template <int NV, int FLUX, int SCHEME, bool CHAR, int MODE, bool GB>
+template <int NV, int FLUX, int SCHEME, bool CHAR, int MODE, bool GB, bool ADAPT>
 __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, const double* __restrict__ Un,
                                               double* __restrict__ out, uint8_t* __restrict__ flags,
                                               Ctrl* __restrict__ ctrl, const Params& P, const StageArgs& A,
-                                              int ty, int ty2, int nseg1, int bx, int by)
+                                              int ty, int ty2, int nseg1, int bx, int by, int seg_par)
 {
     // segment by of the strip: segments 0 .. nseg1-1 hold ty rows each, the
     // later ones ty2 (ty2 == ty: one height; cut flags need one height)
@@ -762,8 +825,30 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
     const size_t plane = (size_t)nx * ny;
     const int lane = threadIdx.x;
     const int x0 = bx * TX;
-    const int y0 = by < nseg1 ? by * ty : nseg1 * ty + (by - nseg1) * ty2;
-    const int y1 = min(y0 + (by < nseg1 ? ty : ty2), ny);
+    int y0 = by < nseg1 ? by * ty : nseg1 * ty + (by - nseg1) * ty2;
+    int y1 = y0 + (by < nseg1 ? ty : ty2);
+    // the segment's duration slot and start time wait in LDS (kept out of
+    // registers through the sweep)
+    __shared__ int seg_slot, seg_p;
+    __shared__ unsigned seg_t0;
+    if constexpr (MODE == MODE_STAGE && ADAPT) {
+        SegCtl* seg = seg_ctl_of(ctrl);
+        int slot = -1;
+        // plain loads of values no wave changes during the launch, kept
+        // uniform (scalar) so that the sweep's row bounds stay scalar
+        if (by < nseg1 && __builtin_amdgcn_readfirstlane(seg->on)) {
+            const int* lrow = seg->tab[seg_par] + (size_t)bx * (nseg1 + 1) + by;
+            y0 = __builtin_amdgcn_readfirstlane(lrow[0]);
+            y1 = __builtin_amdgcn_readfirstlane(lrow[1]);
+            slot = bx * nseg1 + by;
+        }
+        if (threadIdx.x == 0) {
+            seg_slot = slot;
+            seg_p = seg_par;
+            seg_t0 = (unsigned)__builtin_amdgcn_s_memrealtime();
+        }
+    }
+    y1 = min(y1, ny);
     const int c = x0 + lane;
     const bool cell_ok = lane < TX && c < nx;
     const int jx = x0 - 2 + lane;
@@ -920,6 +1005,12 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
     }
     if constexpr (MODE == MODE_STAGE) {
         if (A.stage == 2) flush_speed(ctrl, A.parity, smax_loc, seen);
+        if constexpr (ADAPT) {
+            SegCtl* seg = seg_ctl_of(ctrl);
+            if (__builtin_amdgcn_readfirstlane(seg->on))
+                seg_finish(seg, seg_p, seg_slot, (unsigned)__builtin_amdgcn_s_memrealtime() - seg_t0, nseg1,
+                           reinterpret_cast<int*>(&ring[0][0][0]));
+        }
     }
 }
 
@@ -928,7 +1019,8 @@ __device__ __forceinline__ void sweep2d_block(const double* __restrict__ U, cons
 template <int NV, int FLUX, int SCHEME, bool CHAR, int MODE, bool GB>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2)))
 sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __restrict__ out,
-        uint8_t* __restrict__ flags, Ctrl* __restrict__ ctrl, Params P, StageArgs A, int ty, int ty2, int nseg1)
+        uint8_t* __restrict__ flags, Ctrl* __restrict__ ctrl, Params P, StageArgs A, int ty, int ty2, int nseg1,
+        int seg_par)
 {
     // Segments in strip-fastest order, each height group in its own XCD
     // runs: the strips on either side of a strip, which stage the same halo
@@ -938,7 +1030,8 @@ sweep2d(const double* __restrict__ U, const double* __restrict__ Un, double* __r
     const int L = (int)blockIdx.x + ns * (int)blockIdx.y;
     const int n1 = ns * nseg1;
     const int w = L < n1 ? xcd_order(L, 0, n1) : xcd_order(L, n1, ns * (int)gridDim.y - n1);
-    sweep2d_block<NV, FLUX, SCHEME, CHAR, MODE, GB>(U, Un, out, flags, ctrl, P, A, ty, ty2, nseg1, w % ns, w / ns);
+    sweep2d_block<NV, FLUX, SCHEME, CHAR, MODE, GB, true>(U, Un, out, flags, ctrl, P, A, ty, ty2, nseg1, w % ns,
+                                                      w / ns, seg_par);
 }
 
 // One stage of many independent 2D grids in one launch: block b belongs to
@@ -965,8 +1058,9 @@ sweep2d_multi(const ReqGrid* __restrict__ reqs, const int* __restrict__ map, int
     double* out = stage == 0 ? R.U1 : (stage == 1 ? R.U2 : R.U);
     // one height: every segment of the grid is of the first kind (an exact
     // count keeps nseg1 * ty within the grid)
-    sweep2d_block<NV, FLUX, SCHEME, CHAR, MODE_STAGE, GB>(in, R.U, out, nullptr, R.ctrl, P, A, ty, ty,
-                                                      (P.ny + ty - 1) / ty, local % R.nstrips, local / R.nstrips);
+    sweep2d_block<NV, FLUX, SCHEME, CHAR, MODE_STAGE, GB, false>(in, R.U, out, nullptr, R.ctrl, P, A, ty, ty,
+                                                             (P.ny + ty - 1) / ty, local % R.nstrips,
+                                                             local / R.nstrips, 0);
 }
 
 // ----------------------------------------------------- control kernels
@@ -1030,6 +1124,10 @@ __global__ void ctrl_open(Ctrl* ctrl, int parity)
     ctrl->rec[parity].smax_bits = 0ull;
     ctrl->done = 0;
     ctrl->call_step0 = ctrl->rec[parity].step;
+    // a launch that stopped part of its wavefronts early (a non-physical
+    // state found during it) leaves the adaptive layout's count behind
+    SegCtl* seg = seg_ctl_of(ctrl);
+    if (seg->on) *seg->ctr = 0u;
 }
 
 template <int SYS, int NV>
@@ -1093,6 +1191,14 @@ struct wcnst_solver {
     bool ty_user;  // set by wcnst_set_tuning (else chosen at creation)
     int split_strips;  // 1D Euler stages over at most this many strips run in the latency mode
     int slots;     // wavefront slots of the device
+    // adaptive first-height segment rows of balanced 2D stage launches (in
+    // the workspace; off where the shape does not take them)
+    bool seg_on;
+    int seg_n1;             // first-height segments per strip the tables hold
+    int* seg_tab;           // two tables of LAYOUT_CAP ints
+    unsigned* seg_cost;     // two duration arrays of LAYOUT_CAP
+    unsigned* seg_ctr;
+    mutable long long seg_launch;  // balanced stage launches so far (their parity selects the tables)
     bool prof;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used;
@@ -1189,13 +1295,51 @@ extern "C" wcnst_status wcnst_desc_init(wcnst_desc* d)
     return WCNST_OK;
 }
 
+// Entries of one adaptive layout table (and of one duration array).  The
+// planner also stages a strip's boundaries and durations in the LDS of the
+// 2D stage's row ring: strips * (2 nseg1 + 1) ints, at most LAYOUT_LDS_INTS.
+constexpr int LAYOUT_CAP = 2048;
+constexpr int LAYOUT_LDS_INTS = (int)(sizeof(double) * NSLOT * 4 * XW / sizeof(int));
+static size_t layout_bytes()
+{
+    return 2 * sizeof(int) * LAYOUT_CAP + 2 * sizeof(unsigned) * LAYOUT_CAP + 256;
+}
+
+// Both layout tables at the fixed heights (boundary i of every strip at
+// i * ty), no durations yet, counter clear, and the block beside the
+// control block that points at them (on = 0: fixed heights, nothing else
+// is touched).
+__global__ void __launch_bounds__(256) layout_init(Ctrl* ctrl, int on, int* tab, unsigned* cost, unsigned* ctr,
+                                                   int ns, int n1, int ty, int minr)
+{
+    SegCtl* ctl = seg_ctl_of(ctrl);
+    if (on) {
+        for (int k = (int)threadIdx.x; k < ns * (n1 + 1); k += (int)blockDim.x) {
+            const int i = k % (n1 + 1);
+            tab[k] = i * ty;
+            tab[LAYOUT_CAP + k] = i * ty;
+        }
+        for (int k = (int)threadIdx.x; k < 2 * LAYOUT_CAP; k += (int)blockDim.x) cost[k] = 0u;
+    }
+    if (threadIdx.x == 0) {
+        if (on) *ctr = 0u;
+        ctl->tab[0] = on ? tab : nullptr;
+        ctl->tab[1] = on ? tab + LAYOUT_CAP : nullptr;
+        ctl->cost[0] = on ? cost : nullptr;
+        ctl->cost[1] = on ? cost + LAYOUT_CAP : nullptr;
+        ctl->ctr = on ? ctr : nullptr;
+        ctl->minr = minr;
+        ctl->on = on;
+    }
+}
+
 extern "C" wcnst_status wcnst_workspace_size(const wcnst_desc* d, size_t* bytes)
 {
     wcnst_status st = wcnst_check_desc(d);
     if (st) return st;
     if (!bytes) return fail(WCNST_E_INVALID_ARG, "null size pointer");
     const size_t state = (size_t)wcnst_desc_nvar(d) * d->nx * d->ny * sizeof(double);
-    *bytes = align256(sizeof(Ctrl)) + 2 * align256(state);
+    *bytes = align256(sizeof(Ctrl)) + 2 * align256(state) + (d->ndim == 2 ? align256(layout_bytes()) : 0);
     return WCNST_OK;
 }
 
@@ -1250,6 +1394,8 @@ void wcnst_make_params(const wcnst_desc* d, Params* out)
     *out = P;
 }
 
+static wcnst_status layout_reset(wcnst_solver* s);
+
 extern "C" wcnst_status wcnst_create(const wcnst_desc* d, void* hip_stream, void* workspace,
                                      size_t ws_bytes, wcnst_solver** out)
 {
@@ -1275,6 +1421,12 @@ extern "C" wcnst_status wcnst_create(const wcnst_desc* d, void* hip_stream, void
     s->ctrl = (Ctrl*)ws;
     s->U1 = (double*)(ws + align256(sizeof(Ctrl)));
     s->U2 = (double*)(ws + align256(sizeof(Ctrl)) + align256(state));
+    if (d->ndim == 2) {
+        uint8_t* lw = ws + align256(sizeof(Ctrl)) + 2 * align256(state);
+        s->seg_tab = (int*)lw;
+        s->seg_cost = (unsigned*)(lw + 2 * sizeof(int) * LAYOUT_CAP);
+        s->seg_ctr = (unsigned*)(lw + 2 * sizeof(int) * LAYOUT_CAP + 2 * sizeof(unsigned) * LAYOUT_CAP);
+    }
     s->parity = 0;
     s->slots = wcnst_wave_slots();
     s->ty_user = false;
@@ -1301,6 +1453,11 @@ extern "C" wcnst_status wcnst_create(const wcnst_desc* d, void* hip_stream, void
     if (e != hipSuccess) {
         wcnst_destroy(s);
         return fail(WCNST_E_HIP, "control init launch failed: %s", hipGetErrorString(e));
+    }
+    st = layout_reset(s);
+    if (st) {
+        wcnst_destroy(s);
+        return st;
     }
     *out = s;
     return WCNST_OK;
@@ -1356,6 +1513,26 @@ static SegMap stage_segments(int nstrips, int ny, int ty, int slots, bool balanc
     return SegMap{a, c, na, na + nb};
 }
 
+// Adaptive layout for the solver's balanced stage shape (2D, heights chosen
+// by the library), or off: one height, a shape beyond the tables or the
+// planner's LDS, heights set by the caller, or no tables (the
+// allocation-free solve).
+static wcnst_status layout_reset(wcnst_solver* s)
+{
+    s->seg_on = false;
+    const int ns = (s->d.nx + TX - 1) / TX;
+    const SegMap m = s->d.ndim == 2 ? stage_segments(ns, s->d.ny, s->ty, s->slots, true) : SegMap{1, 1, 1, 1};
+    const bool on = s->d.ndim == 2 && s->seg_tab && !s->ty_user && m.nseg1 < m.nseg &&
+                    (long long)ns * (m.nseg1 + 1) <= LAYOUT_CAP && (long long)ns * (2 * m.nseg1 + 1) <= LAYOUT_LDS_INTS;
+    hipLaunchKernelGGL(layout_init, dim3(1), dim3(256), 0, s->stream, s->ctrl, on ? 1 : 0, s->seg_tab, s->seg_cost,
+                       s->seg_ctr, ns, m.nseg1, m.ty, std::max(1, m.ty / 4));
+    HIP_TRY(hipGetLastError());
+    s->seg_n1 = m.nseg1;
+    s->seg_launch = 0;
+    s->seg_on = on;
+    return WCNST_OK;
+}
+
 template <int SYS, int NV, int FLUX, int SCHEME, bool CHAR, int MODE>
 static void launch_sweep_t(const wcnst_solver* s, const double* U, const double* Un, double* out,
                            uint8_t* flags, const StageArgs& A)
@@ -1364,12 +1541,17 @@ static void launch_sweep_t(const wcnst_solver* s, const double* U, const double*
         const int nstrips = (s->d.nx + TX - 1) / TX;
         // cut flags (right-hand-side launches) need one segment height
         const SegMap m = stage_segments(nstrips, s->d.ny, s->ty, s->slots, MODE == MODE_STAGE && !s->ty_user);
+        int seg_par = 0;
+        if (MODE == MODE_STAGE && s->seg_on && m.nseg1 < m.nseg) {
+            seg_par = (int)(s->seg_launch & 1);
+            s->seg_launch += 1;
+        }
         if (wcnst_general_bc(&s->d))
             hipLaunchKernelGGL((sweep2d<NV, FLUX, SCHEME, CHAR, MODE, true>), dim3(nstrips, m.nseg), dim3(WAVE), 0,
-                               s->stream, U, Un, out, flags, s->ctrl, s->P, A, m.ty, m.ty2, m.nseg1);
+                               s->stream, U, Un, out, flags, s->ctrl, s->P, A, m.ty, m.ty2, m.nseg1, seg_par);
         else
             hipLaunchKernelGGL((sweep2d<NV, FLUX, SCHEME, CHAR, MODE, false>), dim3(nstrips, m.nseg), dim3(WAVE), 0,
-                               s->stream, U, Un, out, flags, s->ctrl, s->P, A, m.ty, m.ty2, m.nseg1);
+                               s->stream, U, Un, out, flags, s->ctrl, s->P, A, m.ty, m.ty2, m.nseg1, seg_par);
     } else if (s->d.diff == WCNST_MD) {
         constexpr int W = strip_cells<DIFF_MD>();
         hipLaunchKernelGGL((sweep1d<SYS, NV, FLUX, SCHEME, CHAR, MODE, DIFF_MD>), dim3((s->d.nx + W - 1) / W),
@@ -1771,10 +1953,25 @@ extern "C" wcnst_status wcnst_set_tuning(wcnst_solver* s, int32_t rows_per_segme
         const int strips = (s->d.nx + TX - 1) / TX, rows = s->d.ny;
         s->ty = s->d.ndim == 2 ? wcnst_auto_rows(&strips, &rows, 1, s->slots) : 35;
         s->ty_user = false;
-        return WCNST_OK;
+        return layout_reset(s);
     }
     s->ty = rows_per_segment;
     s->ty_user = true;
+    return layout_reset(s);
+}
+
+extern "C" wcnst_status wcnst_stage_layout(wcnst_solver* s, int32_t* rows, int32_t cap, int32_t* count)
+{
+    if (!s || !count) return fail(WCNST_E_INVALID_ARG, "null argument");
+    *count = 0;
+    if (!s->seg_on) return WCNST_OK;
+    const int n = ((s->d.nx + TX - 1) / TX) * (s->seg_n1 + 1);
+    *count = n;
+    if (!rows || cap < n) return WCNST_OK;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    // the table the next balanced launch reads
+    const int c = (int)(s->seg_launch & 1);
+    HIP_TRY(hipMemcpy(rows, s->seg_tab + (size_t)c * LAYOUT_CAP, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost));
     return WCNST_OK;
 }
 

@@ -22,6 +22,7 @@ _DIFF = {"mnd": 0, "md": 1, "hwcns": 2}
 
 EXPORTS = ("wcnst_desc_init", "wcnst_workspace_size", "wcnst_create", "wcnst_rhs", "wcnst_step",
            "wcnst_solve", "wcnst_status_sync", "wcnst_reset", "wcnst_set_tuning", "wcnst_stage_shape",
+           "wcnst_stage_layout",
            "wcnst_profile_enable",
            "wcnst_profile_read", "wcnst_destroy", "wcnst_last_error",
            "wcnst_batch_workspace_size", "wcnst_batch_create", "wcnst_batch_offsets", "wcnst_batch_solve",
@@ -80,6 +81,7 @@ def lib(path: str | None = None):
     L.wcnst_reset.argtypes = [vp, ctypes.c_double, ctypes.c_int64]
     L.wcnst_set_tuning.argtypes = [vp, ctypes.c_int32]
     L.wcnst_stage_shape.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 5
+    L.wcnst_stage_layout.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     L.wcnst_profile_enable.argtypes = [vp, ctypes.c_int]
     L.wcnst_profile_read.argtypes = [vp, dp, i64p]
     L.wcnst_destroy.argtypes = [vp]
@@ -273,6 +275,20 @@ class Solver:
         v = [ctypes.c_int32() for _ in range(5)]
         _check(lib().wcnst_stage_shape(self._h, *[ctypes.byref(x) for x in v]))
         return dict(zip(("strips", "rows1", "rows2", "nseg1", "nseg"), (x.value for x in v)))
+
+    def stage_layout(self):
+        """Rows of the first-height segments in the next two-height 2D stage
+        launch, an int32 array [strips][nseg1 + 1] of boundaries, or None
+        where stage launches use fixed heights."""
+        import numpy as np
+        n = ctypes.c_int32()
+        _check(lib().wcnst_stage_layout(self._h, None, 0, ctypes.byref(n)))
+        if n.value == 0:
+            return None
+        out = np.zeros(n.value, dtype=np.int32)
+        _check(lib().wcnst_stage_layout(self._h, out.ctypes.data, n.value, ctypes.byref(n)))
+        strips = self.stage_shape()["strips"]
+        return out.reshape(strips, n.value // strips)
 
     def profile_enable(self, on: bool = True):
         _check(lib().wcnst_profile_enable(self._h, 1 if on else 0))

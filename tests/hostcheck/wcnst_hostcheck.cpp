@@ -208,6 +208,12 @@ void hc_xcd_order(int base, int n, int* out)
     for (int i = 0; i < n; ++i) out[i] = xcd_order(base + i, base, n);
 }
 
+// plan_strip over one strip: boundaries b[0..n], durations d[0..n-1] -> out[0..n]
+void hc_plan_strip(const int* b, const unsigned* d, int n, int minr, int* out)
+{
+    plan_strip(b, d, n, minr, out);
+}
+
 int hc_strip1d_check(int nx, int diff_md)
 {
     return diff_md == 2 ? strip_check<DIFF_HW>(nx) : (diff_md ? strip_check<DIFF_MD>(nx) : strip_check<DIFF_MND>(nx));

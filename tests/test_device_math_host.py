@@ -149,6 +149,52 @@ def test_xcd_order_of_2d_segments(hc):
             assert firsts == sorted(firsts), (base, n)
 
 
+def _plan(hc, b, d, minr):
+    hc.hc_plan_strip.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    b = np.ascontiguousarray(b, dtype=np.int32)
+    d = np.ascontiguousarray(d, dtype=np.uint32)
+    out = np.zeros_like(b)
+    hc.hc_plan_strip(b.ctypes.data, d.ctypes.data, len(d), minr, out.ctypes.data)
+    return out
+
+
+def test_segment_planner_keeps_a_partition_and_balances(hc):
+    """The planner of the 2D stage launch's adaptive segment rows: every
+    plan is a partition of the same rows (ends kept, each segment at least
+    minr rows) whatever the durations; equal durations keep the layout; a
+    zero duration keeps it too; and, iterated against durations drawn from a
+    fixed per-row cost with a heavy band (as a shock gives), the plans
+    converge to segments of about equal cost."""
+    n, ty, minr = 30, 47, 11
+    R = n * ty
+    uniform = np.arange(n + 1) * ty
+    assert np.array_equal(_plan(hc, uniform, np.full(n, 3000), minr), uniform)
+    assert np.array_equal(_plan(hc, uniform, np.r_[np.full(n - 1, 3000), 0], minr), uniform)
+    rng = np.random.default_rng(3)
+    for _ in range(300):
+        cuts = np.sort(rng.choice(np.arange(1, R), size=n - 1, replace=False))
+        b = np.r_[0, cuts, R]
+        d = rng.integers(1, 100000, size=n)
+        out = _plan(hc, b, d, minr)
+        assert out[0] == 0 and out[-1] == R
+        assert np.all(np.diff(out) >= minr)
+    # per-row cost 1, rows 600-700 cost 1.6; a segment also pays 3 rows of overhead
+    rho = np.ones(R)
+    rho[600:700] = 1.6
+    cum = np.r_[0.0, np.cumsum(rho)]
+
+    def seg_costs(b):
+        return np.array([cum[b[i + 1]] - cum[b[i]] + 3.0 for i in range(n)])
+
+    b = uniform.copy()
+    before = seg_costs(b).max() / seg_costs(b).mean()
+    for _ in range(12):
+        b = _plan(hc, b, np.round(100 * seg_costs(b)).astype(np.uint32), minr)
+    after = seg_costs(b).max() / seg_costs(b).mean()
+    assert before > 1.4 and after < 1.06, (before, after)
+    assert b[0] == 0 and b[-1] == R and np.all(np.diff(b) >= minr)
+
+
 def test_ieee_range_predicate(hc):
     """The range test that routes a lane to the ranged reciprocal and root
     (positive x in [2^-767, 2^1022)) at its edges and on special values,

@@ -538,6 +538,39 @@ def test_stage_shape_covers_the_grid(torch, n):
         assert (r1, r2, n1, ns) == (47, 22, 30, 59)
 
 
+def test_adaptive_segment_rows_move_and_keep_the_results(torch):
+    """The first-height segment rows of the 2048^2 stage launch follow the
+    flow: after 30 steps of the four-quadrant problem rows have moved from
+    the segments where the stencil-cut test runs in full to the others, and
+    every strip's boundaries are still a partition of its first 30 x 47 rows.
+    The state equals, bit for bit, that of 30 steps with one fixed segment
+    height.  A tuning turns the layout off; clearing it starts it afresh."""
+    import math
+    _say("adaptive layout 2048^2, 30 steps")
+    d, U0 = W.riemann2d_config3(2048)
+    s = _solver(d)
+    R = 30 * 47
+    L0 = s.stage_layout()
+    assert L0 is not None and L0.shape == (34, 31)
+    assert np.array_equal(L0, np.tile(np.arange(31) * 47, (34, 1)))
+    U = s.new_state(U0)
+    s.solve(U, t_final=math.inf, cfl=0.5, max_steps=30)
+    L = s.stage_layout()
+    rows = np.diff(L, axis=1)
+    assert np.all(L[:, 0] == 0) and np.all(L[:, -1] == R)
+    assert rows.min() >= 11 and rows.min() < 47 and rows.max() > 47
+    s2 = _solver(d)
+    s2.set_tuning(47)
+    assert s2.stage_layout() is None
+    V = s2.new_state(U0)
+    s2.solve(V, t_final=math.inf, cfl=0.5, max_steps=30)
+    assert torch.equal(U, V)
+    s.set_tuning(0)
+    assert np.array_equal(s.stage_layout(), L0)
+    s.close()
+    s2.close()
+
+
 def test_randomised_cases_against_the_oracle(orc, torch):
     """A seeded sweep over random 1D and 2D Euler problems: every flux,
     scheme, characteristic or componentwise interpolation, boundary kind,
