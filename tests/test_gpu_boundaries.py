@@ -117,3 +117,33 @@ def test_rayleigh_taylor_paper_run(torch):
     assert np.isfinite(Vh).all() and rho.min() > 0.5
     assert rho[:240].min() < 1.5 and rho[272:].max() > 1.5
     assert np.abs(Vh[2]).max() > 0.1
+
+
+def test_adaptive_rows_with_walls_fixed_ends_and_gravity(torch):
+    """The adaptive first-height rows with the general-boundary stage kernel:
+    Rayleigh-Taylor (reflecting walls, fixed ends, gravity) on 1024 x 4096,
+    a grid whose stage launch is one round of two wavefronts per SIMD.
+    Ten steps equal, bit for bit, ten steps with one fixed segment height,
+    and every strip's boundaries stay a partition of its first-height rows."""
+    import math
+    _say("adaptive layout, Rayleigh-Taylor 1024 x 4096, 10 steps")
+    d, U0 = W.rayleigh_taylor(1024, 4096)
+    s = _solver(d)
+    sh = s.stage_shape()
+    assert sh["nseg1"] < sh["nseg"]
+    L0 = s.stage_layout()
+    assert L0 is not None and L0.shape == (sh["strips"], sh["nseg1"] + 1)
+    R = sh["nseg1"] * sh["rows1"]
+    U = s.new_state(U0)
+    s.solve(U, t_final=math.inf, cfl=0.5, max_steps=10)
+    L = s.stage_layout()
+    assert np.all(L[:, 0] == 0) and np.all(L[:, -1] == R)
+    assert np.all(np.diff(L, axis=1) >= max(1, sh["rows1"] // 4))
+    s2 = _solver(d)
+    s2.set_tuning(64)
+    V = s2.new_state(U0)
+    s2.solve(V, t_final=math.inf, cfl=0.5, max_steps=10)
+    assert s.status()["status"] == 0 and s2.status()["status"] == 0
+    assert torch.equal(U, V)
+    s.close()
+    s2.close()
